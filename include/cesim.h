@@ -1,0 +1,217 @@
+/*
+ * cesim.h -- C ABI of the MI355X (gfx950) library for conditional simulation
+ * of a stationary Gaussian field by circulant embedding, extended to
+ * irregularly spaced observations by local Kriging.
+ *
+ * Method: Bailey, Bandyopadhyay and Nychka, "Adapting conditional simulation
+ * using circulant embedding for irregularly spaced spatial data"
+ * (arXiv 2109.11044).  Section numbers below refer to that paper.
+ *
+ * Call sequence for one event (one covariance model, grid and data set):
+ *
+ *   ce_setup        -- circulant-embedding eigenvalues of the torus
+ *                      covariance (Section 1; Section 2.1 item (a)).
+ *   offgrid_nnkrige -- local-Kriging weights and conditional variances of
+ *                      the off-grid observations from their (2 n_p)^2
+ *                      nearest grid nodes (Section 2.1 items (b)-(c);
+ *                      Section 3.1; Section 3.6).
+ *   ce_simulate     -- unconditional grid realizations y_r by the CE draw
+ *                      (step 2 of the algorithm in Section 2).
+ *   condition       -- synthetic observations z*_r (step 3 under local
+ *                      Kriging), Kriging of z - z*_r onto the grid with the
+ *                      plain nugget (steps 1, 4, 5 and item (d); eq. (4) of
+ *                      Section 3), in place:
+ *                          v_r = y_r + K12 (K22 + tau^2 I)^{-1} (z - z*_r).
+ *   ce_destroy
+ *
+ * ce_simulate and condition may be repeated for further batches of
+ * realizations; condition always applies to the batch the last ce_simulate
+ * produced.
+ *
+ * Conventions
+ *   - Every entry point returns a cesim_status; nothing throws or aborts
+ *     across the ABI.  cesim_status_string() names a status.
+ *   - The context owns every internal device buffer.  The caller owns the
+ *     host input arrays (copied before the call returns) and the device
+ *     field buffers it passes in.
+ *   - Work is enqueued on the HIP stream given to ce_setup (NULL = the
+ *     default stream).  ce_setup, ce_get_info and a condition() call that
+ *     (re)factorises the observation covariance synchronise that stream;
+ *     everything else is asynchronous.
+ *   - Use a context from one host thread at a time.
+ *   - Fields are stored [r][j][i]: realization, grid row (y), grid column
+ *     (x, fastest).  Grid node (i, j) sits at (x0 + i dx, y0 + j dy).
+ *   - Random numbers: Philox4x32-10 keyed by the 64-bit seed; realization r
+ *     depends only on (seed, r), never on how realizations were batched.
+ *
+ * Precision (cesim_precision)
+ *   CESIM_PREC_FP64  : every step in FP64; fields are double.
+ *   CESIM_PREC_MIXED : eigenvalue setup, local-Kriging solves, the
+ *                      observation Cholesky and its solves in FP64; the CE
+ *                      FFT passes in FP32; the cross-covariance product
+ *                      K12 B in BF16 on matrix cores with FP32 accumulation
+ *                      and a three-product split-precision correction;
+ *                      fields are float.
+ */
+#ifndef CESIM_H
+#define CESIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cesim_ctx_s* cesim_ctx;
+
+typedef enum {
+  CESIM_OK = 0,
+  CESIM_ERR_INVALID_ARG = 1,        /* argument out of range or NULL        */
+  CESIM_ERR_NEGATIVE_EIGENVALUE = 2,/* no admissible torus on the ladder    */
+  CESIM_ERR_NOT_POSITIVE_DEFINITE = 3, /* a Cholesky factorisation failed   */
+  CESIM_ERR_OBS_OUTSIDE_GRID = 4,   /* an observation lies outside the grid */
+  CESIM_ERR_OUT_OF_MEMORY = 5,      /* device allocation failed             */
+  CESIM_ERR_HIP = 6,                /* a HIP runtime call failed            */
+  CESIM_ERR_BAD_STATE = 7           /* call out of order                    */
+} cesim_status;
+
+typedef enum { CESIM_PREC_FP64 = 0, CESIM_PREC_MIXED = 1 } cesim_precision;
+
+/* Matern covariance (Section 3.3):
+ *   C(h) = sigma2 * 2^(1-nu)/Gamma(nu) * (sqrt(2 nu) d/range)^nu
+ *                 * K_nu(sqrt(2 nu) d/range),
+ * with d the anisotropic lag length sqrt(u^2 + aniso_ratio^2 w^2), where
+ * (u, w) is the lag rotated by -aniso_angle (range along aniso_angle,
+ * range/aniso_ratio across it).  nu must be 0.5, 1.0 or 1.5;
+ * sigma2 > 0; range > 0; aniso_ratio >= 1. */
+typedef struct {
+  double nu;
+  double sigma2;
+  double range;
+  double aniso_ratio;
+  double aniso_angle;
+} cesim_cov;
+
+/* Regular m1 x m2 grid with spacing (dx, dy) > 0 and origin (x0, y0).
+ * t1, t2: torus size; 0 chooses it by the ladder S(f m) for
+ * f = 2, 3, 4, 6, 8 (S(n): smallest 2^a 3^b 5^c >= n), the first with
+ * min eigenvalue >= -1e-12 max eigenvalue.  A forced size must be
+ * >= 2 m - 1 on each axis, a product of 2, 3 and 5, and at most 8192. */
+typedef struct {
+  int m1, m2;
+  double x0, y0, dx, dy;
+  int t1, t2;
+} cesim_grid;
+
+typedef struct {
+  int t1, t2;                 /* torus actually used                      */
+  double lam_min, lam_max;    /* eigenvalue extremes of the accepted torus*/
+  double lam_sum;             /* sum of eigenvalues = t1 t2 C(0)          */
+  double max_imag;            /* largest |Im| of the spectrum             */
+  int nobs, k;                /* observations and window size             */
+  double gamma_min, gamma_max;/* local-Kriging conditional variances      */
+  double ms_setup;            /* last ce_setup wall time (ms)             */
+  double ms_offgrid;          /* last offgrid_nnkrige (ms, enqueue only)  */
+  int precision;              /* cesim_precision                          */
+  int torus_tries;            /* ladder entries evaluated                 */
+} cesim_info;
+
+/* Circulant-embedding setup (Section 1; Section 2.1 item (a)).
+ * Builds the torus base c[q2][q1] = C(w(q1) dx, w(q2) dy) in FP64
+ * (w(q) = q for q <= T/2, else q - T; on Nyquist lines the two signs of
+ * that lag component are averaged), its 2D FFT in FP64 on the GPU, and
+ * checks min(lambda) >= -1e-12 max(lambda) in FP64; tiny negatives are
+ * clamped to 0 and sqrt(lambda) is kept in FP64 (and FP32 for
+ * CESIM_PREC_MIXED).  hip_stream: a hipStream_t or NULL.  On success *out
+ * owns a new context.  Errors: INVALID_ARG, NEGATIVE_EIGENVALUE (ladder
+ * exhausted or forced torus rejected; no context is created),
+ * OUT_OF_MEMORY, HIP.  Synchronises the stream. */
+cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid,
+                      cesim_precision prec, void* hip_stream,
+                      cesim_ctx* out);
+
+/* Unconditional draw of nreal realizations, absolute indices first_real ..
+ * first_real + nreal - 1 (step 2 of Section 2; Section 2.1 item (a)):
+ *   y_r = Re(IFFT2(sqrt(lambda) FFT2(eps_r)))[0:m2, 0:m1],
+ * eps_r the t2 x t1 torus noise of Philox stream 0 (element q = j t1 + i:
+ * block q/4, word q%4, counter (block, r, 0, 0), Box-Muller).  Two
+ * realizations share one complex transform.  fields_dev: caller-owned
+ * device buffer of nreal*m2*m1 doubles (FP64) or floats (MIXED), written
+ * asynchronously.  Records (seed, first_real, nreal) for condition().
+ * Errors: INVALID_ARG (nreal < 1, first_real < 0, NULL), OUT_OF_MEMORY,
+ * HIP. */
+cesim_status ce_simulate(cesim_ctx ctx, int nreal, uint64_t seed,
+                         int first_real, void* fields_dev);
+
+/* Local-Kriging setup (Section 2.1; Section 3.1; Section 3.6).
+ * obs_xy_host: nobs (x, y) pairs, host memory, copied.  k = (2 n_p)^2 in
+ * {4, 16, 36, 64} and 2 n_p <= min(m1, m2).  Window of s: lower-left node
+ * a = clamp(floor((sx - x0)/dx) - n_p + 1, 0, m1 - 2 n_p), likewise b;
+ * nodes (a+p, b+q), index q*2n_p + p.  Computes in FP64 the Cholesky factor
+ * of the window covariance K11 (identical for every window) and per
+ * observation w_i = K11^{-1} k_i and gamma_i = C(0) - k_i . w_i (>= 0).
+ * Errors: INVALID_ARG, OBS_OUTSIDE_GRID (any point outside
+ * [x0, x0 + (m1-1) dx] x [y0, y0 + (m2-1) dy] or not finite),
+ * NOT_POSITIVE_DEFINITE (K11), OUT_OF_MEMORY, HIP.  Invalidates the
+ * factorisation held for condition(). */
+cesim_status offgrid_nnkrige(cesim_ctx ctx, int nobs, const double* obs_xy_host,
+                             int k);
+
+/* Conditioning (steps 1, 3, 4, 5 of Section 2 with items (c), (d) of
+ * Section 2.1; eq. (4) of Section 3), in place on the batch last produced
+ * by ce_simulate into fields_dev (the same buffer and type):
+ *   z*_{r,i} = w_i . y_r[window_i] + sqrt(nugget + gamma_i) xi_{r,i}
+ *       (xi from Philox stream 1: block i/4, word i%4, counter
+ *        (block, r, 0, 1)),
+ *   B_r     = (K22 + nugget I)^{-1} (z - z*_r)        (FP64 Cholesky),
+ *   v_r     = y_r + K12 B_r,  K12[g, i] = C(g - s_i).
+ * z_host: nobs observed values, host memory, copied.  nugget >= 0.  The
+ * Cholesky factor of K22 + nugget I is kept and reused while the nugget and
+ * the observation set are unchanged.  Errors: BAD_STATE (no offgrid_nnkrige
+ * or no ce_simulate before), INVALID_ARG, NOT_POSITIVE_DEFINITE,
+ * OUT_OF_MEMORY, HIP. */
+cesim_status condition(cesim_ctx ctx, const double* z_host, double nugget,
+                       void* fields_dev);
+
+/* Statistics of the context; synchronises the stream. */
+cesim_status ce_get_info(cesim_ctx ctx, cesim_info* info);
+
+/* Copies sqrt(lambda) / (t1 t2) (FP64, t2 x t1, row-major) -- the spectral
+ * multiplier the draw applies -- into a caller-owned device buffer. */
+cesim_status ce_copy_spectrum(cesim_ctx ctx, double* dev_out);
+
+/* Copies the local-Kriging results of the last offgrid_nnkrige into
+ * caller-owned device buffers (any may be NULL): window corners as int32
+ * pairs (a, b) [nobs][2], weights [nobs][k] FP64, gamma [nobs] FP64. */
+cesim_status offgrid_copy_weights(cesim_ctx ctx, int* corners_dev,
+                                  double* weights_dev, double* gamma_dev);
+
+/* Copies the Kriging coefficients B_r = (K22 + nugget I)^{-1} (z - z*_r) of
+ * the last condition() call ([nreal][nobs] FP64) into a caller-owned device
+ * buffer. */
+cesim_status condition_copy_coefficients(cesim_ctx ctx, double* dev_out);
+
+/* Host evaluation of the library's covariance code (the same source the
+ * kernels run) at n lags (hx[i], hy[i]) into out[i], FP64.  For tests. */
+cesim_status cesim_covariance_host(const cesim_cov* cov, int n,
+                                   const double* hx, const double* hy,
+                                   double* out);
+
+/* Host evaluation of the library's Philox4x32-10 (same source as the
+ * kernels): out[4*i .. 4*i+3] = words of counter (ctr0[i], c1, c2, c3). */
+cesim_status cesim_philox_host(uint64_t seed, int n, const uint32_t* ctr0,
+                               uint32_t c1, uint32_t c2, uint32_t c3,
+                               uint32_t* out);
+
+const char* cesim_status_string(cesim_status s);
+
+/* Releases the context and every device buffer it owns (after
+ * synchronising its stream).  NULL is ignored. */
+void ce_destroy(cesim_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CESIM_H */

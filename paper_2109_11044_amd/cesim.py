@@ -1,0 +1,244 @@
+"""ctypes binding of libcesim.so (include/cesim.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  PyTorch supplies device memory (field buffers are torch tensors on
+the GPU) and the current HIP stream.  The library must have been built
+(``paper_2109_11044_amd/build_lib.py`` or ``__graft_entry__.build()``);
+loading fails loudly otherwise -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcesim.so")
+
+OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "NEGATIVE_EIGENVALUE",
+                3: "NOT_POSITIVE_DEFINITE", 4: "OBS_OUTSIDE_GRID",
+                5: "OUT_OF_MEMORY", 6: "HIP", 7: "BAD_STATE"}
+PREC = {"fp64": 0, "mixed": 1}
+
+EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
+           "ce_get_info", "ce_copy_spectrum", "offgrid_copy_weights",
+           "condition_copy_coefficients", "cesim_covariance_host",
+           "cesim_philox_host", "cesim_status_string", "ce_destroy"]
+
+
+class CesimError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {self.name} ({_status_string(status)})")
+
+
+class Cov(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("sigma2", ctypes.c_double),
+                ("range", ctypes.c_double), ("aniso_ratio", ctypes.c_double),
+                ("aniso_angle", ctypes.c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("m1", ctypes.c_int), ("m2", ctypes.c_int),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("t1", ctypes.c_int), ("t2", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("t1", ctypes.c_int), ("t2", ctypes.c_int),
+                ("lam_min", ctypes.c_double), ("lam_max", ctypes.c_double),
+                ("lam_sum", ctypes.c_double), ("max_imag", ctypes.c_double),
+                ("nobs", ctypes.c_int), ("k", ctypes.c_int),
+                ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double),
+                ("ms_setup", ctypes.c_double), ("ms_offgrid", ctypes.c_double),
+                ("precision", ctypes.c_int), ("torus_tries", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcesim.so once; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not built: run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.ce_setup.argtypes = [ctypes.POINTER(Cov), ctypes.POINTER(Grid), i, vp,
+                           ctypes.POINTER(vp)]
+    L.ce_simulate.argtypes = [vp, i, u64, i, vp]
+    L.offgrid_nnkrige.argtypes = [vp, i, dp, i]
+    L.condition.argtypes = [vp, dp, d, vp]
+    L.ce_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.ce_copy_spectrum.argtypes = [vp, vp]
+    L.offgrid_copy_weights.argtypes = [vp, vp, vp, vp]
+    L.condition_copy_coefficients.argtypes = [vp, vp]
+    L.cesim_covariance_host.argtypes = [ctypes.POINTER(Cov), i, dp, dp, dp]
+    L.cesim_philox_host.argtypes = [u64, i, ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint32,
+                                    ctypes.POINTER(ctypes.c_uint32)]
+    L.cesim_status_string.argtypes = [i]
+    L.cesim_status_string.restype = ctypes.c_char_p
+    L.ce_destroy.argtypes = [vp]
+    L.ce_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("cesim_status_string", "ce_destroy"):
+            getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def _status_string(s):
+    try:
+        return lib().cesim_status_string(s).decode()
+    except Exception:
+        return "?"
+
+
+def _check(status, where):
+    if status != OK:
+        raise CesimError(status, where)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_cov(nu=0.5, sigma2=1.0, range=0.1, aniso_ratio=1.0, aniso_angle=0.0):
+    return Cov(float(nu), float(sigma2), float(range), float(aniso_ratio),
+               float(aniso_angle))
+
+
+def unit_square_grid(m, torus=0):
+    dx = 1.0 / (m - 1)
+    return Grid(m, m, 0.0, 0.0, dx, dx, torus, torus)
+
+
+def covariance_host(cov, hx, hy):
+    """The library's covariance source evaluated on the host (FP64)."""
+    hx = np.ascontiguousarray(hx, dtype=np.float64).ravel()
+    hy = np.ascontiguousarray(hy, dtype=np.float64).ravel()
+    out = np.empty_like(hx)
+    _check(lib().cesim_covariance_host(ctypes.byref(cov), hx.size, _dptr(hx),
+                                       _dptr(hy), _dptr(out)), "covariance_host")
+    return out
+
+
+def philox_host(seed, ctr0, c1, c2, c3):
+    ctr0 = np.ascontiguousarray(ctr0, dtype=np.uint32).ravel()
+    out = np.empty((ctr0.size, 4), dtype=np.uint32)
+    P = ctypes.POINTER(ctypes.c_uint32)
+    _check(lib().cesim_philox_host(int(seed), ctr0.size, ctr0.ctypes.data_as(P),
+                                   int(c1), int(c2), int(c3),
+                                   out.ctypes.data_as(P)), "philox_host")
+    return out
+
+
+class Context:
+    """One event: covariance, grid and precision; owns the C context."""
+
+    def __init__(self, cov, grid, precision="fp64", stream=None):
+        import torch
+        self._torch = torch
+        self.cov, self.grid = cov, grid
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().ce_setup(ctypes.byref(cov), ctypes.byref(grid),
+                              PREC[precision], ctypes.c_void_p(stream.cuda_stream),
+                              ctypes.byref(h)), "ce_setup")
+        self._h = h
+        self.nobs = 0
+        self.k = 0
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ce_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _fields_check(self, fields, nreal):
+        t = self._torch
+        g = self.grid
+        if not (isinstance(fields, t.Tensor) and fields.is_cuda and
+                fields.dtype == self.dtype and fields.is_contiguous() and
+                fields.numel() >= nreal * g.m1 * g.m2):
+            raise ValueError("fields must be a contiguous CUDA tensor of "
+                             f"{self.dtype} with nreal*m2*m1 elements")
+
+    def simulate(self, nreal, seed, first_real=0, out=None):
+        t = self._torch
+        g = self.grid
+        if out is None:
+            out = t.empty((nreal, g.m2, g.m1), dtype=self.dtype, device="cuda")
+        self._fields_check(out, nreal)
+        _check(lib().ce_simulate(self._h, int(nreal), int(seed), int(first_real),
+                                 ctypes.c_void_p(out.data_ptr())), "ce_simulate")
+        self.nreal = nreal
+        return out
+
+    def offgrid(self, obs_xy, k):
+        xy = np.ascontiguousarray(obs_xy, dtype=np.float64).reshape(-1, 2)
+        _check(lib().offgrid_nnkrige(self._h, xy.shape[0], _dptr(xy), int(k)),
+               "offgrid_nnkrige")
+        self.nobs, self.k = xy.shape[0], int(k)
+
+    def condition(self, z, nugget, fields):
+        z = np.ascontiguousarray(z, dtype=np.float64).ravel()
+        if z.size != self.nobs:
+            raise ValueError("z must hold one value per observation")
+        self._fields_check(fields, getattr(self, "nreal", 1))
+        _check(lib().condition(self._h, _dptr(z), float(nugget),
+                               ctypes.c_void_p(fields.data_ptr())), "condition")
+        return fields
+
+    def info(self):
+        inf = Info()
+        _check(lib().ce_get_info(self._h, ctypes.byref(inf)), "ce_get_info")
+        return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def spectrum(self):
+        t = self._torch
+        inf = self.info()
+        out = t.empty((inf["t2"], inf["t1"]), dtype=t.float64, device="cuda")
+        _check(lib().ce_copy_spectrum(self._h, ctypes.c_void_p(out.data_ptr())),
+               "ce_copy_spectrum")
+        return out
+
+    def weights(self):
+        t = self._torch
+        cor = t.empty((self.nobs, 2), dtype=t.int32, device="cuda")
+        w = t.empty((self.nobs, self.k), dtype=t.float64, device="cuda")
+        gm = t.empty((self.nobs,), dtype=t.float64, device="cuda")
+        _check(lib().offgrid_copy_weights(self._h, ctypes.c_void_p(cor.data_ptr()),
+                                          ctypes.c_void_p(w.data_ptr()),
+                                          ctypes.c_void_p(gm.data_ptr())),
+               "offgrid_copy_weights")
+        return cor, w, gm
+
+    def coefficients(self):
+        t = self._torch
+        out = t.empty((self.nreal, self.nobs), dtype=t.float64, device="cuda")
+        _check(lib().condition_copy_coefficients(self._h, ctypes.c_void_p(out.data_ptr())),
+               "condition_copy_coefficients")
+        return out

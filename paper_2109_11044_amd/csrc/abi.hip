@@ -1,0 +1,357 @@
+// abi.hip -- the extern "C" entry points of include/cesim.h: argument
+// checks, the torus ladder, context lifetime and host-side test hooks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cesim {
+
+cesim_status DevBuf::reserve(size_t n) {
+  if (n <= bytes && p) return CESIM_OK;
+  release();
+  if (n == 0) n = 16;
+  if (hipMalloc(&p, n) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    bytes = 0;
+    return CESIM_ERR_OUT_OF_MEMORY;
+  }
+  bytes = n;
+  return CESIM_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+namespace {
+
+bool isfin(double x) { return std::isfinite(x); }
+
+bool smooth(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+int next_smooth(int n) {
+  n = std::max(n, 1);
+  while (!smooth(n)) ++n;
+  return n;
+}
+
+constexpr int kMaxTorus = 8192;
+
+int nu_code(double nu) {
+  if (nu == 0.5) return 0;
+  if (nu == 1.0) return 1;
+  if (nu == 1.5) return 2;
+  return -1;
+}
+
+CovDev make_cov(const cesim_cov& c) {
+  CovDev d;
+  d.nu_code = nu_code(c.nu);
+  d.sigma2 = c.sigma2;
+  const double cs = std::cos(c.aniso_angle), sn = std::sin(c.aniso_angle);
+  const double a = c.aniso_ratio, it = 1.0 / c.range;
+  if (a == 1.0 && c.aniso_angle == 0.0) {
+    d.u00 = it; d.u01 = 0.0; d.u10 = 0.0; d.u11 = it;
+  } else {
+    d.u00 = cs * it; d.u01 = sn * it; d.u10 = -a * sn * it; d.u11 = a * cs * it;
+  }
+  return d;
+}
+
+cesim_status check_cov(const cesim_cov* c) {
+  if (!c) return CESIM_ERR_INVALID_ARG;
+  if (nu_code(c->nu) < 0) return CESIM_ERR_INVALID_ARG;
+  if (!(isfin(c->sigma2) && c->sigma2 > 0)) return CESIM_ERR_INVALID_ARG;
+  if (!(isfin(c->range) && c->range > 0)) return CESIM_ERR_INVALID_ARG;
+  if (!(isfin(c->aniso_ratio) && c->aniso_ratio >= 1.0)) return CESIM_ERR_INVALID_ARG;
+  if (!isfin(c->aniso_angle)) return CESIM_ERR_INVALID_ARG;
+  return CESIM_OK;
+}
+
+cesim_status check_grid(const cesim_grid* g) {
+  if (!g) return CESIM_ERR_INVALID_ARG;
+  if (g->m1 < 2 || g->m2 < 2 || g->m1 > kMaxTorus / 2 || g->m2 > kMaxTorus / 2)
+    return CESIM_ERR_INVALID_ARG;
+  if (!(isfin(g->x0) && isfin(g->y0) && isfin(g->dx) && isfin(g->dy)))
+    return CESIM_ERR_INVALID_ARG;
+  if (!(g->dx > 0 && g->dy > 0)) return CESIM_ERR_INVALID_ARG;
+  const bool auto_t = g->t1 == 0 && g->t2 == 0;
+  if (!auto_t) {
+    for (int a = 0; a < 2; ++a) {
+      const int t = a ? g->t2 : g->t1, m = a ? g->m2 : g->m1;
+      if (t < 2 * m - 1 || t > kMaxTorus || !smooth(t)) return CESIM_ERR_INVALID_ARG;
+    }
+  }
+  return CESIM_OK;
+}
+
+}  // namespace
+}  // namespace cesim
+
+using namespace cesim;
+
+extern "C" {
+
+const char* cesim_status_string(cesim_status s) {
+  switch (s) {
+    case CESIM_OK: return "ok";
+    case CESIM_ERR_INVALID_ARG: return "invalid argument";
+    case CESIM_ERR_NEGATIVE_EIGENVALUE: return "negative circulant eigenvalue (no admissible torus)";
+    case CESIM_ERR_NOT_POSITIVE_DEFINITE: return "matrix not positive definite";
+    case CESIM_ERR_OBS_OUTSIDE_GRID: return "observation outside the grid";
+    case CESIM_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case CESIM_ERR_HIP: return "HIP runtime error";
+    case CESIM_ERR_BAD_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+void ce_destroy(cesim_ctx c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->tt.tw1_64, &c->tt.tw2_64, &c->tt.tw1_32, &c->tt.tw2_32, &c->s64,
+                    &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
+                    &c->corners, &c->weights, &c->gamma, &c->phi, &c->amat, &c->dinv,
+                    &c->zdev, &c->coef, &c->coef_b16, &c->info_dev};
+  for (DevBuf* b : bufs) b->release();
+  delete c;
+}
+
+cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precision prec,
+                      void* hip_stream, cesim_ctx* out) {
+  if (!out) return CESIM_ERR_INVALID_ARG;
+  *out = nullptr;
+  CESIM_TRY(check_cov(cov));
+  CESIM_TRY(check_grid(grid));
+  if (prec != CESIM_PREC_FP64 && prec != CESIM_PREC_MIXED) return CESIM_ERR_INVALID_ARG;
+  const auto t_start = std::chrono::steady_clock::now();
+  cesim_ctx c = new (std::nothrow) cesim_ctx_s();
+  if (!c) return CESIM_ERR_OUT_OF_MEMORY;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->cov = *cov;
+  c->grid = *grid;
+  c->prec = prec;
+  c->covd = make_cov(*cov);
+  c->gridd = {grid->m1, grid->m2, grid->x0, grid->y0, grid->dx, grid->dy};
+  cesim_status st = c->info_dev.reserve(sizeof(int) * 4);
+  if (st != CESIM_OK) { ce_destroy(c); return st; }
+  std::vector<std::pair<int, int>> cands;
+  if (grid->t1 == 0 && grid->t2 == 0) {
+    for (int f : {2, 3, 4, 6, 8}) {
+      const int a = next_smooth(f * grid->m1), b = next_smooth(f * grid->m2);
+      if (a > kMaxTorus || b > kMaxTorus) break;
+      if (cands.empty() || cands.back() != std::make_pair(a, b)) cands.push_back({a, b});
+    }
+  } else {
+    cands.push_back({grid->t1, grid->t2});
+  }
+  bool ok = false;
+  for (auto [a, b] : cands) {
+    c->torus_tries++;
+    bool acc = false;
+    st = ce_setup_device(c, a, b, acc);
+    if (st != CESIM_OK) { ce_destroy(c); return st; }
+    if (acc) {
+      c->t1 = a;
+      c->t2 = b;
+      ok = true;
+      break;
+    }
+  }
+  if (!ok) { ce_destroy(c); return CESIM_ERR_NEGATIVE_EIGENVALUE; }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) { ce_destroy(c); return CESIM_ERR_HIP; }
+  c->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                          t_start).count();
+  *out = c;
+  return CESIM_OK;
+}
+
+cesim_status ce_simulate(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields) {
+  if (!c || !fields || nreal < 1 || first_real < 0) return CESIM_ERR_INVALID_ARG;
+  if ((long)first_real + nreal > 0x7fffffffL) return CESIM_ERR_INVALID_ARG;
+  CESIM_TRY(ce_draw_device(c, nreal, seed, first_real, fields));
+  c->have_fields = true;
+  c->seed = seed;
+  c->first_real = first_real;
+  c->nreal = nreal;
+  return CESIM_OK;
+}
+
+cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
+  if (!c || !xy || nobs < 1) return CESIM_ERR_INVALID_ARG;
+  int npp = 0;
+  switch (k) {
+    case 4: npp = 1; break;
+    case 16: npp = 2; break;
+    case 36: npp = 3; break;
+    case 64: npp = 4; break;
+    default: return CESIM_ERR_INVALID_ARG;
+  }
+  const cesim_grid& g = c->grid;
+  if (2 * npp > std::min(g.m1, g.m2)) return CESIM_ERR_INVALID_ARG;
+  const double xmax = g.x0 + (g.m1 - 1) * g.dx, ymax = g.y0 + (g.m2 - 1) * g.dy;
+  for (int i = 0; i < nobs; ++i) {
+    const double x = xy[2 * i], y = xy[2 * i + 1];
+    if (!(isfin(x) && isfin(y))) return CESIM_ERR_OBS_OUTSIDE_GRID;
+    if (x < g.x0 || x > xmax || y < g.y0 || y > ymax) return CESIM_ERR_OBS_OUTSIDE_GRID;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  CESIM_HIP(hipStreamSynchronize(c->stream));   // host staging below is reused
+  c->chol_valid = false;
+  c->nobs = 0;
+  c->obs_host.assign(xy, xy + 2 * (size_t)nobs);
+  CESIM_TRY(c->obs_xy.reserve(sizeof(double) * 2 * nobs));
+  CESIM_TRY(c->obs_t64.reserve(sizeof(double2) * nobs));
+  CESIM_TRY(c->obs_t32.reserve(sizeof(float2) * nobs));
+  CESIM_TRY(c->corners.reserve(sizeof(int2) * nobs));
+  CESIM_TRY(c->weights.reserve(sizeof(double) * (size_t)nobs * k));
+  CESIM_TRY(c->gamma.reserve(sizeof(double) * nobs));
+  CESIM_TRY(c->phi.reserve(sizeof(double) * nobs));
+  // transformed coordinates: FP64 path U (s - origin); mixed path kappa U (s - origin)
+  const CovDev& d = c->covd;
+  const double kappa = d.nu_code == 0 ? kLog2e : (d.nu_code == 2 ? kSqrt3 : kSqrt2);
+  std::vector<double2> t64(nobs);
+  std::vector<float2> t32(nobs);
+  for (int i = 0; i < nobs; ++i) {
+    const double hx = xy[2 * i] - g.x0, hy = xy[2 * i + 1] - g.y0;
+    const double a = d.u00 * hx + d.u01 * hy, b = d.u10 * hx + d.u11 * hy;
+    t64[i] = {a, b};
+    t32[i] = {(float)(kappa * a), (float)(kappa * b)};
+  }
+  hipStream_t s = c->stream;
+  CESIM_HIP(hipMemcpyAsync(c->obs_xy.p, c->obs_host.data(), sizeof(double) * 2 * nobs,
+                           hipMemcpyHostToDevice, s));
+  CESIM_HIP(hipMemcpyAsync(c->obs_t64.p, t64.data(), sizeof(double2) * nobs,
+                           hipMemcpyHostToDevice, s));
+  CESIM_HIP(hipMemcpyAsync(c->obs_t32.p, t32.data(), sizeof(float2) * nobs,
+                           hipMemcpyHostToDevice, s));
+  c->nobs = nobs;
+  c->k = k;
+  c->npp = npp;
+  CESIM_TRY(lk_setup_device(c));
+  int info[4];
+  CESIM_HIP(hipMemcpyAsync(info, c->info_dev.p, sizeof(info), hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipStreamSynchronize(s));           // also retires the staging vectors
+  if (info[0] & 1) {
+    c->nobs = 0;
+    return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+  }
+  c->ms_offgrid = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                            t_start).count();
+  return CESIM_OK;
+}
+
+cesim_status condition(cesim_ctx c, const double* z, double nugget, void* fields) {
+  if (!c || !z || !fields) return CESIM_ERR_INVALID_ARG;
+  if (c->nobs < 1 || !c->have_fields) return CESIM_ERR_BAD_STATE;
+  if (!(isfin(nugget) && nugget >= 0.0)) return CESIM_ERR_INVALID_ARG;
+  const int n = c->nobs;
+  for (int i = 0; i < n; ++i)
+    if (!isfin(z[i])) return CESIM_ERR_INVALID_ARG;
+  if (c->z_host_cached.size() != (size_t)n ||
+      std::memcmp(c->z_host_cached.data(), z, sizeof(double) * n) != 0) {
+    CESIM_HIP(hipStreamSynchronize(c->stream));   // previous upload retired
+    c->z_host_cached.assign(z, z + n);
+    CESIM_TRY(c->zdev.reserve(sizeof(double) * n));
+    CESIM_HIP(hipMemcpyAsync(c->zdev.p, c->z_host_cached.data(), sizeof(double) * n,
+                             hipMemcpyHostToDevice, c->stream));
+  }
+  return condition_device(c, nugget, fields);
+}
+
+cesim_status ce_get_info(cesim_ctx c, cesim_info* info) {
+  if (!c || !info) return CESIM_ERR_INVALID_ARG;
+  CESIM_HIP(hipStreamSynchronize(c->stream));
+  cesim_info r{};
+  r.t1 = c->t1;
+  r.t2 = c->t2;
+  r.lam_min = c->lam_min;
+  r.lam_max = c->lam_max;
+  r.lam_sum = c->lam_sum;
+  r.max_imag = c->max_imag;
+  r.nobs = c->nobs;
+  r.k = c->k;
+  r.ms_setup = c->ms_setup;
+  r.ms_offgrid = c->ms_offgrid;
+  r.precision = (int)c->prec;
+  r.torus_tries = c->torus_tries;
+  if (c->nobs > 0) {
+    std::vector<double> gm(c->nobs);
+    CESIM_HIP(hipMemcpy(gm.data(), c->gamma.p, sizeof(double) * c->nobs, hipMemcpyDeviceToHost));
+    r.gamma_min = *std::min_element(gm.begin(), gm.end());
+    r.gamma_max = *std::max_element(gm.begin(), gm.end());
+  }
+  *info = r;
+  return CESIM_OK;
+}
+
+cesim_status ce_copy_spectrum(cesim_ctx c, double* dev_out) {
+  if (!c || !dev_out) return CESIM_ERR_INVALID_ARG;
+  CESIM_HIP(hipMemcpyAsync(dev_out, c->s64.p, sizeof(double) * (size_t)c->t1 * c->t2,
+                           hipMemcpyDeviceToDevice, c->stream));
+  return CESIM_OK;
+}
+
+cesim_status offgrid_copy_weights(cesim_ctx c, int* corners, double* w, double* gam) {
+  if (!c) return CESIM_ERR_INVALID_ARG;
+  if (c->nobs < 1) return CESIM_ERR_BAD_STATE;
+  const size_t n = c->nobs;
+  if (corners)
+    CESIM_HIP(hipMemcpyAsync(corners, c->corners.p, sizeof(int2) * n, hipMemcpyDeviceToDevice,
+                             c->stream));
+  if (w)
+    CESIM_HIP(hipMemcpyAsync(w, c->weights.p, sizeof(double) * n * c->k,
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (gam)
+    CESIM_HIP(hipMemcpyAsync(gam, c->gamma.p, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                             c->stream));
+  return CESIM_OK;
+}
+
+cesim_status condition_copy_coefficients(cesim_ctx c, double* dev_out) {
+  if (!c || !dev_out) return CESIM_ERR_INVALID_ARG;
+  if (c->nobs < 1 || !c->coef.p) return CESIM_ERR_BAD_STATE;
+  CESIM_HIP(hipMemcpyAsync(dev_out, c->coef.p, sizeof(double) * (size_t)c->nobs * c->nreal,
+                           hipMemcpyDeviceToDevice, c->stream));
+  return CESIM_OK;
+}
+
+cesim_status cesim_covariance_host(const cesim_cov* cov, int n, const double* hx,
+                                   const double* hy, double* out) {
+  CESIM_TRY(check_cov(cov));
+  if (n < 0 || (n > 0 && (!hx || !hy || !out))) return CESIM_ERR_INVALID_ARG;
+  const CovDev d = make_cov(*cov);
+  for (int i = 0; i < n; ++i) out[i] = cov_eval(d, hx[i], hy[i]);
+  return CESIM_OK;
+}
+
+cesim_status cesim_philox_host(uint64_t seed, int n, const uint32_t* ctr0, uint32_t c1,
+                               uint32_t c2, uint32_t c3, uint32_t* out) {
+  if (n < 0 || (n > 0 && (!ctr0 || !out))) return CESIM_ERR_INVALID_ARG;
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  for (int i = 0; i < n; ++i) {
+    const u32x4 w = philox4x32_10({ctr0[i], c1, c2, c3}, k0, k1);
+    out[4 * i] = w.x;
+    out[4 * i + 1] = w.y;
+    out[4 * i + 2] = w.z;
+    out[4 * i + 3] = w.w;
+  }
+  return CESIM_OK;
+}
+
+}  // extern "C"

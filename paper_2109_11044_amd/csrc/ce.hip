@@ -1,0 +1,437 @@
+// ce.hip -- circulant-embedding setup and the batched unconditional draw.
+//
+// Setup (Section 1; Section 2.1 item (a)): the torus base
+//   c[q2][q1] = C(w(q1) dx, w(q2) dy),  w(q) = q (q <= T/2) else q - T,
+// Nyquist lines averaged over the sign of their lag component, its 2D FFT in
+// FP64, the eigenvalue checks in FP64, and sqrt(lambda) / (t1 t2) kept in
+// FP64 and FP32.
+//
+// Draw (step 2 of Section 2): per pair of realizations (2p, 2p+1)
+//   pass 1: Philox noise eps_{2p} + i eps_{2p+1} -> forward FFT of every
+//           torus row (x) in LDS -> pair buffer;
+//   pass 2: per panel of columns: forward FFT along y, multiply by
+//           sqrt(lambda)/N, inverse FFT along y; only the m2 rows the crop
+//           keeps are written back;
+//   pass 3: per kept row: inverse FFT along x; the first m1 outputs give
+//           field 2p (real part) and field 2p+1 (imaginary part).
+// Because lambda is real and even the map eps -> field is real, so the two
+// realizations in one complex transform do not mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace cesim {
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_twiddles(int T, double2* tw64, float2* tw32) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double s, c;
+  sincospi(-2.0 * (double)t / (double)T, &s, &c);
+  tw64[t] = {c, s};
+  tw32[t] = {(float)c, (float)s};
+}
+
+__device__ inline int wrapped_lag(int q, int T) { return q <= T / 2 ? q : q - T; }
+
+__global__ void k_torus_base(CovDev cov, double dx, double dy, int t1, int t2, double2* out) {
+  const int q1 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q2 = blockIdx.y;
+  if (q1 >= t1) return;
+  const double hx = (double)wrapped_lag(q1, t1) * dx;
+  const double hy = (double)wrapped_lag(q2, t2) * dy;
+  const bool nyq1 = (t1 % 2 == 0) && (2 * q1 == t1);
+  const bool nyq2 = (t2 % 2 == 0) && (2 * q2 == t2);
+  double c;
+  if (nyq1) {
+    c = 0.5 * (cov_eval(cov, hx, hy) + cov_eval(cov, -hx, hy));
+  } else if (nyq2) {
+    c = 0.5 * (cov_eval(cov, hx, hy) + cov_eval(cov, hx, -hy));
+  } else {
+    c = cov_eval(cov, hx, hy);
+  }
+  out[(size_t)q2 * t1 + q1] = {c, 0.0};
+}
+
+// Noise for torus rows [j0, j0 + nrows) of pair p into LDS as
+// eps_{r0} + i eps_{r1}; element q = j t1 + i uses block q / 4, word q % 4.
+template <typename real, int NTHR>
+__device__ void noise_rows(cpx<real>* lds, int t1, int j0, int nrows, uint32_t k0, uint32_t k1,
+                           int r0, bool has_r1) {
+  const long q_lo = (long)j0 * t1;
+  const long q_hi = q_lo + (long)nrows * t1;
+  const long b_lo = q_lo >> 2, b_hi = (q_hi - 1) >> 2;
+  for (long b = b_lo + threadIdx.x; b <= b_hi; b += NTHR) {
+    real za[4], zb[4] = {0, 0, 0, 0};
+    if constexpr (sizeof(real) == 8) {
+      normals4_f64(k0, k1, (uint32_t)b, (uint32_t)r0, 0u, 0u, za);
+      if (has_r1) normals4_f64(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), 0u, 0u, zb);
+    } else {
+      normals4_f32(k0, k1, (uint32_t)b, (uint32_t)r0, 0u, 0u, za);
+      if (has_r1) normals4_f32(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), 0u, 0u, zb);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const long q = 4 * b + w;
+      if (q >= q_lo && q < q_hi) lds[q - q_lo] = {za[w], zb[w]};
+    }
+  }
+}
+
+// Forward FFT of nb torus rows per workgroup.  NOISE: the input is the pair
+// noise; otherwise it is read from buf.  Output overwrites buf.
+template <typename real, int NTHR, int E, bool NOISE>
+__global__ void __launch_bounds__(NTHR)
+k_rows_fwd(cpx<real>* __restrict__ buf, int t1, int t2, int nb, Plan plan,
+           const cpx<real>* __restrict__ tw, uint32_t k0, uint32_t k1, int first_real,
+           int nreal, int pair0) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
+  const int p = blockIdx.y;
+  const int j0 = blockIdx.x * nb;
+  const int nr = min(nb, t2 - j0);
+  cpx<real>* base = buf + ((size_t)p * t2 + j0) * t1;
+  if constexpr (NOISE) {
+    const int pg = pair0 + p;               // pair index within this call
+    const int r0 = first_real + 2 * pg;
+    noise_rows<real, NTHR>(lds, t1, j0, nr, k0, k1, r0, 2 * pg + 1 < nreal);
+  } else {
+    for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
+  }
+  __syncthreads();
+  fft_lds<false, NTHR, E, false, real>(lds, plan, nr, 1, t1, tw);
+  for (int e = threadIdx.x; e < nr * t1; e += NTHR) base[e] = lds[e];
+}
+
+// Column panel of cp columns of every pair: forward FFT along y; with SCALE
+// also multiply by s[ky][kx] and inverse FFT along y, writing rows < rows_out.
+template <typename real, int NTHR, int E, bool SCALE>
+__global__ void __launch_bounds__(NTHR)
+k_cols(cpx<real>* __restrict__ buf, int t1, int t2, int cp, int rows_out, Plan plan,
+       const cpx<real>* __restrict__ tw, const real* __restrict__ s) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
+  const int p = blockIdx.y;
+  const int c0 = blockIdx.x * cp;
+  const int cw = min(cp, t1 - c0);
+  cpx<real>* base = buf + (size_t)p * t2 * t1 + c0;
+  for (int e = threadIdx.x; e < t2 * cp; e += NTHR) {
+    const int row = e / cp, c = e - row * cp;
+    lds[e] = c < cw ? base[(size_t)row * t1 + c] : cpx<real>{0, 0};
+  }
+  __syncthreads();
+  fft_lds<false, NTHR, E, true, real>(lds, plan, cp, cp, 1, tw);
+  if constexpr (SCALE) {
+    for (int e = threadIdx.x; e < t2 * cp; e += NTHR) {
+      const int row = e / cp, c = e - row * cp;
+      if (c < cw) {
+        const real m = s[(size_t)row * t1 + c0 + c];
+        lds[e] = {lds[e].x * m, lds[e].y * m};
+      }
+    }
+    __syncthreads();
+    fft_lds<true, NTHR, E, true, real>(lds, plan, cp, cp, 1, tw);
+  }
+  for (int e = threadIdx.x; e < rows_out * cp; e += NTHR) {
+    const int row = e / cp, c = e - row * cp;
+    if (c < cw) base[(size_t)row * t1 + c] = lds[e];
+  }
+}
+
+// Inverse FFT along x of nb kept rows (y < m2) and the crop: the first m1
+// outputs of the row of pair p become fields 2p (real) and 2p+1 (imag).
+template <typename real, int NTHR, int E>
+__global__ void __launch_bounds__(NTHR)
+k_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, int t1, int t2,
+                int m1, int m2, int nb, Plan plan, const cpx<real>* __restrict__ tw, int nreal,
+                int pair0) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
+  const int p = blockIdx.y;
+  const int j0 = blockIdx.x * nb;
+  const int nr = min(nb, m2 - j0);
+  const cpx<real>* base = buf + ((size_t)p * t2 + j0) * t1;
+  for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
+  __syncthreads();
+  fft_lds<true, NTHR, E, false, real>(lds, plan, nr, 1, t1, tw);
+  const int pg = pair0 + p;
+  const size_t M = (size_t)m1 * m2;
+  real* f0 = fields + (size_t)(2 * pg) * M + (size_t)j0 * m1;
+  const bool has1 = 2 * pg + 1 < nreal;
+  for (int e = threadIdx.x; e < nr * m1; e += NTHR) {
+    const int row = e / m1, x = e - row * m1;
+    const cpx<real> v = lds[row * t1 + x];
+    f0[(size_t)row * m1 + x] = v.x;
+    if (has1) f0[M + (size_t)row * m1 + x] = v.y;
+  }
+}
+
+// Eigenvalue statistics: min, max, sum of Re and max |Im|.
+__global__ void k_eig_partial(const double2* lam, size_t N, double* part) {
+  __shared__ double smin[256], smax[256], ssum[256], sim[256];
+  double mn = INFINITY, mx = -INFINITY, sm = 0.0, im = 0.0;
+  for (size_t q = blockIdx.x * 256 + threadIdx.x; q < N; q += (size_t)gridDim.x * 256) {
+    const double2 v = lam[q];
+    mn = fmin(mn, v.x);
+    mx = fmax(mx, v.x);
+    sm += v.x;
+    im = fmax(im, fabs(v.y));
+  }
+  smin[threadIdx.x] = mn; smax[threadIdx.x] = mx; ssum[threadIdx.x] = sm; sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + h]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + h];
+      sim[threadIdx.x] = fmax(sim[threadIdx.x], sim[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x + 0] = smin[0];
+    part[4 * blockIdx.x + 1] = smax[0];
+    part[4 * blockIdx.x + 2] = ssum[0];
+    part[4 * blockIdx.x + 3] = sim[0];
+  }
+}
+
+__global__ void k_eig_final(const double* part, int nparts, double* out) {
+  if (threadIdx.x != 0) return;
+  double mn = INFINITY, mx = -INFINITY, sm = 0.0, im = 0.0;
+  for (int i = 0; i < nparts; ++i) {
+    mn = fmin(mn, part[4 * i]);
+    mx = fmax(mx, part[4 * i + 1]);
+    sm += part[4 * i + 2];
+    im = fmax(im, part[4 * i + 3]);
+  }
+  out[0] = mn; out[1] = mx; out[2] = sm; out[3] = im;
+}
+
+__global__ void k_sqrt_lambda(const double2* lam, size_t N, double inv_n, double* s64, float* s32) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N) return;
+  const double v = sqrt(fmax(lam[q].x, 0.0)) * inv_n;
+  s64[q] = v;
+  if (s32) s32[q] = (float)v;
+}
+
+// ------------------------------------------------------------------- host
+
+cesim_status make_plan(int T, Plan& p) {
+  p.T = T;
+  p.nst = 0;
+  int n = T;
+  int twos = 0;
+  while (n % 2 == 0) { n /= 2; ++twos; }
+  while (twos >= 3 && !(twos == 4)) {       // prefer 8s, finish 2^4 as 4 * 4
+    p.rad[p.nst++] = 8;
+    twos -= 3;
+  }
+  while (twos >= 2) { p.rad[p.nst++] = 4; twos -= 2; }
+  if (twos == 1) p.rad[p.nst++] = 2;
+  while (n % 3 == 0) { p.rad[p.nst++] = 3; n /= 3; }
+  while (n % 5 == 0) { p.rad[p.nst++] = 5; n /= 5; }
+  if (n != 1 || p.nst > 16) return CESIM_ERR_INVALID_ARG;
+  return CESIM_OK;
+}
+
+cesim_status make_twiddles(int T, DevBuf& tw64, DevBuf& tw32, hipStream_t s) {
+  CESIM_TRY(tw64.reserve(sizeof(double2) * T));
+  CESIM_TRY(tw32.reserve(sizeof(float2) * T));
+  k_twiddles<<<(T + 255) / 256, 256, 0, s>>>(T, tw64.as<double2>(), tw32.as<float2>());
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+namespace {
+
+constexpr int kRowThreads = 256;
+constexpr int kColThreads = 1024;
+constexpr size_t kLdsBudget = 128 * 1024;
+
+// Rows per workgroup and elements per thread for the row kernels.
+template <typename real>
+void row_config(int T, int& nb, int& E) {
+  const int cap = (int)(kLdsBudget / sizeof(cpx<real>)) / 2;   // elements per WG
+  const int tgt = std::min(cap, 4096);
+  nb = std::max(1, tgt / T);
+  const int el = nb * T;
+  E = el <= 16 * kRowThreads ? 16 : 32;
+}
+
+template <typename real>
+void col_config(int T, int t1, int& cp, int& E) {
+  const int cap = (int)(kLdsBudget / sizeof(cpx<real>));
+  cp = std::max(1, std::min(16, cap / T));
+  int c = 1;
+  while (c * 2 <= cp) c *= 2;
+  cp = std::min(c, std::max(1, t1));
+  const int el = cp * T;
+  E = el <= 4 * kColThreads ? 4 : el <= 8 * kColThreads ? 8 : el <= 16 * kColThreads ? 16 : 32;
+}
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename real, bool NOISE>
+cesim_status launch_rows_fwd(cpx<real>* buf, int t1, int t2, int npairs, const Plan& plan,
+                             const cpx<real>* tw, uint32_t k0, uint32_t k1, int first_real,
+                             int nreal, int pair0, hipStream_t s) {
+  int nb, E;
+  row_config<real>(t1, nb, E);
+  const size_t lds = sizeof(cpx<real>) * (size_t)nb * t1;
+  dim3 grid((t2 + nb - 1) / nb, npairs);
+  if (E == 16) {
+    auto k = k_rows_fwd<real, kRowThreads, 16, NOISE>;
+    allow_lds(k, lds);
+    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, k0, k1, first_real, nreal, pair0);
+  } else {
+    auto k = k_rows_fwd<real, kRowThreads, 32, NOISE>;
+    allow_lds(k, lds);
+    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, k0, k1, first_real, nreal, pair0);
+  }
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+template <typename real, bool SCALE>
+cesim_status launch_cols(cpx<real>* buf, int t1, int t2, int npairs, int rows_out, const Plan& plan,
+                         const cpx<real>* tw, const real* sl, hipStream_t s) {
+  int cp, E;
+  col_config<real>(t2, t1, cp, E);
+  const size_t lds = sizeof(cpx<real>) * (size_t)cp * t2;
+  dim3 grid((t1 + cp - 1) / cp, npairs);
+#define CESIM_COLS(EE)                                                       \
+  {                                                                          \
+    auto k = k_cols<real, kColThreads, EE, SCALE>;                           \
+    allow_lds(k, lds);                                                       \
+    k<<<grid, kColThreads, lds, s>>>(buf, t1, t2, cp, rows_out, plan, tw, sl); \
+  }
+  switch (E) {
+    case 4: CESIM_COLS(4) break;
+    case 8: CESIM_COLS(8) break;
+    case 16: CESIM_COLS(16) break;
+    default: CESIM_COLS(32) break;
+  }
+#undef CESIM_COLS
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+template <typename real>
+cesim_status launch_rows_inv_crop(const cpx<real>* buf, real* fields, int t1, int t2, int m1,
+                                  int m2, int npairs, const Plan& plan, const cpx<real>* tw,
+                                  int nreal, int pair0, hipStream_t s) {
+  int nb, E;
+  row_config<real>(t1, nb, E);
+  const size_t lds = sizeof(cpx<real>) * (size_t)nb * t1;
+  dim3 grid((m2 + nb - 1) / nb, npairs);
+  if (E == 16) {
+    auto k = k_rows_inv_crop<real, kRowThreads, 16>;
+    allow_lds(k, lds);
+    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, nreal, pair0);
+  } else {
+    auto k = k_rows_inv_crop<real, kRowThreads, 32>;
+    allow_lds(k, lds);
+    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, nreal, pair0);
+  }
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+}  // namespace
+
+cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
+  hipStream_t s = c->stream;
+  Plan p1, p2;
+  CESIM_TRY(make_plan(t1, p1));
+  CESIM_TRY(make_plan(t2, p2));
+  c->tt.p1 = p1;
+  c->tt.p2 = p2;
+  CESIM_TRY(make_twiddles(t1, c->tt.tw1_64, c->tt.tw1_32, s));
+  CESIM_TRY(make_twiddles(t2, c->tt.tw2_64, c->tt.tw2_32, s));
+  const size_t N = (size_t)t1 * t2;
+  CESIM_TRY(c->work.reserve(sizeof(double2) * N));
+  double2* buf = c->work.as<double2>();
+  k_torus_base<<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy, t1,
+                                                          t2, buf);
+  CESIM_HIP(hipGetLastError());
+  CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, p1, c->tt.tw1_64.as<double2>(), 0, 0,
+                                            0, 0, 0, s)));
+  CESIM_TRY((launch_cols<double, false>(buf, t1, t2, 1, t2, p2, c->tt.tw2_64.as<double2>(),
+                                        nullptr, s)));
+  const int nparts = 512;
+  CESIM_TRY(c->scratch.reserve(sizeof(double) * (4 * nparts + 8)));
+  double* part = c->scratch.as<double>();
+  k_eig_partial<<<nparts, 256, 0, s>>>(buf, N, part);
+  k_eig_final<<<1, 64, 0, s>>>(part, nparts, part + 4 * nparts);
+  CESIM_HIP(hipGetLastError());
+  double st[4];
+  CESIM_HIP(hipMemcpyAsync(st, part + 4 * nparts, sizeof(st), hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipStreamSynchronize(s));
+  c->lam_min = st[0];
+  c->lam_max = st[1];
+  c->lam_sum = st[2];
+  c->max_imag = st[3];
+  accepted = std::isfinite(st[0]) && std::isfinite(st[1]) && st[0] >= -1e-12 * st[1];
+  if (!accepted) return CESIM_OK;
+  CESIM_TRY(c->s64.reserve(sizeof(double) * N));
+  float* s32 = nullptr;
+  if (c->prec == CESIM_PREC_MIXED) {
+    CESIM_TRY(c->s32.reserve(sizeof(float) * N));
+    s32 = c->s32.as<float>();
+  }
+  k_sqrt_lambda<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(buf, N, 1.0 / (double)N,
+                                                            c->s64.as<double>(), s32);
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+namespace {
+
+template <typename real>
+cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, real* fields,
+                        const cpx<real>* tw1, const cpx<real>* tw2, const real* sl) {
+  hipStream_t s = c->stream;
+  const int t1 = c->t1, t2 = c->t2, m1 = c->grid.m1, m2 = c->grid.m2;
+  const size_t pair_bytes = sizeof(cpx<real>) * (size_t)t1 * t2;
+  const int npairs = (nreal + 1) / 2;
+  const size_t budget = (size_t)2 << 30;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(npairs, budget / pair_bytes));
+  CESIM_TRY(c->work.reserve(pair_bytes * chunk));
+  cpx<real>* buf = c->work.as<cpx<real>>();
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  for (int pair0 = 0; pair0 < npairs; pair0 += chunk) {
+    const int np = std::min(chunk, npairs - pair0);
+    CESIM_TRY((launch_rows_fwd<real, true>(buf, t1, t2, np, c->tt.p1, tw1, k0, k1, first_real,
+                                           nreal, pair0, s)));
+    CESIM_TRY((launch_cols<real, true>(buf, t1, t2, np, m2, c->tt.p2, tw2, sl, s)));
+    CESIM_TRY((launch_rows_inv_crop<real>(buf, fields, t1, t2, m1, m2, np, c->tt.p1, tw1, nreal,
+                                          pair0, s)));
+  }
+  return CESIM_OK;
+}
+
+}  // namespace
+
+cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields) {
+  if (c->prec == CESIM_PREC_FP64)
+    return draw_typed<double>(c, nreal, seed, first_real, static_cast<double*>(fields),
+                              c->tt.tw1_64.as<double2>(), c->tt.tw2_64.as<double2>(),
+                              c->s64.as<double>());
+  return draw_typed<float>(c, nreal, seed, first_real, static_cast<float*>(fields),
+                           c->tt.tw1_32.as<float2>(), c->tt.tw2_32.as<float2>(),
+                           c->s32.as<float>());
+}
+
+}  // namespace cesim

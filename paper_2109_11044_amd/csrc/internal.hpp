@@ -1,0 +1,103 @@
+// internal.hpp -- context and host-side plumbing shared by the library's
+// translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/cesim.h"
+#include "devmath.hpp"
+#include "fft.hpp"
+
+namespace cesim {
+
+#define CESIM_HIP(call)                                     \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return CESIM_ERR_HIP;             \
+  } while (0)
+
+#define CESIM_TRY(call)                                     \
+  do {                                                      \
+    cesim_status s_ = (call);                               \
+    if (s_ != CESIM_OK) return s_;                          \
+  } while (0)
+
+// Grid in device form.
+struct GridDev {
+  int m1, m2;
+  double x0, y0, dx, dy;
+};
+
+// A device allocation owned by the context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  cesim_status reserve(size_t n);   // grows, never shrinks; contents lost
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct TorusTables {
+  Plan p1, p2;                      // plans along x (t1) and y (t2)
+  DevBuf tw1_64, tw2_64, tw1_32, tw2_32;   // twiddles exp(-2 pi i t / T)
+};
+
+}  // namespace cesim
+
+struct cesim_ctx_s {
+  hipStream_t stream = nullptr;
+  cesim_cov cov{};
+  cesim_grid grid{};
+  cesim_precision prec = CESIM_PREC_FP64;
+  cesim::CovDev covd{};
+  cesim::GridDev gridd{};
+  int t1 = 0, t2 = 0;
+  double lam_min = 0, lam_max = 0, lam_sum = 0, max_imag = 0;
+  int torus_tries = 0;
+  double ms_setup = 0, ms_offgrid = 0;
+
+  cesim::TorusTables tt;
+  cesim::DevBuf s64, s32;           // sqrt(lambda) / (t1 t2), [t2][t1]
+  cesim::DevBuf work;               // pair buffers of the draw / setup FFT
+  cesim::DevBuf scratch;            // small reductions
+
+  // local Kriging
+  int nobs = 0, k = 0, npp = 0;
+  cesim::DevBuf obs_xy;             // [n][2] FP64
+  cesim::DevBuf obs_t32;            // [n] float2: transformed coordinates (mixed)
+  cesim::DevBuf obs_t64;            // [n] double2: transformed coordinates (FP64)
+  cesim::DevBuf corners, weights, gamma, phi;
+  double gamma_min = 0, gamma_max = 0;
+  std::vector<double> obs_host;
+
+  // conditioning
+  bool chol_valid = false;
+  double chol_nugget = -1.0;
+  cesim::DevBuf amat;               // n x n: K22 + tau^2 I, then its Cholesky factor
+  cesim::DevBuf dinv;               // inverses of the diagonal blocks
+  cesim::DevBuf zdev;               // observed values
+  cesim::DevBuf coef;               // [R][n] FP64: z - z*, then the coefficients
+  cesim::DevBuf coef_b16;           // [R][n] bf16 hi / lo pairs (mixed)
+  cesim::DevBuf info_dev;           // int flags
+  std::vector<double> z_host_cached;
+
+  // last simulate
+  bool have_fields = false;
+  uint64_t seed = 0;
+  int first_real = 0, nreal = 0;
+};
+
+namespace cesim {
+
+// Kernels launched from the ABI layer (defined in the .hip files).
+cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted);
+cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields);
+cesim_status lk_setup_device(cesim_ctx c);
+cesim_status condition_device(cesim_ctx c, double nugget, void* fields);
+cesim_status make_plan(int T, Plan& p);
+cesim_status make_twiddles(int T, DevBuf& tw64, DevBuf& tw32, hipStream_t s);
+
+}  // namespace cesim

@@ -1,0 +1,302 @@
+// linalg.hip -- FP64 Kriging system of the observations (eq. (4), Section 3;
+// steps 1 and 4 of Section 2):
+//   A = K22 + tau^2 I,  A = L L^T (blocked right-looking Cholesky),
+//   X = A^{-1} RHS for all realizations (blocked forward and backward
+//   substitution with the inverses of the diagonal blocks).
+// The O(n^3) trailing updates and O(n^2 R) solve updates run in one generic
+// FP64 matrix-core GEMM (v_mfma_f64_16x16x4f64, 64 x 64 tiles).
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cesim {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kNB = 64;   // Cholesky / solve block size
+
+__global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, double tau2,
+                             double* __restrict__ A) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n) return;
+  double v = cov_eval(cov, obs[2 * i] - obs[2 * j], obs[2 * i + 1] - obs[2 * j + 1]);
+  if (i == j) v += tau2;
+  A[(size_t)i * n + j] = v;
+}
+
+// Factor the nbk x nbk diagonal block at (k0, k0) in LDS; write L back and
+// the inverse of L to dinv (kNB x kNB, row-major, zero above the diagonal).
+__global__ void __launch_bounds__(256)
+k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
+             int* __restrict__ info) {
+  __shared__ double L[kNB][kNB + 1];
+  __shared__ double Li[kNB][kNB + 1];
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    L[r][c] = (r < nbk && c < nbk) ? A[(size_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < nbk; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = L[j][j];
+      if (!(d > 0.0)) atomicOr(info, 2);
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < nbk; i += 256) L[i][j] /= L[j][j];
+    __syncthreads();
+    const int rem = nbk - j - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += 256) {
+      const int i = j + 1 + e / rem, l = j + 1 + e % rem;
+      if (l <= i) L[i][l] -= L[i][j] * L[l][j];
+    }
+    __syncthreads();
+  }
+  // inverse of L: column c solves L x = e_c (one thread per column)
+  if (threadIdx.x < kNB) {
+    const int c = threadIdx.x;
+    for (int r = 0; r < kNB; ++r) {
+      double t = (r == c) ? 1.0 : 0.0;
+      if (r >= c) {
+        for (int q = c; q < r; ++q) t -= L[r][q] * Li[q][c];
+        t /= L[r][r];
+      } else {
+        t = 0.0;
+      }
+      Li[r][c] = t;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    dinv[e] = Li[r][c];
+    if (r < nbk && c <= r) A[(size_t)(k0 + r) * n + k0 + c] = L[r][c];
+  }
+}
+
+// Panel below the diagonal block: A[i, k0:k0+nbk] <- A[i, k0:k0+nbk] L_kk^{-T}
+// for 64 rows per workgroup.
+__global__ void __launch_bounds__(256)
+k_trsm_panel(double* __restrict__ A, int n, int k0, int nbk, const double* __restrict__ dinv) {
+  __shared__ double T[kNB][kNB + 1];
+  __shared__ double Li[kNB][kNB + 1];
+  const int i0 = k0 + nbk + blockIdx.x * kNB;
+  const int nr = min(kNB, n - i0);
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    T[r][c] = (r < nr && c < nbk) ? A[(size_t)(i0 + r) * n + k0 + c] : 0.0;
+    Li[r][c] = dinv[e];
+  }
+  __syncthreads();
+  double out[16];
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / kNB, c = e % kNB;
+    double s = 0.0;
+    for (int t = 0; t <= c; ++t) s += T[r][t] * Li[c][t];
+    out[u] = s;
+  }
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / kNB, c = e % kNB;
+    if (r < nr && c < nbk) A[(size_t)(i0 + r) * n + k0 + c] = out[u];
+  }
+}
+
+// Diagonal-block solve of the batched right-hand sides X[r][i] (row-major by
+// realization): forward  X[r][k0+c] <- sum_t Linv[c][t] X[r][k0+t],
+//              backward X[r][k0+c] <- sum_t Linv[t][c] X[r][k0+t].
+template <bool BACK>
+__global__ void __launch_bounds__(256)
+k_trsm_diag(double* __restrict__ X, int n, int R, int k0, int nbk, const double* __restrict__ dinv) {
+  __shared__ double Xs[kNB][kNB + 1];     // [r][t]
+  __shared__ double Li[kNB][kNB + 1];
+  const int r0 = blockIdx.x * kNB;
+  const int nr = min(kNB, R - r0);
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, t = e % kNB;
+    Xs[r][t] = (r < nr && t < nbk) ? X[(size_t)(r0 + r) * n + k0 + t] : 0.0;
+    Li[r][t] = dinv[e];
+  }
+  __syncthreads();
+  double out[16];
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / kNB, c = e % kNB;
+    double s = 0.0;
+    if (!BACK) {
+      for (int t = 0; t <= c; ++t) s += Li[c][t] * Xs[r][t];
+    } else {
+      for (int t = c; t < kNB; ++t) s += Li[t][c] * Xs[r][t];
+    }
+    out[u] = s;
+  }
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / kNB, c = e % kNB;
+    if (r < nr && c < nbk) X[(size_t)(r0 + r) * n + k0 + c] = out[u];
+  }
+}
+
+// Generic FP64 GEMM on matrix cores: C = alpha A B + beta C with element
+// strides A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj],
+// C(i,j) = C[i sci + j scj].  64 x 64 tiles, 4 waves of 32 x 32, k-step 16.
+// LOWER: skip tiles strictly above the diagonal (symmetric updates).
+struct GemmArgs {
+  int M, N, K;
+  double alpha, beta;
+  const double* A; long sai, sak;
+  const double* B; long sbk, sbj;
+  double* C; long sci, scj;
+};
+
+template <bool LOWER>
+__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ double As[TK][TM + 2];
+  __shared__ double Bs[TK][TN + 2];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (LOWER && bj > bi) return;
+  const int i0 = bi * TM, j0 = bj * TN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (doublex4){0.0, 0.0, 0.0, 0.0};
+  const bool a_ifast = (g.sai == 1);
+  const bool b_jfast = (g.sbj == 1);
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      int ii, kk;
+      if (a_ifast) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < g.M && gk < g.K) ? g.A[gi * g.sai + gk * g.sak] : 0.0;
+      int jj;
+      if (b_jfast) { jj = e % TN; kk = e / TN; } else { kk = e % TK; jj = e / TK; }
+      const int gj = j0 + jj, gk2 = k0 + kk;
+      Bs[kk][jj] = (gj < g.N && gk2 < g.K) ? g.B[gk2 * g.sbk + gj * g.sbj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[kk][wr + 16 * t + (lane & 15)];
+        b[t] = Bs[kk][wc + 16 * t + (lane & 15)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wr + 16 * x + 4 * (lane >> 4) + v;
+        const int gj = j0 + wc + 16 * y + (lane & 15);
+        if (gi < g.M && gj < g.N) {
+          double* cp = g.C + gi * g.sci + gj * g.scj;
+          const double prev = g.beta != 0.0 ? *cp : 0.0;
+          *cp = g.alpha * acc[x][y][v] + g.beta * prev;
+        }
+      }
+}
+
+cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0) return CESIM_OK;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+  if (lower) k_gemm_f64<true><<<grid, 256, 0, s>>>(g);
+  else k_gemm_f64<false><<<grid, 256, 0, s>>>(g);
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+// Factor A = K22 + tau^2 I in place (lower triangle).  Synchronises and
+// reports NOT_POSITIVE_DEFINITE on a non-positive pivot.
+cesim_status chol_factor_device(cesim_ctx c, double tau2) {
+  hipStream_t s = c->stream;
+  const int n = c->nobs;
+  const int nblk = (n + kNB - 1) / kNB;
+  CESIM_TRY(c->amat.reserve(sizeof(double) * (size_t)n * n));
+  CESIM_TRY(c->dinv.reserve(sizeof(double) * (size_t)nblk * kNB * kNB));
+  double* A = c->amat.as<double>();
+  double* D = c->dinv.as<double>();
+  int* info = c->info_dev.as<int>();
+  CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
+  k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd, tau2,
+                                                         A);
+  CESIM_HIP(hipGetLastError());
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
+    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
+    CESIM_HIP(hipGetLastError());
+    const int rest = n - k0 - nbk;
+    if (rest <= 0) break;
+    k_trsm_panel<<<(rest + kNB - 1) / kNB, 256, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB);
+    CESIM_HIP(hipGetLastError());
+    GemmArgs g;
+    g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+    g.A = A + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
+    g.B = A + (size_t)(k0 + nbk) * n + k0; g.sbk = 1; g.sbj = n;
+    g.C = A + (size_t)(k0 + nbk) * n + (k0 + nbk); g.sci = n; g.scj = 1;
+    CESIM_TRY(gemm_f64(g, true, s));
+  }
+  int hinfo[4];
+  CESIM_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipStreamSynchronize(s));
+  if (hinfo[0] & 2) return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+  return CESIM_OK;
+}
+
+// X[r][.] <- A^{-1} X[r][.] for r < R with the factor held in c->amat.
+cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
+  hipStream_t s = c->stream;
+  const int n = c->nobs;
+  const int nblk = (n + kNB - 1) / kNB;
+  const double* L = c->amat.as<double>();
+  const double* D = c->dinv.as<double>();
+  const dim3 gdiag((R + kNB - 1) / kNB);
+  for (int kb = 0; kb < nblk; ++kb) {          // L Y = X
+    const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
+    k_trsm_diag<false><<<gdiag, 256, 0, s>>>(X, n, R, k0, nbk, D + (size_t)kb * kNB * kNB);
+    CESIM_HIP(hipGetLastError());
+    const int rest = n - k0 - nbk;
+    if (rest <= 0) break;
+    GemmArgs g;
+    g.M = rest; g.N = R; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+    g.A = L + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
+    g.B = X + k0; g.sbk = 1; g.sbj = n;
+    g.C = X + k0 + nbk; g.sci = 1; g.scj = n;
+    CESIM_TRY(gemm_f64(g, false, s));
+  }
+  for (int kb = nblk - 1; kb >= 0; --kb) {     // L^T X = Y
+    const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
+    k_trsm_diag<true><<<gdiag, 256, 0, s>>>(X, n, R, k0, nbk, D + (size_t)kb * kNB * kNB);
+    CESIM_HIP(hipGetLastError());
+    if (k0 == 0) break;
+    GemmArgs g;
+    g.M = k0; g.N = R; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+    g.A = L + (size_t)k0 * n; g.sai = 1; g.sak = n;      // (L^T)(i, k0+t) = L(k0+t, i)
+    g.B = X + k0; g.sbk = 1; g.sbj = n;
+    g.C = X; g.sci = 1; g.scj = n;
+    CESIM_TRY(gemm_f64(g, false, s));
+  }
+  return CESIM_OK;
+}
+
+}  // namespace cesim

@@ -1,0 +1,170 @@
+// lk.hip -- local Kriging of the off-grid observations (Section 2.1 items
+// (b)-(c); Section 3.1; Section 3.6).
+//
+// Setup kernel: every workgroup assembles the window covariance K11 (k x k,
+// identical for all windows of a stationary field, Section 3.6) in LDS and
+// factors it by Cholesky in FP64; each thread then takes one observation,
+// finds its window, evaluates k_i = [C(g_alpha - s_i)], solves
+// K11 w_i = k_i with the shared factor and forms
+// gamma_i = C(0) - k_i^T K11^{-1} k_i = C(0) - |L^{-1} k_i|^2 (>= 0).
+//
+// Synthetic-data kernel (step 3): for each (realization, observation)
+//   z*_{r,i} = w_i . y_r[window_i] + phi_i xi_{r,i},  phi_i = sqrt(tau^2 + gamma_i),
+// with xi from Philox stream 1, and stores the right-hand side z_i - z*_{r,i}
+// of the grid Kriging in FP64.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace cesim {
+
+template <int NPP>
+__global__ void __launch_bounds__(128)
+k_lk_setup(const double* __restrict__ obs, int n, GridDev g, CovDev cov, int2* __restrict__ corners,
+           double* __restrict__ W, double* __restrict__ gam, int* __restrict__ info) {
+  constexpr int W2 = 2 * NPP;
+  constexpr int K = W2 * W2;
+  __shared__ double L[K][K + 1];
+  // assemble K11 from index lags
+  for (int e = threadIdx.x; e < K * K; e += 128) {
+    const int a = e / K, b = e % K;
+    const int pa = a % W2, qa = a / W2, pb = b % W2, qb = b / W2;
+    L[a][b] = cov_eval(cov, (double)(pa - pb) * g.dx, (double)(qa - qb) * g.dy);
+  }
+  __syncthreads();
+  // right-looking Cholesky, lower triangle
+  for (int j = 0; j < K; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = L[j][j];
+      if (!(d > 0.0) && blockIdx.x == 0) atomicOr(info, 1);
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < K; i += 128) L[i][j] /= L[j][j];
+    __syncthreads();
+    const int rem = K - j - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += 128) {
+      const int i = j + 1 + e / rem, l = j + 1 + e % rem;
+      if (l <= i) L[i][l] -= L[i][j] * L[l][j];
+    }
+    __syncthreads();
+  }
+  const int i = blockIdx.x * 128 + threadIdx.x;
+  if (i >= n) return;
+  const double sx = obs[2 * i], sy = obs[2 * i + 1];
+  int a = (int)floor((sx - g.x0) / g.dx) - NPP + 1;
+  int b = (int)floor((sy - g.y0) / g.dy) - NPP + 1;
+  a = min(max(a, 0), g.m1 - W2);
+  b = min(max(b, 0), g.m2 - W2);
+  double v[K];
+#pragma unroll
+  for (int al = 0; al < K; ++al) {
+    const int p = al % W2, q = al / W2;
+    // node coordinate written out without contraction, as x0 + i dx
+    const double gx = __dadd_rn(g.x0, __dmul_rn((double)(a + p), g.dx));
+    const double gy = __dadd_rn(g.y0, __dmul_rn((double)(b + q), g.dy));
+    v[al] = cov_eval(cov, gx - sx, gy - sy);
+  }
+  // forward substitution: v <- L^{-1} k
+  double ss = 0.0;
+#pragma unroll
+  for (int al = 0; al < K; ++al) {
+    double t = v[al];
+#pragma unroll
+    for (int be = 0; be < al; ++be) t -= L[al][be] * v[be];
+    v[al] = t / L[al][al];
+    ss += v[al] * v[al];
+  }
+  // back substitution: v <- L^{-T} v = K11^{-1} k
+#pragma unroll
+  for (int al = K - 1; al >= 0; --al) {
+    double t = v[al];
+#pragma unroll
+    for (int be = al + 1; be < K; ++be) t -= L[be][al] * v[be];
+    v[al] = t / L[al][al];
+  }
+#pragma unroll
+  for (int al = 0; al < K; ++al) W[(size_t)i * K + al] = v[al];
+  gam[i] = fmax(0.0, cov.sigma2 - ss);
+  corners[i] = make_int2(a, b);
+}
+
+__global__ void k_phi(const double* __restrict__ gam, int n, double tau2, double* __restrict__ phi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) phi[i] = sqrt(tau2 + gam[i]);
+}
+
+// rhs[r][i] = z_i - (w_i . y_r[window_i] + phi_i xi_{r,i})
+template <typename F>
+__global__ void __launch_bounds__(256)
+k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict__ corners,
+            const double* __restrict__ W, const double* __restrict__ phi,
+            const double* __restrict__ z, int n, int K, int w2, uint32_t k0, uint32_t k1,
+            int first_real, double* __restrict__ rhs) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  const int2 ab = corners[i];
+  const F* y = fields + (size_t)r * m1 * m2 + (size_t)ab.y * m1 + ab.x;
+  const double* w = W + (size_t)i * K;
+  double acc = 0.0;
+  for (int q = 0; q < w2; ++q)
+    for (int p = 0; p < w2; ++p) acc += w[q * w2 + p] * (double)y[(size_t)q * m1 + p];
+  // xi_{r,i}: block i/4, word i%4 of Philox stream 1
+  const u32x4 wd = philox4x32_10({(uint32_t)(i >> 2), (uint32_t)(first_real + r), 0u, 1u}, k0, k1);
+  const int word = i & 3;
+  double z0, z1;
+  if (word < 2) box_muller_f64(wd.x, wd.y, z0, z1);
+  else box_muller_f64(wd.z, wd.w, z0, z1);
+  const double xi = (word & 1) ? z1 : z0;
+  rhs[(size_t)r * n + i] = z[i] - (acc + phi[i] * xi);
+}
+
+cesim_status lk_setup_device(cesim_ctx c) {
+  hipStream_t s = c->stream;
+  const int n = c->nobs;
+  CESIM_HIP(hipMemsetAsync(c->info_dev.p, 0, sizeof(int) * 4, s));
+  dim3 grid((n + 127) / 128);
+  int* info = c->info_dev.as<int>();
+  auto* obs = c->obs_xy.as<double>();
+  auto* cor = c->corners.as<int2>();
+  auto* W = c->weights.as<double>();
+  auto* gm = c->gamma.as<double>();
+  switch (c->npp) {
+    case 1: k_lk_setup<1><<<grid, 128, 0, s>>>(obs, n, c->gridd, c->covd, cor, W, gm, info); break;
+    case 2: k_lk_setup<2><<<grid, 128, 0, s>>>(obs, n, c->gridd, c->covd, cor, W, gm, info); break;
+    case 3: k_lk_setup<3><<<grid, 128, 0, s>>>(obs, n, c->gridd, c->covd, cor, W, gm, info); break;
+    case 4: k_lk_setup<4><<<grid, 128, 0, s>>>(obs, n, c->gridd, c->covd, cor, W, gm, info); break;
+    default: return CESIM_ERR_INVALID_ARG;
+  }
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+cesim_status lk_phi_device(cesim_ctx c, double tau2) {
+  k_phi<<<(c->nobs + 255) / 256, 256, 0, c->stream>>>(c->gamma.as<double>(), c->nobs, tau2,
+                                                      c->phi.as<double>());
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs) {
+  const int n = c->nobs;
+  dim3 grid((n + 255) / 256, c->nreal);
+  const uint32_t k0 = (uint32_t)(c->seed & 0xffffffffu), k1 = (uint32_t)(c->seed >> 32);
+  const int w2 = 2 * c->npp;
+  if (c->prec == CESIM_PREC_FP64)
+    k_synth_rhs<double><<<grid, 256, 0, c->stream>>>(
+        static_cast<const double*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
+        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, k0, k1,
+        c->first_real, rhs);
+  else
+    k_synth_rhs<float><<<grid, 256, 0, c->stream>>>(
+        static_cast<const float*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
+        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, k0, k1,
+        c->first_real, rhs);
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+}  // namespace cesim
