@@ -152,7 +152,8 @@ cesim_status ce_simulate(cesim_ctx ctx, int nreal, uint64_t seed,
  * of the window covariance K11 (identical for every window) and per
  * observation w_i = K11^{-1} k_i and gamma_i = C(0) - k_i . w_i (>= 0).
  * Errors: INVALID_ARG, OBS_OUTSIDE_GRID (any point outside
- * [x0, x0 + (m1-1) dx] x [y0, y0 + (m2-1) dy] or not finite),
+ * [x0, x0 + (m1-1) dx] x [y0, y0 + (m2-1) dy], widened by 1e-12 of the
+ * extent for rounding, or not finite),
  * NOT_POSITIVE_DEFINITE (K11), OUT_OF_MEMORY, HIP.  Invalidates the
  * factorisation held for condition(). */
 cesim_status offgrid_nnkrige(cesim_ctx ctx, int nobs, const double* obs_xy_host,

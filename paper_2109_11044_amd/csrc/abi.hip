@@ -204,11 +204,15 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   }
   const cesim_grid& g = c->grid;
   if (2 * npp > std::min(g.m1, g.m2)) return CESIM_ERR_INVALID_ARG;
-  const double xmax = g.x0 + (g.m1 - 1) * g.dx, ymax = g.y0 + (g.m2 - 1) * g.dy;
+  // grid extent with a slack of 1e-12 of its length: (m - 1) dx may round
+  // just below the intended edge (for example 1 on the unit square)
+  const double ex = (g.m1 - 1) * g.dx, ey = (g.m2 - 1) * g.dy;
+  const double xlo = g.x0 - 1e-12 * ex, xhi = g.x0 + ex * (1.0 + 1e-12);
+  const double ylo = g.y0 - 1e-12 * ey, yhi = g.y0 + ey * (1.0 + 1e-12);
   for (int i = 0; i < nobs; ++i) {
     const double x = xy[2 * i], y = xy[2 * i + 1];
     if (!(isfin(x) && isfin(y))) return CESIM_ERR_OBS_OUTSIDE_GRID;
-    if (x < g.x0 || x > xmax || y < g.y0 || y > ymax) return CESIM_ERR_OBS_OUTSIDE_GRID;
+    if (x < xlo || x > xhi || y < ylo || y > yhi) return CESIM_ERR_OBS_OUTSIDE_GRID;
   }
   const auto t_start = std::chrono::steady_clock::now();
   CESIM_HIP(hipStreamSynchronize(c->stream));   // host staging below is reused

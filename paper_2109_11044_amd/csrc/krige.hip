@@ -86,7 +86,7 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
     for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int g = g0 + 32 * wave + 16 * x + 4 * (lane >> 4) + v;
+        const int g = g0 + 32 * wave + 16 * x + (lane >> 4) + 4 * v;   // D[l/16 + 4v][l%16]
         const int r = r0 + 16 * y + (lane & 15);
         if (g < M && r < R) fields[(size_t)r * M + g] += acc[x][y][v];
       }

@@ -145,6 +145,8 @@ k_trsm_diag(double* __restrict__ X, int n, int R, int k0, int nbk, const double*
 // strides A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj],
 // C(i,j) = C[i sci + j scj].  64 x 64 tiles, 4 waves of 32 x 32, k-step 16.
 // LOWER: skip tiles strictly above the diagonal (symmetric updates).
+// Operand layouts of v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator v of lane l is D[l / 16 + 4 v][l % 16].
 struct GemmArgs {
   int M, N, K;
   double alpha, beta;
@@ -207,7 +209,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = i0 + wr + 16 * x + 4 * (lane >> 4) + v;
+        const int gi = i0 + wr + 16 * x + (lane >> 4) + 4 * v;
         const int gj = j0 + wc + 16 * y + (lane & 15);
         if (gi < g.M && gj < g.N) {
           double* cp = g.C + gi * g.sci + gj * g.scj;

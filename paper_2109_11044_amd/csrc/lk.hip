@@ -25,6 +25,7 @@ k_lk_setup(const double* __restrict__ obs, int n, GridDev g, CovDev cov, int2* _
   constexpr int W2 = 2 * NPP;
   constexpr int K = W2 * W2;
   __shared__ double L[K][K + 1];
+  __shared__ double V[K][129];          // per-thread vectors, one column each
   // assemble K11 from index lags
   for (int e = threadIdx.x; e < K * K; e += 128) {
     const int a = e / K, b = e % K;
@@ -56,35 +57,32 @@ k_lk_setup(const double* __restrict__ obs, int n, GridDev g, CovDev cov, int2* _
   int b = (int)floor((sy - g.y0) / g.dy) - NPP + 1;
   a = min(max(a, 0), g.m1 - W2);
   b = min(max(b, 0), g.m2 - W2);
-  double v[K];
-#pragma unroll
+  // this thread's vector lives in LDS column threadIdx.x (conflict-free)
+  double* v = &V[0][threadIdx.x];
+  constexpr int LD = 129;
   for (int al = 0; al < K; ++al) {
     const int p = al % W2, q = al / W2;
     // node coordinate written out without contraction, as x0 + i dx
     const double gx = __dadd_rn(g.x0, __dmul_rn((double)(a + p), g.dx));
     const double gy = __dadd_rn(g.y0, __dmul_rn((double)(b + q), g.dy));
-    v[al] = cov_eval(cov, gx - sx, gy - sy);
+    v[al * LD] = cov_eval(cov, gx - sx, gy - sy);
   }
-  // forward substitution: v <- L^{-1} k
+  // forward substitution: v <- L^{-1} k; gamma = C(0) - |L^{-1} k|^2
   double ss = 0.0;
-#pragma unroll
   for (int al = 0; al < K; ++al) {
-    double t = v[al];
-#pragma unroll
-    for (int be = 0; be < al; ++be) t -= L[al][be] * v[be];
-    v[al] = t / L[al][al];
-    ss += v[al] * v[al];
+    double t = v[al * LD];
+    for (int be = 0; be < al; ++be) t -= L[al][be] * v[be * LD];
+    t /= L[al][al];
+    v[al * LD] = t;
+    ss += t * t;
   }
   // back substitution: v <- L^{-T} v = K11^{-1} k
-#pragma unroll
   for (int al = K - 1; al >= 0; --al) {
-    double t = v[al];
-#pragma unroll
-    for (int be = al + 1; be < K; ++be) t -= L[be][al] * v[be];
-    v[al] = t / L[al][al];
+    double t = v[al * LD];
+    for (int be = al + 1; be < K; ++be) t -= L[be][al] * v[be * LD];
+    v[al * LD] = t / L[al][al];
   }
-#pragma unroll
-  for (int al = 0; al < K; ++al) W[(size_t)i * K + al] = v[al];
+  for (int al = 0; al < K; ++al) W[(size_t)i * K + al] = v[al * LD];
   gam[i] = fmax(0.0, cov.sigma2 - ss);
   corners[i] = make_int2(a, b);
 }
