@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Throughput of conditional simulation by circulant embedding with local
+Kriging (arXiv 2109.11044) on one MI355X.
+
+One step is the whole method for one synthetic event, every row of the hot
+path inside the timed region:
+  ce_setup          torus base + FP64 2D FFT + eigenvalue check
+  offgrid_nnkrige   local-Kriging weights and variances of the stations
+  ce_simulate       R unconditional grid realizations (CE draw)
+  condition         synthetic data, observation Cholesky + solves, and the
+                    cross-covariance product onto the grid, in place.
+Workload (default): 1024 x 1024 unit-square grid, exponential covariance
+(sigma^2 = 1, range 0.02), nugget 0.02, 5000 clustered stations, 6 x 6
+local-Kriging windows, R = 1000 realizations per step.  Inputs are seeded
+synthetic data already resident on the device when the timed region starts
+(station coordinates and values are host arrays the ABI copies, as a caller
+would).  The headline value is the mixed-precision path; the plain FP64 path
+is measured beside it for the speed ratio.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--m", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=5000)
+    ap.add_argument("--nreal", type=int, default=1000)
+    ap.add_argument("--batch", type=int, default=0, help="realizations per call (0: all)")
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--json-out", default="")
+    return ap.parse_args()
+
+
+def algorithmic_units(name, wl, R, t1, t2, bytes_per_real):
+    """Algorithmic bytes (or flops) of one step for a stage, by its I/O
+    contract: pair buffer traffic of the draw passes (sqrt(lambda) reads are
+    amortised and not counted), 2 M n R flops for the grid GEMM."""
+    N = t1 * t2
+    M = wl.m * wl.m
+    frac = wl.m / t2                      # rows the crop keeps
+    b = bytes_per_real                    # 4 (FP32) or 8 (FP64) per real value
+    per_real = {
+        "draw_noise_rowfft": b * N,                 # writes the pair buffer: 2 b N per pair
+        "draw_colfft_scale_icolfft": (2 * b * N + 2 * b * N * frac) / 2,
+        "draw_irowfft_crop": (2 * b * N * frac + 2 * b * M) / 2,
+    }
+    if name in per_real:
+        return per_real[name] * R, "bytes"
+    if name == "krige_grid_gemm":
+        return 2.0 * M * wl.n * R, "flops"
+    return None, None
+
+
+def run_path(prec, wl, xy, z, args, torch, cesim):
+    R = wl.nreal
+    batch = args.batch or R
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    fields = torch.empty((R, wl.m, wl.m), dtype=dtype, device="cuda")
+    cov = cesim.make_cov(wl.nu, wl.sigma2, wl.range)
+    grid = cesim.unit_square_grid(wl.m)
+    info = {}
+
+    def step():
+        ctx = cesim.Context(cov, grid, prec)
+        ctx.offgrid(xy, wl.k)
+        for b0 in range(0, R, batch):
+            nb = min(batch, R - b0)
+            f = fields[b0:b0 + nb]
+            ctx.simulate(nb, args.seed, b0, out=f)
+            ctx.condition(z, wl.tau2, f)
+        st = ctx.stage_times(reset=True)
+        info.update(ctx.info())
+        ctx.close()
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stages = {}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        st = step()
+        for k, (ms, calls) in st.items():
+            a = stages.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += calls
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1000.0 * wall / args.steps
+    finite = bool(torch.isfinite(fields).all().item())
+    del fields
+    torch.cuda.empty_cache()
+    kernels = []
+    bpr = 8 if prec == "fp64" else 4
+    for name, (ms, calls) in stages.items():
+        if calls == 0:
+            continue
+        units, kind = algorithmic_units(name, wl, R, info["t1"], info["t2"], bpr)
+        k = {"name": name, "ms_per_step": ms / args.steps, "launches_per_step": calls / args.steps,
+             "avg_launch_ms": ms / calls}
+        if kind == "bytes":
+            gbs = units / (ms / args.steps / 1000.0) / 1e9
+            k.update(bound="hbm", achieved=gbs, unit="GB/s", peak=HBM_PEAK_GBS,
+                     frac=gbs / HBM_PEAK_GBS, algorithmic_bytes_per_launch=units / (calls / args.steps))
+        elif kind == "flops":
+            tf = units / (ms / args.steps / 1000.0) / 1e12
+            peak = PEAK_TFLOPS["fp64" if prec == "fp64" else "bf16"]
+            k.update(bound="mfma", achieved=tf, unit="TFLOP/s", peak=peak, frac=tf / peak,
+                     algorithmic_flops_per_launch=units / (calls / args.steps))
+        kernels.append(k)
+    kernels.sort(key=lambda k: -k["ms_per_step"])
+    return dict(ms_per_step=ms_step, value=R / (ms_step / 1000.0), kernels=kernels,
+                event_ms_per_step=ev0.elapsed_time(ev1) / args.steps, t1=info["t1"],
+                finite=finite, gamma_max=info.get("gamma_max"))
+
+
+def cpu_baseline(wl, xy, z, seed):
+    """The oracle timed on a bounded sample of the same workload, scaled to
+    one step of R realizations."""
+    from oracle import ce, kriging, localkrige, philox
+    from oracle.covariance import Cov
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    cov = Cov(wl.nu, wl.sigma2, wl.range)
+    dx = wl.dx
+    R = wl.nreal
+    t = {}
+    s0 = time.perf_counter()
+    t1, t2, s, _ = ce.ce_setup(cov, dx, dx, wl.m, wl.m)
+    t["setup"] = time.perf_counter() - s0
+    s0 = time.perf_counter()
+    a, b, W, gamma = localkrige.local_krige(xy, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, wl.k)
+    t["offgrid"] = time.perf_counter() - s0
+    s0 = time.perf_counter()
+    fac = kriging.factor(xy, cov, wl.tau2)
+    t["cholesky"] = time.perf_counter() - s0
+    nd = 2
+    s0 = time.perf_counter()
+    eps = philox.torus_noise(seed, t1, t2, range(nd))
+    y = ce.ce_draw(s, eps, wl.m, wl.m)
+    xi = philox.offgrid_noise(seed, len(xy), range(nd))
+    zs = localkrige.synthetic_obs(y, a, b, W, gamma, wl.tau2, xi)
+    t["per_real_draw_synth"] = (time.perf_counter() - s0) / nd
+    zsR = np.repeat(zs, R // nd + 1, axis=0)[:R]
+    s0 = time.perf_counter()
+    B = kriging.coefficients(fac, z, zsR)
+    t["solve_R"] = time.perf_counter() - s0
+    rows = np.arange(8)
+    s0 = time.perf_counter()
+    kriging.krige_to_grid(B, xy, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, rows=rows, chunk_rows=8)
+    t["krige_rows"] = time.perf_counter() - s0
+    step = (t["setup"] + t["offgrid"] + t["cholesky"] + R * t["per_real_draw_synth"]
+            + t["solve_R"] + t["krige_rows"] * wl.m / rows.size)
+    return {"value": R / step, "unit": "conditional realizations/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"full setup, local Kriging and Cholesky; {nd} of {R} CE draws and "
+                       f"synthetic data; solves for all {R}; {rows.size} of {wl.m} grid rows "
+                       f"of the K12 product; scaled to one step of {R} realizations"),
+            "seconds_measured": sum(t.values()), "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
+              "(realizations would shard across GPUs with no per-realization exchange).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_2109_11044_amd import cesim, workloads
+    cesim.lib()
+    cesim.set_default_timing(True)
+    wl = workloads.DM
+    wl.m, wl.n, wl.nreal = args.m, args.n, args.nreal
+    xy = wl.obs_xy()
+    z = workloads.iid_values(wl.n, wl.sigma2 + wl.tau2)
+    res = {}
+    for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        res[prec] = run_path(prec, wl, xy, z, args, torch, cesim)
+    head = res.get("mixed") or res["fp64"]
+    dom = head["kernels"][0]
+    gemm = [k for k in head["kernels"] if k.get("bound")]
+    dom_k = max(gemm, key=lambda k: k["ms_per_step"]) if gemm else dom
+    roof = {"bound": dom_k.get("bound"), "kernel": dom_k["name"],
+            "achieved": dom_k.get("achieved"), "peak": dom_k.get("peak"),
+            "unit": dom_k.get("unit"), "frac": dom_k.get("frac"), "traffic": None,
+            "avg_launch_ms": dom_k["avg_launch_ms"]}
+    out = {
+        "metric": "conditional realizations/sec at 1024^2 grid (mixed vs FP64 path); HBM GB/s %",
+        "value": head["value"],
+        "unit": "conditional realizations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 FFT / bf16x3 GEMM (f64 setup, Cholesky, solves)" if "mixed" in res else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name if (args.m, args.n, args.nreal) == (1024, 5000, 1000)
+                   else f"exp{args.m}_n{args.n}cl_k36_R{args.nreal}",
+                   "grid": f"{wl.m}x{wl.m}", "torus": head["t1"], "n_obs": wl.n, "k": wl.k,
+                   "covariance": "exponential sigma2=1 range=0.02", "nugget": wl.tau2,
+                   "realizations_per_step": wl.nreal, "batch": args.batch or wl.nreal},
+        "roofline": roof,
+    }
+    if "fp64" in res and "mixed" in res:
+        out["fp64_path"] = {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"]}
+        out["mixed_over_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    out["kernels"] = {p: r["kernels"] for p, r in res.items()}
+    out["fft_passes_hbm_frac"] = {k["name"]: k["frac"] for k in head["kernels"]
+                                  if k.get("bound") == "hbm"}
+    out["finite"] = all(r["finite"] for r in res.values())
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, xy, z, args.seed)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

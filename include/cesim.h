@@ -207,6 +207,38 @@ cesim_status cesim_philox_host(uint64_t seed, int n, const uint32_t* ctr0,
 
 const char* cesim_status_string(cesim_status s);
 
+/* ---- instrumentation and memory (not part of the method) ----
+ * Stage timing: when enabled, the library records a pair of HIP events on
+ * the context's stream around each stage it launches (per launch or per
+ * chunk of launches); times accumulate until read with reset != 0.
+ * Stages, in order (CESIM_NUM_STAGES of them): torus base, setup FFT,
+ * eigenvalue check, draw pass 1 (noise + row FFT), draw pass 2 (column
+ * FFT, scale, inverse column FFT), draw pass 3 (inverse row FFT + crop),
+ * local-Kriging setup, observation Cholesky, synthetic observations and
+ * right-hand sides, observation solves, bf16 split of the coefficients,
+ * cross-covariance GEMM onto the grid. */
+#define CESIM_NUM_STAGES 12
+
+/* Default timing state of contexts created afterwards (process-wide). */
+void cesim_set_default_timing(int enable);
+
+/* Enables (1) or disables (0) stage timing on one context. */
+cesim_status ce_set_timing(cesim_ctx ctx, int enable);
+
+/* Accumulated stage times in ms and launch counts (either array may be
+ * NULL) for the first nstages stages; synchronises the stream.  reset != 0
+ * clears the accumulators after reading. */
+cesim_status ce_get_stage_times(cesim_ctx ctx, double* ms, long long* calls,
+                                int nstages, int reset);
+
+/* Name of stage i, or "unknown". */
+const char* cesim_stage_name(int stage);
+
+/* Device memory freed by destroyed contexts is cached by the library for
+ * reuse (so repeated set-ups do not call hipMalloc); this returns the cache
+ * to the runtime.  Call only while no context is in use. */
+void cesim_release_cached_memory(void);
+
 /* Releases the context and every device buffer it owns (after
  * synchronising its stream).  NULL is ignored. */
 void ce_destroy(cesim_ctx ctx);

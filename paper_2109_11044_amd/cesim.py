@@ -23,7 +23,12 @@ PREC = {"fp64": 0, "mixed": 1}
 EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "ce_get_info", "ce_copy_spectrum", "offgrid_copy_weights",
            "condition_copy_coefficients", "cesim_covariance_host",
-           "cesim_philox_host", "cesim_status_string", "ce_destroy"]
+           "cesim_philox_host", "cesim_status_string", "ce_destroy",
+           "cesim_set_default_timing", "ce_set_timing", "ce_get_stage_times",
+           "cesim_stage_name", "cesim_release_cached_memory"]
+NUM_STAGES = 12
+VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",
+                "cesim_stage_name", "cesim_release_cached_memory")
 
 
 class CesimError(RuntimeError):
@@ -87,8 +92,16 @@ def lib():
     L.cesim_status_string.restype = ctypes.c_char_p
     L.ce_destroy.argtypes = [vp]
     L.ce_destroy.restype = None
+    L.cesim_set_default_timing.argtypes = [i]
+    L.cesim_set_default_timing.restype = None
+    L.ce_set_timing.argtypes = [vp, i]
+    L.ce_get_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), i, i]
+    L.cesim_stage_name.argtypes = [i]
+    L.cesim_stage_name.restype = ctypes.c_char_p
+    L.cesim_release_cached_memory.argtypes = []
+    L.cesim_release_cached_memory.restype = None
     for name in EXPORTS:
-        if name not in ("cesim_status_string", "ce_destroy"):
+        if name not in VOID_EXPORTS:
             getattr(L, name).restype = i
     _lib = L
     return L
@@ -138,6 +151,18 @@ def philox_host(seed, ctr0, c1, c2, c3):
                                    int(c1), int(c2), int(c3),
                                    out.ctypes.data_as(P)), "philox_host")
     return out
+
+
+def stage_names():
+    return [lib().cesim_stage_name(i).decode() for i in range(NUM_STAGES)]
+
+
+def set_default_timing(enable):
+    lib().cesim_set_default_timing(1 if enable else 0)
+
+
+def release_cached_memory():
+    lib().cesim_release_cached_memory()
 
 
 class Context:
@@ -216,6 +241,18 @@ class Context:
         inf = Info()
         _check(lib().ce_get_info(self._h, ctypes.byref(inf)), "ce_get_info")
         return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def set_timing(self, enable):
+        _check(lib().ce_set_timing(self._h, 1 if enable else 0), "ce_set_timing")
+
+    def stage_times(self, reset=True):
+        """{stage: (ms, launches)} accumulated since the last reset."""
+        ms = np.zeros(NUM_STAGES)
+        calls = np.zeros(NUM_STAGES, dtype=np.int64)
+        _check(lib().ce_get_stage_times(self._h, _dptr(ms),
+                                        calls.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                        NUM_STAGES, 1 if reset else 0), "ce_get_stage_times")
+        return {n: (float(ms[i]), int(calls[i])) for i, n in enumerate(stage_names())}
 
     def spectrum(self):
         t = self._torch

@@ -6,6 +6,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -13,24 +15,133 @@
 
 namespace cesim {
 
+// ------------------------------------------------------- caching allocator
+namespace {
+std::mutex g_cache_mu;
+std::multimap<size_t, void*> g_cache;     // size -> block
+size_t g_cached_bytes = 0;
+constexpr size_t kCacheCap = (size_t)64 << 30;
+constexpr size_t kRound = (size_t)2 << 20;
+bool g_default_timing = false;
+}  // namespace
+
+void* cache_alloc(size_t bytes, size_t* got) {
+  bytes = (bytes + kRound - 1) / kRound * kRound;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.lower_bound(bytes);
+    if (it != g_cache.end() && it->first <= 2 * bytes) {
+      void* p = it->second;
+      *got = it->first;
+      g_cached_bytes -= it->first;
+      g_cache.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    cache_trim();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  *got = bytes;
+  return p;
+}
+
+void cache_free(void* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_cached_bytes + bytes > kCacheCap) {
+    (void)hipFree(p);
+    return;
+  }
+  g_cache.emplace(bytes, p);
+  g_cached_bytes += bytes;
+}
+
+void cache_trim() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& kv : g_cache) (void)hipFree(kv.second);
+  g_cache.clear();
+  g_cached_bytes = 0;
+}
+
 cesim_status DevBuf::reserve(size_t n) {
   if (n <= bytes && p) return CESIM_OK;
   release();
-  if (n == 0) n = 16;
-  if (hipMalloc(&p, n) != hipSuccess) {
-    (void)hipGetLastError();
-    p = nullptr;
+  size_t got = 0;
+  p = cache_alloc(n ? n : 16, &got);
+  if (!p) {
     bytes = 0;
     return CESIM_ERR_OUT_OF_MEMORY;
   }
-  bytes = n;
+  bytes = got;
   return CESIM_OK;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    (void)hipStreamSynchronize(stream);     // work that used the block is done
+    cache_free(p, bytes);
+  }
   p = nullptr;
   bytes = 0;
+}
+
+// ------------------------------------------------------------ stage timer
+hipEvent_t StageTimer::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+int StageTimer::begin(int stage, hipStream_t s) {
+  if (!enabled) return -1;
+  hipEvent_t a = get();
+  if (!a) return -1;
+  (void)hipEventRecord(a, s);
+  pending.push_back({stage, a, nullptr});
+  return (int)pending.size() - 1;
+}
+
+void StageTimer::end(int rec, hipStream_t s) {
+  if (rec < 0 || rec >= (int)pending.size()) return;
+  hipEvent_t b = get();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  pending[rec].b = b;
+}
+
+void StageTimer::resolve() {
+  for (Rec& r : pending) {
+    if (r.b) {
+      float ms_ = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms_, r.a, r.b) == hipSuccess) {
+        ms[r.stage] += ms_;
+        calls[r.stage] += 1;
+      }
+      pool.push_back(r.b);
+    }
+    pool.push_back(r.a);
+  }
+  pending.clear();
+}
+
+void StageTimer::destroy() {
+  resolve();
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
 }
 
 namespace {
@@ -121,15 +232,55 @@ const char* cesim_status_string(cesim_status s) {
   return "unknown status";
 }
 
+static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
+  return {&c->tt.tw1_64, &c->tt.tw2_64, &c->tt.tw1_32, &c->tt.tw2_32, &c->s64,
+          &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
+          &c->corners, &c->weights, &c->gamma, &c->phi, &c->amat, &c->dinv,
+          &c->zdev, &c->coef, &c->coef_b16, &c->info_dev};
+}
+
 void ce_destroy(cesim_ctx c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  DevBuf* bufs[] = {&c->tt.tw1_64, &c->tt.tw2_64, &c->tt.tw1_32, &c->tt.tw2_32, &c->s64,
-                    &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
-                    &c->corners, &c->weights, &c->gamma, &c->phi, &c->amat, &c->dinv,
-                    &c->zdev, &c->coef, &c->coef_b16, &c->info_dev};
-  for (DevBuf* b : bufs) b->release();
+  c->timer.destroy();
+  for (DevBuf* b : all_bufs(c)) b->release();
   delete c;
+}
+
+void cesim_release_cached_memory(void) { cache_trim(); }
+
+void cesim_set_default_timing(int enable) { g_default_timing = enable != 0; }
+
+cesim_status ce_set_timing(cesim_ctx c, int enable) {
+  if (!c) return CESIM_ERR_INVALID_ARG;
+  c->timer.enabled = enable != 0;
+  return CESIM_OK;
+}
+
+cesim_status ce_get_stage_times(cesim_ctx c, double* ms, long long* calls, int nstages,
+                                int reset) {
+  if (!c || nstages < 0 || nstages > ST_COUNT) return CESIM_ERR_INVALID_ARG;
+  CESIM_HIP(hipStreamSynchronize(c->stream));
+  c->timer.resolve();
+  for (int i = 0; i < nstages; ++i) {
+    if (ms) ms[i] = c->timer.ms[i];
+    if (calls) calls[i] = c->timer.calls[i];
+  }
+  if (reset) {
+    for (int i = 0; i < ST_COUNT; ++i) {
+      c->timer.ms[i] = 0;
+      c->timer.calls[i] = 0;
+    }
+  }
+  return CESIM_OK;
+}
+
+const char* cesim_stage_name(int stage) {
+  static const char* names[ST_COUNT] = {
+      "setup_torus_base", "setup_fft2_fp64", "setup_eigen_check", "draw_noise_rowfft",
+      "draw_colfft_scale_icolfft", "draw_irowfft_crop", "offgrid_local_krige",
+      "obs_cholesky", "synth_obs_rhs", "obs_solve", "coef_split_bf16", "krige_grid_gemm"};
+  return (stage >= 0 && stage < ST_COUNT) ? names[stage] : "unknown";
 }
 
 cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precision prec,
@@ -148,6 +299,8 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
   c->prec = prec;
   c->covd = make_cov(*cov);
   c->gridd = {grid->m1, grid->m2, grid->x0, grid->y0, grid->dx, grid->dy};
+  for (DevBuf* b : all_bufs(c)) b->stream = c->stream;
+  c->timer.enabled = g_default_timing;
   cesim_status st = c->info_dev.reserve(sizeof(int) * 4);
   if (st != CESIM_OK) { ce_destroy(c); return st; }
   std::vector<std::pair<int, int>> cands;

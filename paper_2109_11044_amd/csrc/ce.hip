@@ -363,19 +363,25 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
   const size_t N = (size_t)t1 * t2;
   CESIM_TRY(c->work.reserve(sizeof(double2) * N));
   double2* buf = c->work.as<double2>();
+  int tr = c->timer.begin(ST_SETUP_BASE, s);
   k_torus_base<<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy, t1,
                                                           t2, buf);
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
+  tr = c->timer.begin(ST_SETUP_FFT, s);
   CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, p1, c->tt.tw1_64.as<double2>(), 0, 0,
                                             0, 0, 0, s)));
   CESIM_TRY((launch_cols<double, false>(buf, t1, t2, 1, t2, p2, c->tt.tw2_64.as<double2>(),
                                         nullptr, s)));
+  c->timer.end(tr, s);
   const int nparts = 512;
   CESIM_TRY(c->scratch.reserve(sizeof(double) * (4 * nparts + 8)));
   double* part = c->scratch.as<double>();
+  tr = c->timer.begin(ST_SETUP_EIG, s);
   k_eig_partial<<<nparts, 256, 0, s>>>(buf, N, part);
   k_eig_final<<<1, 64, 0, s>>>(part, nparts, part + 4 * nparts);
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
   double st[4];
   CESIM_HIP(hipMemcpyAsync(st, part + 4 * nparts, sizeof(st), hipMemcpyDeviceToHost, s));
   CESIM_HIP(hipStreamSynchronize(s));
@@ -391,9 +397,11 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
     CESIM_TRY(c->s32.reserve(sizeof(float) * N));
     s32 = c->s32.as<float>();
   }
+  tr = c->timer.begin(ST_SETUP_EIG, s);
   k_sqrt_lambda<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(buf, N, 1.0 / (double)N,
                                                             c->s64.as<double>(), s32);
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
   return CESIM_OK;
 }
 
@@ -413,11 +421,17 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   for (int pair0 = 0; pair0 < npairs; pair0 += chunk) {
     const int np = std::min(chunk, npairs - pair0);
+    int tr = c->timer.begin(ST_DRAW_PASS1, s);
     CESIM_TRY((launch_rows_fwd<real, true>(buf, t1, t2, np, c->tt.p1, tw1, k0, k1, first_real,
                                            nreal, pair0, s)));
+    c->timer.end(tr, s);
+    tr = c->timer.begin(ST_DRAW_PASS2, s);
     CESIM_TRY((launch_cols<real, true>(buf, t1, t2, np, m2, c->tt.p2, tw2, sl, s)));
+    c->timer.end(tr, s);
+    tr = c->timer.begin(ST_DRAW_PASS3, s);
     CESIM_TRY((launch_rows_inv_crop<real>(buf, fields, t1, t2, m1, m2, np, c->tt.p1, tw1, nreal,
                                           pair0, s)));
+    c->timer.end(tr, s);
   }
   return CESIM_OK;
 }

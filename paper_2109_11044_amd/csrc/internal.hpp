@@ -31,13 +31,42 @@ struct GridDev {
   double x0, y0, dx, dy;
 };
 
+// Process-wide caching allocator: freed blocks are kept for reuse so that
+// repeated set-ups do not call hipMalloc / hipFree (which synchronise the
+// device).  A block is handed back only after the stream that used it has
+// drained.
+void* cache_alloc(size_t bytes, size_t* got);
+void cache_free(void* p, size_t bytes);
+void cache_trim();
+
 // A device allocation owned by the context.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t stream = nullptr;     // stream whose work last used the block
   cesim_status reserve(size_t n);   // grows, never shrinks; contents lost
   void release();
   template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Stages timed with HIP events when timing is enabled on a context.
+enum Stage {
+  ST_SETUP_BASE = 0, ST_SETUP_FFT, ST_SETUP_EIG, ST_DRAW_PASS1, ST_DRAW_PASS2, ST_DRAW_PASS3,
+  ST_LK_SETUP, ST_CHOL, ST_SYNTH_RHS, ST_SOLVE, ST_COEF_SPLIT, ST_KRIGE_GEMM, ST_COUNT
+};
+
+struct StageTimer {
+  bool enabled = false;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[ST_COUNT] = {0};
+  long calls[ST_COUNT] = {0};
+  hipEvent_t get();
+  int begin(int stage, hipStream_t s);      // returns a record index or -1
+  void end(int rec, hipStream_t s);
+  void resolve();                           // after a stream synchronise
+  void destroy();
 };
 
 struct TorusTables {
@@ -60,6 +89,7 @@ struct cesim_ctx_s {
   double ms_setup = 0, ms_offgrid = 0;
 
   cesim::TorusTables tt;
+  cesim::StageTimer timer;
   cesim::DevBuf s64, s32;           // sqrt(lambda) / (t1 t2), [t2][t1]
   cesim::DevBuf work;               // pair buffers of the draw / setup FFT
   cesim::DevBuf scratch;            // small reductions

@@ -221,10 +221,12 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     double ux, uxy, uyx, uy;
     cov_map(c, 1.0, ux, uxy, uyx, uy);
     dim3 grid((M + 127) / 128, (R + 63) / 64);
+    const int tr = c->timer.begin(ST_KRIGE_GEMM, s);
     k_krige_f64<<<grid, 256, 0, s>>>(static_cast<double*>(fields), m1, M, R, X, n,
                                      c->obs_t64.as<double2>(), ux, uxy, uyx, uy, dx, dy,
                                      c->covd.nu_code, c->covd.sigma2);
     CESIM_HIP(hipGetLastError());
+    c->timer.end(tr, s);
     return CESIM_OK;
   }
   const int Rp = (R + 255) / 256 * 256;
@@ -232,16 +234,20 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   CESIM_TRY(c->coef_b16.reserve(sizeof(__bf16) * 2 * (size_t)npad * Rp));
   __bf16* Bh = c->coef_b16.as<__bf16>();
   __bf16* Bl = Bh + (size_t)npad * Rp;
+  int tr = c->timer.begin(ST_COEF_SPLIT, s);
   k_split_coef<<<dim3((npad + 255) / 256, Rp), 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, Bh, Bl);
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
   const double kappa = c->covd.nu_code == 0 ? kLog2e : (c->covd.nu_code == 2 ? kSqrt3 : kSqrt2);
   double ux, uxy, uyx, uy;
   cov_map(c, kappa, ux, uxy, uyx, uy);
   dim3 grid((M + 127) / 128, Rp / 256);
+  tr = c->timer.begin(ST_KRIGE_GEMM, s);
   k_krige_bf16x3<<<grid, 256, 0, s>>>(static_cast<float*>(fields), m1, M, R, Rp, Bh, Bl, n,
                                       c->obs_t32.as<float2>(), (float)ux, (float)uxy, (float)uyx,
                                       (float)uy, (float)dx, (float)dy, c->covd.nu_code);
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
   return CESIM_OK;
 }
 

@@ -240,6 +240,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
   double* D = c->dinv.as<double>();
   int* info = c->info_dev.as<int>();
   CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
+  const int tr = c->timer.begin(ST_CHOL, s);
   k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd, tau2,
                                                          A);
   CESIM_HIP(hipGetLastError());
@@ -258,6 +259,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
     g.C = A + (size_t)(k0 + nbk) * n + (k0 + nbk); g.sci = n; g.scj = 1;
     CESIM_TRY(gemm_f64(g, true, s));
   }
+  c->timer.end(tr, s);
   int hinfo[4];
   CESIM_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   CESIM_HIP(hipStreamSynchronize(s));
@@ -273,6 +275,7 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
   const double* L = c->amat.as<double>();
   const double* D = c->dinv.as<double>();
   const dim3 gdiag((R + kNB - 1) / kNB);
+  const int tr = c->timer.begin(ST_SOLVE, s);
   for (int kb = 0; kb < nblk; ++kb) {          // L Y = X
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
     k_trsm_diag<false><<<gdiag, 256, 0, s>>>(X, n, R, k0, nbk, D + (size_t)kb * kNB * kNB);
@@ -298,6 +301,7 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
     g.C = X; g.sci = 1; g.scj = n;
     CESIM_TRY(gemm_f64(g, false, s));
   }
+  c->timer.end(tr, s);
   return CESIM_OK;
 }
 

@@ -128,6 +128,7 @@ cesim_status lk_setup_device(cesim_ctx c) {
   auto* cor = c->corners.as<int2>();
   auto* W = c->weights.as<double>();
   auto* gm = c->gamma.as<double>();
+  const int tr = c->timer.begin(ST_LK_SETUP, s);
   switch (c->npp) {
     case 1: k_lk_setup<1><<<grid, 128, 0, s>>>(obs, n, c->gridd, c->covd, cor, W, gm, info); break;
     case 2: k_lk_setup<2><<<grid, 128, 0, s>>>(obs, n, c->gridd, c->covd, cor, W, gm, info); break;
@@ -136,13 +137,16 @@ cesim_status lk_setup_device(cesim_ctx c) {
     default: return CESIM_ERR_INVALID_ARG;
   }
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
   return CESIM_OK;
 }
 
 cesim_status lk_phi_device(cesim_ctx c, double tau2) {
+  const int tr = c->timer.begin(ST_SYNTH_RHS, c->stream);
   k_phi<<<(c->nobs + 255) / 256, 256, 0, c->stream>>>(c->gamma.as<double>(), c->nobs, tau2,
                                                       c->phi.as<double>());
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, c->stream);
   return CESIM_OK;
 }
 
@@ -151,6 +155,7 @@ cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs) {
   dim3 grid((n + 255) / 256, c->nreal);
   const uint32_t k0 = (uint32_t)(c->seed & 0xffffffffu), k1 = (uint32_t)(c->seed >> 32);
   const int w2 = 2 * c->npp;
+  const int tr = c->timer.begin(ST_SYNTH_RHS, c->stream);
   if (c->prec == CESIM_PREC_FP64)
     k_synth_rhs<double><<<grid, 256, 0, c->stream>>>(
         static_cast<const double*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
@@ -162,6 +167,7 @@ cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs) {
         c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, k0, k1,
         c->first_real, rhs);
   CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, c->stream);
   return CESIM_OK;
 }
 
