@@ -58,6 +58,17 @@ __global__ void k_torus_base(CovDev cov, double dx, double dy, int t1, int t2, d
   out[(size_t)q2 * t1 + q1] = {c, 0.0};
 }
 
+// Copies the twiddle table into LDS after the data (when it fits) so that
+// the stages read it without global-memory latency; the caller's barrier
+// after loading the data also covers this copy.
+template <typename real, int NTHR>
+__device__ inline const cpx<real>* stage_twiddles(cpx<real>* dst, const cpx<real>* __restrict__ tw,
+                                                 int T, bool tw_lds) {
+  if (!tw_lds) return tw;
+  for (int t = threadIdx.x; t < T; t += NTHR) dst[t] = tw[t];
+  return dst;
+}
+
 // Noise for torus rows [j0, j0 + nrows) of pair p into LDS as
 // eps_{r0} + i eps_{r1}; element q = j t1 + i uses block q / 4, word q % 4.
 template <typename real, int NTHR>
@@ -88,14 +99,15 @@ __device__ void noise_rows(cpx<real>* lds, int t1, int j0, int nrows, uint32_t k
 template <typename real, int NTHR, int E, bool NOISE>
 __global__ void __launch_bounds__(NTHR)
 k_rows_fwd(cpx<real>* __restrict__ buf, int t1, int t2, int nb, Plan plan,
-           const cpx<real>* __restrict__ tw, uint32_t k0, uint32_t k1, int first_real,
-           int nreal, int pair0) {
+           const cpx<real>* __restrict__ tw, bool tw_lds, uint32_t k0, uint32_t k1,
+           int first_real, int nreal, int pair0) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
   const int p = blockIdx.y;
   const int j0 = blockIdx.x * nb;
   const int nr = min(nb, t2 - j0);
   cpx<real>* base = buf + ((size_t)p * t2 + j0) * t1;
+  const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + nb * t1, tw, t1, tw_lds);
   if constexpr (NOISE) {
     const int pg = pair0 + p;               // pair index within this call
     const int r0 = first_real + 2 * pg;
@@ -104,7 +116,7 @@ k_rows_fwd(cpx<real>* __restrict__ buf, int t1, int t2, int nb, Plan plan,
     for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
   }
   __syncthreads();
-  fft_lds<false, NTHR, E, false, real>(lds, plan, nr, 1, t1, tw);
+  fft_lds<false, NTHR, E, false, real>(lds, plan, nr, 1, t1, twl);
   for (int e = threadIdx.x; e < nr * t1; e += NTHR) base[e] = lds[e];
 }
 
@@ -113,9 +125,10 @@ k_rows_fwd(cpx<real>* __restrict__ buf, int t1, int t2, int nb, Plan plan,
 template <typename real, int NTHR, int E, bool SCALE>
 __global__ void __launch_bounds__(NTHR)
 k_cols(cpx<real>* __restrict__ buf, int t1, int t2, int cp, int rows_out, Plan plan,
-       const cpx<real>* __restrict__ tw, const real* __restrict__ s) {
+       const cpx<real>* __restrict__ tw, bool tw_lds, const real* __restrict__ s) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
+  const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + cp * t2, tw, t2, tw_lds);
   const int p = blockIdx.y;
   const int c0 = blockIdx.x * cp;
   const int cw = min(cp, t1 - c0);
@@ -125,7 +138,7 @@ k_cols(cpx<real>* __restrict__ buf, int t1, int t2, int cp, int rows_out, Plan p
     lds[e] = c < cw ? base[(size_t)row * t1 + c] : cpx<real>{0, 0};
   }
   __syncthreads();
-  fft_lds<false, NTHR, E, true, real>(lds, plan, cp, cp, 1, tw);
+  fft_lds<false, NTHR, E, true, real>(lds, plan, cp, cp, 1, twl);
   if constexpr (SCALE) {
     for (int e = threadIdx.x; e < t2 * cp; e += NTHR) {
       const int row = e / cp, c = e - row * cp;
@@ -135,7 +148,7 @@ k_cols(cpx<real>* __restrict__ buf, int t1, int t2, int cp, int rows_out, Plan p
       }
     }
     __syncthreads();
-    fft_lds<true, NTHR, E, true, real>(lds, plan, cp, cp, 1, tw);
+    fft_lds<true, NTHR, E, true, real>(lds, plan, cp, cp, 1, twl);
   }
   for (int e = threadIdx.x; e < rows_out * cp; e += NTHR) {
     const int row = e / cp, c = e - row * cp;
@@ -148,17 +161,18 @@ k_cols(cpx<real>* __restrict__ buf, int t1, int t2, int cp, int rows_out, Plan p
 template <typename real, int NTHR, int E>
 __global__ void __launch_bounds__(NTHR)
 k_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, int t1, int t2,
-                int m1, int m2, int nb, Plan plan, const cpx<real>* __restrict__ tw, int nreal,
-                int pair0) {
+                int m1, int m2, int nb, Plan plan, const cpx<real>* __restrict__ tw, bool tw_lds,
+                int nreal, int pair0) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
+  const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + nb * t1, tw, t1, tw_lds);
   const int p = blockIdx.y;
   const int j0 = blockIdx.x * nb;
   const int nr = min(nb, m2 - j0);
   const cpx<real>* base = buf + ((size_t)p * t2 + j0) * t1;
   for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
   __syncthreads();
-  fft_lds<true, NTHR, E, false, real>(lds, plan, nr, 1, t1, tw);
+  fft_lds<true, NTHR, E, false, real>(lds, plan, nr, 1, t1, twl);
   const int pg = pair0 + p;
   const size_t M = (size_t)m1 * m2;
   real* f0 = fields + (size_t)(2 * pg) * M + (size_t)j0 * m1;
@@ -252,26 +266,32 @@ cesim_status make_twiddles(int T, DevBuf& tw64, DevBuf& tw32, hipStream_t s) {
 namespace {
 
 constexpr int kRowThreads = 256;
-constexpr int kColThreads = 1024;
-constexpr size_t kLdsBudget = 128 * 1024;
+constexpr int kColThreads = 512;
+constexpr size_t kLdsTotal = 160 * 1024;
 
-// Rows per workgroup and elements per thread for the row kernels.
+// Rows per workgroup, elements per thread and whether the twiddle table
+// sits in LDS, for the row kernels.
 template <typename real>
-void row_config(int T, int& nb, int& E) {
-  const int cap = (int)(kLdsBudget / sizeof(cpx<real>)) / 2;   // elements per WG
-  const int tgt = std::min(cap, 4096);
-  nb = std::max(1, tgt / T);
+void row_config(int T, int& nb, int& E, bool& tw_lds, size_t& lds) {
+  const size_t cs = sizeof(cpx<real>);
+  nb = std::max(1, 4096 / T);
+  while (nb > 1 && (size_t)nb * T * cs > kLdsTotal / 2) --nb;
+  tw_lds = (size_t)(nb + 1) * T * cs <= kLdsTotal;
+  lds = (size_t)(nb + (tw_lds ? 1 : 0)) * T * cs;
   const int el = nb * T;
   E = el <= 16 * kRowThreads ? 16 : 32;
 }
 
 template <typename real>
-void col_config(int T, int t1, int& cp, int& E) {
-  const int cap = (int)(kLdsBudget / sizeof(cpx<real>));
-  cp = std::max(1, std::min(16, cap / T));
+void col_config(int T, int t1, int& cp, int& E, bool& tw_lds, size_t& lds) {
+  const size_t cs = sizeof(cpx<real>);
+  tw_lds = (size_t)2 * T * cs <= kLdsTotal;          // table and at least one column
+  const size_t cap = (kLdsTotal - (tw_lds ? T * cs : 0)) / cs;
+  cp = std::max(1, (int)std::min<size_t>(16, cap / T));
   int c = 1;
   while (c * 2 <= cp) c *= 2;
   cp = std::min(c, std::max(1, t1));
+  lds = ((size_t)cp * T + (tw_lds ? T : 0)) * cs;
   const int el = cp * T;
   E = el <= 4 * kColThreads ? 4 : el <= 8 * kColThreads ? 8 : el <= 16 * kColThreads ? 16 : 32;
 }
@@ -288,17 +308,20 @@ cesim_status launch_rows_fwd(cpx<real>* buf, int t1, int t2, int npairs, const P
                              const cpx<real>* tw, uint32_t k0, uint32_t k1, int first_real,
                              int nreal, int pair0, hipStream_t s) {
   int nb, E;
-  row_config<real>(t1, nb, E);
-  const size_t lds = sizeof(cpx<real>) * (size_t)nb * t1;
+  bool twl;
+  size_t lds;
+  row_config<real>(t1, nb, E, twl, lds);
   dim3 grid((t2 + nb - 1) / nb, npairs);
   if (E == 16) {
     auto k = k_rows_fwd<real, kRowThreads, 16, NOISE>;
     allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, k0, k1, first_real, nreal, pair0);
+    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, k0, k1, first_real, nreal,
+                                     pair0);
   } else {
     auto k = k_rows_fwd<real, kRowThreads, 32, NOISE>;
     allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, k0, k1, first_real, nreal, pair0);
+    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, k0, k1, first_real, nreal,
+                                     pair0);
   }
   CESIM_HIP(hipGetLastError());
   return CESIM_OK;
@@ -308,14 +331,15 @@ template <typename real, bool SCALE>
 cesim_status launch_cols(cpx<real>* buf, int t1, int t2, int npairs, int rows_out, const Plan& plan,
                          const cpx<real>* tw, const real* sl, hipStream_t s) {
   int cp, E;
-  col_config<real>(t2, t1, cp, E);
-  const size_t lds = sizeof(cpx<real>) * (size_t)cp * t2;
+  bool twl;
+  size_t lds;
+  col_config<real>(t2, t1, cp, E, twl, lds);
   dim3 grid((t1 + cp - 1) / cp, npairs);
-#define CESIM_COLS(EE)                                                       \
-  {                                                                          \
-    auto k = k_cols<real, kColThreads, EE, SCALE>;                           \
-    allow_lds(k, lds);                                                       \
-    k<<<grid, kColThreads, lds, s>>>(buf, t1, t2, cp, rows_out, plan, tw, sl); \
+#define CESIM_COLS(EE)                                                            \
+  {                                                                               \
+    auto k = k_cols<real, kColThreads, EE, SCALE>;                                \
+    allow_lds(k, lds);                                                            \
+    k<<<grid, kColThreads, lds, s>>>(buf, t1, t2, cp, rows_out, plan, tw, twl, sl); \
   }
   switch (E) {
     case 4: CESIM_COLS(4) break;
@@ -333,17 +357,20 @@ cesim_status launch_rows_inv_crop(const cpx<real>* buf, real* fields, int t1, in
                                   int m2, int npairs, const Plan& plan, const cpx<real>* tw,
                                   int nreal, int pair0, hipStream_t s) {
   int nb, E;
-  row_config<real>(t1, nb, E);
-  const size_t lds = sizeof(cpx<real>) * (size_t)nb * t1;
+  bool twl;
+  size_t lds;
+  row_config<real>(t1, nb, E, twl, lds);
   dim3 grid((m2 + nb - 1) / nb, npairs);
   if (E == 16) {
     auto k = k_rows_inv_crop<real, kRowThreads, 16>;
     allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, nreal, pair0);
+    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, twl, nreal,
+                                     pair0);
   } else {
     auto k = k_rows_inv_crop<real, kRowThreads, 32>;
     allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, nreal, pair0);
+    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, twl, nreal,
+                                     pair0);
   }
   CESIM_HIP(hipGetLastError());
   return CESIM_OK;

@@ -21,19 +21,22 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------ FP64 kernel
-// Workgroup: 4 waves, tile 128 grid nodes x 64 realizations; wave w owns
-// nodes [32w, 32w + 32) as 2 x 4 blocks of 16 x 16.  k-chunks of 16
-// observations are staged in LDS (coefficients and coordinates).
-__global__ void __launch_bounds__(256)
+// D[r][g] = sum_i X[r][i] K12[g][i] on v_mfma_f64_16x16x4f64 (lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator v of lane l is
+// D[l / 16 + 4 v][l % 16]): grid nodes run along the lanes, so stores are
+// runs of 16 consecutive nodes.  Workgroup: 4 waves, 128 nodes x 128
+// realizations; wave w owns nodes [32w, 32w + 32) (2 blocks of 16) and all
+// 8 blocks of 16 realizations.  Chunks of 16 observations are double-buffered
+// in LDS, the next one fetched into registers during the current product.
+__global__ void __launch_bounds__(256, 2)
 k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __restrict__ X,
             int n, const double2* __restrict__ st, double ux, double uxy, double uyx, double uy,
             double dx, double dy, int nu_code, double sigma2) {
-  constexpr int TG = 128, TR = 64, TK = 16;
-  __shared__ double Bs[TK][TR + 2];
-  __shared__ double2 Ss[TK];
+  constexpr int TG = 128, TR = 128, TK = 16;
+  __shared__ double Xs[2][TK][TR + 1];
+  __shared__ double2 Ss[2][TK];
   const int g0 = blockIdx.x * TG, r0 = blockIdx.y * TR;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // transformed coordinates of this lane's two grid nodes
   double gxt[2], gyt[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -42,87 +45,112 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
     gxt[t] = ux * gx + uxy * gy;
     gyt[t] = uyx * gx + uy * gy;
   }
-  doublex4 acc[2][4];
+  doublex4 acc[2][8];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (doublex4){0.0, 0.0, 0.0, 0.0};
-  for (int i0 = 0; i0 < n; i0 += TK) {
+    for (int b = 0; b < 8; ++b) acc[a][b] = (doublex4){0.0, 0.0, 0.0, 0.0};
+  // fetch: thread t loads 8 coefficients of realization row t/2, half t%2
+  const int frow = threadIdx.x >> 1, fhalf = (threadIdx.x & 1) * 8;
+  double pv[8];
+  double2 ps = {0.0, 0.0};
+  auto fetch = [&](int i0) {
+    const int gr = r0 + frow;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int kk = e % TK, rr = e / TK;
-      const int gi = i0 + kk, gr = r0 + rr;
-      Bs[kk][rr] = (gi < n && gr < R) ? X[(size_t)gr * n + gi] : 0.0;
+    for (int u = 0; u < 8; ++u) {
+      const int gi = i0 + fhalf + u;
+      pv[u] = (gr < R && gi < n) ? X[(size_t)gr * n + gi] : 0.0;
     }
-    if (threadIdx.x < TK) {
-      const int gi = i0 + threadIdx.x;
-      Ss[threadIdx.x] = gi < n ? st[gi] : st[n - 1];
-    }
-    __syncthreads();
+    if (threadIdx.x < TK) ps = st[min(i0 + (int)threadIdx.x, n - 1)];
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Xs[buf][fhalf + u][frow] = pv[u];
+    if (threadIdx.x < TK) Ss[buf][threadIdx.x] = ps;
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int nchunks = (n + TK - 1) / TK;
+  for (int kc = 0; kc < nchunks; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nchunks) fetch((kc + 1) * TK);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
-      const double2 sv = Ss[kk];
-      double a[2], b[4];
+      const double2 sv = Ss[buf][kk];
+      double kg[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const double hx = gxt[t] - sv.x, hy = gyt[t] - sv.y;
-        a[t] = sigma2 * matern_rho(nu_code, sqrt(hx * hx + hy * hy));
+        kg[t] = sigma2 * matern_rho(nu_code, sqrt(hx * hx + hy * hy));
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) b[t] = Bs[kk][16 * t + (lane & 15)];
+      for (int b = 0; b < 8; ++b) {
+        const double a = Xs[buf][kk][16 * b + (lane & 15)];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+        for (int t = 0; t < 2; ++t)
+          acc[t][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, kg[t], acc[t][b], 0, 0, 0);
+      }
     }
+    if (kc + 1 < nchunks) stash(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int t = 0; t < 2; ++t) {
+    const int g = g0 + 32 * wave + 16 * t + (lane & 15);
+    if (g >= M) continue;
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int b = 0; b < 8; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int g = g0 + 32 * wave + 16 * x + (lane >> 4) + 4 * v;   // D[l/16 + 4v][l%16]
-        const int r = r0 + 16 * y + (lane & 15);
-        if (g < M && r < R) fields[(size_t)r * M + g] += acc[x][y][v];
+        const int r = r0 + 16 * b + (lane >> 4) + 4 * v;
+        if (r < R) fields[(size_t)r * M + g] += acc[t][b][v];
       }
+  }
 }
 
 // ----------------------------------------------------------- mixed kernel
-// B split: Bh/Bl[kc][r][16] bf16 (observation chunk kc of 16, realization r)
-// from FP64 X[r][i] with sigma^2 folded in.
+constexpr int kKC = 32;     // observations per k-chunk of the mixed kernel
+
+// B split: Bh/Bl[kc][r][32] bf16 (observation chunk kc of 32, realization r)
+// from FP64 X[r][i] with sigma^2 folded in; hi = bf16(v), lo = bf16(v - hi).
 __global__ void k_split_coef(const double* __restrict__ X, int n, int R, int Rp, double scale,
                              __bf16* __restrict__ Bh, __bf16* __restrict__ Bl) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  const int npad = (n + 15) / 16 * 16;
+  const int npad = (n + kKC - 1) / kKC * kKC;
   if (i >= npad) return;
   const double v = (i < n && r < R) ? scale * X[(size_t)r * n + i] : 0.0;
   const float f = (float)v;
   const __bf16 h = (__bf16)f;
   const __bf16 l = (__bf16)(float)(v - (double)(float)h);
-  const size_t o = ((size_t)(i / 16) * Rp + r) * 16 + (i % 16);
+  const size_t o = ((size_t)(i / kKC) * Rp + r) * kKC + (i % kKC);
   Bh[o] = h;
   Bl[o] = l;
 }
 
-// Workgroup: 4 waves, tile 128 grid nodes x 256 realizations; wave w owns
-// nodes [32w, 32w + 32) x all 256 realizations as 8 blocks of 32 x 32.
-// Per chunk of 16 observations each lane evaluates 8 correlations.
-// Coordinates are pre-scaled so that rho_scaled_f32 applies directly.
-__global__ void __launch_bounds__(256)
+// Grid GEMM, mixed precision.  The product is formed transposed,
+// D[r][g] = sum_i B[r][i] K12[g][i], so that the accumulator's lane index
+// runs over grid nodes and every store writes runs of 32 consecutive nodes.
+// Workgroup: 4 waves, 128 grid nodes x 256 realizations; wave w owns nodes
+// [32w, 32w + 32) and all 8 blocks of 32 realizations.  Coefficient chunks of
+// 32 observations are double-buffered in LDS: the next chunk is fetched into
+// registers while the current one is multiplied.  Per chunk each lane
+// evaluates 16 correlations (its node, 2 x 8 observations) in FP32 and splits
+// them into bf16 hi/lo; 3 products hi.hi + lo.hi + hi.lo per block.
+// Layout of v_mfma_f32_32x32x16_bf16: lane l holds A[l % 32][8 (l/32) + j]
+// and B[8 (l/32) + j][l % 32]; accumulator e of lane l is
+// D[8 (e/4) + 4 (l/32) + e % 4][l % 32].
+__global__ void __launch_bounds__(256, 2)
 k_krige_bf16x3(float* __restrict__ fields, int m1, int M, int R, int Rp,
                const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int n,
                const float2* __restrict__ st, float ux, float uxy, float uyx, float uy, float dx,
                float dy, int nu_code) {
-  constexpr int TG = 128, TR = 256, TK = 16;
-  __shared__ __align__(16) __bf16 Sh[TR * TK];
-  __shared__ __align__(16) __bf16 Sl[TR * TK];
-  __shared__ float2 Ss[TK];
+  constexpr int TG = 128, TR = 256;
+  __shared__ __align__(16) __bf16 Sh[2][TR * kKC];
+  __shared__ __align__(16) __bf16 Sl[2][TR * kKC];
+  __shared__ float2 Ss[2][kKC];
   const int g0 = blockIdx.x * TG, r0 = blockIdx.y * TR;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = min(g0 + 32 * wave + (lane & 31), M - 1);
@@ -134,55 +162,77 @@ k_krige_bf16x3(float* __restrict__ fields, int m1, int M, int R, int Rp,
   for (int b = 0; b < 8; ++b)
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[b][e] = 0.0f;
-  const int nchunks = (n + TK - 1) / TK;
-  const int rvalid = min(TR, Rp - r0);
+  const int nchunks = (n + kKC - 1) / kKC;
+  // each thread moves 4 uint4 of hi and 4 of lo per chunk (256 r x 32 k bf16)
+  uint4 ph[4], pl[4];
+  float2 ps = {0.f, 0.f};
+  auto fetch = [&](int kc) {
+    const uint4* gh = reinterpret_cast<const uint4*>(Bh + ((size_t)kc * Rp + r0) * kKC);
+    const uint4* gl = reinterpret_cast<const uint4*>(Bl + ((size_t)kc * Rp + r0) * kKC);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ph[u] = gh[threadIdx.x + 256 * u];
+      pl[u] = gl[threadIdx.x + 256 * u];
+    }
+    if (threadIdx.x < kKC) ps = st[min(kc * kKC + (int)threadIdx.x, n - 1)];
+  };
+  // LDS rows of 4 x 16 B; the 16-byte column is XOR-swizzled by bits 2-3
+  // of the row so that 16 consecutive rows read at one column hit 16
+  // distinct bank groups.
+  auto stash = [&](int buf) {
+    uint4* sh = reinterpret_cast<uint4*>(Sh[buf]);
+    uint4* sl = reinterpret_cast<uint4*>(Sl[buf]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = threadIdx.x + 256 * u, row = q >> 2;
+      const int pq = (row << 2) | ((q & 3) ^ ((row >> 2) & 3));
+      sh[pq] = ph[u];
+      sl[pq] = pl[u];
+    }
+    if (threadIdx.x < kKC) Ss[buf][threadIdx.x] = ps;
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
   for (int kc = 0; kc < nchunks; ++kc) {
-    // stage B chunk: rows r0 .. r0+TR of 16 bf16 each (contiguous per chunk)
-    const uint4* gh = reinterpret_cast<const uint4*>(Bh + ((size_t)kc * Rp + r0) * TK);
-    const uint4* gl = reinterpret_cast<const uint4*>(Bl + ((size_t)kc * Rp + r0) * TK);
-    uint4* sh = reinterpret_cast<uint4*>(Sh);
-    uint4* sl = reinterpret_cast<uint4*>(Sl);
-    for (int e = threadIdx.x; e < TR * 2; e += 256) {
-      const bool ok = (e >> 1) < rvalid;
-      sh[e] = ok ? gh[e] : make_uint4(0, 0, 0, 0);
-      sl[e] = ok ? gl[e] : make_uint4(0, 0, 0, 0);
-    }
-    if (threadIdx.x < TK) {
-      const int gi = kc * TK + threadIdx.x;
-      Ss[threadIdx.x] = st[min(gi, n - 1)];
-    }
-    __syncthreads();
-    bf16x8 ah, al;
+    const int buf = kc & 1;
+    if (kc + 1 < nchunks) fetch(kc + 1);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float2 sv = Ss[kb + j];
-      const float hx = gxt - sv.x, hy = gyt - sv.y;
-      const float c = rho_scaled_f32(nu_code, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
-      const __bf16 h = (__bf16)c;
-      ah[j] = h;
-      al[j] = (__bf16)(c - (float)h);
-    }
+    for (int ks = 0; ks < kKC; ks += 16) {
+      bf16x8 ah, al;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int rr = 32 * b + (lane & 31);
-      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(Sh + rr * TK + kb);
-      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Sl + rr * TK + kb);
-      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[b], 0, 0, 0);
-      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[b], 0, 0, 0);
-      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[b], 0, 0, 0);
+      for (int j = 0; j < 8; ++j) {
+        const float2 sv = Ss[buf][ks + kb + j];
+        const float hx = gxt - sv.x, hy = gyt - sv.y;
+        const float c = rho_scaled_f32(nu_code, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+        const __bf16 h = (__bf16)c;
+        ah[j] = h;
+        al[j] = (__bf16)(c - (float)h);
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int rr = 32 * b + (lane & 31);
+        const int pc = ((ks + kb) >> 3) ^ ((rr >> 2) & 3);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Sh[buf][rr * kKC + 8 * pc]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Sl[buf][rr * kKC + 8 * pc]);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, ah, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, al, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl, ah, acc[b], 0, 0, 0);
+      }
     }
+    if (kc + 1 < nchunks) stash(buf ^ 1);
     __syncthreads();
   }
-  // accumulator layout of the 32x32 result: lane l, element e holds
-  // row 8 (e / 4) + 4 (l / 32) + (e % 4) and column l % 32.
+  const int gg = g0 + 32 * wave + (lane & 31);
+  if (gg < M) {
 #pragma unroll
-  for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < 8; ++b)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int gg = g0 + 32 * wave + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      const int r = r0 + 32 * b + (lane & 31);
-      if (gg < M && r < R) fields[(size_t)r * M + gg] += acc[b][e];
-    }
+      for (int e = 0; e < 16; ++e) {
+        const int r = r0 + 32 * b + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (r < R) fields[(size_t)r * M + gg] += acc[b][e];
+      }
+  }
 }
 
 // ------------------------------------------------------------------- host
@@ -220,7 +270,7 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   if (c->prec == CESIM_PREC_FP64) {
     double ux, uxy, uyx, uy;
     cov_map(c, 1.0, ux, uxy, uyx, uy);
-    dim3 grid((M + 127) / 128, (R + 63) / 64);
+    dim3 grid((M + 127) / 128, (R + 127) / 128);
     const int tr = c->timer.begin(ST_KRIGE_GEMM, s);
     k_krige_f64<<<grid, 256, 0, s>>>(static_cast<double*>(fields), m1, M, R, X, n,
                                      c->obs_t64.as<double2>(), ux, uxy, uyx, uy, dx, dy,
@@ -230,7 +280,7 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     return CESIM_OK;
   }
   const int Rp = (R + 255) / 256 * 256;
-  const int npad = (n + 15) / 16 * 16;
+  const int npad = (n + kKC - 1) / kKC * kKC;
   CESIM_TRY(c->coef_b16.reserve(sizeof(__bf16) * 2 * (size_t)npad * Rp));
   __bf16* Bh = c->coef_b16.as<__bf16>();
   __bf16* Bl = Bh + (size_t)npad * Rp;

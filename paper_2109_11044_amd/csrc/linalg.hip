@@ -27,53 +27,43 @@ __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, 
   A[(size_t)i * n + j] = v;
 }
 
-// Factor the nbk x nbk diagonal block at (k0, k0) in LDS; write L back and
-// the inverse of L to dinv (kNB x kNB, row-major, zero above the diagonal).
-__global__ void __launch_bounds__(256)
+// Factor the nbk x nbk diagonal block at (k0, k0) with one wave: left-looking
+// (column by column) in LDS, lane l owning row l; then the inverse of L,
+// lane c owning column c.  Writes L back and the inverse to dinv (kNB x kNB,
+// row-major, zero above the diagonal; padded with the identity past nbk).
+__global__ void __launch_bounds__(64)
 k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
              int* __restrict__ info) {
   __shared__ double L[kNB][kNB + 1];
   __shared__ double Li[kNB][kNB + 1];
-  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    L[r][c] = (r < nbk && c < nbk) ? A[(size_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
+  const int l = threadIdx.x;
+  for (int c = 0; c < kNB; ++c)
+    L[l][c] = (l < nbk && c < nbk) ? A[(size_t)(k0 + l) * n + k0 + c] : (l == c ? 1.0 : 0.0);
+  __syncthreads();
+  for (int j = 0; j < kNB; ++j) {
+    double sv = L[l][j];
+    for (int t = 0; t < j; ++t) sv -= L[l][t] * L[j][t];
+    const double d = __shfl(sv, j);
+    if (l == j && j < nbk && !(d > 0.0)) atomicOr(info, 2);
+    const double piv = sqrt(d);
+    if (l == j) L[j][j] = piv;
+    else if (l > j) L[l][j] = sv / piv;
+    __syncthreads();
+  }
+  const int c = l;
+  for (int r = 0; r < kNB; ++r) {
+    double t = 0.0;
+    if (r >= c) {
+      t = (r == c) ? 1.0 : 0.0;
+      for (int q = c; q < r; ++q) t -= L[r][q] * Li[q][c];
+      t /= L[r][r];
+    }
+    Li[r][c] = t;
   }
   __syncthreads();
-  for (int j = 0; j < nbk; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = L[j][j];
-      if (!(d > 0.0)) atomicOr(info, 2);
-      L[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < nbk; i += 256) L[i][j] /= L[j][j];
-    __syncthreads();
-    const int rem = nbk - j - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += 256) {
-      const int i = j + 1 + e / rem, l = j + 1 + e % rem;
-      if (l <= i) L[i][l] -= L[i][j] * L[l][j];
-    }
-    __syncthreads();
-  }
-  // inverse of L: column c solves L x = e_c (one thread per column)
-  if (threadIdx.x < kNB) {
-    const int c = threadIdx.x;
-    for (int r = 0; r < kNB; ++r) {
-      double t = (r == c) ? 1.0 : 0.0;
-      if (r >= c) {
-        for (int q = c; q < r; ++q) t -= L[r][q] * Li[q][c];
-        t /= L[r][r];
-      } else {
-        t = 0.0;
-      }
-      Li[r][c] = t;
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    dinv[e] = Li[r][c];
-    if (r < nbk && c <= r) A[(size_t)(k0 + r) * n + k0 + c] = L[r][c];
+  for (int r = 0; r < kNB; ++r) {
+    dinv[r * kNB + l] = Li[r][l];
+    if (r < nbk && l <= r) A[(size_t)(k0 + r) * n + k0 + l] = L[r][l];
   }
 }
 
@@ -109,36 +99,25 @@ k_trsm_panel(double* __restrict__ A, int n, int k0, int nbk, const double* __res
 // Diagonal-block solve of the batched right-hand sides X[r][i] (row-major by
 // realization): forward  X[r][k0+c] <- sum_t Linv[c][t] X[r][k0+t],
 //              backward X[r][k0+c] <- sum_t Linv[t][c] X[r][k0+t].
+// One thread per output (4 realizations x 64 rows per workgroup).
 template <bool BACK>
 __global__ void __launch_bounds__(256)
 k_trsm_diag(double* __restrict__ X, int n, int R, int k0, int nbk, const double* __restrict__ dinv) {
-  __shared__ double Xs[kNB][kNB + 1];     // [r][t]
   __shared__ double Li[kNB][kNB + 1];
-  const int r0 = blockIdx.x * kNB;
-  const int nr = min(kNB, R - r0);
-  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, t = e % kNB;
-    Xs[r][t] = (r < nr && t < nbk) ? X[(size_t)(r0 + r) * n + k0 + t] : 0.0;
-    Li[r][t] = dinv[e];
-  }
+  __shared__ double Xs[4][kNB];
+  const int r0 = blockIdx.x * 4;
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) Li[e / kNB][e % kNB] = dinv[e];
+  const int rl = threadIdx.x >> 6, c = threadIdx.x & 63;
+  const int r = r0 + rl;
+  Xs[rl][c] = (r < R && c < nbk) ? X[(size_t)r * n + k0 + c] : 0.0;
   __syncthreads();
-  double out[16];
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + 256 * u;
-    const int r = e / kNB, c = e % kNB;
-    double s = 0.0;
-    if (!BACK) {
-      for (int t = 0; t <= c; ++t) s += Li[c][t] * Xs[r][t];
-    } else {
-      for (int t = c; t < kNB; ++t) s += Li[t][c] * Xs[r][t];
-    }
-    out[u] = s;
+  double s = 0.0;
+  if (!BACK) {
+    for (int t = 0; t <= c; ++t) s += Li[c][t] * Xs[rl][t];
+  } else {
+    for (int t = c; t < kNB; ++t) s += Li[t][c] * Xs[rl][t];
   }
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + 256 * u;
-    const int r = e / kNB, c = e % kNB;
-    if (r < nr && c < nbk) X[(size_t)(r0 + r) * n + k0 + c] = out[u];
-  }
+  if (r < R && c < nbk) X[(size_t)r * n + k0 + c] = s;
 }
 
 // Generic FP64 GEMM on matrix cores: C = alpha A B + beta C with element
@@ -246,7 +225,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
   CESIM_HIP(hipGetLastError());
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
+    k_potrf_diag<<<1, 64, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
     CESIM_HIP(hipGetLastError());
     const int rest = n - k0 - nbk;
     if (rest <= 0) break;
@@ -274,7 +253,7 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
   const int nblk = (n + kNB - 1) / kNB;
   const double* L = c->amat.as<double>();
   const double* D = c->dinv.as<double>();
-  const dim3 gdiag((R + kNB - 1) / kNB);
+  const dim3 gdiag((R + 3) / 4);
   const int tr = c->timer.begin(ST_SOLVE, s);
   for (int kb = 0; kb < nblk; ++kb) {          // L Y = X
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
