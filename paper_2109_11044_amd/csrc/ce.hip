@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "fft_pow2.hpp"
 
 namespace cesim {
 
@@ -182,6 +183,129 @@ k_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, in
     const cpx<real> v = lds[row * t1 + x];
     f0[(size_t)row * m1 + x] = v.x;
     if (has1) f0[M + (size_t)row * m1 + x] = v.y;
+  }
+}
+
+// ------------------------------------------- power-of-two draw kernels
+// Same three passes as above with the transform length fixed at compile
+// time and the data held in registers (see fft_pow2.hpp).
+
+// Pass 1: noise of ROWS torus rows (natural order into LDS), forward row
+// FFT, result written from registers.
+template <typename real, int T>
+__global__ void __launch_bounds__(P2Rows<T>::NTHR)
+k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict__ tw, uint32_t k0,
+                uint32_t k1, int first_real, int nreal, int pair0) {
+  using C = cpx<real>;
+  using G = P2Rows<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int p = blockIdx.y;
+  const int j0 = blockIdx.x * G::ROWS;
+  const int pg = pair0 + p;
+  const int r0 = first_real + 2 * pg;
+  const bool has1 = 2 * pg + 1 < nreal;
+  // Philox blocks of 4 consecutive elements; T is a multiple of 4, so a
+  // block never straddles two rows.
+  constexpr int BPR = T / 4;
+  for (int blk = threadIdx.x; blk < G::ROWS * BPR; blk += G::NTHR) {
+    const int b = blk / BPR, i0 = (blk % BPR) * 4;
+    if (j0 + b >= t2) continue;
+    const uint32_t gb = (uint32_t)((((long)(j0 + b)) * T + i0) >> 2);
+    real za[4], zb[4] = {0, 0, 0, 0};
+    if constexpr (sizeof(real) == 8) {
+      normals4_f64(k0, k1, gb, (uint32_t)r0, 0u, 0u, za);
+      if (has1) normals4_f64(k0, k1, gb, (uint32_t)(r0 + 1), 0u, 0u, zb);
+    } else {
+      normals4_f32(k0, k1, gb, (uint32_t)r0, 0u, 0u, za);
+      if (has1) normals4_f32(k0, k1, gb, (uint32_t)(r0 + 1), 0u, 0u, zb);
+    }
+    const RowLds<C> rl{lds + b * G::LD};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) rl.store(i0 + w, C{za[w], zb[w]});
+  }
+  __syncthreads();
+  const int b = threadIdx.x / G::S, base = threadIdx.x % G::S;
+  const RowLds<C> rl{lds + b * G::LD};
+  C x[16];
+#pragma unroll
+  for (int h = 0; h < 16; ++h) x[h] = rl.load(base + G::S * h);
+  p2_fft<real, T, false>(x, base, tw, rl);
+  if (j0 + b < t2) {
+    C* out = buf + ((size_t)p * t2 + j0 + b) * T;
+#pragma unroll
+    for (int h = 0; h < 16; ++h) out[base + G::S * h] = x[h];
+  }
+}
+
+// Pass 2: CP columns per workgroup, loaded straight into registers; forward
+// FFT along y, sqrt(lambda)/N in registers, inverse FFT, rows < rows_out
+// stored.
+template <typename real, int T>
+__global__ void __launch_bounds__((P2Cols<real, T>::NTHR))
+k_p2_cols(cpx<real>* __restrict__ buf, int t1, int rows_out, const cpx<real>* __restrict__ tw,
+          const real* __restrict__ sl) {
+  using C = cpx<real>;
+  using G = P2Cols<real, T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int p = blockIdx.y;
+  const int c = threadIdx.x % G::CP, base = threadIdx.x / G::CP;
+  const int col = blockIdx.x * G::CP + c;
+  const bool ok = col < t1;
+  C* colp = buf + (size_t)p * T * t1 + col;
+  C x[16];
+#pragma unroll
+  for (int h = 0; h < 16; ++h) x[h] = ok ? colp[(size_t)(base + G::S * h) * t1] : C{0, 0};
+  const ColLds<C, G::CP> cl{lds, c};
+  p2_fft<real, T, false>(x, base, tw, cl);
+#pragma unroll
+  for (int h = 0; h < 16; ++h) {
+    const real m = ok ? sl[(size_t)(base + G::S * h) * t1 + col] : (real)0;
+    x[h] = {x[h].x * m, x[h].y * m};
+  }
+  p2_fft<real, T, true>(x, base, tw, cl);
+  if (ok) {
+#pragma unroll
+    for (int h = 0; h < 16; ++h) {
+      const int row = base + G::S * h;
+      if (row < rows_out) colp[(size_t)row * t1] = x[h];
+    }
+  }
+}
+
+// Pass 3: ROWS kept rows per workgroup: inverse row FFT and the crop into
+// fields 2p (real part) and 2p+1 (imaginary part).
+template <typename real, int T>
+__global__ void __launch_bounds__(P2Rows<T>::NTHR)
+k_p2_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, int t2, int m1,
+                   int m2, const cpx<real>* __restrict__ tw, int nreal, int pair0) {
+  using C = cpx<real>;
+  using G = P2Rows<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int p = blockIdx.y;
+  const int b = threadIdx.x / G::S, base = threadIdx.x % G::S;
+  const int j = blockIdx.x * G::ROWS + b;
+  const bool ok = j < m2;
+  const C* in = buf + ((size_t)p * t2 + (ok ? j : 0)) * T;
+  C x[16];
+#pragma unroll
+  for (int h = 0; h < 16; ++h) x[h] = ok ? in[base + G::S * h] : C{0, 0};
+  const RowLds<C> rl{lds + b * G::LD};
+  p2_fft<real, T, true>(x, base, tw, rl);
+  if (!ok) return;
+  const int pg = pair0 + p;
+  const size_t M = (size_t)m1 * m2;
+  real* f0 = fields + (size_t)(2 * pg) * M + (size_t)j * m1;
+  const bool has1 = 2 * pg + 1 < nreal;
+#pragma unroll
+  for (int h = 0; h < 16; ++h) {
+    const int xcol = base + G::S * h;
+    if (xcol < m1) {
+      f0[xcol] = x[h].x;
+      if (has1) f0[M + xcol] = x[h].y;
+    }
   }
 }
 
@@ -434,6 +558,63 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
 
 namespace {
 
+template <typename real, int T1, int T2>
+cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np, const cpx<real>* tw1,
+                           const cpx<real>* tw2, const real* sl, uint32_t k0, uint32_t k1,
+                           int first_real, int nreal, int pair0, StageTimer& tm, hipStream_t s) {
+  using GR = P2Rows<T1>;
+  using GC = P2Cols<real, T2>;
+  const size_t lr = sizeof(cpx<real>) * GR::ROWS * GR::LD;
+  const size_t lc = sizeof(cpx<real>) * GC::CP * GC::LD;
+  int tr = tm.begin(ST_DRAW_PASS1, s);
+  {
+    auto k = k_p2_rows_noise<real, T1>;
+    allow_lds(k, lr);
+    k<<<dim3((T2 + GR::ROWS - 1) / GR::ROWS, np), GR::NTHR, lr, s>>>(buf, T2, tw1, k0, k1,
+                                                                    first_real, nreal, pair0);
+    CESIM_HIP(hipGetLastError());
+  }
+  tm.end(tr, s);
+  tr = tm.begin(ST_DRAW_PASS2, s);
+  {
+    auto k = k_p2_cols<real, T2>;
+    allow_lds(k, lc);
+    k<<<dim3((T1 + GC::CP - 1) / GC::CP, np), GC::NTHR, lc, s>>>(buf, T1, m2, tw2, sl);
+    CESIM_HIP(hipGetLastError());
+  }
+  tm.end(tr, s);
+  tr = tm.begin(ST_DRAW_PASS3, s);
+  {
+    auto k = k_p2_rows_inv_crop<real, T1>;
+    allow_lds(k, lr);
+    k<<<dim3((m2 + GR::ROWS - 1) / GR::ROWS, np), GR::NTHR, lr, s>>>(buf, fields, T2, m1, m2, tw1,
+                                                                    nreal, pair0);
+    CESIM_HIP(hipGetLastError());
+  }
+  tm.end(tr, s);
+  return CESIM_OK;
+}
+
+// Square power-of-two tori from 128 to 8192 take the register path.
+template <typename real>
+bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m2, int np,
+                     const cpx<real>* tw1, const cpx<real>* tw2, const real* sl, uint32_t k0,
+                     uint32_t k1, int first_real, int nreal, int pair0, StageTimer& tm,
+                     hipStream_t s, cesim_status& st) {
+  if (t1 != t2) return false;
+  switch (t1) {
+#define CESIM_P2(TT)                                                                        \
+  case TT:                                                                                  \
+    st = draw_chunk_p2<real, TT, TT>(buf, fields, m1, m2, np, tw1, tw2, sl, k0, k1, first_real, \
+                                     nreal, pair0, tm, s);                                  \
+    return true;
+    CESIM_P2(128) CESIM_P2(256) CESIM_P2(512) CESIM_P2(1024) CESIM_P2(2048) CESIM_P2(4096)
+    CESIM_P2(8192)
+#undef CESIM_P2
+    default: return false;
+  }
+}
+
 template <typename real>
 cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, real* fields,
                         const cpx<real>* tw1, const cpx<real>* tw2, const real* sl) {
@@ -448,6 +629,12 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   for (int pair0 = 0; pair0 < npairs; pair0 += chunk) {
     const int np = std::min(chunk, npairs - pair0);
+    cesim_status st = CESIM_OK;
+    if (draw_chunk_pow2<real>(t1, t2, buf, fields, m1, m2, np, tw1, tw2, sl, k0, k1, first_real,
+                              nreal, pair0, c->timer, s, st)) {
+      CESIM_TRY(st);
+      continue;
+    }
     int tr = c->timer.begin(ST_DRAW_PASS1, s);
     CESIM_TRY((launch_rows_fwd<real, true>(buf, t1, t2, np, c->tt.p1, tw1, k0, k1, first_real,
                                            nreal, pair0, s)));

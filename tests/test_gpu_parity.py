@@ -54,7 +54,11 @@ def test_ladder_moves_past_negative_torus():
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
-@pytest.mark.parametrize("m,torus,nreal,first", [(64, 128, 5, 0), (24, 0, 3, 7), (30, 75, 4, 1)])
+@pytest.mark.parametrize("m,torus,nreal,first", [
+    (64, 128, 5, 0), (24, 0, 3, 7), (30, 75, 4, 1),          # small, radix 3 and 5
+    (128, 256, 3, 0), (512, 1024, 2, 5),                     # power-of-two register path
+    (1024, 2048, 3, 997),                                    # full-size torus of the benchmark
+])
 def test_unconditional_draw_matches_oracle(prec, tol, m, torus, nreal, first):
     cov = (0.5, 1.0, 0.1)
     with ctx_for(*cov, m, prec, torus) as ctx:
@@ -65,6 +69,19 @@ def test_unconditional_draw_matches_oracle(prec, tol, m, torus, nreal, first):
     ref = oce.ce_draw(sref, eps, m, m)
     err = rel_rms(f, ref)
     assert np.all(err < tol), err
+
+
+def test_rectangular_grid_draw():
+    """m1 != m2 (different torus sizes per axis) through the general path."""
+    cov = OCov(1.5, 1.0, 0.12, 2.0, 0.3)
+    g = cesim.Grid(40, 24, 0.0, 0.0, 0.02, 0.03, 0, 0)
+    with cesim.Context(cesim.make_cov(1.5, 1.0, 0.12, 2.0, 0.3), g, "fp64") as ctx:
+        f = ctx.simulate(3, seed=4).cpu().numpy()
+        t1, t2 = ctx.info()["t1"], ctx.info()["t2"]
+    og = OGrid(40, 24, 0.0, 0.0, 0.02, 0.03)
+    _, _, sref, _ = setup(cov, og, t1, t2)
+    ref = oce.ce_draw(sref, philox.torus_noise(4, t1, t2, range(3)), 40, 24)
+    assert np.all(rel_rms(f, ref) < FP64_TOL)
 
 
 def test_draw_independent_of_batching():
