@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--nreal", type=int, default=1000)
     ap.add_argument("--batch", type=int, default=0, help="realizations per call (0: all)")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--gemm-nf", type=int, default=0, help="node fragments per wave (0: library default)")
+    ap.add_argument("--chunk-pairs", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default="")
     return ap.parse_args()
@@ -81,6 +83,10 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
 
     def step():
         ctx = cesim.Context(cov, grid, prec)
+        if args.gemm_nf:
+            ctx.set_param(cesim.PARAM_GEMM_NODE_FRAGMENTS, args.gemm_nf)
+        if args.chunk_pairs:
+            ctx.set_param(cesim.PARAM_DRAW_CHUNK_PAIRS, args.chunk_pairs)
         ctx.offgrid(xy, wl.k)
         for b0 in range(0, R, batch):
             nb = min(batch, R - b0)

@@ -219,6 +219,15 @@ const char* cesim_status_string(cesim_status s);
  * cross-covariance GEMM onto the grid. */
 #define CESIM_NUM_STAGES 12
 
+/* Launch-shape parameters (performance only; results do not change):
+ *   CESIM_PARAM_GEMM_NODE_FRAGMENTS: 32-node fragments per wave in the mixed
+ *     cross-covariance GEMM, 1 (default) or 2.
+ *   CESIM_PARAM_DRAW_CHUNK_PAIRS: realization pairs per launch of the draw
+ *     passes (bounds the pair buffer); 0 (default) chooses up to 2 GiB. */
+#define CESIM_PARAM_GEMM_NODE_FRAGMENTS 1
+#define CESIM_PARAM_DRAW_CHUNK_PAIRS 2
+cesim_status ce_set_param(cesim_ctx ctx, int param, int value);
+
 /* Default timing state of contexts created afterwards (process-wide). */
 void cesim_set_default_timing(int enable);
 

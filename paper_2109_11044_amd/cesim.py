@@ -25,7 +25,9 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "condition_copy_coefficients", "cesim_covariance_host",
            "cesim_philox_host", "cesim_status_string", "ce_destroy",
            "cesim_set_default_timing", "ce_set_timing", "ce_get_stage_times",
-           "cesim_stage_name", "cesim_release_cached_memory"]
+           "cesim_stage_name", "cesim_release_cached_memory", "ce_set_param"]
+PARAM_GEMM_NODE_FRAGMENTS = 1
+PARAM_DRAW_CHUNK_PAIRS = 2
 NUM_STAGES = 12
 VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",
                 "cesim_stage_name", "cesim_release_cached_memory")
@@ -95,6 +97,7 @@ def lib():
     L.cesim_set_default_timing.argtypes = [i]
     L.cesim_set_default_timing.restype = None
     L.ce_set_timing.argtypes = [vp, i]
+    L.ce_set_param.argtypes = [vp, i, i]
     L.ce_get_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), i, i]
     L.cesim_stage_name.argtypes = [i]
     L.cesim_stage_name.restype = ctypes.c_char_p
@@ -241,6 +244,9 @@ class Context:
         inf = Info()
         _check(lib().ce_get_info(self._h, ctypes.byref(inf)), "ce_get_info")
         return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def set_param(self, param, value):
+        _check(lib().ce_set_param(self._h, int(param), int(value)), "ce_set_param")
 
     def set_timing(self, enable):
         _check(lib().ce_set_timing(self._h, 1 if enable else 0), "ce_set_timing")

@@ -251,6 +251,22 @@ void cesim_release_cached_memory(void) { cache_trim(); }
 
 void cesim_set_default_timing(int enable) { g_default_timing = enable != 0; }
 
+cesim_status ce_set_param(cesim_ctx c, int param, int value) {
+  if (!c) return CESIM_ERR_INVALID_ARG;
+  switch (param) {
+    case CESIM_PARAM_GEMM_NODE_FRAGMENTS:
+      if (value != 1 && value != 2) return CESIM_ERR_INVALID_ARG;
+      c->gemm_nf = value;
+      return CESIM_OK;
+    case CESIM_PARAM_DRAW_CHUNK_PAIRS:
+      if (value < 0) return CESIM_ERR_INVALID_ARG;
+      c->draw_chunk_pairs = value;
+      return CESIM_OK;
+    default:
+      return CESIM_ERR_INVALID_ARG;
+  }
+}
+
 cesim_status ce_set_timing(cesim_ctx c, int enable) {
   if (!c) return CESIM_ERR_INVALID_ARG;
   c->timer.enabled = enable != 0;

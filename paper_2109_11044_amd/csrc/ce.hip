@@ -623,7 +623,8 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
   const size_t pair_bytes = sizeof(cpx<real>) * (size_t)t1 * t2;
   const int npairs = (nreal + 1) / 2;
   const size_t budget = (size_t)2 << 30;
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(npairs, budget / pair_bytes));
+  int chunk = (int)std::max<size_t>(1, std::min<size_t>(npairs, budget / pair_bytes));
+  if (c->draw_chunk_pairs > 0) chunk = std::min(npairs, c->draw_chunk_pairs);
   CESIM_TRY(c->work.reserve(pair_bytes * chunk));
   cpx<real>* buf = c->work.as<cpx<real>>();
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);

@@ -114,6 +114,9 @@ struct cesim_ctx_s {
   cesim::DevBuf info_dev;           // int flags
   std::vector<double> z_host_cached;
 
+  int gemm_nf = 1;                  // node fragments per wave in the mixed grid GEMM
+  int draw_chunk_pairs = 0;         // pairs per draw launch (0: by a 2 GiB budget)
+
   // last simulate
   bool have_fields = false;
   uint64_t seed = 0;

@@ -19,6 +19,7 @@ namespace cesim {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));   // 16 bytes, register-promotable
 
 // ------------------------------------------------------------ FP64 kernel
 // D[r][g] = sum_i X[r][i] K12[g][i] on v_mfma_f64_16x16x4f64 (lane l holds
@@ -54,27 +55,27 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
   const int frow = threadIdx.x >> 1, fhalf = (threadIdx.x & 1) * 8;
   double pv[8];
   double2 ps = {0.0, 0.0};
-  auto fetch = [&](int i0) {
-    const int gr = r0 + frow;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int gi = i0 + fhalf + u;
-      pv[u] = (gr < R && gi < n) ? X[(size_t)gr * n + gi] : 0.0;
-    }
-    if (threadIdx.x < TK) ps = st[min(i0 + (int)threadIdx.x, n - 1)];
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) Xs[buf][fhalf + u][frow] = pv[u];
-    if (threadIdx.x < TK) Ss[buf][threadIdx.x] = ps;
-  };
-  fetch(0);
-  stash(0);
+#define CESIM_FETCH64(I0)                                                    \
+  {                                                                          \
+    const int gr_ = r0 + frow;                                               \
+    _Pragma("unroll") for (int u = 0; u < 8; ++u) {                          \
+      const int gi_ = (I0) + fhalf + u;                                      \
+      pv[u] = (gr_ < R && gi_ < n) ? X[(size_t)gr_ * n + gi_] : 0.0;         \
+    }                                                                        \
+    if (threadIdx.x < TK) ps = st[min((I0) + (int)threadIdx.x, n - 1)];      \
+  }
+#define CESIM_STASH64(BUF)                                                   \
+  {                                                                          \
+    _Pragma("unroll") for (int u = 0; u < 8; ++u) Xs[BUF][fhalf + u][frow] = pv[u]; \
+    if (threadIdx.x < TK) Ss[BUF][threadIdx.x] = ps;                         \
+  }
+  CESIM_FETCH64(0)
+  CESIM_STASH64(0)
   __syncthreads();
   const int nchunks = (n + TK - 1) / TK;
   for (int kc = 0; kc < nchunks; ++kc) {
     const int buf = kc & 1;
-    if (kc + 1 < nchunks) fetch((kc + 1) * TK);
+    if (kc + 1 < nchunks) CESIM_FETCH64((kc + 1) * TK)
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
@@ -93,9 +94,11 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
           acc[t][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, kg[t], acc[t][b], 0, 0, 0);
       }
     }
-    if (kc + 1 < nchunks) stash(buf ^ 1);
+    if (kc + 1 < nchunks) CESIM_STASH64(buf ^ 1)
     __syncthreads();
   }
+#undef CESIM_FETCH64
+#undef CESIM_STASH64
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int g = g0 + 32 * wave + 16 * t + (lane & 15);
@@ -133,104 +136,136 @@ __global__ void k_split_coef(const double* __restrict__ X, int n, int R, int Rp,
 // Grid GEMM, mixed precision.  The product is formed transposed,
 // D[r][g] = sum_i B[r][i] K12[g][i], so that the accumulator's lane index
 // runs over grid nodes and every store writes runs of 32 consecutive nodes.
-// Workgroup: 4 waves, 128 grid nodes x 256 realizations; wave w owns nodes
-// [32w, 32w + 32) and all 8 blocks of 32 realizations.  Coefficient chunks of
-// 32 observations are double-buffered in LDS: the next chunk is fetched into
-// registers while the current one is multiplied.  Per chunk each lane
-// evaluates 16 correlations (its node, 2 x 8 observations) in FP32 and splits
+// Workgroup: 4 waves, 128 NF grid nodes x 256 realizations; wave w owns
+// nodes [32 NF w, 32 NF (w + 1)) as NF 32-node fragments and all 8 blocks of
+// 32 realizations (8 NF accumulators).  Coefficient chunks of 32
+// observations are double-buffered in LDS: the next chunk is fetched into
+// registers while the current one is multiplied, and each coefficient
+// fragment read from LDS feeds all NF node fragments.  Per chunk each lane
+// evaluates 16 NF correlations (NF nodes x 16 observations) in FP32 and splits
 // them into bf16 hi/lo; 3 products hi.hi + lo.hi + hi.lo per block.
 // Layout of v_mfma_f32_32x32x16_bf16: lane l holds A[l % 32][8 (l/32) + j]
 // and B[8 (l/32) + j][l % 32]; accumulator e of lane l is
 // D[8 (e/4) + 4 (l/32) + e % 4][l % 32].
-__global__ void __launch_bounds__(256, 2)
+template <int NU>
+__device__ __forceinline__ void k12_frag(float gxt, float gyt, const float2* __restrict__ sv,
+                                         bf16x8& ah, bf16x8& al) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float hx = gxt - sv[j].x, hy = gyt - sv[j].y;
+    const float c = rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+    const __bf16 h = (__bf16)c;
+    ah[j] = h;
+    al[j] = (__bf16)(c - (float)h);
+  }
+}
+
+template <int NU, int NF>
+__global__ void __launch_bounds__(256, 3 - NF)
 k_krige_bf16x3(float* __restrict__ fields, int m1, int M, int R, int Rp,
                const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int n,
                const float2* __restrict__ st, float ux, float uxy, float uyx, float uy, float dx,
-               float dy, int nu_code) {
-  constexpr int TG = 128, TR = 256;
+               float dy) {
+  constexpr int TG = 128 * NF, TR = 256;
   __shared__ __align__(16) __bf16 Sh[2][TR * kKC];
   __shared__ __align__(16) __bf16 Sl[2][TR * kKC];
   __shared__ float2 Ss[2][kKC];
   const int g0 = blockIdx.x * TG, r0 = blockIdx.y * TR;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = min(g0 + 32 * wave + (lane & 31), M - 1);
-  const float gx = (float)(g % m1) * dx, gy = (float)(g / m1) * dy;
-  const float gxt = ux * gx + uxy * gy, gyt = uyx * gx + uy * gy;
+  float gxt[NF], gyt[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int g = min(g0 + 32 * NF * wave + 32 * f + (lane & 31), M - 1);
+    const float gx = (float)(g % m1) * dx, gy = (float)(g / m1) * dy;
+    gxt[f] = ux * gx + uxy * gy;
+    gyt[f] = uyx * gx + uy * gy;
+  }
   const int kb = (lane >> 5) * 8;
-  floatx16 acc[8];
+  floatx16 acc[NF][8];
 #pragma unroll
-  for (int b = 0; b < 8; ++b)
+  for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[b][e] = 0.0f;
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[f][b][e] = 0.0f;
   const int nchunks = (n + kKC - 1) / kKC;
-  // each thread moves 4 uint4 of hi and 4 of lo per chunk (256 r x 32 k bf16)
-  uint4 ph[4], pl[4];
+  u32x4v ph[4], pl[4];
   float2 ps = {0.f, 0.f};
-  auto fetch = [&](int kc) {
-    const uint4* gh = reinterpret_cast<const uint4*>(Bh + ((size_t)kc * Rp + r0) * kKC);
-    const uint4* gl = reinterpret_cast<const uint4*>(Bl + ((size_t)kc * Rp + r0) * kKC);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ph[u] = gh[threadIdx.x + 256 * u];
-      pl[u] = gl[threadIdx.x + 256 * u];
-    }
-    if (threadIdx.x < kKC) ps = st[min(kc * kKC + (int)threadIdx.x, n - 1)];
-  };
+#define CESIM_FETCH(KC)                                                                     \
+  {                                                                                         \
+    const u32x4v* gh_ = reinterpret_cast<const u32x4v*>(Bh + ((size_t)(KC) * Rp + r0) * kKC); \
+    const u32x4v* gl_ = reinterpret_cast<const u32x4v*>(Bl + ((size_t)(KC) * Rp + r0) * kKC); \
+    ph[0] = gh_[threadIdx.x];                                                               \
+    ph[1] = gh_[threadIdx.x + 256];                                                         \
+    ph[2] = gh_[threadIdx.x + 512];                                                         \
+    ph[3] = gh_[threadIdx.x + 768];                                                         \
+    pl[0] = gl_[threadIdx.x];                                                               \
+    pl[1] = gl_[threadIdx.x + 256];                                                         \
+    pl[2] = gl_[threadIdx.x + 512];                                                         \
+    pl[3] = gl_[threadIdx.x + 768];                                                         \
+    if (threadIdx.x < kKC) ps = st[min((KC) * kKC + (int)threadIdx.x, n - 1)];              \
+  }
   // LDS rows of 4 x 16 B; the 16-byte column is XOR-swizzled by bits 2-3
   // of the row so that 16 consecutive rows read at one column hit 16
   // distinct bank groups.
-  auto stash = [&](int buf) {
-    uint4* sh = reinterpret_cast<uint4*>(Sh[buf]);
-    uint4* sl = reinterpret_cast<uint4*>(Sl[buf]);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = threadIdx.x + 256 * u, row = q >> 2;
-      const int pq = (row << 2) | ((q & 3) ^ ((row >> 2) & 3));
-      sh[pq] = ph[u];
-      sl[pq] = pl[u];
-    }
-    if (threadIdx.x < kKC) Ss[buf][threadIdx.x] = ps;
-  };
-  fetch(0);
-  stash(0);
+#define CESIM_ST1(U)                                                      \
+  {                                                                       \
+    const int q = threadIdx.x + 256 * (U), row = q >> 2;                  \
+    const int pq = (row << 2) | ((q & 3) ^ ((row >> 2) & 3));             \
+    sh_[pq] = ph[U];                                                      \
+    sl_[pq] = pl[U];                                                      \
+  }
+#define CESIM_STASH(BUF)                                                  \
+  {                                                                       \
+    u32x4v* sh_ = reinterpret_cast<u32x4v*>(Sh[BUF]);                     \
+    u32x4v* sl_ = reinterpret_cast<u32x4v*>(Sl[BUF]);                     \
+    CESIM_ST1(0) CESIM_ST1(1) CESIM_ST1(2) CESIM_ST1(3)                    \
+    if (threadIdx.x < kKC) Ss[BUF][threadIdx.x] = ps;                     \
+  }
+  CESIM_FETCH(0)
+  CESIM_STASH(0)
   __syncthreads();
   for (int kc = 0; kc < nchunks; ++kc) {
     const int buf = kc & 1;
-    if (kc + 1 < nchunks) fetch(kc + 1);
+    if (kc + 1 < nchunks) CESIM_FETCH(kc + 1)
 #pragma unroll
     for (int ks = 0; ks < kKC; ks += 16) {
-      bf16x8 ah, al;
+      float2 sv[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float2 sv = Ss[buf][ks + kb + j];
-        const float hx = gxt - sv.x, hy = gyt - sv.y;
-        const float c = rho_scaled_f32(nu_code, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
-        const __bf16 h = (__bf16)c;
-        ah[j] = h;
-        al[j] = (__bf16)(c - (float)h);
-      }
+      for (int j = 0; j < 8; ++j) sv[j] = Ss[buf][ks + kb + j];
+      bf16x8 ah[NF], al[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) k12_frag<NU>(gxt[f], gyt[f], sv, ah[f], al[f]);
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         const int rr = 32 * b + (lane & 31);
         const int pc = ((ks + kb) >> 3) ^ ((rr >> 2) & 3);
         const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Sh[buf][rr * kKC + 8 * pc]);
         const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Sl[buf][rr * kKC + 8 * pc]);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, ah, acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, al, acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl, ah, acc[b], 0, 0, 0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          acc[f][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, ah[f], acc[f][b], 0, 0, 0);
+          acc[f][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, al[f], acc[f][b], 0, 0, 0);
+          acc[f][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl, ah[f], acc[f][b], 0, 0, 0);
+        }
       }
     }
-    if (kc + 1 < nchunks) stash(buf ^ 1);
+    if (kc + 1 < nchunks) CESIM_STASH(buf ^ 1)
     __syncthreads();
   }
-  const int gg = g0 + 32 * wave + (lane & 31);
-  if (gg < M) {
+#undef CESIM_FETCH
+#undef CESIM_STASH
+#undef CESIM_ST1
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int gg = g0 + 32 * NF * wave + 32 * f + (lane & 31);
+    if (gg >= M) continue;
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int r = r0 + 32 * b + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (r < R) fields[(size_t)r * M + gg] += acc[b][e];
+        if (r < R) fields[(size_t)r * M + gg] += acc[f][b][e];
       }
   }
 }
@@ -291,11 +326,29 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   const double kappa = c->covd.nu_code == 0 ? kLog2e : (c->covd.nu_code == 2 ? kSqrt3 : kSqrt2);
   double ux, uxy, uyx, uy;
   cov_map(c, kappa, ux, uxy, uyx, uy);
-  dim3 grid((M + 127) / 128, Rp / 256);
   tr = c->timer.begin(ST_KRIGE_GEMM, s);
-  k_krige_bf16x3<<<grid, 256, 0, s>>>(static_cast<float*>(fields), m1, M, R, Rp, Bh, Bl, n,
-                                      c->obs_t32.as<float2>(), (float)ux, (float)uxy, (float)uyx,
-                                      (float)uy, (float)dx, (float)dy, c->covd.nu_code);
+  float* F = static_cast<float*>(fields);
+  const float2* S2 = c->obs_t32.as<float2>();
+  const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
+  const float fdx = (float)dx, fdy = (float)dy;
+  const int nf = c->gemm_nf == 2 ? 2 : 1;
+  dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
+#define CESIM_KB(NU, NF) \
+  k_krige_bf16x3<NU, NF><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, Bh, Bl, n, S2, a, b, cc, d, fdx, fdy)
+  if (nf == 1) {
+    switch (c->covd.nu_code) {
+      case 0: CESIM_KB(0, 1); break;
+      case 1: CESIM_KB(1, 1); break;
+      default: CESIM_KB(2, 1); break;
+    }
+  } else {
+    switch (c->covd.nu_code) {
+      case 0: CESIM_KB(0, 2); break;
+      case 1: CESIM_KB(1, 2); break;
+      default: CESIM_KB(2, 2); break;
+    }
+  }
+#undef CESIM_KB
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   return CESIM_OK;
