@@ -251,7 +251,12 @@ k_p2_cols(cpx<real>* __restrict__ buf, int t1, int rows_out, const cpx<real>* __
   C* lds = reinterpret_cast<C*>(smem);
   const int p = blockIdx.y;
   const int c = threadIdx.x % G::CP, base = threadIdx.x / G::CP;
-  const int col = blockIdx.x * G::CP + c;
+  // Workgroups are dealt to the 8 XCDs round-robin; when the panel count is
+  // a multiple of 8, panels are renumbered so that one XCD takes adjacent
+  // panels in turn and the halves of each cache line meet in its L2.
+  int panel = blockIdx.x;
+  if ((gridDim.x & 7) == 0) panel = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int col = panel * G::CP + c;
   const bool ok = col < t1;
   C* colp = buf + (size_t)p * T * t1 + col;
   C x[16];

@@ -28,9 +28,11 @@ __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, 
 }
 
 // Factor the nbk x nbk diagonal block at (k0, k0) with one wave: left-looking
-// (column by column) in LDS, lane l owning row l; then the inverse of L,
-// lane c owning column c.  Writes L back and the inverse to dinv (kNB x kNB,
-// row-major, zero above the diagonal; padded with the identity past nbk).
+// (column by column) in LDS, lane l owning row l; then the inverse of L, lane
+// c owning column c.  The dot products are unrolled by 8 into four partial
+// sums so that the LDS reads of a group are in flight together.  Writes L
+// back and the inverse to dinv (kNB x kNB, row-major, zero above the
+// diagonal; padded with the identity past nbk).
 __global__ void __launch_bounds__(64)
 k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
              int* __restrict__ info) {
@@ -41,8 +43,16 @@ k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict_
     L[l][c] = (l < nbk && c < nbk) ? A[(size_t)(k0 + l) * n + k0 + c] : (l == c ? 1.0 : 0.0);
   __syncthreads();
   for (int j = 0; j < kNB; ++j) {
-    double sv = L[l][j];
-    for (int t = 0; t < j; ++t) sv -= L[l][t] * L[j][t];
+    double p0 = L[l][j], p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    int t = 0;
+    for (; t + 4 <= j; t += 4) {
+      p0 -= L[l][t] * L[j][t];
+      p1 -= L[l][t + 1] * L[j][t + 1];
+      p2 -= L[l][t + 2] * L[j][t + 2];
+      p3 -= L[l][t + 3] * L[j][t + 3];
+    }
+    for (; t < j; ++t) p0 -= L[l][t] * L[j][t];
+    const double sv = (p0 + p1) + (p2 + p3);
     const double d = __shfl(sv, j);
     if (l == j && j < nbk && !(d > 0.0)) atomicOr(info, 2);
     const double piv = sqrt(d);
@@ -52,13 +62,20 @@ k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict_
   }
   const int c = l;
   for (int r = 0; r < kNB; ++r) {
-    double t = 0.0;
+    double t0 = 0.0;
     if (r >= c) {
-      t = (r == c) ? 1.0 : 0.0;
-      for (int q = c; q < r; ++q) t -= L[r][q] * Li[q][c];
-      t /= L[r][r];
+      double p0 = (r == c) ? 1.0 : 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      int q = c;
+      for (; q + 4 <= r; q += 4) {
+        p0 -= L[r][q] * Li[q][c];
+        p1 -= L[r][q + 1] * Li[q + 1][c];
+        p2 -= L[r][q + 2] * Li[q + 2][c];
+        p3 -= L[r][q + 3] * Li[q + 3][c];
+      }
+      for (; q < r; ++q) p0 -= L[r][q] * Li[q][c];
+      t0 = ((p0 + p1) + (p2 + p3)) / L[r][r];
     }
-    Li[r][c] = t;
+    Li[r][c] = t0;
   }
   __syncthreads();
   for (int r = 0; r < kNB; ++r) {
