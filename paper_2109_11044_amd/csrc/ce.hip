@@ -344,16 +344,27 @@ __global__ void k_eig_partial(const double2* lam, size_t N, double* part) {
   }
 }
 
-__global__ void k_eig_final(const double* part, int nparts, double* out) {
-  if (threadIdx.x != 0) return;
-  double mn = INFINITY, mx = -INFINITY, sm = 0.0, im = 0.0;
-  for (int i = 0; i < nparts; ++i) {
-    mn = fmin(mn, part[4 * i]);
-    mx = fmax(mx, part[4 * i + 1]);
-    sm += part[4 * i + 2];
-    im = fmax(im, part[4 * i + 3]);
+__global__ void __launch_bounds__(512) k_eig_final(const double* part, int nparts, double* out) {
+  __shared__ double smin[512], smax[512], ssum[512], sim[512];
+  const int t = threadIdx.x;
+  const bool ok = t < nparts;
+  smin[t] = ok ? part[4 * t] : INFINITY;
+  smax[t] = ok ? part[4 * t + 1] : -INFINITY;
+  ssum[t] = ok ? part[4 * t + 2] : 0.0;
+  sim[t] = ok ? part[4 * t + 3] : 0.0;
+  __syncthreads();
+  for (int h = 256; h > 0; h >>= 1) {
+    if (t < h) {
+      smin[t] = fmin(smin[t], smin[t + h]);
+      smax[t] = fmax(smax[t], smax[t + h]);
+      ssum[t] += ssum[t + h];
+      sim[t] = fmax(sim[t], sim[t + h]);
+    }
+    __syncthreads();
   }
-  out[0] = mn; out[1] = mx; out[2] = sm; out[3] = im;
+  if (t == 0) {
+    out[0] = smin[0]; out[1] = smax[0]; out[2] = ssum[0]; out[3] = sim[0];
+  }
 }
 
 __global__ void k_sqrt_lambda(const double2* lam, size_t N, double inv_n, double* s64, float* s32) {
@@ -535,7 +546,7 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
   double* part = c->scratch.as<double>();
   tr = c->timer.begin(ST_SETUP_EIG, s);
   k_eig_partial<<<nparts, 256, 0, s>>>(buf, N, part);
-  k_eig_final<<<1, 64, 0, s>>>(part, nparts, part + 4 * nparts);
+  k_eig_final<<<1, 512, 0, s>>>(part, nparts, part + 4 * nparts);
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   double st[4];

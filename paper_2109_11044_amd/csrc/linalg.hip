@@ -3,6 +3,9 @@
 //   A = K22 + tau^2 I,  A = L L^T (blocked right-looking Cholesky),
 //   X = A^{-1} RHS for all realizations (blocked forward and backward
 //   substitution with the inverses of the diagonal blocks).
+// Besides the single-wave diagonal factorisation, every step (panel solves,
+// trailing updates, diagonal-block applications, solve updates) is one call
+// of the FP64 matrix-core GEMM below.
 // The O(n^3) trailing updates and O(n^2 R) solve updates run in one generic
 // FP64 matrix-core GEMM (v_mfma_f64_16x16x4f64, 64 x 64 tiles).
 #include <hip/hip_runtime.h>
@@ -27,114 +30,123 @@ __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, 
   A[(size_t)i * n + j] = v;
 }
 
-// Factor the nbk x nbk diagonal block at (k0, k0) with one wave: left-looking
-// (column by column) in LDS, lane l owning row l; then the inverse of L, lane
-// c owning column c.  The dot products are unrolled by 8 into four partial
-// sums so that the LDS reads of a group are in flight together.  Writes L
-// back and the inverse to dinv (kNB x kNB, row-major, zero above the
-// diagonal; padded with the identity past nbk).
-__global__ void __launch_bounds__(64)
+// Factor the nbk x nbk diagonal block at (k0, k0): 256 threads, thread t
+// holding the 4 x 4 register tile (rows 4 (t / 16) + i, columns
+// 4 (t % 16) + k).  Right-looking: at step j the pivot's owner forms
+// sqrt(d), the owners of column j scale it and publish it to LDS, and every
+// thread applies the rank-one update to its tile (two barriers per step, no
+// LDS read-modify-write).  The inverse of L is formed the same way on an
+// identity tile set.  Writes L back and the inverse to dinv (kNB x kNB,
+// row-major, zero above the diagonal; padded with the identity past nbk).
+__device__ __forceinline__ double tile_get(const double (&a)[4][4], int i, int k) {
+  double v = 0.0;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) v = (ii == i && kk == k) ? a[ii][kk] : v;
+  return v;
+}
+
+__global__ void __launch_bounds__(256)
 k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
              int* __restrict__ info) {
-  __shared__ double L[kNB][kNB + 1];
-  __shared__ double Li[kNB][kNB + 1];
-  const int l = threadIdx.x;
-  for (int c = 0; c < kNB; ++c)
-    L[l][c] = (l < nbk && c < nbk) ? A[(size_t)(k0 + l) * n + k0 + c] : (l == c ? 1.0 : 0.0);
-  __syncthreads();
-  for (int j = 0; j < kNB; ++j) {
-    double p0 = L[l][j], p1 = 0.0, p2 = 0.0, p3 = 0.0;
-    int t = 0;
-    for (; t + 4 <= j; t += 4) {
-      p0 -= L[l][t] * L[j][t];
-      p1 -= L[l][t + 1] * L[j][t + 1];
-      p2 -= L[l][t + 2] * L[j][t + 2];
-      p3 -= L[l][t + 3] * L[j][t + 3];
+  __shared__ double Lf[kNB][kNB + 1];
+  __shared__ double col[kNB];
+  __shared__ double rdiag[kNB];                 // 1 / L[j][j]
+  __shared__ double pv;
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  const int r0 = 4 * ti, c0 = 4 * tj;
+  double a[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = r0 + i, c = c0 + k;
+      a[i][k] = (r < nbk && c < nbk) ? A[(size_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
     }
-    for (; t < j; ++t) p0 -= L[l][t] * L[j][t];
-    const double sv = (p0 + p1) + (p2 + p3);
-    const double d = __shfl(sv, j);
-    if (l == j && j < nbk && !(d > 0.0)) atomicOr(info, 2);
-    const double piv = sqrt(d);
-    if (l == j) L[j][j] = piv;
-    else if (l > j) L[l][j] = sv / piv;
+  for (int j = 0; j < kNB; ++j) {
+    const int jt = j >> 2, jj = j & 3;
+    if (ti == jt && tj == jt) {
+      const double d = tile_get(a, jj, jj);
+      if (j < nbk && !(d > 0.0)) atomicOr(info, 2);
+      const double sq = sqrt(d);
+      pv = sq;
+      rdiag[j] = 1.0 / sq;
+    }
+    __syncthreads();
+    const double piv = pv, rinv = rdiag[j];
+    if (tj == jt) {               // column j: L[r][j] = a[r][j] / piv (r > j), piv on the diagonal
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = r0 + i;
+        double v = tile_get(a, i, jj);
+        v = (r == j) ? piv : (r > j ? v * rinv : 0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k == jj) a[i][k] = (r >= j) ? v : a[i][k];
+        col[r] = v;
+      }
+    }
+    __syncthreads();
+    double cr[4], cc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cr[i] = col[r0 + i];
+      cc[i] = col[c0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (r0 + i > j && c0 + k > j) a[i][k] -= cr[i] * cc[k];
+  }
+  // publish L (lower part; zero above the diagonal)
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = r0 + i, c = c0 + k;
+      Lf[r][c] = (c <= r) ? a[i][k] : 0.0;
+      if (r < nbk && c <= r) A[(size_t)(k0 + r) * n + k0 + c] = a[i][k];
+      a[i][k] = (r == c) ? 1.0 : 0.0;          // X = I, becomes L^{-1}
+    }
+  __syncthreads();
+  // right-looking: row q of X /= L[q][q]; rows r > q: X[r] -= L[r][q] X[q]
+  for (int q = 0; q < kNB; ++q) {
+    const int qt = q >> 2, qq = q & 3;
+    if (ti == qt) {
+      const double inv = rdiag[q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v = (i == qq) ? a[i][k] * inv : v;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i == qq) a[i][k] = v;
+        col[c0 + k] = v;
+      }
+    }
+    __syncthreads();
+    double xr[4], lr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xr[k] = col[c0 + k];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lr[i] = Lf[r0 + i][q];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (r0 + i > q) a[i][k] -= lr[i] * xr[k];
     __syncthreads();
   }
-  const int c = l;
-  for (int r = 0; r < kNB; ++r) {
-    double t0 = 0.0;
-    if (r >= c) {
-      double p0 = (r == c) ? 1.0 : 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-      int q = c;
-      for (; q + 4 <= r; q += 4) {
-        p0 -= L[r][q] * Li[q][c];
-        p1 -= L[r][q + 1] * Li[q + 1][c];
-        p2 -= L[r][q + 2] * Li[q + 2][c];
-        p3 -= L[r][q + 3] * Li[q + 3][c];
-      }
-      for (; q < r; ++q) p0 -= L[r][q] * Li[q][c];
-      t0 = ((p0 + p1) + (p2 + p3)) / L[r][r];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = r0 + i, c = c0 + k;
+      dinv[r * kNB + c] = (c <= r) ? a[i][k] : 0.0;
     }
-    Li[r][c] = t0;
-  }
-  __syncthreads();
-  for (int r = 0; r < kNB; ++r) {
-    dinv[r * kNB + l] = Li[r][l];
-    if (r < nbk && l <= r) A[(size_t)(k0 + r) * n + k0 + l] = L[r][l];
-  }
-}
-
-// Panel below the diagonal block: A[i, k0:k0+nbk] <- A[i, k0:k0+nbk] L_kk^{-T}
-// for 64 rows per workgroup.
-__global__ void __launch_bounds__(256)
-k_trsm_panel(double* __restrict__ A, int n, int k0, int nbk, const double* __restrict__ dinv) {
-  __shared__ double T[kNB][kNB + 1];
-  __shared__ double Li[kNB][kNB + 1];
-  const int i0 = k0 + nbk + blockIdx.x * kNB;
-  const int nr = min(kNB, n - i0);
-  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    T[r][c] = (r < nr && c < nbk) ? A[(size_t)(i0 + r) * n + k0 + c] : 0.0;
-    Li[r][c] = dinv[e];
-  }
-  __syncthreads();
-  double out[16];
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + 256 * u;
-    const int r = e / kNB, c = e % kNB;
-    double s = 0.0;
-    for (int t = 0; t <= c; ++t) s += T[r][t] * Li[c][t];
-    out[u] = s;
-  }
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + 256 * u;
-    const int r = e / kNB, c = e % kNB;
-    if (r < nr && c < nbk) A[(size_t)(i0 + r) * n + k0 + c] = out[u];
-  }
-}
-
-// Diagonal-block solve of the batched right-hand sides X[r][i] (row-major by
-// realization): forward  X[r][k0+c] <- sum_t Linv[c][t] X[r][k0+t],
-//              backward X[r][k0+c] <- sum_t Linv[t][c] X[r][k0+t].
-// One thread per output (4 realizations x 64 rows per workgroup).
-template <bool BACK>
-__global__ void __launch_bounds__(256)
-k_trsm_diag(double* __restrict__ X, int n, int R, int k0, int nbk, const double* __restrict__ dinv) {
-  __shared__ double Li[kNB][kNB + 1];
-  __shared__ double Xs[4][kNB];
-  const int r0 = blockIdx.x * 4;
-  for (int e = threadIdx.x; e < kNB * kNB; e += 256) Li[e / kNB][e % kNB] = dinv[e];
-  const int rl = threadIdx.x >> 6, c = threadIdx.x & 63;
-  const int r = r0 + rl;
-  Xs[rl][c] = (r < R && c < nbk) ? X[(size_t)r * n + k0 + c] : 0.0;
-  __syncthreads();
-  double s = 0.0;
-  if (!BACK) {
-    for (int t = 0; t <= c; ++t) s += Li[c][t] * Xs[rl][t];
-  } else {
-    for (int t = c; t < kNB; ++t) s += Li[t][c] * Xs[rl][t];
-  }
-  if (r < R && c < nbk) X[(size_t)r * n + k0 + c] = s;
 }
 
 // Generic FP64 GEMM on matrix cores: C = alpha A B + beta C with element
@@ -242,12 +254,19 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
   CESIM_HIP(hipGetLastError());
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    k_potrf_diag<<<1, 64, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
+    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
     CESIM_HIP(hipGetLastError());
     const int rest = n - k0 - nbk;
     if (rest <= 0) break;
-    k_trsm_panel<<<(rest + kNB - 1) / kNB, 256, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB);
-    CESIM_HIP(hipGetLastError());
+    {   // panel: A[i, k0:k0+nbk] <- A[i, k0:k0+nbk] Linv^T (in place: each
+        // workgroup reads its whole row block before writing it)
+      GemmArgs g;
+      g.M = rest; g.N = nbk; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+      g.A = A + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
+      g.B = D + (size_t)kb * kNB * kNB; g.sbk = 1; g.sbj = kNB;     // B(t, c) = Linv[c][t]
+      g.C = A + (size_t)(k0 + nbk) * n + k0; g.sci = n; g.scj = 1;
+      CESIM_TRY(gemm_f64(g, false, s));
+    }
     GemmArgs g;
     g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
     g.A = A + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
@@ -270,12 +289,17 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
   const int nblk = (n + kNB - 1) / kNB;
   const double* L = c->amat.as<double>();
   const double* D = c->dinv.as<double>();
-  const dim3 gdiag((R + 3) / 4);
   const int tr = c->timer.begin(ST_SOLVE, s);
   for (int kb = 0; kb < nblk; ++kb) {          // L Y = X
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    k_trsm_diag<false><<<gdiag, 256, 0, s>>>(X, n, R, k0, nbk, D + (size_t)kb * kNB * kNB);
-    CESIM_HIP(hipGetLastError());
+    {   // X[r][k0+c] <- sum_t Linv[c][t] X[r][k0+t]  (in place, see above)
+      GemmArgs g;
+      g.M = nbk; g.N = R; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+      g.A = D + (size_t)kb * kNB * kNB; g.sai = kNB; g.sak = 1;
+      g.B = X + k0; g.sbk = 1; g.sbj = n;
+      g.C = X + k0; g.sci = 1; g.scj = n;
+      CESIM_TRY(gemm_f64(g, false, s));
+    }
     const int rest = n - k0 - nbk;
     if (rest <= 0) break;
     GemmArgs g;
@@ -287,8 +311,14 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
   }
   for (int kb = nblk - 1; kb >= 0; --kb) {     // L^T X = Y
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    k_trsm_diag<true><<<gdiag, 256, 0, s>>>(X, n, R, k0, nbk, D + (size_t)kb * kNB * kNB);
-    CESIM_HIP(hipGetLastError());
+    {   // X[r][k0+c] <- sum_t Linv[t][c] X[r][k0+t]
+      GemmArgs g;
+      g.M = nbk; g.N = R; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+      g.A = D + (size_t)kb * kNB * kNB; g.sai = 1; g.sak = kNB;
+      g.B = X + k0; g.sbk = 1; g.sbj = n;
+      g.C = X + k0; g.sci = 1; g.scj = n;
+      CESIM_TRY(gemm_f64(g, false, s));
+    }
     if (k0 == 0) break;
     GemmArgs g;
     g.M = k0; g.N = R; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
