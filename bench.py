@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--gemm-nf", type=int, default=0, help="node fragments per wave (0: library default)")
     ap.add_argument("--chunk-pairs", type=int, default=0)
+    ap.add_argument("--split", choices=["fp16", "bf16"], default="fp16",
+                    help="half type of the three-product split in the mixed GEMM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default="")
     return ap.parse_args()
@@ -87,6 +89,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
             ctx.set_param(cesim.PARAM_GEMM_NODE_FRAGMENTS, args.gemm_nf)
         if args.chunk_pairs:
             ctx.set_param(cesim.PARAM_DRAW_CHUNK_PAIRS, args.chunk_pairs)
+        ctx.set_param(cesim.PARAM_GEMM_SPLIT, 0 if args.split == "fp16" else 1)
         ctx.offgrid(xy, wl.k)
         for b0 in range(0, R, batch):
             nb = min(batch, R - b0)

@@ -49,9 +49,10 @@
  *   CESIM_PREC_MIXED : eigenvalue setup, local-Kriging solves, the
  *                      observation Cholesky and its solves in FP64; the CE
  *                      FFT passes in FP32; the cross-covariance product
- *                      K12 B in BF16 on matrix cores with FP32 accumulation
- *                      and a three-product split-precision correction;
- *                      fields are float.
+ *                      K12 B on matrix cores in half precision (FP16 by
+ *                      default, BF16 selectable) with FP32 accumulation and
+ *                      a three-product split-precision correction; fields
+ *                      are float.
  */
 #ifndef CESIM_H
 #define CESIM_H
@@ -223,9 +224,13 @@ const char* cesim_status_string(cesim_status s);
  *   CESIM_PARAM_GEMM_NODE_FRAGMENTS: 32-node fragments per wave in the mixed
  *     cross-covariance GEMM, 1 (default) or 2.
  *   CESIM_PARAM_DRAW_CHUNK_PAIRS: realization pairs per launch of the draw
- *     passes (bounds the pair buffer); 0 (default) chooses up to 2 GiB. */
+ *     passes (bounds the pair buffer); 0 (default) chooses up to 2 GiB.
+ *   CESIM_PARAM_GEMM_SPLIT (changes rounding, not the method): half type of
+ *     the three-product split in the mixed GEMM, 0 = FP16 (default, about
+ *     22 significant bits per operand) or 1 = BF16 (about 16 bits). */
 #define CESIM_PARAM_GEMM_NODE_FRAGMENTS 1
 #define CESIM_PARAM_DRAW_CHUNK_PAIRS 2
+#define CESIM_PARAM_GEMM_SPLIT 3
 cesim_status ce_set_param(cesim_ctx ctx, int param, int value);
 
 /* Default timing state of contexts created afterwards (process-wide). */

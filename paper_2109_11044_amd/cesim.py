@@ -28,6 +28,7 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "cesim_stage_name", "cesim_release_cached_memory", "ce_set_param"]
 PARAM_GEMM_NODE_FRAGMENTS = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
+PARAM_GEMM_SPLIT = 3
 NUM_STAGES = 12
 VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",
                 "cesim_stage_name", "cesim_release_cached_memory")

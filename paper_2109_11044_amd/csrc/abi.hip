@@ -258,6 +258,10 @@ cesim_status ce_set_param(cesim_ctx c, int param, int value) {
       if (value != 1 && value != 2) return CESIM_ERR_INVALID_ARG;
       c->gemm_nf = value;
       return CESIM_OK;
+    case CESIM_PARAM_GEMM_SPLIT:
+      if (value != 0 && value != 1) return CESIM_ERR_INVALID_ARG;
+      c->gemm_split = value;
+      return CESIM_OK;
     case CESIM_PARAM_DRAW_CHUNK_PAIRS:
       if (value < 0) return CESIM_ERR_INVALID_ARG;
       c->draw_chunk_pairs = value;

@@ -110,11 +110,12 @@ struct cesim_ctx_s {
   cesim::DevBuf dinv;               // inverses of the diagonal blocks
   cesim::DevBuf zdev;               // observed values
   cesim::DevBuf coef;               // [R][n] FP64: z - z*, then the coefficients
-  cesim::DevBuf coef_b16;           // [R][n] bf16 hi / lo pairs (mixed)
+  cesim::DevBuf coef_b16;           // half-precision hi / lo coefficients + column scales (mixed)
   cesim::DevBuf info_dev;           // int flags
   std::vector<double> z_host_cached;
 
   int gemm_nf = 1;                  // node fragments per wave in the mixed grid GEMM
+  int gemm_split = 0;               // 0: FP16 x3, 1: BF16 x3
   int draw_chunk_pairs = 0;         // pairs per draw launch (0: by a 2 GiB budget)
 
   // last simulate

@@ -7,9 +7,13 @@
 // coordinates: x = |U g - U s| is the lag length in range units.
 //
 //   FP64 path : v_mfma_f64_16x16x4f64, K12 and B in FP64.
-//   mixed path: K12 in FP32, split into bf16 hi + lo; B split likewise (with
-//               sigma^2 folded in); three v_mfma_f32_32x32x16_bf16 products
-//               hi.hi + hi.lo + lo.hi accumulate in FP32.
+//   mixed path: K12 in FP32, split into half-precision hi + lo; B scaled per
+//               realization into [-1, 1] and split likewise; three 32x32x16
+//               matrix-core products hi.hi + hi.lo + lo.hi accumulate in FP32.
+//               The half type is FP16 (11-bit significands: the split keeps
+//               about 22 bits, and K12 is scaled by 2^12 so that small
+//               correlations stay normal) or BF16 (8-bit significands: about
+//               16 bits); both run at the same matrix-core rate.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -20,6 +24,23 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));   // 16 bytes, register-promotable
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// Half-precision element types of the split product: the vector type and
+// the matching 32x32x16 matrix-core instruction.
+template <typename H> struct HalfOps;
+template <> struct HalfOps<__bf16> {
+  using V = bf16x8;
+  static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct HalfOps<_Float16> {
+  using V = f16x8;
+  static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
 
 // ------------------------------------------------------------ FP64 kernel
 // D[r][g] = sum_i X[r][i] K12[g][i] on v_mfma_f64_16x16x4f64 (lane l holds
@@ -116,21 +137,39 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
 // ----------------------------------------------------------- mixed kernel
 constexpr int kKC = 32;     // observations per k-chunk of the mixed kernel
 
-// B split: Bh/Bl[kc][r][32] bf16 (observation chunk kc of 32, realization r)
-// from FP64 X[r][i] with sigma^2 folded in; hi = bf16(v), lo = bf16(v - hi).
-__global__ void k_split_coef(const double* __restrict__ X, int n, int R, int Rp, double scale,
-                             __bf16* __restrict__ Bh, __bf16* __restrict__ Bl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
+// Coefficient split, one workgroup per realization r (r < Rp; rows r >= R
+// are zero): scale_r = max_i |X[r][i]|, v = X[r][i] / scale_r in [-1, 1],
+// hi = half(v), lo = half(v - hi), stored as Bh/Bl[kc][r][32] (observation
+// chunk kc of 32).  colscale[r] = scale_r sigma^2 / KS undoes the scaling in
+// the GEMM epilogue (KS is the factor the correlations are multiplied by
+// before conversion, keeping FP16 values in the normal range).
+template <typename H>
+__global__ void __launch_bounds__(256)
+k_split_coef(const double* __restrict__ X, int n, int R, int Rp, double sigma2, double ks,
+             H* __restrict__ Bh, H* __restrict__ Bl, float* __restrict__ colscale) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
   const int npad = (n + kKC - 1) / kKC * kKC;
-  if (i >= npad) return;
-  const double v = (i < n && r < R) ? scale * X[(size_t)r * n + i] : 0.0;
-  const float f = (float)v;
-  const __bf16 h = (__bf16)f;
-  const __bf16 l = (__bf16)(float)(v - (double)(float)h);
-  const size_t o = ((size_t)(i / kKC) * Rp + r) * kKC + (i % kKC);
-  Bh[o] = h;
-  Bl[o] = l;
+  double mx = 0.0;
+  if (r < R)
+    for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, fabs(X[(size_t)r * n + i]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double sc = red[0];
+  const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+  for (int i = threadIdx.x; i < npad; i += 256) {
+    const double v = (i < n && r < R) ? X[(size_t)r * n + i] * inv : 0.0;
+    const H h = (H)(float)v;
+    const H l = (H)(float)(v - (double)(float)h);
+    const size_t o = ((size_t)(i / kKC) * Rp + r) * kKC + (i % kKC);
+    Bh[o] = h;
+    Bl[o] = l;
+  }
+  if (threadIdx.x == 0) colscale[r] = (float)(sc * sigma2 / ks);
 }
 
 // Grid GEMM, mixed precision.  The product is formed transposed,
@@ -147,28 +186,30 @@ __global__ void k_split_coef(const double* __restrict__ X, int n, int R, int Rp,
 // Layout of v_mfma_f32_32x32x16_bf16: lane l holds A[l % 32][8 (l/32) + j]
 // and B[8 (l/32) + j][l % 32]; accumulator e of lane l is
 // D[8 (e/4) + 4 (l/32) + e % 4][l % 32].
-template <int NU>
+template <int NU, typename H>
 __device__ __forceinline__ void k12_frag(float gxt, float gyt, const float2* __restrict__ sv,
-                                         bf16x8& ah, bf16x8& al) {
+                                         float ks, typename HalfOps<H>::V& ah,
+                                         typename HalfOps<H>::V& al) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const float hx = gxt - sv[j].x, hy = gyt - sv[j].y;
-    const float c = rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
-    const __bf16 h = (__bf16)c;
+    const float c = ks * rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+    const H h = (H)c;
     ah[j] = h;
-    al[j] = (__bf16)(c - (float)h);
+    al[j] = (H)(c - (float)h);
   }
 }
 
-template <int NU, int NF>
+template <int NU, int NF, typename H>
 __global__ void __launch_bounds__(256, 3 - NF)
-k_krige_bf16x3(float* __restrict__ fields, int m1, int M, int R, int Rp,
-               const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int n,
-               const float2* __restrict__ st, float ux, float uxy, float uyx, float uy, float dx,
-               float dy) {
+k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
+               const H* __restrict__ Bh, const H* __restrict__ Bl,
+               const float* __restrict__ colscale, int n, const float2* __restrict__ st,
+               float ux, float uxy, float uyx, float uy, float dx, float dy, float kscale) {
+  using HV = typename HalfOps<H>::V;
   constexpr int TG = 128 * NF, TR = 256;
-  __shared__ __align__(16) __bf16 Sh[2][TR * kKC];
-  __shared__ __align__(16) __bf16 Sl[2][TR * kKC];
+  __shared__ __align__(16) H Sh[2][TR * kKC];
+  __shared__ __align__(16) H Sl[2][TR * kKC];
   __shared__ float2 Ss[2][kKC];
   const int g0 = blockIdx.x * TG, r0 = blockIdx.y * TR;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -233,20 +274,20 @@ k_krige_bf16x3(float* __restrict__ fields, int m1, int M, int R, int Rp,
       float2 sv[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) sv[j] = Ss[buf][ks + kb + j];
-      bf16x8 ah[NF], al[NF];
+      HV ah[NF], al[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) k12_frag<NU>(gxt[f], gyt[f], sv, ah[f], al[f]);
+      for (int f = 0; f < NF; ++f) k12_frag<NU, H>(gxt[f], gyt[f], sv, kscale, ah[f], al[f]);
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         const int rr = 32 * b + (lane & 31);
         const int pc = ((ks + kb) >> 3) ^ ((rr >> 2) & 3);
-        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Sh[buf][rr * kKC + 8 * pc]);
-        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Sl[buf][rr * kKC + 8 * pc]);
+        const HV bh = *reinterpret_cast<const HV*>(&Sh[buf][rr * kKC + 8 * pc]);
+        const HV bl = *reinterpret_cast<const HV*>(&Sl[buf][rr * kKC + 8 * pc]);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-          acc[f][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, ah[f], acc[f][b], 0, 0, 0);
-          acc[f][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh, al[f], acc[f][b], 0, 0, 0);
-          acc[f][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl, ah[f], acc[f][b], 0, 0, 0);
+          acc[f][b] = HalfOps<H>::mfma(bh, ah[f], acc[f][b]);
+          acc[f][b] = HalfOps<H>::mfma(bh, al[f], acc[f][b]);
+          acc[f][b] = HalfOps<H>::mfma(bl, ah[f], acc[f][b]);
         }
       }
     }
@@ -265,7 +306,7 @@ k_krige_bf16x3(float* __restrict__ fields, int m1, int M, int R, int Rp,
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int r = r0 + 32 * b + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (r < R) fields[(size_t)r * M + gg] += acc[f][b][e];
+        if (r < R) fields[(size_t)r * M + gg] += acc[f][b][e] * colscale[r];
       }
   }
 }
@@ -316,11 +357,23 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   }
   const int Rp = (R + 255) / 256 * 256;
   const int npad = (n + kKC - 1) / kKC * kKC;
-  CESIM_TRY(c->coef_b16.reserve(sizeof(__bf16) * 2 * (size_t)npad * Rp));
-  __bf16* Bh = c->coef_b16.as<__bf16>();
-  __bf16* Bl = Bh + (size_t)npad * Rp;
+  const bool f16 = c->gemm_split == 0;
+  // correlations enter FP16 multiplied by 2^12 (values up to 4096), which
+  // keeps products of small correlations out of the subnormal range
+  const double ks = f16 ? 4096.0 : 1.0;
+  CESIM_TRY(c->coef_b16.reserve(sizeof(uint16_t) * 2 * (size_t)npad * Rp + sizeof(float) * Rp));
+  uint16_t* Hh = c->coef_b16.as<uint16_t>();
+  uint16_t* Hl = Hh + (size_t)npad * Rp;
+  float* colscale = reinterpret_cast<float*>(Hl + (size_t)npad * Rp);
   int tr = c->timer.begin(ST_COEF_SPLIT, s);
-  k_split_coef<<<dim3((npad + 255) / 256, Rp), 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, Bh, Bl);
+  if (f16)
+    k_split_coef<_Float16><<<Rp, 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, ks,
+                                              reinterpret_cast<_Float16*>(Hh),
+                                              reinterpret_cast<_Float16*>(Hl), colscale);
+  else
+    k_split_coef<__bf16><<<Rp, 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, ks,
+                                            reinterpret_cast<__bf16*>(Hh),
+                                            reinterpret_cast<__bf16*>(Hl), colscale);
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   const double kappa = c->covd.nu_code == 0 ? kLog2e : (c->covd.nu_code == 2 ? kSqrt3 : kSqrt2);
@@ -330,25 +383,26 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   float* F = static_cast<float*>(fields);
   const float2* S2 = c->obs_t32.as<float2>();
   const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
-  const float fdx = (float)dx, fdy = (float)dy;
+  const float fdx = (float)dx, fdy = (float)dy, fks = (float)ks;
   const int nf = c->gemm_nf == 2 ? 2 : 1;
   dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
-#define CESIM_KB(NU, NF) \
-  k_krige_bf16x3<NU, NF><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, Bh, Bl, n, S2, a, b, cc, d, fdx, fdy)
-  if (nf == 1) {
-    switch (c->covd.nu_code) {
-      case 0: CESIM_KB(0, 1); break;
-      case 1: CESIM_KB(1, 1); break;
-      default: CESIM_KB(2, 1); break;
-    }
-  } else {
-    switch (c->covd.nu_code) {
-      case 0: CESIM_KB(0, 2); break;
-      case 1: CESIM_KB(1, 2); break;
-      default: CESIM_KB(2, 2); break;
-    }
+#define CESIM_KS(NU, NF, H)                                                                     \
+  k_krige_split3<NU, NF, H><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh), \
+                                                 reinterpret_cast<const H*>(Hl), colscale, n, S2, \
+                                                 a, b, cc, d, fdx, fdy, fks)
+#define CESIM_KS_NU(NF, H)                  \
+  switch (c->covd.nu_code) {                \
+    case 0: CESIM_KS(0, NF, H); break;      \
+    case 1: CESIM_KS(1, NF, H); break;      \
+    default: CESIM_KS(2, NF, H); break;     \
   }
-#undef CESIM_KB
+  if (f16) {
+    if (nf == 1) { CESIM_KS_NU(1, _Float16) } else { CESIM_KS_NU(2, _Float16) }
+  } else {
+    if (nf == 1) { CESIM_KS_NU(1, __bf16) } else { CESIM_KS_NU(2, __bf16) }
+  }
+#undef CESIM_KS_NU
+#undef CESIM_KS
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   return CESIM_OK;
