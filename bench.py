@@ -51,6 +51,9 @@ def parse():
                     help="half type of the three-product split in the mixed GEMM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB once (a "
+                         "reference kernel of known traffic for hardware-counter runs)")
     return ap.parse_args()
 
 
@@ -169,7 +172,7 @@ def cpu_baseline(wl, xy, z, seed):
     s0 = time.perf_counter()
     fac = kriging.factor(xy, cov, wl.tau2)
     t["cholesky"] = time.perf_counter() - s0
-    nd = 2
+    nd = 4
     s0 = time.perf_counter()
     eps = philox.torus_noise(seed, t1, t2, range(nd))
     y = ce.ce_draw(s, eps, wl.m, wl.m)
@@ -180,7 +183,7 @@ def cpu_baseline(wl, xy, z, seed):
     s0 = time.perf_counter()
     B = kriging.coefficients(fac, z, zsR)
     t["solve_R"] = time.perf_counter() - s0
-    rows = np.arange(8)
+    rows = np.arange(32)
     s0 = time.perf_counter()
     kriging.krige_to_grid(B, xy, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, rows=rows, chunk_rows=8)
     t["krige_rows"] = time.perf_counter() - s0
@@ -250,6 +253,15 @@ def main():
     out["finite"] = all(r["finite"] for r in res.values())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, xy, z, args.seed)
+    if args.copy_probe_mib:
+        nel = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * nel * 4
+        del src, dst
     line = json.dumps(out)
     print(line, flush=True)
     if args.json_out:
