@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6}
+PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp64": 78.6}   # dense matrix-core peaks
 
 
 def parse():
@@ -139,7 +139,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
                      frac=gbs / HBM_PEAK_GBS, algorithmic_bytes_per_launch=units / (calls / args.steps))
         elif kind == "flops":
             tf = units / (ms / args.steps / 1000.0) / 1e12
-            peak = PEAK_TFLOPS["fp64" if prec == "fp64" else "bf16"]
+            peak = PEAK_TFLOPS["fp64" if prec == "fp64" else args.split]
             k.update(bound="mfma", achieved=tf, unit="TFLOP/s", peak=peak, frac=tf / peak,
                      algorithmic_flops_per_launch=units / (calls / args.steps))
         kernels.append(k)
@@ -263,7 +263,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 FFT / bf16x3 GEMM (f64 setup, Cholesky, solves)" if "mixed" in res else "f64",
+        "dtype": (f"f32 FFT / {args.split}x3 GEMM (f64 setup, Cholesky, solves)" if "mixed" in res
+                  else "f64"),
         "data": "synthetic",
         "config": {"workload": wl.name if (args.m, args.n, args.nreal) == (1024, 5000, 1000)
                    else f"exp{args.m}_n{args.n}cl_k36_R{args.nreal}",
