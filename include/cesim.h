@@ -136,7 +136,7 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid,
  * first_real + nreal - 1 (step 2 of Section 2; Section 2.1 item (a)):
  *   y_r = Re(IFFT2(sqrt(lambda) FFT2(eps_r)))[0:m2, 0:m1],
  * eps_r the t2 x t1 torus noise of Philox stream 0 (element q = j t1 + i:
- * block q/4, word q%4, counter (block, r, 0, 0), Box-Muller).  Two
+ * block q/4, word q%4, counter (block, r, event id, 0), Box-Muller).  Two
  * realizations share one complex transform.  fields_dev: caller-owned
  * device buffer of nreal*m2*m1 doubles (FP64) or floats (MIXED), written
  * asynchronously.  Records (seed, first_real, nreal) for condition().
@@ -165,7 +165,7 @@ cesim_status offgrid_nnkrige(cesim_ctx ctx, int nobs, const double* obs_xy_host,
  * by ce_simulate into fields_dev (the same buffer and type):
  *   z*_{r,i} = w_i . y_r[window_i] + sqrt(nugget + gamma_i) xi_{r,i}
  *       (xi from Philox stream 1: block i/4, word i%4, counter
- *        (block, r, 0, 1)),
+ *        (block, r, event id, 1)),
  *   B_r     = (K22 + nugget I)^{-1} (z - z*_r)        (FP64 Cholesky),
  *   v_r     = y_r + K12 B_r,  K12[g, i] = C(g - s_i).
  * z_host: nobs observed values, host memory, copied.  nugget >= 0.  The
@@ -231,7 +231,71 @@ const char* cesim_status_string(cesim_status s);
 #define CESIM_PARAM_GEMM_NODE_FRAGMENTS 1
 #define CESIM_PARAM_DRAW_CHUNK_PAIRS 2
 #define CESIM_PARAM_GEMM_SPLIT 3
+/*   CESIM_PARAM_EVENT_ID (changes the realizations): word 2 of the Philox
+ *     counter of the torus noise and of xi, >= 0 (default 0); a context with
+ *     event id e draws exactly what event e of a batch draws. */
+#define CESIM_PARAM_EVENT_ID 4
 cesim_status ce_set_param(cesim_ctx ctx, int param, int value);
+
+/* ---- batches of independent events ----
+ * One event is the whole conditional simulation above (Section 2 with the
+ * local Kriging of Section 2.1) for its own covariance, grid, stations,
+ * values and realization count.  A batch plans many events once and then
+ * runs all of them with one HIP graph launch per call of cesim_batch_run.
+ * Event e draws the realizations that a context created with the same
+ * covariance, grid and precision, with CESIM_PARAM_EVENT_ID = event_id,
+ * would draw with ce_simulate(nreal, seed, first_real + offset) followed by
+ * offgrid_nnkrige / condition with the same stations, values and nugget
+ * (bit for bit: the same kernels run). */
+typedef struct {
+  cesim_cov cov;
+  cesim_grid grid;            /* t1 = t2 = 0: torus from the ladder */
+  int nobs;                   /* >= 1 */
+  const double* obs_xy;       /* host [nobs][2]; read during cesim_batch_create only */
+  const double* z;            /* host [nobs] observed values; idem */
+  double nugget;              /* tau^2 >= 0 */
+  int k;                      /* window nodes: 4, 16, 36 or 64 */
+  int nreal;                  /* realizations per run, >= 1 */
+  int first_real;             /* absolute index of the first realization at offset 0 */
+  uint64_t seed;              /* Philox key */
+  uint32_t event_id;          /* word 2 of the Philox counter */
+  void* fields;               /* device, caller-owned [nreal][m2][m1], double (FP64) or
+                                 float (mixed); overwritten by every run */
+} cesim_event;
+
+typedef struct cesim_batch_s* cesim_batch;
+
+/* Plans a batch (synchronises hip_stream first): for every event the torus
+ * ladder and sqrt(lambda), the local-Kriging set-up and phi; then one
+ * grouped FP64 Cholesky of all the K22 + nugget I; then captures the run
+ * (per event: CE draw, synthetic observations, the grouped solves of all
+ * events, grid GEMM) into one graph.  event_status (nevents entries, may be
+ * NULL) receives each event's status (INVALID_ARG, NEGATIVE_EIGENVALUE,
+ * OBS_OUTSIDE_GRID, NOT_POSITIVE_DEFINITE, ...); on any failure nothing is
+ * kept, *out is NULL and the first failure is returned.  The event table and
+ * its host arrays may be freed after the call; the fields buffers must stay
+ * allocated until cesim_batch_destroy. */
+cesim_status cesim_batch_create(const cesim_event* events, int nevents,
+                                cesim_precision prec, void* hip_stream,
+                                cesim_status* event_status, cesim_batch* out);
+
+/* Runs every event of the batch once, asynchronously on the batch's stream,
+ * drawing realizations first_real + real_offset .. + nreal - 1 of each event
+ * into its fields buffer.  real_offset >= 0.  Calls on one batch are ordered
+ * on its stream. */
+cesim_status cesim_batch_run(cesim_batch b, int real_offset);
+
+/* Statistics of event e (as ce_get_info); synchronises. */
+cesim_status cesim_batch_get_info(cesim_batch b, int e, cesim_info* info);
+
+/* Waits for the batch's runs and releases everything it owns.  NULL is
+ * ignored. */
+void cesim_batch_destroy(cesim_batch b);
+
+/* create + one run at offset 0 + destroy (returns after the run ended). */
+cesim_status cesim_run_events(const cesim_event* events, int nevents,
+                              cesim_precision prec, void* hip_stream,
+                              cesim_status* event_status);
 
 /* Default timing state of contexts created afterwards (process-wide). */
 void cesim_set_default_timing(int enable);

@@ -10,7 +10,7 @@ local-Kriging approximation of steps 2-4:
   (d) the grid prediction uses tau^2 alone.
 
 Random inputs: eps_r from Philox stream 0 and xi_r from stream 1, both keyed
-by the seed and the absolute realization index r (event 0).
+by the seed, the absolute realization index r and the event index.
 
 Test-only helpers build, for tiny problems, the explicit linear map of the
 pipeline from (eps, xi) to v - y_hat, the paper's closed-form covariance of
@@ -67,17 +67,18 @@ def draw_observations(obs_xy, cov: Cov, tau2, seed=0):
 
 
 def conditional_simulation(cov: Cov, grid: Grid, obs_xy, z, tau2, k, seed,
-                           nreal, first_real=0, t1=None, t2=None):
-    """Run steps 1-5 for realizations first_real .. first_real + nreal - 1.
+                           nreal, first_real=0, t1=None, t2=None, event=0):
+    """Run steps 1-5 for realizations first_real .. first_real + nreal - 1
+    (noise counters carry ``event`` in their third word).
 
     Returns a dict of every intermediate: torus, sqrt_lam, eps, y, window
     corners a/b, W, gamma, xi, zstar, B, v."""
     t1, t2, s, info = setup(cov, grid, t1, t2)
     reals = np.arange(first_real, first_real + nreal)
-    eps = philox.torus_noise(seed, t1, t2, reals)
+    eps = philox.torus_noise(seed, t1, t2, reals, event)
     y = ce.ce_draw(s, eps, grid.m1, grid.m2)
     a, b, W, gamma = offgrid_setup(obs_xy, cov, grid, k)
-    xi = philox.offgrid_noise(seed, len(obs_xy), reals)
+    xi = philox.offgrid_noise(seed, len(obs_xy), reals, event)
     zstar = localkrige.synthetic_obs(y, a, b, W, gamma, tau2, xi)
     fac = kriging.factor(obs_xy, cov, tau2)
     B = kriging.coefficients(fac, z, zstar)

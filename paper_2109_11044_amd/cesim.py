@@ -25,13 +25,16 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "condition_copy_coefficients", "cesim_covariance_host",
            "cesim_philox_host", "cesim_status_string", "ce_destroy",
            "cesim_set_default_timing", "ce_set_timing", "ce_get_stage_times",
-           "cesim_stage_name", "cesim_release_cached_memory", "ce_set_param"]
+           "cesim_stage_name", "cesim_release_cached_memory", "ce_set_param",
+           "cesim_batch_create", "cesim_batch_run", "cesim_batch_get_info",
+           "cesim_batch_destroy", "cesim_run_events"]
 PARAM_GEMM_NODE_FRAGMENTS = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
+PARAM_EVENT_ID = 4
 NUM_STAGES = 12
 VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",
-                "cesim_stage_name", "cesim_release_cached_memory")
+                "cesim_stage_name", "cesim_release_cached_memory", "cesim_batch_destroy")
 
 
 class CesimError(RuntimeError):
@@ -62,6 +65,15 @@ class Info(ctypes.Structure):
                 ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double),
                 ("ms_setup", ctypes.c_double), ("ms_offgrid", ctypes.c_double),
                 ("precision", ctypes.c_int), ("torus_tries", ctypes.c_int)]
+
+
+class Event(ctypes.Structure):
+    _fields_ = [("cov", Cov), ("grid", Grid), ("nobs", ctypes.c_int),
+                ("obs_xy", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("nugget", ctypes.c_double), ("k", ctypes.c_int),
+                ("nreal", ctypes.c_int), ("first_real", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("event_id", ctypes.c_uint32),
+                ("fields", ctypes.c_void_p)]
 
 
 _lib = None
@@ -104,6 +116,13 @@ def lib():
     L.cesim_stage_name.restype = ctypes.c_char_p
     L.cesim_release_cached_memory.argtypes = []
     L.cesim_release_cached_memory.restype = None
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.cesim_batch_create.argtypes = [ctypes.POINTER(Event), i, i, vp, ip, ctypes.POINTER(vp)]
+    L.cesim_batch_run.argtypes = [vp, i]
+    L.cesim_batch_get_info.argtypes = [vp, i, ctypes.POINTER(Info)]
+    L.cesim_batch_destroy.argtypes = [vp]
+    L.cesim_batch_destroy.restype = None
+    L.cesim_run_events.argtypes = [ctypes.POINTER(Event), i, i, vp, ip]
     for name in EXPORTS:
         if name not in VOID_EXPORTS:
             getattr(L, name).restype = i
@@ -286,3 +305,79 @@ class Context:
         _check(lib().condition_copy_coefficients(self._h, ctypes.c_void_p(out.data_ptr())),
                "condition_copy_coefficients")
         return out
+
+
+class BatchError(CesimError):
+    """A batch could not be planned; .event_status lists each event's status."""
+
+    def __init__(self, status, where, event_status):
+        super().__init__(status, where)
+        self.event_status = list(event_status)
+
+
+class Batch:
+    """Independent events planned once and run with one graph launch each.
+
+    ``events`` is a list of dicts with keys cov, grid, obs_xy, z, nugget, k,
+    nreal, seed and optionally first_real (0) and event_id (its position).
+    Field tensors are allocated here ([nreal, m2, m1]; float64 for "fp64",
+    float32 for "mixed") and overwritten by every run."""
+
+    def __init__(self, events, precision="fp64", stream=None):
+        import torch
+        self._torch = torch
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        ne = len(events)
+        self.fields, keep = [], []
+        table = (Event * ne)()
+        for e, ev in enumerate(events):
+            g = ev["grid"]
+            xy = np.ascontiguousarray(ev["obs_xy"], dtype=np.float64).reshape(-1, 2)
+            z = np.ascontiguousarray(ev["z"], dtype=np.float64).ravel()
+            if z.size != xy.shape[0]:
+                raise ValueError(f"event {e}: z must hold one value per observation")
+            f = torch.empty((int(ev["nreal"]), g.m2, g.m1), dtype=self.dtype, device="cuda")
+            self.fields.append(f)
+            keep += [xy, z]
+            table[e] = Event(ev["cov"], g, xy.shape[0], xy.ctypes.data, z.ctypes.data,
+                             float(ev["nugget"]), int(ev["k"]), int(ev["nreal"]),
+                             int(ev.get("first_real", 0)), int(ev["seed"]),
+                             int(ev.get("event_id", e)), f.data_ptr())
+        st = (ctypes.c_int * ne)()
+        h = ctypes.c_void_p()
+        rc = lib().cesim_batch_create(table, ne, PREC[precision],
+                                      ctypes.c_void_p(stream.cuda_stream), st, ctypes.byref(h))
+        self.event_status = [STATUS_NAMES.get(v, str(v)) for v in st]
+        if rc != OK:
+            raise BatchError(rc, "cesim_batch_create", self.event_status)
+        self._h = h
+
+    def run(self, real_offset=0):
+        _check(lib().cesim_batch_run(self._h, int(real_offset)), "cesim_batch_run")
+        return self.fields
+
+    def info(self, e):
+        inf = Info()
+        _check(lib().cesim_batch_get_info(self._h, int(e), ctypes.byref(inf)),
+               "cesim_batch_get_info")
+        return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().cesim_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -266,6 +266,10 @@ cesim_status ce_set_param(cesim_ctx c, int param, int value) {
       if (value < 0) return CESIM_ERR_INVALID_ARG;
       c->draw_chunk_pairs = value;
       return CESIM_OK;
+    case CESIM_PARAM_EVENT_ID:
+      if (value < 0) return CESIM_ERR_INVALID_ARG;
+      c->event_id = (uint32_t)value;
+      return CESIM_OK;
     default:
       return CESIM_ERR_INVALID_ARG;
   }

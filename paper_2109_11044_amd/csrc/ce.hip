@@ -73,19 +73,20 @@ __device__ inline const cpx<real>* stage_twiddles(cpx<real>* dst, const cpx<real
 // Noise for torus rows [j0, j0 + nrows) of pair p into LDS as
 // eps_{r0} + i eps_{r1}; element q = j t1 + i uses block q / 4, word q % 4.
 template <typename real, int NTHR>
-__device__ void noise_rows(cpx<real>* lds, int t1, int j0, int nrows, uint32_t k0, uint32_t k1,
+__device__ void noise_rows(cpx<real>* lds, int t1, int j0, int nrows, const NoiseKey& key,
                            int r0, bool has_r1) {
+  const uint32_t k0 = key.k0, k1 = key.k1, ev = key.event;
   const long q_lo = (long)j0 * t1;
   const long q_hi = q_lo + (long)nrows * t1;
   const long b_lo = q_lo >> 2, b_hi = (q_hi - 1) >> 2;
   for (long b = b_lo + threadIdx.x; b <= b_hi; b += NTHR) {
     real za[4], zb[4] = {0, 0, 0, 0};
     if constexpr (sizeof(real) == 8) {
-      normals4_f64(k0, k1, (uint32_t)b, (uint32_t)r0, 0u, 0u, za);
-      if (has_r1) normals4_f64(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), 0u, 0u, zb);
+      normals4_f64(k0, k1, (uint32_t)b, (uint32_t)r0, ev, 0u, za);
+      if (has_r1) normals4_f64(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), ev, 0u, zb);
     } else {
-      normals4_f32(k0, k1, (uint32_t)b, (uint32_t)r0, 0u, 0u, za);
-      if (has_r1) normals4_f32(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), 0u, 0u, zb);
+      normals4_f32(k0, k1, (uint32_t)b, (uint32_t)r0, ev, 0u, za);
+      if (has_r1) normals4_f32(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), ev, 0u, zb);
     }
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
@@ -100,8 +101,7 @@ __device__ void noise_rows(cpx<real>* lds, int t1, int j0, int nrows, uint32_t k
 template <typename real, int NTHR, int E, bool NOISE>
 __global__ void __launch_bounds__(NTHR)
 k_rows_fwd(cpx<real>* __restrict__ buf, int t1, int t2, int nb, Plan plan,
-           const cpx<real>* __restrict__ tw, bool tw_lds, uint32_t k0, uint32_t k1,
-           int first_real, int nreal, int pair0) {
+           const cpx<real>* __restrict__ tw, bool tw_lds, NoiseKey key, int nreal, int pair0) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
   const int p = blockIdx.y;
@@ -111,8 +111,8 @@ k_rows_fwd(cpx<real>* __restrict__ buf, int t1, int t2, int nb, Plan plan,
   const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + nb * t1, tw, t1, tw_lds);
   if constexpr (NOISE) {
     const int pg = pair0 + p;               // pair index within this call
-    const int r0 = first_real + 2 * pg;
-    noise_rows<real, NTHR>(lds, t1, j0, nr, k0, k1, r0, 2 * pg + 1 < nreal);
+    const int r0 = key.base() + 2 * pg;
+    noise_rows<real, NTHR>(lds, t1, j0, nr, key, r0, 2 * pg + 1 < nreal);
   } else {
     for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
   }
@@ -194,8 +194,8 @@ k_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, in
 // FFT, result written from registers.
 template <typename real, int T>
 __global__ void __launch_bounds__(P2Rows<T>::NTHR)
-k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict__ tw, uint32_t k0,
-                uint32_t k1, int first_real, int nreal, int pair0) {
+k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict__ tw, NoiseKey key,
+                int nreal, int pair0) {
   using C = cpx<real>;
   using G = P2Rows<T>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -203,8 +203,9 @@ k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict
   const int p = blockIdx.y;
   const int j0 = blockIdx.x * G::ROWS;
   const int pg = pair0 + p;
-  const int r0 = first_real + 2 * pg;
+  const int r0 = key.base() + 2 * pg;
   const bool has1 = 2 * pg + 1 < nreal;
+  const uint32_t k0 = key.k0, k1 = key.k1, ev = key.event;
   // Philox blocks of 4 consecutive elements; T is a multiple of 4, so a
   // block never straddles two rows.
   constexpr int BPR = T / 4;
@@ -214,11 +215,11 @@ k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict
     const uint32_t gb = (uint32_t)((((long)(j0 + b)) * T + i0) >> 2);
     real za[4], zb[4] = {0, 0, 0, 0};
     if constexpr (sizeof(real) == 8) {
-      normals4_f64(k0, k1, gb, (uint32_t)r0, 0u, 0u, za);
-      if (has1) normals4_f64(k0, k1, gb, (uint32_t)(r0 + 1), 0u, 0u, zb);
+      normals4_f64(k0, k1, gb, (uint32_t)r0, ev, 0u, za);
+      if (has1) normals4_f64(k0, k1, gb, (uint32_t)(r0 + 1), ev, 0u, zb);
     } else {
-      normals4_f32(k0, k1, gb, (uint32_t)r0, 0u, 0u, za);
-      if (has1) normals4_f32(k0, k1, gb, (uint32_t)(r0 + 1), 0u, 0u, zb);
+      normals4_f32(k0, k1, gb, (uint32_t)r0, ev, 0u, za);
+      if (has1) normals4_f32(k0, k1, gb, (uint32_t)(r0 + 1), ev, 0u, zb);
     }
     const RowLds<C> rl{lds + b * G::LD};
 #pragma unroll
@@ -445,8 +446,8 @@ void allow_lds(K kernel, size_t bytes) {
 
 template <typename real, bool NOISE>
 cesim_status launch_rows_fwd(cpx<real>* buf, int t1, int t2, int npairs, const Plan& plan,
-                             const cpx<real>* tw, uint32_t k0, uint32_t k1, int first_real,
-                             int nreal, int pair0, hipStream_t s) {
+                             const cpx<real>* tw, const NoiseKey& key, int nreal, int pair0,
+                             hipStream_t s) {
   int nb, E;
   bool twl;
   size_t lds;
@@ -455,13 +456,11 @@ cesim_status launch_rows_fwd(cpx<real>* buf, int t1, int t2, int npairs, const P
   if (E == 16) {
     auto k = k_rows_fwd<real, kRowThreads, 16, NOISE>;
     allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, k0, k1, first_real, nreal,
-                                     pair0);
+    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, key, nreal, pair0);
   } else {
     auto k = k_rows_fwd<real, kRowThreads, 32, NOISE>;
     allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, k0, k1, first_real, nreal,
-                                     pair0);
+    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, key, nreal, pair0);
   }
   CESIM_HIP(hipGetLastError());
   return CESIM_OK;
@@ -536,8 +535,8 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   tr = c->timer.begin(ST_SETUP_FFT, s);
-  CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, p1, c->tt.tw1_64.as<double2>(), 0, 0,
-                                            0, 0, 0, s)));
+  CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, p1, c->tt.tw1_64.as<double2>(),
+                                            NoiseKey{}, 0, 0, s)));
   CESIM_TRY((launch_cols<double, false>(buf, t1, t2, 1, t2, p2, c->tt.tw2_64.as<double2>(),
                                         nullptr, s)));
   c->timer.end(tr, s);
@@ -576,8 +575,8 @@ namespace {
 
 template <typename real, int T1, int T2>
 cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np, const cpx<real>* tw1,
-                           const cpx<real>* tw2, const real* sl, uint32_t k0, uint32_t k1,
-                           int first_real, int nreal, int pair0, StageTimer& tm, hipStream_t s) {
+                           const cpx<real>* tw2, const real* sl, const NoiseKey& key, int nreal,
+                           int pair0, StageTimer& tm, hipStream_t s) {
   using GR = P2Rows<T1>;
   using GC = P2Cols<real, T2>;
   const size_t lr = sizeof(cpx<real>) * GR::ROWS * GR::LD;
@@ -586,8 +585,8 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
   {
     auto k = k_p2_rows_noise<real, T1>;
     allow_lds(k, lr);
-    k<<<dim3((T2 + GR::ROWS - 1) / GR::ROWS, np), GR::NTHR, lr, s>>>(buf, T2, tw1, k0, k1,
-                                                                    first_real, nreal, pair0);
+    k<<<dim3((T2 + GR::ROWS - 1) / GR::ROWS, np), GR::NTHR, lr, s>>>(buf, T2, tw1, key, nreal,
+                                                                    pair0);
     CESIM_HIP(hipGetLastError());
   }
   tm.end(tr, s);
@@ -614,15 +613,15 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
 // Square power-of-two tori from 128 to 8192 take the register path.
 template <typename real>
 bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m2, int np,
-                     const cpx<real>* tw1, const cpx<real>* tw2, const real* sl, uint32_t k0,
-                     uint32_t k1, int first_real, int nreal, int pair0, StageTimer& tm,
+                     const cpx<real>* tw1, const cpx<real>* tw2, const real* sl,
+                     const NoiseKey& key, int nreal, int pair0, StageTimer& tm,
                      hipStream_t s, cesim_status& st) {
   if (t1 != t2) return false;
   switch (t1) {
 #define CESIM_P2(TT)                                                                        \
   case TT:                                                                                  \
-    st = draw_chunk_p2<real, TT, TT>(buf, fields, m1, m2, np, tw1, tw2, sl, k0, k1, first_real, \
-                                     nreal, pair0, tm, s);                                  \
+    st = draw_chunk_p2<real, TT, TT>(buf, fields, m1, m2, np, tw1, tw2, sl, key, nreal, pair0, \
+                                     tm, s);                                                \
     return true;
     CESIM_P2(128) CESIM_P2(256) CESIM_P2(512) CESIM_P2(1024) CESIM_P2(2048) CESIM_P2(4096)
     CESIM_P2(8192)
@@ -638,23 +637,28 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
   const int t1 = c->t1, t2 = c->t2, m1 = c->grid.m1, m2 = c->grid.m2;
   const size_t pair_bytes = sizeof(cpx<real>) * (size_t)t1 * t2;
   const int npairs = (nreal + 1) / 2;
-  const size_t budget = (size_t)2 << 30;
-  int chunk = (int)std::max<size_t>(1, std::min<size_t>(npairs, budget / pair_bytes));
-  if (c->draw_chunk_pairs > 0) chunk = std::min(npairs, c->draw_chunk_pairs);
-  CESIM_TRY(c->work.reserve(pair_bytes * chunk));
-  cpx<real>* buf = c->work.as<cpx<real>>();
-  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  int chunk = draw_chunk_pairs(c, nreal);
+  cpx<real>* buf;
+  if (c->ext_work) {                // pair buffers lent by a batch
+    chunk = std::min<size_t>(chunk, c->ext_work_bytes / pair_bytes);
+    if (chunk < 1) return CESIM_ERR_INVALID_ARG;
+    buf = static_cast<cpx<real>*>(c->ext_work);
+  } else {
+    CESIM_TRY(c->work.reserve(pair_bytes * chunk));
+    buf = c->work.as<cpx<real>>();
+  }
+  const NoiseKey key{(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), first_real,
+                     c->event_id, c->roff};
   for (int pair0 = 0; pair0 < npairs; pair0 += chunk) {
     const int np = std::min(chunk, npairs - pair0);
     cesim_status st = CESIM_OK;
-    if (draw_chunk_pow2<real>(t1, t2, buf, fields, m1, m2, np, tw1, tw2, sl, k0, k1, first_real,
-                              nreal, pair0, c->timer, s, st)) {
+    if (draw_chunk_pow2<real>(t1, t2, buf, fields, m1, m2, np, tw1, tw2, sl, key, nreal, pair0,
+                              c->timer, s, st)) {
       CESIM_TRY(st);
       continue;
     }
     int tr = c->timer.begin(ST_DRAW_PASS1, s);
-    CESIM_TRY((launch_rows_fwd<real, true>(buf, t1, t2, np, c->tt.p1, tw1, k0, k1, first_real,
-                                           nreal, pair0, s)));
+    CESIM_TRY((launch_rows_fwd<real, true>(buf, t1, t2, np, c->tt.p1, tw1, key, nreal, pair0, s)));
     c->timer.end(tr, s);
     tr = c->timer.begin(ST_DRAW_PASS2, s);
     CESIM_TRY((launch_cols<real, true>(buf, t1, t2, np, m2, c->tt.p2, tw2, sl, s)));
@@ -668,6 +672,21 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
 }
 
 }  // namespace
+
+size_t draw_pair_bytes(cesim_ctx c) {
+  const size_t el = c->prec == CESIM_PREC_FP64 ? sizeof(double2) : sizeof(float2);
+  return el * (size_t)c->t1 * c->t2;
+}
+
+// Pairs per draw launch: all of them within a 2 GiB buffer, or the count
+// set with CESIM_PARAM_DRAW_CHUNK_PAIRS.
+int draw_chunk_pairs(cesim_ctx c, int nreal) {
+  const int npairs = (nreal + 1) / 2;
+  const size_t budget = (size_t)2 << 30;
+  int chunk = (int)std::max<size_t>(1, std::min<size_t>(npairs, budget / draw_pair_bytes(c)));
+  if (c->draw_chunk_pairs > 0) chunk = std::min(npairs, c->draw_chunk_pairs);
+  return chunk;
+}
 
 cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields) {
   if (c->prec == CESIM_PREC_FP64)

@@ -187,6 +187,18 @@ __device__ inline void box_muller_f32(uint32_t a, uint32_t b, float& z0, float& 
   z1 = rad * __builtin_amdgcn_sinf(ub);
 }
 
+// Key and counter words of one call's noise: realization r of the call uses
+// counter word 1 = first + (*roff when roff is given) + r and word 2 = event.
+// roff lets a captured launch sequence be replayed for later realizations
+// by rewriting one device integer.
+struct NoiseKey {
+  uint32_t k0, k1;
+  int first;
+  uint32_t event;
+  const int* roff;
+  __device__ __forceinline__ int base() const { return first + (roff ? *roff : 0); }
+};
+
 // Four normals of block `blk` of (realization r, event, stream).
 __device__ inline void normals4_f64(uint32_t k0, uint32_t k1, uint32_t blk, uint32_t r,
                                     uint32_t event, uint32_t stream, double z[4]) {

@@ -69,6 +69,43 @@ struct StageTimer {
   void destroy();
 };
 
+// FP64 GEMM C = alpha A B + beta C with element strides A(i,k) = A[i sai + k sak],
+// B(k,j) = B[k sbk + j sbj], C(i,j) = C[i sci + j scj].
+struct GemmArgs {
+  int M, N, K;
+  double alpha, beta;
+  const double* A; long sai, sak;
+  const double* B; long sbk, sbj;
+  double* C; long sci, scj;
+};
+
+// One 64 x 64 diagonal block of a blocked Cholesky factorisation.
+struct DiagDesc {
+  double* A;        // n x n, row-major, factored in place (lower)
+  int n, k0, nbk;
+  double* dinv;     // 64 x 64 inverse of the block's factor
+  int* info;        // bit 2 set on a non-positive pivot
+};
+
+// A recorded sequence of grouped launches over several independent systems
+// (diagonal factorisations and FP64 GEMMs), uploaded once and then launched
+// any number of times without host work beyond the launches themselves.
+struct GroupedSeq {
+  struct Launch { int kind, first, count, blocks, pfx; };   // kind: 0 diag, 1 GEMM, 2 lower GEMM
+  std::vector<DiagDesc> diag;
+  std::vector<GemmArgs> gemm;
+  std::vector<int> pfx;
+  std::vector<Launch> launches;
+  DevBuf dev;
+  DiagDesc* d_diag = nullptr;
+  GemmArgs* d_gemm = nullptr;
+  int* d_pfx = nullptr;
+  void add_diag(const std::vector<DiagDesc>& v);
+  void add_gemm(const std::vector<GemmArgs>& v, bool lower);   // empty problems are dropped
+  cesim_status upload(hipStream_t s);                          // synchronises s
+  cesim_status launch(hipStream_t s) const;
+};
+
 struct TorusTables {
   Plan p1, p2;                      // plans along x (t1) and y (t2)
   DevBuf tw1_64, tw2_64, tw1_32, tw2_32;   // twiddles exp(-2 pi i t / T)
@@ -118,6 +155,12 @@ struct cesim_ctx_s {
   int gemm_split = 0;               // 0: FP16 x3, 1: BF16 x3
   int draw_chunk_pairs = 0;         // pairs per draw launch (0: by a 2 GiB budget)
 
+  // batched runs: Philox event word, device realization offset, lent pair buffers
+  uint32_t event_id = 0;
+  const int* roff = nullptr;
+  void* ext_work = nullptr;
+  size_t ext_work_bytes = 0;
+
   // last simulate
   bool have_fields = false;
   uint64_t seed = 0;
@@ -131,7 +174,18 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted);
 cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields);
 cesim_status lk_setup_device(cesim_ctx c);
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields);
+cesim_status lk_phi_device(cesim_ctx c, double tau2);
+cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs);
+cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields);
+cesim_status krige_reserve(cesim_ctx c, int R);
+cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vector<double>& tau2,
+                               hipStream_t s, std::vector<int>& not_pd);
+cesim_status chol_solve_batch_plan(const std::vector<cesim_ctx>& cs,
+                                   const std::vector<double*>& X, const std::vector<int>& R,
+                                   GroupedSeq& seq);
 cesim_status make_plan(int T, Plan& p);
+size_t draw_pair_bytes(cesim_ctx c);
+int draw_chunk_pairs(cesim_ctx c, int nreal);
 cesim_status make_twiddles(int T, DevBuf& tw64, DevBuf& tw32, hipStream_t s);
 
 }  // namespace cesim

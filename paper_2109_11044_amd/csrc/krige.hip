@@ -315,8 +315,6 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
 
 cesim_status chol_factor_device(cesim_ctx c, double tau2);
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R);
-cesim_status lk_phi_device(cesim_ctx c, double tau2);
-cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs);
 
 // Linear map U (range units) and the per-path coordinate scale.
 static void cov_map(const cesim_ctx c, double scale, double& ux, double& uxy, double& uyx,
@@ -325,6 +323,19 @@ static void cov_map(const cesim_ctx c, double scale, double& ux, double& uxy, do
   uxy = c->covd.u01 * scale;
   uyx = c->covd.u10 * scale;
   uy = c->covd.u11 * scale;
+}
+
+// Coefficient buffers for R realizations: [R][n] FP64 and, on the mixed
+// path, the half-precision hi / lo split with its column scales.
+cesim_status krige_reserve(cesim_ctx c, int R) {
+  const int n = c->nobs;
+  CESIM_TRY(c->coef.reserve(sizeof(double) * (size_t)n * R));
+  if (c->prec == CESIM_PREC_MIXED) {
+    const int Rp = (R + 255) / 256 * 256;
+    const int npad = (n + kKC - 1) / kKC * kKC;
+    CESIM_TRY(c->coef_b16.reserve(sizeof(uint16_t) * 2 * (size_t)npad * Rp + sizeof(float) * Rp));
+  }
+  return CESIM_OK;
 }
 
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
@@ -337,10 +348,18 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     c->chol_nugget = nugget;
   }
   CESIM_TRY(lk_phi_device(c, nugget));
-  CESIM_TRY(c->coef.reserve(sizeof(double) * (size_t)n * R));
+  CESIM_TRY(krige_reserve(c, R));
   double* X = c->coef.as<double>();
   CESIM_TRY(lk_synth_rhs_device(c, fields, X));
   CESIM_TRY(chol_solve_device(c, X, R));
+  return krige_grid_device(c, X, fields);
+}
+
+// fields[r] += K12 X[r] for the c->nreal realizations of the last draw
+// (Section 2, step 5), FP64 or three-product half-precision split.
+cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
+  hipStream_t s = c->stream;
+  const int n = c->nobs, R = c->nreal;
   const int m1 = c->grid.m1, M = c->grid.m1 * c->grid.m2;
   const double dx = c->grid.dx, dy = c->grid.dy;
   if (c->prec == CESIM_PREC_FP64) {
@@ -361,7 +380,7 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   // correlations enter FP16 multiplied by 2^12 (values up to 4096), which
   // keeps products of small correlations out of the subnormal range
   const double ks = f16 ? 4096.0 : 1.0;
-  CESIM_TRY(c->coef_b16.reserve(sizeof(uint16_t) * 2 * (size_t)npad * Rp + sizeof(float) * Rp));
+  CESIM_TRY(krige_reserve(c, R));
   uint16_t* Hh = c->coef_b16.as<uint16_t>();
   uint16_t* Hl = Hh + (size_t)npad * Rp;
   float* colscale = reinterpret_cast<float*>(Hl + (size_t)npad * Rp);

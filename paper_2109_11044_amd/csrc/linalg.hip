@@ -47,9 +47,8 @@ __device__ __forceinline__ double tile_get(const double (&a)[4][4], int i, int k
   return v;
 }
 
-__global__ void __launch_bounds__(256)
-k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
-             int* __restrict__ info) {
+__device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, int k0, int nbk,
+                                                double* __restrict__ dinv, int* __restrict__ info) {
   __shared__ double Lf[kNB][kNB + 1];
   __shared__ double col[kNB];
   __shared__ double rdiag[kNB];                 // 1 / L[j][j]
@@ -149,26 +148,27 @@ k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict_
     }
 }
 
-// Generic FP64 GEMM on matrix cores: C = alpha A B + beta C with element
-// strides A(i,k) = A[i sai + k sak], B(k,j) = B[k sbk + j sbj],
-// C(i,j) = C[i sci + j scj].  64 x 64 tiles, 4 waves of 32 x 32, k-step 16.
+__global__ void __launch_bounds__(256)
+k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
+             int* __restrict__ info) {
+  potrf_diag_body(A, n, k0, nbk, dinv, info);
+}
+
+// One diagonal block of each of several systems: workgroup q takes d[q].
+__global__ void __launch_bounds__(256) k_potrf_diag_grp(const DiagDesc* __restrict__ d) {
+  const DiagDesc e = d[blockIdx.x];
+  potrf_diag_body(e.A, e.n, e.k0, e.nbk, e.dinv, e.info);
+}
+
+// Generic FP64 GEMM on matrix cores (GemmArgs): 64 x 64 tiles, 4 waves of 32 x 32, k-step 16.
 // LOWER: skip tiles strictly above the diagonal (symmetric updates).
 // Operand layouts of v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16]
 // and B[l / 16][l % 16]; accumulator v of lane l is D[l / 16 + 4 v][l % 16].
-struct GemmArgs {
-  int M, N, K;
-  double alpha, beta;
-  const double* A; long sai, sak;
-  const double* B; long sbk, sbj;
-  double* C; long sci, scj;
-};
-
 template <bool LOWER>
-__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
   constexpr int TM = 64, TN = 64, TK = 16;
   __shared__ double As[TK][TM + 2];
   __shared__ double Bs[TK][TN + 2];
-  const int bi = blockIdx.y, bj = blockIdx.x;
   if (LOWER && bj > bi) return;
   const int i0 = bi * TM, j0 = bj * TN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -225,6 +225,30 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
           *cp = g.alpha * acc[x][y][v] + g.beta * prev;
         }
       }
+}
+
+template <bool LOWER>
+__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
+  gemm_tile<LOWER>(g, blockIdx.y, blockIdx.x);
+}
+
+// Several independent GEMMs in one launch: group q owns workgroups
+// [tile0[q], tile0[q + 1]) (ascending, no empty groups), its tiles in
+// row-major order of its 64 x 64 tile grid.
+template <bool LOWER>
+__global__ void __launch_bounds__(256)
+k_gemm_f64_grp(const GemmArgs* __restrict__ gs, const int* __restrict__ tile0, int ngroups) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile0[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const GemmArgs g = gs[lo];
+  const int t = b - tile0[lo];
+  const int tn = (g.N + 63) / 64;
+  gemm_tile<LOWER>(g, t / tn, t % tn);
 }
 
 cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s) {
@@ -328,6 +352,189 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
     CESIM_TRY(gemm_f64(g, false, s));
   }
   c->timer.end(tr, s);
+  return CESIM_OK;
+}
+
+
+// ------------------------------------------------ grouped systems (batches)
+
+void GroupedSeq::add_diag(const std::vector<DiagDesc>& v) {
+  if (v.empty()) return;
+  launches.push_back({0, (int)diag.size(), (int)v.size(), (int)v.size(), 0});
+  diag.insert(diag.end(), v.begin(), v.end());
+}
+
+void GroupedSeq::add_gemm(const std::vector<GemmArgs>& v, bool lower) {
+  Launch l{lower ? 2 : 1, (int)gemm.size(), 0, 0, (int)pfx.size()};
+  int tiles = 0;
+  for (const GemmArgs& g : v) {
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0) continue;
+    pfx.push_back(tiles);
+    tiles += ((g.M + 63) / 64) * ((g.N + 63) / 64);
+    gemm.push_back(g);
+    ++l.count;
+  }
+  if (l.count == 0) return;
+  pfx.push_back(tiles);
+  l.blocks = tiles;
+  launches.push_back(l);
+}
+
+cesim_status GroupedSeq::upload(hipStream_t s) {
+  const size_t bd = sizeof(DiagDesc) * diag.size(), bg = sizeof(GemmArgs) * gemm.size();
+  const size_t bp = sizeof(int) * pfx.size();
+  const size_t og = (bd + 255) / 256 * 256, op = og + (bg + 255) / 256 * 256;
+  CESIM_TRY(dev.reserve(op + bp + 256));
+  unsigned char* base = dev.as<unsigned char>();
+  if (bd) CESIM_HIP(hipMemcpyAsync(base, diag.data(), bd, hipMemcpyHostToDevice, s));
+  if (bg) CESIM_HIP(hipMemcpyAsync(base + og, gemm.data(), bg, hipMemcpyHostToDevice, s));
+  if (bp) CESIM_HIP(hipMemcpyAsync(base + op, pfx.data(), bp, hipMemcpyHostToDevice, s));
+  CESIM_HIP(hipStreamSynchronize(s));
+  d_diag = reinterpret_cast<DiagDesc*>(base);
+  d_gemm = reinterpret_cast<GemmArgs*>(base + og);
+  d_pfx = reinterpret_cast<int*>(base + op);
+  return CESIM_OK;
+}
+
+cesim_status GroupedSeq::launch(hipStream_t s) const {
+  for (const Launch& l : launches) {
+    if (l.kind == 0)
+      k_potrf_diag_grp<<<l.blocks, 256, 0, s>>>(d_diag + l.first);
+    else if (l.kind == 1)
+      k_gemm_f64_grp<false><<<l.blocks, 256, 0, s>>>(d_gemm + l.first, d_pfx + l.pfx, l.count);
+    else
+      k_gemm_f64_grp<true><<<l.blocks, 256, 0, s>>>(d_gemm + l.first, d_pfx + l.pfx, l.count);
+    CESIM_HIP(hipGetLastError());
+  }
+  return CESIM_OK;
+}
+
+// Factor A_e = K22_e + tau_e^2 I of every context at once: step kb runs the
+// diagonal block kb of every system that has one, then its panel and
+// trailing update, each as one grouped launch.  The arithmetic per system
+// is that of chol_factor_device.  Synchronises; not_pd[e] = 1 marks a
+// non-positive pivot.
+cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vector<double>& tau2,
+                               hipStream_t s, std::vector<int>& not_pd) {
+  const int ne = (int)cs.size();
+  not_pd.assign(ne, 0);
+  int maxnb = 0;
+  for (int e = 0; e < ne; ++e) {
+    cesim_ctx c = cs[e];
+    const int n = c->nobs, nblk = (n + kNB - 1) / kNB;
+    maxnb = std::max(maxnb, nblk);
+    CESIM_TRY(c->amat.reserve(sizeof(double) * (size_t)n * n));
+    CESIM_TRY(c->dinv.reserve(sizeof(double) * (size_t)nblk * kNB * kNB));
+    CESIM_HIP(hipMemsetAsync(c->info_dev.p, 0, sizeof(int) * 4, s));
+    k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd,
+                                                           tau2[e], c->amat.as<double>());
+    CESIM_HIP(hipGetLastError());
+  }
+  GroupedSeq seq;
+  for (int kb = 0; kb < maxnb; ++kb) {
+    std::vector<DiagDesc> dd;
+    std::vector<GemmArgs> panel, syrk;
+    for (int e = 0; e < ne; ++e) {
+      cesim_ctx c = cs[e];
+      const int n = c->nobs, k0 = kb * kNB;
+      if (k0 >= n) continue;
+      const int nbk = std::min(kNB, n - k0), rest = n - k0 - nbk;
+      double* A = c->amat.as<double>();
+      double* D = c->dinv.as<double>() + (size_t)kb * kNB * kNB;
+      dd.push_back({A, n, k0, nbk, D, c->info_dev.as<int>()});
+      if (rest <= 0) continue;
+      GemmArgs g;
+      g.M = rest; g.N = nbk; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+      g.A = A + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
+      g.B = D; g.sbk = 1; g.sbj = kNB;
+      g.C = A + (size_t)(k0 + nbk) * n + k0; g.sci = n; g.scj = 1;
+      panel.push_back(g);
+      g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = A + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
+      g.B = A + (size_t)(k0 + nbk) * n + k0; g.sbk = 1; g.sbj = n;
+      g.C = A + (size_t)(k0 + nbk) * n + (k0 + nbk); g.sci = n; g.scj = 1;
+      syrk.push_back(g);
+    }
+    seq.add_diag(dd);
+    seq.add_gemm(panel, false);
+    seq.add_gemm(syrk, true);
+  }
+  CESIM_TRY(seq.upload(s));
+  CESIM_TRY(seq.launch(s));
+  std::vector<int> flags(4 * ne);
+  for (int e = 0; e < ne; ++e)
+    CESIM_HIP(hipMemcpyAsync(&flags[4 * e], cs[e]->info_dev.p, sizeof(int) * 4,
+                             hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipStreamSynchronize(s));
+  for (int e = 0; e < ne; ++e) {
+    not_pd[e] = (flags[4 * e] & 2) ? 1 : 0;
+    cs[e]->chol_valid = !not_pd[e];
+    cs[e]->chol_nugget = tau2[e];
+  }
+  seq.dev.release();
+  return CESIM_OK;
+}
+
+// Record X_e <- A_e^{-1} X_e ([R_e][n_e], FP64) for every context with the
+// factors held in the contexts: forward steps aligned at the first block,
+// backward steps at each system's last block.  Same arithmetic per system
+// as chol_solve_device.
+cesim_status chol_solve_batch_plan(const std::vector<cesim_ctx>& cs,
+                                   const std::vector<double*>& X, const std::vector<int>& R,
+                                   GroupedSeq& seq) {
+  const int ne = (int)cs.size();
+  int maxnb = 0;
+  for (cesim_ctx c : cs) maxnb = std::max(maxnb, (c->nobs + kNB - 1) / kNB);
+  for (int kb = 0; kb < maxnb; ++kb) {          // L Y = X
+    std::vector<GemmArgs> dg, up;
+    for (int e = 0; e < ne; ++e) {
+      cesim_ctx c = cs[e];
+      const int n = c->nobs, k0 = kb * kNB;
+      if (k0 >= n) continue;
+      const int nbk = std::min(kNB, n - k0), rest = n - k0 - nbk;
+      const double* L = c->amat.as<double>();
+      const double* D = c->dinv.as<double>();
+      GemmArgs g;
+      g.M = nbk; g.N = R[e]; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+      g.A = D + (size_t)kb * kNB * kNB; g.sai = kNB; g.sak = 1;
+      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
+      g.C = X[e] + k0; g.sci = 1; g.scj = n;
+      dg.push_back(g);
+      if (rest <= 0) continue;
+      g.M = rest; g.N = R[e]; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = L + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
+      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
+      g.C = X[e] + k0 + nbk; g.sci = 1; g.scj = n;
+      up.push_back(g);
+    }
+    seq.add_gemm(dg, false);
+    seq.add_gemm(up, false);
+  }
+  for (int st = 0; st < maxnb; ++st) {          // L^T X = Y
+    std::vector<GemmArgs> dg, up;
+    for (int e = 0; e < ne; ++e) {
+      cesim_ctx c = cs[e];
+      const int n = c->nobs, nblk = (n + kNB - 1) / kNB, kb = nblk - 1 - st;
+      if (kb < 0) continue;
+      const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
+      const double* L = c->amat.as<double>();
+      const double* D = c->dinv.as<double>();
+      GemmArgs g;
+      g.M = nbk; g.N = R[e]; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+      g.A = D + (size_t)kb * kNB * kNB; g.sai = 1; g.sak = kNB;
+      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
+      g.C = X[e] + k0; g.sci = 1; g.scj = n;
+      dg.push_back(g);
+      if (k0 == 0) continue;
+      g.M = k0; g.N = R[e]; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = L + (size_t)k0 * n; g.sai = 1; g.sak = n;
+      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
+      g.C = X[e]; g.sci = 1; g.scj = n;
+      up.push_back(g);
+    }
+    seq.add_gemm(dg, false);
+    seq.add_gemm(up, false);
+  }
   return CESIM_OK;
 }
 

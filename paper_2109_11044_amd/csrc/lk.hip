@@ -97,8 +97,8 @@ template <typename F>
 __global__ void __launch_bounds__(256)
 k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict__ corners,
             const double* __restrict__ W, const double* __restrict__ phi,
-            const double* __restrict__ z, int n, int K, int w2, uint32_t k0, uint32_t k1,
-            int first_real, double* __restrict__ rhs) {
+            const double* __restrict__ z, int n, int K, int w2, NoiseKey key,
+            double* __restrict__ rhs) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
   if (i >= n) return;
@@ -109,7 +109,8 @@ k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict
   for (int q = 0; q < w2; ++q)
     for (int p = 0; p < w2; ++p) acc += w[q * w2 + p] * (double)y[(size_t)q * m1 + p];
   // xi_{r,i}: block i/4, word i%4 of Philox stream 1
-  const u32x4 wd = philox4x32_10({(uint32_t)(i >> 2), (uint32_t)(first_real + r), 0u, 1u}, k0, k1);
+  const u32x4 wd = philox4x32_10({(uint32_t)(i >> 2), (uint32_t)(key.base() + r), key.event, 1u},
+                                 key.k0, key.k1);
   const int word = i & 3;
   double z0, z1;
   if (word < 2) box_muller_f64(wd.x, wd.y, z0, z1);
@@ -153,19 +154,18 @@ cesim_status lk_phi_device(cesim_ctx c, double tau2) {
 cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs) {
   const int n = c->nobs;
   dim3 grid((n + 255) / 256, c->nreal);
-  const uint32_t k0 = (uint32_t)(c->seed & 0xffffffffu), k1 = (uint32_t)(c->seed >> 32);
+  const NoiseKey key{(uint32_t)(c->seed & 0xffffffffu), (uint32_t)(c->seed >> 32), c->first_real,
+                     c->event_id, c->roff};
   const int w2 = 2 * c->npp;
   const int tr = c->timer.begin(ST_SYNTH_RHS, c->stream);
   if (c->prec == CESIM_PREC_FP64)
     k_synth_rhs<double><<<grid, 256, 0, c->stream>>>(
         static_cast<const double*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, k0, k1,
-        c->first_real, rhs);
+        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, key, rhs);
   else
     k_synth_rhs<float><<<grid, 256, 0, c->stream>>>(
         static_cast<const float*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, k0, k1,
-        c->first_real, rhs);
+        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, key, rhs);
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, c->stream);
   return CESIM_OK;

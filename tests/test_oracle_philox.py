@@ -79,3 +79,14 @@ def test_element_to_block_mapping():
     assert z[9] == pytest.approx(np.sqrt(-2 * np.log(u[0])) * np.sin(2 * np.pi * u[1]), rel=1e-15)
     zz = philox.normals(2, 12, 5, 0, 0)
     assert zz[10] == pytest.approx(r * np.cos(2 * np.pi * u[3]), rel=1e-15)
+
+
+def test_event_word_selects_an_independent_stream():
+    from oracle import philox
+    a0 = philox.torus_noise(5, 8, 8, [0, 1])
+    assert np.array_equal(a0, philox.torus_noise(5, 8, 8, [0, 1], 0))
+    a1 = philox.torus_noise(5, 8, 8, [0, 1], 1)
+    assert not np.any(a0 == a1)
+    w0 = philox.raw_words(5, np.arange(4), 0, 0, philox.STREAM_OFFGRID)
+    w1 = philox.raw_words(5, np.arange(4), 0, 1, philox.STREAM_OFFGRID)
+    assert not np.any(w0 == w1)
