@@ -51,6 +51,11 @@ def parse():
                     help="half type of the three-product split in the mixed GEMM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--workload", choices=["dm", "events64"], default="dm",
+                    help="dm: the 1024^2 single-event workload; events64: 64 uneven events "
+                         "run as one batch (one graph launch per step)")
+    ap.add_argument("--no-unbatched", action="store_true",
+                    help="events64: skip the one-context-per-event comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB once (a "
                          "reference kernel of known traffic for hardware-counter runs)")
@@ -219,6 +224,91 @@ def cpu_baseline(wl, xy, z, seed):
             "seconds_measured": sum(t.values()), "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def events_main(args, torch, cesim, workloads):
+    """64 uneven events (grids 128^2 / 256^2 / 512^2, Matern 1/2 or 3/2,
+    anisotropic, 100-3000 clustered stations, 200 realizations each) planned
+    as one batch; a step is one graph launch drawing the next 200 conditional
+    realizations of every event.  The one-context-per-event path is timed
+    beside it on the same events (steady state, factorisations reused)."""
+    prec = "mixed" if args.precision in ("both", "mixed") else "fp64"
+    table = workloads.event_table(64)
+    evs = []
+    for e, wl in enumerate(table):
+        evs.append(dict(cov=cesim.make_cov(wl.nu, wl.sigma2, wl.range, wl.aniso_ratio,
+                                           wl.aniso_angle),
+                        grid=cesim.unit_square_grid(wl.m), obs_xy=wl.obs_xy(),
+                        z=workloads.iid_values(wl.n, wl.sigma2 + wl.tau2, seed=2000 + e),
+                        nugget=wl.tau2, k=wl.k, nreal=wl.nreal, first_real=0,
+                        seed=args.seed, event_id=e))
+    R = sum(ev["nreal"] for ev in evs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = cesim.Batch(evs, prec)
+    plan_ms = 1000.0 * (time.perf_counter() - t0)
+    tori = [b.info(e)["t1"] for e in range(len(evs))]
+    for w in range(args.warmup):
+        b.run(w * 200)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for st in range(args.steps):
+        b.run((args.warmup + st) * 200)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1000.0 * wall / args.steps
+    finite = all(bool(torch.isfinite(f).all().item()) for f in b.fields)
+    b.close()
+    out = {
+        "metric": "conditional realizations/sec, 64 uneven events in one graph launch",
+        "value": R / (ms_step / 1000.0), "unit": "conditional realizations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 FFT / fp16x3 GEMM (f64 setup, Cholesky, solves)" if prec == "mixed"
+                 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "events64_uneven_R200", "events": len(evs),
+                   "realizations_per_step": R, "grids": sorted({wl.m for wl in table}),
+                   "tori": sorted(set(tori)), "stations_total": sum(wl.n for wl in table),
+                   "per_event": [[wl.m, t, wl.n] for wl, t in zip(table, tori)]},
+        "events_per_s": len(evs) / (ms_step / 1000.0),
+        "plan_ms": plan_ms, "graph_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
+        "finite": finite,
+    }
+    if not args.no_unbatched:
+        ctxs = []
+        for ev in evs:
+            c = cesim.Context(ev["cov"], ev["grid"], prec)
+            c.set_param(cesim.PARAM_EVENT_ID, ev["event_id"])
+            c.offgrid(ev["obs_xy"], ev["k"])
+            ctxs.append((c, torch.empty((ev["nreal"], ev["grid"].m2, ev["grid"].m1),
+                                        dtype=torch.float32 if prec == "mixed"
+                                        else torch.float64, device="cuda")))
+
+        def unbatched(off):
+            for (c, f), ev in zip(ctxs, evs):
+                c.simulate(ev["nreal"], ev["seed"], off, out=f)
+                c.condition(ev["z"], ev["nugget"], f)
+        unbatched(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for st in range(args.steps):
+            unbatched((1 + st) * 200)
+        torch.cuda.synchronize()
+        ms_u = 1000.0 * (time.perf_counter() - t0) / args.steps
+        for c, _ in ctxs:
+            c.close()
+        out["unbatched"] = {"ms_per_step": ms_u, "value": R / (ms_u / 1000.0),
+                            "batched_speedup": ms_u / ms_step}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -234,6 +324,8 @@ def main():
     torch.cuda.set_device(0)
     from paper_2109_11044_amd import cesim, workloads
     cesim.lib()
+    if args.workload == "events64":
+        return events_main(args, torch, cesim, workloads)
     cesim.set_default_timing(True)
     wl = workloads.DM
     wl.m, wl.n, wl.nreal = args.m, args.n, args.nreal

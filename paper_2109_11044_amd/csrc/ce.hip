@@ -228,14 +228,14 @@ k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict
   __syncthreads();
   const int b = threadIdx.x / G::S, base = threadIdx.x % G::S;
   const RowLds<C> rl{lds + b * G::LD};
-  C x[16];
+  C x[G::E];
 #pragma unroll
-  for (int h = 0; h < 16; ++h) x[h] = rl.load(base + G::S * h);
+  for (int h = 0; h < G::E; ++h) x[h] = rl.load(base + G::S * h);
   p2_fft<real, T, false>(x, base, tw, rl);
   if (j0 + b < t2) {
     C* out = buf + ((size_t)p * t2 + j0 + b) * T;
 #pragma unroll
-    for (int h = 0; h < 16; ++h) out[base + G::S * h] = x[h];
+    for (int h = 0; h < G::E; ++h) out[base + G::S * h] = x[h];
   }
 }
 
@@ -260,20 +260,20 @@ k_p2_cols(cpx<real>* __restrict__ buf, int t1, int rows_out, const cpx<real>* __
   const int col = panel * G::CP + c;
   const bool ok = col < t1;
   C* colp = buf + (size_t)p * T * t1 + col;
-  C x[16];
+  C x[G::E];
 #pragma unroll
-  for (int h = 0; h < 16; ++h) x[h] = ok ? colp[(size_t)(base + G::S * h) * t1] : C{0, 0};
+  for (int h = 0; h < G::E; ++h) x[h] = ok ? colp[(size_t)(base + G::S * h) * t1] : C{0, 0};
   const ColLds<C, G::CP> cl{lds, c};
   p2_fft<real, T, false>(x, base, tw, cl);
 #pragma unroll
-  for (int h = 0; h < 16; ++h) {
+  for (int h = 0; h < G::E; ++h) {
     const real m = ok ? sl[(size_t)(base + G::S * h) * t1 + col] : (real)0;
     x[h] = {x[h].x * m, x[h].y * m};
   }
   p2_fft<real, T, true>(x, base, tw, cl);
   if (ok) {
 #pragma unroll
-    for (int h = 0; h < 16; ++h) {
+    for (int h = 0; h < G::E; ++h) {
       const int row = base + G::S * h;
       if (row < rows_out) colp[(size_t)row * t1] = x[h];
     }
@@ -295,9 +295,9 @@ k_p2_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields,
   const int j = blockIdx.x * G::ROWS + b;
   const bool ok = j < m2;
   const C* in = buf + ((size_t)p * t2 + (ok ? j : 0)) * T;
-  C x[16];
+  C x[G::E];
 #pragma unroll
-  for (int h = 0; h < 16; ++h) x[h] = ok ? in[base + G::S * h] : C{0, 0};
+  for (int h = 0; h < G::E; ++h) x[h] = ok ? in[base + G::S * h] : C{0, 0};
   const RowLds<C> rl{lds + b * G::LD};
   p2_fft<real, T, true>(x, base, tw, rl);
   if (!ok) return;
@@ -306,7 +306,7 @@ k_p2_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields,
   real* f0 = fields + (size_t)(2 * pg) * M + (size_t)j * m1;
   const bool has1 = 2 * pg + 1 < nreal;
 #pragma unroll
-  for (int h = 0; h < 16; ++h) {
+  for (int h = 0; h < G::E; ++h) {
     const int xcol = base + G::S * h;
     if (xcol < m1) {
       f0[xcol] = x[h].x;
@@ -610,7 +610,9 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
   return CESIM_OK;
 }
 
-// Square power-of-two tori from 128 to 8192 take the register path.
+// Square tori of 2^a from 128 to 8192 take the register path, and in FP32
+// also 3 * 2^a from 384 to 6144 (48 elements per thread; in FP64 these
+// would not fit the register file and stay on the LDS path).
 template <typename real>
 bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m2, int np,
                      const cpx<real>* tw1, const cpx<real>* tw2, const real* sl,
@@ -625,9 +627,16 @@ bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m
     return true;
     CESIM_P2(128) CESIM_P2(256) CESIM_P2(512) CESIM_P2(1024) CESIM_P2(2048) CESIM_P2(4096)
     CESIM_P2(8192)
-#undef CESIM_P2
-    default: return false;
+    default: break;
   }
+  if constexpr (sizeof(real) == 4) {
+    switch (t1) {
+      CESIM_P2(384) CESIM_P2(768) CESIM_P2(1536) CESIM_P2(3072) CESIM_P2(6144)
+      default: break;
+    }
+  }
+#undef CESIM_P2
+  return false;
 }
 
 template <typename real>

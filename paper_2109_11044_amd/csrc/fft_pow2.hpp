@@ -1,16 +1,18 @@
-// fft_pow2.hpp -- register-resident Stockham FFT for power-of-two lengths
-// known at compile time (the draw's hot path).
+// fft_pow2.hpp -- register-resident Stockham FFT for lengths T = 2^a or
+// T = 3 * 2^a known at compile time (the draw's hot path).
 //
-// Each thread owns E = 16 elements of one transform, its "home" positions
-// base + S h (h < 16, S = T / 16 threads per transform).  A stage of radix R
-// (R | 16) treats them as U = 16 / R butterflies j = base + S u with inputs
-// h = u + q U, applies the Stockham twiddles and an in-register radix-R DFT.
-// Its outputs belong at positions (j / Ns) Ns R + (j mod Ns) + q Ns; unless
-// the stage is the last one (whose outputs land on the home positions), they
-// are exchanged through LDS and every thread reloads its home positions.
-// Forward plans are [16, ..., 16, r] and inverse plans [r, 16, ..., 16]
-// (r = T / 16^k), so a forward transform followed by an inverse one needs no
-// exchange in between: pointwise scaling happens in registers.
+// Each thread owns E elements of one transform (E = 16, or 48 when 3 | T),
+// its "home" positions base + S h (h < E, S = T / E threads per
+// transform).  A stage of radix R (R | E) treats them as U = E / R
+// butterflies j = base + S u with inputs h = u + q U (positions j + q T / R),
+// applies the Stockham twiddles and an in-register radix-R DFT.  Its outputs
+// belong at positions (j / Ns) Ns R + (j mod Ns) + q Ns; unless the stage is
+// the last one (whose outputs land on the home positions), they are
+// exchanged through LDS and every thread reloads its home positions.
+// Forward plans are [16, ..., 16, r, 3] and inverse plans the reverse
+// (r = the remaining power of two, the 3 only when 3 | T), so a forward
+// transform followed by an inverse one needs no exchange in between:
+// pointwise scaling happens in registers.
 // Twiddles: w1 = table[k T / (Ns R)] from exp(-2 pi i t / T), higher powers
 // by binary powering (each a product of at most four rounded factors).
 #pragma once
@@ -21,14 +23,21 @@ namespace cesim {
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
+// Elements per thread for length T.
+template <int T>
+constexpr int p2_elems() { return T % 3 == 0 ? 48 : 16; }
+
 template <int T, bool INV>
 struct P2Plan {
-  static constexpr int L = ilog2c(T);
+  static constexpr bool THREE = T % 3 == 0;
+  static constexpr int L = ilog2c(THREE ? T / 3 : T);
   static constexpr int REM = L % 4;
-  static constexpr int NST = L / 4 + (REM ? 1 : 0);
-  static constexpr int radix(int s) {
-    return REM == 0 ? 16 : (INV ? (s == 0 ? (1 << REM) : 16) : (s == NST - 1 ? (1 << REM) : 16));
+  static constexpr int N16 = L / 4;
+  static constexpr int NST = N16 + (REM ? 1 : 0) + (THREE ? 1 : 0);
+  static constexpr int fwd_radix(int s) {
+    return s < N16 ? 16 : ((s == N16 && REM) ? (1 << REM) : 3);
   }
+  static constexpr int radix(int s) { return INV ? fwd_radix(NST - 1 - s) : fwd_radix(s); }
   static constexpr int ns(int s) {
     int n = 1;
     for (int i = 0; i < s; ++i) n *= radix(i);
@@ -115,12 +124,13 @@ struct ColLds {
 };
 
 template <typename real, int T, bool INV, int s, typename Lds>
-__device__ __forceinline__ void p2_stages(cpx<real> (&x)[16], int base,
+__device__ __forceinline__ void p2_stages(cpx<real> (&x)[p2_elems<T>()], int base,
                                           const cpx<real>* __restrict__ tw, const Lds& lds) {
   using PL = P2Plan<T, INV>;
   using C = cpx<real>;
+  constexpr int E = p2_elems<T>();
   if constexpr (s < PL::NST) {
-    constexpr int R = PL::radix(s), Ns = PL::ns(s), S = T / 16, U = 16 / R;
+    constexpr int R = PL::radix(s), Ns = PL::ns(s), S = T / E, U = E / R;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = base + S * u;
@@ -128,7 +138,7 @@ __device__ __forceinline__ void p2_stages(cpx<real> (&x)[16], int base,
 #pragma unroll
       for (int q = 0; q < R; ++q) v[q] = x[u + q * U];
       if constexpr (Ns > 1) {
-        const int k = j & (Ns - 1);
+        const int k = j % Ns;
         C w[R];
         powers<R>(tw[k * (T / (Ns * R))], w);
 #pragma unroll
@@ -143,13 +153,13 @@ __device__ __forceinline__ void p2_stages(cpx<real> (&x)[16], int base,
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = base + S * u;
-        const int ob = (j / Ns) * Ns * R + (j & (Ns - 1));
+        const int ob = (j / Ns) * Ns * R + j % Ns;
 #pragma unroll
         for (int q = 0; q < R; ++q) lds.store(ob + q * Ns, x[u + q * U]);
       }
       __syncthreads();
 #pragma unroll
-      for (int h = 0; h < 16; ++h) x[h] = lds.load(base + S * h);
+      for (int h = 0; h < E; ++h) x[h] = lds.load(base + S * h);
       p2_stages<real, T, INV, s + 1>(x, base, tw, lds);
     }
   }
@@ -157,15 +167,16 @@ __device__ __forceinline__ void p2_stages(cpx<real> (&x)[16], int base,
 
 // Whole transform on the home layout (input and output on home positions).
 template <typename real, int T, bool INV, typename Lds>
-__device__ __forceinline__ void p2_fft(cpx<real> (&x)[16], int base, const cpx<real>* __restrict__ tw,
-                                       const Lds& lds) {
+__device__ __forceinline__ void p2_fft(cpx<real> (&x)[p2_elems<T>()], int base,
+                                       const cpx<real>* __restrict__ tw, const Lds& lds) {
   p2_stages<real, T, INV, 0>(x, base, tw, lds);
 }
 
-// Launch shapes of the power-of-two kernels.
+// Launch shapes of the register-FFT kernels.
 template <int T>
 struct P2Rows {
-  static constexpr int S = T / 16;                    // threads per row
+  static constexpr int E = p2_elems<T>();
+  static constexpr int S = T / E;                     // threads per row
   static constexpr int ROWS = S >= 256 ? 1 : 256 / S;  // rows per workgroup
   static constexpr int NTHR = ROWS * S;
   static constexpr int LD = T + T / 16;               // padded row length
@@ -173,7 +184,8 @@ struct P2Rows {
 
 template <typename real, int T>
 struct P2Cols {
-  static constexpr int S = T / 16;
+  static constexpr int E = p2_elems<T>();
+  static constexpr int S = T / E;
   static constexpr int LD = T + T / 16;
   static constexpr int cap_thr = 1024 / S;
   static constexpr int cap_lds = (int)((160 * 1024) / (LD * sizeof(cpx<real>)));

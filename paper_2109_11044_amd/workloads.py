@@ -81,7 +81,7 @@ class Workload:
         return 1.0 / (self.m - 1)
 
     def obs_xy(self):
-        return locations(self.locs, self.n)
+        return locations(self.locs, self.n, self.extra.get("loc_seed", SEED_LOCATIONS))
 
 
 # Small exact case: exponential, 64^2 grid, 200 uniform points, 4x4 windows.

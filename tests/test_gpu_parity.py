@@ -58,6 +58,8 @@ def test_ladder_moves_past_negative_torus():
     (64, 128, 5, 0), (24, 0, 3, 7), (30, 75, 4, 1),          # small, radix 3 and 5
     (128, 256, 3, 0), (512, 1024, 2, 5),                     # power-of-two register path
     (1024, 2048, 3, 997),                                    # full-size torus of the benchmark
+    (128, 384, 3, 0), (256, 768, 2, 1), (512, 1536, 3, 2),   # 3 * 2^a: FP32 register path
+    (1024, 3072, 1, 0), (1024, 6144, 1, 4),
 ])
 def test_unconditional_draw_matches_oracle(prec, tol, m, torus, nreal, first):
     cov = (0.5, 1.0, 0.1)
