@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--workload", choices=["dm", "events64"], default="dm",
                     help="dm: the 1024^2 single-event workload; events64: 64 uneven events "
                          "run as one batch (one graph launch per step)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune launch shapes before the warm-up (one-off, reported as tune_ms)")
     ap.add_argument("--no-unbatched", action="store_true",
                     help="events64: skip the one-context-per-event comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -109,6 +111,13 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
         ctx.close()
         return st
 
+    if args.autotune:
+        t0 = time.perf_counter()
+        with cesim.Context(cov, grid, prec) as ctx:
+            ctx.set_param(cesim.PARAM_GEMM_SPLIT, 0 if args.split == "fp16" else 1)
+            ctx.offgrid(xy, wl.k)
+            ctx.autotune(batch, fields[:batch])
+        info["tune_ms"] = 1000.0 * (time.perf_counter() - t0)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -151,7 +160,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
     kernels.sort(key=lambda k: -k["ms_per_step"])
     return dict(ms_per_step=ms_step, value=R / (ms_step / 1000.0), kernels=kernels,
                 event_ms_per_step=ev0.elapsed_time(ev1) / args.steps, t1=info["t1"],
-                finite=finite, gamma_max=info.get("gamma_max"))
+                finite=finite, gamma_max=info.get("gamma_max"), tune_ms=info.get("tune_ms"))
 
 
 def recorded_traffic(stage, workload):
@@ -243,7 +252,7 @@ def events_main(args, torch, cesim, workloads):
     R = sum(ev["nreal"] for ev in evs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b = cesim.Batch(evs, prec)
+    b = cesim.Batch(evs, prec, autotune=args.autotune)
     plan_ms = 1000.0 * (time.perf_counter() - t0)
     tori = [b.info(e)["t1"] for e in range(len(evs))]
     for w in range(args.warmup):
@@ -274,7 +283,8 @@ def events_main(args, torch, cesim, workloads):
                    "tori": sorted(set(tori)), "stations_total": sum(wl.n for wl in table),
                    "per_event": [[wl.m, t, wl.n] for wl, t in zip(table, tori)]},
         "events_per_s": len(evs) / (ms_step / 1000.0),
-        "plan_ms": plan_ms, "graph_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
+        "plan_ms": plan_ms, "autotuned_in_plan": bool(args.autotune),
+        "graph_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
         "finite": finite,
     }
     if not args.no_unbatched:

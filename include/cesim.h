@@ -222,7 +222,14 @@ const char* cesim_status_string(cesim_status s);
 
 /* Launch-shape parameters (performance only; results do not change):
  *   CESIM_PARAM_GEMM_NODE_FRAGMENTS: 32-node fragments per wave in the mixed
- *     cross-covariance GEMM, 1 (default) or 2.
+ *     cross-covariance GEMM, 1 or 2; 0 (default) takes the tuning table's
+ *     choice for the problem's shape, else 1.
+ *   CESIM_PARAM_DRAW_ROWS_FWD, CESIM_PARAM_DRAW_COLS, CESIM_PARAM_DRAW_ROWS_INV:
+ *     torus rows per workgroup of draw pass 1, columns per workgroup of
+ *     pass 2, rows per workgroup of pass 3 on the register-FFT path
+ *     (square tori of 2^a from 128 to 8192, and of 3 * 2^a from 384 to 6144
+ *     in MIXED precision); powers of two, clamped to each kernel's largest
+ *     shape; 0 (default) takes the tuning table's choice, else the largest.
  *   CESIM_PARAM_DRAW_CHUNK_PAIRS: realization pairs per launch of the draw
  *     passes (bounds the pair buffer); 0 (default) chooses up to 2 GiB.
  *   CESIM_PARAM_GEMM_SPLIT (changes rounding, not the method): half type of
@@ -235,7 +242,34 @@ const char* cesim_status_string(cesim_status s);
  *     counter of the torus noise and of xi, >= 0 (default 0); a context with
  *     event id e draws exactly what event e of a batch draws. */
 #define CESIM_PARAM_EVENT_ID 4
+#define CESIM_PARAM_DRAW_ROWS_FWD 5
+#define CESIM_PARAM_DRAW_COLS 6
+#define CESIM_PARAM_DRAW_ROWS_INV 7
 cesim_status ce_set_param(cesim_ctx ctx, int param, int value);
+
+/* ---- launch-shape autotuning ----
+ * ce_autotune times the candidate tile shapes of the three draw passes (on
+ * the register-FFT path: the largest shape and three successively halved
+ * ones, each pass timed on its own with HIP events) and, on the MIXED path
+ * after offgrid_nnkrige, 1 or 2 node fragments of the grid GEMM, on
+ * min(nreal, 64) realizations written into fields_dev (caller-owned,
+ * [nreal][m2][m1]; its contents and the coefficients of the last
+ * condition() are overwritten).  The fastest shapes go into a process-wide
+ * table keyed by precision and torus size (draw) and by split type,
+ * smoothness, grid size, observation count / 512 and realizations rounded
+ * up to 256 (GEMM); contexts and batches use table entries unless a
+ * parameter above is set.  No result depends on these shapes.  Explicit
+ * parameters of ctx are left as they were.  Synchronises. */
+cesim_status ce_autotune(cesim_ctx ctx, int nreal, void* fields_dev);
+
+/* The tuning table as JSON lines {"key": "...", "v": [a, b, c]}: save
+ * writes every entry; load adds or replaces entries and fails with
+ * INVALID_ARG on a line it cannot read or a file it cannot open (entries
+ * read before that line are kept). */
+cesim_status cesim_tune_save(const char* path);
+cesim_status cesim_tune_load(const char* path);
+int cesim_tune_entries(void);
+void cesim_tune_clear(void);
 
 /* ---- batches of independent events ----
  * One event is the whole conditional simulation above (Section 2 with the
@@ -275,8 +309,11 @@ typedef struct cesim_batch_s* cesim_batch;
  * kept, *out is NULL and the first failure is returned.  The event table and
  * its host arrays may be freed after the call; the fields buffers must stay
  * allocated until cesim_batch_destroy. */
+#define CESIM_BATCH_AUTOTUNE 1   /* flags: run ce_autotune (below) on every event
+                                    whose shapes the tuning table lacks, before
+                                    the capture (overwrites its fields buffer) */
 cesim_status cesim_batch_create(const cesim_event* events, int nevents,
-                                cesim_precision prec, void* hip_stream,
+                                cesim_precision prec, void* hip_stream, int flags,
                                 cesim_status* event_status, cesim_batch* out);
 
 /* Runs every event of the batch once, asynchronously on the batch's stream,

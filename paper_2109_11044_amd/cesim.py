@@ -27,14 +27,20 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "cesim_set_default_timing", "ce_set_timing", "ce_get_stage_times",
            "cesim_stage_name", "cesim_release_cached_memory", "ce_set_param",
            "cesim_batch_create", "cesim_batch_run", "cesim_batch_get_info",
-           "cesim_batch_destroy", "cesim_run_events"]
+           "cesim_batch_destroy", "cesim_run_events", "ce_autotune",
+           "cesim_tune_save", "cesim_tune_load", "cesim_tune_entries", "cesim_tune_clear"]
 PARAM_GEMM_NODE_FRAGMENTS = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
 PARAM_EVENT_ID = 4
+PARAM_DRAW_ROWS_FWD = 5
+PARAM_DRAW_COLS = 6
+PARAM_DRAW_ROWS_INV = 7
+BATCH_AUTOTUNE = 1
 NUM_STAGES = 12
 VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",
-                "cesim_stage_name", "cesim_release_cached_memory", "cesim_batch_destroy")
+                "cesim_stage_name", "cesim_release_cached_memory", "cesim_batch_destroy",
+                "cesim_tune_clear")
 
 
 class CesimError(RuntimeError):
@@ -117,12 +123,18 @@ def lib():
     L.cesim_release_cached_memory.argtypes = []
     L.cesim_release_cached_memory.restype = None
     ip = ctypes.POINTER(ctypes.c_int)
-    L.cesim_batch_create.argtypes = [ctypes.POINTER(Event), i, i, vp, ip, ctypes.POINTER(vp)]
+    L.cesim_batch_create.argtypes = [ctypes.POINTER(Event), i, i, vp, i, ip, ctypes.POINTER(vp)]
     L.cesim_batch_run.argtypes = [vp, i]
     L.cesim_batch_get_info.argtypes = [vp, i, ctypes.POINTER(Info)]
     L.cesim_batch_destroy.argtypes = [vp]
     L.cesim_batch_destroy.restype = None
     L.cesim_run_events.argtypes = [ctypes.POINTER(Event), i, i, vp, ip]
+    L.ce_autotune.argtypes = [vp, i, vp]
+    L.cesim_tune_save.argtypes = [ctypes.c_char_p]
+    L.cesim_tune_load.argtypes = [ctypes.c_char_p]
+    L.cesim_tune_entries.argtypes = []
+    L.cesim_tune_clear.argtypes = []
+    L.cesim_tune_clear.restype = None
     for name in EXPORTS:
         if name not in VOID_EXPORTS:
             getattr(L, name).restype = i
@@ -186,6 +198,22 @@ def set_default_timing(enable):
 
 def release_cached_memory():
     lib().cesim_release_cached_memory()
+
+
+def tune_save(path):
+    _check(lib().cesim_tune_save(os.fsencode(path)), "cesim_tune_save")
+
+
+def tune_load(path):
+    _check(lib().cesim_tune_load(os.fsencode(path)), "cesim_tune_load")
+
+
+def tune_entries():
+    return lib().cesim_tune_entries()
+
+
+def tune_clear():
+    lib().cesim_tune_clear()
 
 
 class Context:
@@ -265,6 +293,13 @@ class Context:
         _check(lib().ce_get_info(self._h, ctypes.byref(inf)), "ce_get_info")
         return {f: getattr(inf, f) for f, _ in Info._fields_}
 
+    def autotune(self, nreal, fields):
+        """Tune the launch shapes for this context's problem (overwrites
+        ``fields``); the choice goes into the process-wide table."""
+        self._fields_check(fields, nreal)
+        _check(lib().ce_autotune(self._h, int(nreal), ctypes.c_void_p(fields.data_ptr())),
+               "ce_autotune")
+
     def set_param(self, param, value):
         _check(lib().ce_set_param(self._h, int(param), int(value)), "ce_set_param")
 
@@ -323,7 +358,7 @@ class Batch:
     Field tensors are allocated here ([nreal, m2, m1]; float64 for "fp64",
     float32 for "mixed") and overwritten by every run."""
 
-    def __init__(self, events, precision="fp64", stream=None):
+    def __init__(self, events, precision="fp64", stream=None, autotune=False):
         import torch
         self._torch = torch
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -349,7 +384,8 @@ class Batch:
         st = (ctypes.c_int * ne)()
         h = ctypes.c_void_p()
         rc = lib().cesim_batch_create(table, ne, PREC[precision],
-                                      ctypes.c_void_p(stream.cuda_stream), st, ctypes.byref(h))
+                                      ctypes.c_void_p(stream.cuda_stream),
+                                      BATCH_AUTOTUNE if autotune else 0, st, ctypes.byref(h))
         self.event_status = [STATUS_NAMES.get(v, str(v)) for v in st]
         if rc != OK:
             raise BatchError(rc, "cesim_batch_create", self.event_status)

@@ -255,8 +255,17 @@ cesim_status ce_set_param(cesim_ctx c, int param, int value) {
   if (!c) return CESIM_ERR_INVALID_ARG;
   switch (param) {
     case CESIM_PARAM_GEMM_NODE_FRAGMENTS:
-      if (value != 1 && value != 2) return CESIM_ERR_INVALID_ARG;
+      if (value < 0 || value > 2) return CESIM_ERR_INVALID_ARG;
       c->gemm_nf = value;
+      return CESIM_OK;
+    case CESIM_PARAM_DRAW_ROWS_FWD:
+    case CESIM_PARAM_DRAW_ROWS_INV:
+      if (value < 0 || (value & (value - 1))) return CESIM_ERR_INVALID_ARG;
+      (param == CESIM_PARAM_DRAW_ROWS_FWD ? c->draw_force.rows1 : c->draw_force.rows3) = value;
+      return CESIM_OK;
+    case CESIM_PARAM_DRAW_COLS:
+      if (value < 0 || (value & (value - 1))) return CESIM_ERR_INVALID_ARG;
+      c->draw_force.lcp2 = value == 0 ? -1 : __builtin_ctz((unsigned)value);
       return CESIM_OK;
     case CESIM_PARAM_GEMM_SPLIT:
       if (value != 0 && value != 1) return CESIM_ERR_INVALID_ARG;

@@ -8,7 +8,8 @@
 //   local-Kriging setup, upload of the observed values, phi = sqrt(tau^2 +
 //   gamma); then one grouped blocked Cholesky over all events (step kb
 //   factors diagonal block kb of every system at once); buffers for every
-//   later step are reserved here.
+//   later step are reserved here; optionally the launch shapes of shapes not
+//   yet in the tuning table are tuned.
 // Run (cesim_batch_run, asynchronous): one graph holding, for every event,
 //   the CE draw, the synthetic observations and right-hand sides, the
 //   grouped forward / backward solves of all events, and the grid GEMM.
@@ -89,7 +90,7 @@ cesim_status record_run(cesim_batch b) {
   return CESIM_OK;
 }
 
-cesim_status plan(cesim_batch b, cesim_status* status) {
+cesim_status plan(cesim_batch b, cesim_status* status, int flags) {
   const int ne = (int)b->ev.size();
   std::vector<double> tau2(ne);
   // per-event set-up: ladder, local Kriging, values, phi
@@ -152,6 +153,10 @@ cesim_status plan(cesim_batch b, cesim_status* status) {
     c->first_real = ev.first_real;
     c->nreal = ev.nreal;
   }
+  if (flags & CESIM_BATCH_AUTOTUNE)
+    for (int e = 0; e < ne; ++e)
+      if (!tune_has_entries(b->ctx[e], b->ev[e].nreal))
+        CESIM_TRY(ce_autotune(b->ctx[e], b->ev[e].nreal, b->ev[e].fields));
   CESIM_TRY(chol_solve_batch_plan(b->ctx, X, R, b->solve));
   CESIM_TRY(b->solve.upload(b->own));
   // capture the run
@@ -174,10 +179,11 @@ cesim_status plan(cesim_batch b, cesim_status* status) {
 extern "C" {
 
 cesim_status cesim_batch_create(const cesim_event* events, int nevents, cesim_precision prec,
-                                void* hip_stream, cesim_status* event_status, cesim_batch* out) {
+                                void* hip_stream, int flags, cesim_status* event_status,
+                                cesim_batch* out) {
   if (!out) return CESIM_ERR_INVALID_ARG;
   *out = nullptr;
-  if (!events || nevents < 1) return CESIM_ERR_INVALID_ARG;
+  if (!events || nevents < 1 || (flags & ~CESIM_BATCH_AUTOTUNE)) return CESIM_ERR_INVALID_ARG;
   if (prec != CESIM_PREC_FP64 && prec != CESIM_PREC_MIXED) return CESIM_ERR_INVALID_ARG;
   cesim_status first = CESIM_OK;
   for (int e = 0; e < nevents; ++e) {
@@ -199,7 +205,7 @@ cesim_status cesim_batch_create(const cesim_event* events, int nevents, cesim_pr
     return CESIM_ERR_HIP;
   }
   b->work.stream = b->roff.stream = b->solve.dev.stream = b->own;
-  const cesim_status st = plan(b, event_status);
+  const cesim_status st = plan(b, event_status, flags);
   for (auto& ev : b->ev) {
     ev.obs_xy = nullptr;
     ev.z = nullptr;
@@ -235,7 +241,7 @@ void cesim_batch_destroy(cesim_batch b) { destroy_batch(b); }
 cesim_status cesim_run_events(const cesim_event* events, int nevents, cesim_precision prec,
                               void* hip_stream, cesim_status* event_status) {
   cesim_batch b = nullptr;
-  CESIM_TRY(cesim_batch_create(events, nevents, prec, hip_stream, event_status, &b));
+  CESIM_TRY(cesim_batch_create(events, nevents, prec, hip_stream, 0, event_status, &b));
   const cesim_status st = cesim_batch_run(b, 0);
   destroy_batch(b);              // synchronises the stream first
   return st;

@@ -201,7 +201,8 @@ k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int p = blockIdx.y;
-  const int j0 = blockIdx.x * G::ROWS;
+  const int rows = blockDim.x / G::S;
+  const int j0 = blockIdx.x * rows;
   const int pg = pair0 + p;
   const int r0 = key.base() + 2 * pg;
   const bool has1 = 2 * pg + 1 < nreal;
@@ -209,7 +210,7 @@ k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict
   // Philox blocks of 4 consecutive elements; T is a multiple of 4, so a
   // block never straddles two rows.
   constexpr int BPR = T / 4;
-  for (int blk = threadIdx.x; blk < G::ROWS * BPR; blk += G::NTHR) {
+  for (int blk = threadIdx.x; blk < rows * BPR; blk += blockDim.x) {
     const int b = blk / BPR, i0 = (blk % BPR) * 4;
     if (j0 + b >= t2) continue;
     const uint32_t gb = (uint32_t)((((long)(j0 + b)) * T + i0) >> 2);
@@ -245,25 +246,26 @@ k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict
 template <typename real, int T>
 __global__ void __launch_bounds__((P2Cols<real, T>::NTHR))
 k_p2_cols(cpx<real>* __restrict__ buf, int t1, int rows_out, const cpx<real>* __restrict__ tw,
-          const real* __restrict__ sl) {
+          const real* __restrict__ sl, int lcp) {
   using C = cpx<real>;
   using G = P2Cols<real, T>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int p = blockIdx.y;
-  const int c = threadIdx.x % G::CP, base = threadIdx.x / G::CP;
+  const int cp = 1 << lcp;
+  const int c = threadIdx.x & (cp - 1), base = threadIdx.x >> lcp;
   // Workgroups are dealt to the 8 XCDs round-robin; when the panel count is
   // a multiple of 8, panels are renumbered so that one XCD takes adjacent
   // panels in turn and the halves of each cache line meet in its L2.
   int panel = blockIdx.x;
   if ((gridDim.x & 7) == 0) panel = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-  const int col = panel * G::CP + c;
+  const int col = panel * cp + c;
   const bool ok = col < t1;
   C* colp = buf + (size_t)p * T * t1 + col;
   C x[G::E];
 #pragma unroll
   for (int h = 0; h < G::E; ++h) x[h] = ok ? colp[(size_t)(base + G::S * h) * t1] : C{0, 0};
-  const ColLds<C, G::CP> cl{lds, c};
+  const ColLds<C> cl{lds, c, lcp};
   p2_fft<real, T, false>(x, base, tw, cl);
 #pragma unroll
   for (int h = 0; h < G::E; ++h) {
@@ -292,7 +294,7 @@ k_p2_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields,
   C* lds = reinterpret_cast<C*>(smem);
   const int p = blockIdx.y;
   const int b = threadIdx.x / G::S, base = threadIdx.x % G::S;
-  const int j = blockIdx.x * G::ROWS + b;
+  const int j = blockIdx.x * (blockDim.x / G::S) + b;
   const bool ok = j < m2;
   const C* in = buf + ((size_t)p * t2 + (ok ? j : 0)) * T;
   C x[G::E];
@@ -573,37 +575,59 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
 
 namespace {
 
+// Tile shape of the register path: rows per workgroup of passes 1 and 3 and
+// log2 of the columns per workgroup of pass 2, clamped to each kernel's
+// maximum (results do not depend on it).
+template <typename real, int T1, int T2>
+DrawShape clamp_shape(DrawShape d) {
+  using GR = P2Rows<T1>;
+  using GC = P2Cols<real, T2>;
+  auto fix_rows = [](int r) {
+    int v = GR::ROWS;
+    if (r > 0) while (v > 1 && v > r) v >>= 1;
+    return v;
+  };
+  d.rows1 = fix_rows(d.rows1);
+  d.rows3 = fix_rows(d.rows3);
+  const int lmax = ilog2c(GC::CP);
+  d.lcp2 = (d.lcp2 < 0 || d.lcp2 > lmax) ? lmax : d.lcp2;
+  return d;
+}
+
 template <typename real, int T1, int T2>
 cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np, const cpx<real>* tw1,
                            const cpx<real>* tw2, const real* sl, const NoiseKey& key, int nreal,
-                           int pair0, StageTimer& tm, hipStream_t s) {
+                           int pair0, const DrawShape& shape, StageTimer& tm, hipStream_t s) {
   using GR = P2Rows<T1>;
   using GC = P2Cols<real, T2>;
-  const size_t lr = sizeof(cpx<real>) * GR::ROWS * GR::LD;
-  const size_t lc = sizeof(cpx<real>) * GC::CP * GC::LD;
+  const DrawShape d = clamp_shape<real, T1, T2>(shape);
+  const int cp = 1 << d.lcp2;
+  const size_t lr1 = sizeof(cpx<real>) * d.rows1 * GR::LD;
+  const size_t lr3 = sizeof(cpx<real>) * d.rows3 * GR::LD;
+  const size_t lc = sizeof(cpx<real>) * cp * GC::LD;
   int tr = tm.begin(ST_DRAW_PASS1, s);
   {
     auto k = k_p2_rows_noise<real, T1>;
-    allow_lds(k, lr);
-    k<<<dim3((T2 + GR::ROWS - 1) / GR::ROWS, np), GR::NTHR, lr, s>>>(buf, T2, tw1, key, nreal,
-                                                                    pair0);
+    allow_lds(k, sizeof(cpx<real>) * GR::ROWS * GR::LD);
+    k<<<dim3((T2 + d.rows1 - 1) / d.rows1, np), d.rows1 * GR::S, lr1, s>>>(buf, T2, tw1, key,
+                                                                           nreal, pair0);
     CESIM_HIP(hipGetLastError());
   }
   tm.end(tr, s);
   tr = tm.begin(ST_DRAW_PASS2, s);
   {
     auto k = k_p2_cols<real, T2>;
-    allow_lds(k, lc);
-    k<<<dim3((T1 + GC::CP - 1) / GC::CP, np), GC::NTHR, lc, s>>>(buf, T1, m2, tw2, sl);
+    allow_lds(k, sizeof(cpx<real>) * GC::CP * GC::LD);
+    k<<<dim3((T1 + cp - 1) / cp, np), cp * GC::S, lc, s>>>(buf, T1, m2, tw2, sl, d.lcp2);
     CESIM_HIP(hipGetLastError());
   }
   tm.end(tr, s);
   tr = tm.begin(ST_DRAW_PASS3, s);
   {
     auto k = k_p2_rows_inv_crop<real, T1>;
-    allow_lds(k, lr);
-    k<<<dim3((m2 + GR::ROWS - 1) / GR::ROWS, np), GR::NTHR, lr, s>>>(buf, fields, T2, m1, m2, tw1,
-                                                                    nreal, pair0);
+    allow_lds(k, sizeof(cpx<real>) * GR::ROWS * GR::LD);
+    k<<<dim3((m2 + d.rows3 - 1) / d.rows3, np), d.rows3 * GR::S, lr3, s>>>(buf, fields, T2, m1,
+                                                                           m2, tw1, nreal, pair0);
     CESIM_HIP(hipGetLastError());
   }
   tm.end(tr, s);
@@ -616,14 +640,14 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
 template <typename real>
 bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m2, int np,
                      const cpx<real>* tw1, const cpx<real>* tw2, const real* sl,
-                     const NoiseKey& key, int nreal, int pair0, StageTimer& tm,
-                     hipStream_t s, cesim_status& st) {
+                     const NoiseKey& key, int nreal, int pair0, const DrawShape& shape,
+                     StageTimer& tm, hipStream_t s, cesim_status& st) {
   if (t1 != t2) return false;
   switch (t1) {
 #define CESIM_P2(TT)                                                                        \
   case TT:                                                                                  \
     st = draw_chunk_p2<real, TT, TT>(buf, fields, m1, m2, np, tw1, tw2, sl, key, nreal, pair0, \
-                                     tm, s);                                                \
+                                     shape, tm, s);                                         \
     return true;
     CESIM_P2(128) CESIM_P2(256) CESIM_P2(512) CESIM_P2(1024) CESIM_P2(2048) CESIM_P2(4096)
     CESIM_P2(8192)
@@ -658,11 +682,12 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
   }
   const NoiseKey key{(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), first_real,
                      c->event_id, c->roff};
+  const DrawShape shape = draw_shape(c);
   for (int pair0 = 0; pair0 < npairs; pair0 += chunk) {
     const int np = std::min(chunk, npairs - pair0);
     cesim_status st = CESIM_OK;
     if (draw_chunk_pow2<real>(t1, t2, buf, fields, m1, m2, np, tw1, tw2, sl, key, nreal, pair0,
-                              c->timer, s, st)) {
+                              shape, c->timer, s, st)) {
       CESIM_TRY(st);
       continue;
     }
@@ -681,6 +706,30 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
 }
 
 }  // namespace
+
+bool register_draw_path(cesim_ctx c) {
+  if (c->t1 != c->t2) return false;
+  switch (c->t1) {
+    case 128: case 256: case 512: case 1024: case 2048: case 4096: case 8192: return true;
+    case 384: case 768: case 1536: case 3072: case 6144: return c->prec == CESIM_PREC_MIXED;
+    default: return false;
+  }
+}
+
+DrawShape draw_shape_limits(cesim_ctx c) {
+  const bool f64 = c->prec == CESIM_PREC_FP64;
+  switch (c->t1) {
+#define CESIM_LIM(TT) \
+  case TT: return f64 ? clamp_shape<double, TT, TT>(DrawShape{}) : clamp_shape<float, TT, TT>(DrawShape{});
+    CESIM_LIM(128) CESIM_LIM(256) CESIM_LIM(512) CESIM_LIM(1024) CESIM_LIM(2048) CESIM_LIM(4096)
+    CESIM_LIM(8192)
+#undef CESIM_LIM
+#define CESIM_LIM(TT) case TT: return clamp_shape<float, TT, TT>(DrawShape{});
+    CESIM_LIM(384) CESIM_LIM(768) CESIM_LIM(1536) CESIM_LIM(3072) CESIM_LIM(6144)
+#undef CESIM_LIM
+    default: return DrawShape{1, 0, 1};
+  }
+}
 
 size_t draw_pair_bytes(cesim_ctx c) {
   const size_t el = c->prec == CESIM_PREC_FP64 ? sizeof(double2) : sizeof(float2);

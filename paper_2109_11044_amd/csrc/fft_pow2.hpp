@@ -115,12 +115,14 @@ struct RowLds {
   __device__ __forceinline__ C load(int pos) const { return p[pos + (pos >> 4)]; }
   __device__ __forceinline__ void store(int pos, C v) const { p[pos + (pos >> 4)] = v; }
 };
-template <typename C, int CP>
-struct ColLds {
+template <typename C>
+struct ColLds {              // 2^lcp interleaved columns
   C* p;
-  int c;
-  __device__ __forceinline__ C load(int pos) const { return p[(pos + (pos >> 4)) * CP + c]; }
-  __device__ __forceinline__ void store(int pos, C v) const { p[(pos + (pos >> 4)) * CP + c] = v; }
+  int c, lcp;
+  __device__ __forceinline__ C load(int pos) const { return p[((pos + (pos >> 4)) << lcp) + c]; }
+  __device__ __forceinline__ void store(int pos, C v) const {
+    p[((pos + (pos >> 4)) << lcp) + c] = v;
+  }
 };
 
 template <typename real, int T, bool INV, int s, typename Lds>
@@ -172,7 +174,8 @@ __device__ __forceinline__ void p2_fft(cpx<real> (&x)[p2_elems<T>()], int base,
   p2_stages<real, T, INV, 0>(x, base, tw, lds);
 }
 
-// Launch shapes of the register-FFT kernels.
+// Largest launch shapes of the register-FFT kernels (the kernels take any
+// power-of-two number of rows or columns per workgroup up to these).
 template <int T>
 struct P2Rows {
   static constexpr int E = p2_elems<T>();

@@ -106,6 +106,13 @@ struct GroupedSeq {
   cesim_status launch(hipStream_t s) const;
 };
 
+// Tile shape of the register-FFT draw passes: rows per workgroup of passes
+// 1 and 3 (0: largest) and log2 of the columns per workgroup of pass 2
+// (-1: largest).  Results do not depend on it.
+struct DrawShape {
+  int rows1 = 0, lcp2 = -1, rows3 = 0;
+};
+
 struct TorusTables {
   Plan p1, p2;                      // plans along x (t1) and y (t2)
   DevBuf tw1_64, tw2_64, tw1_32, tw2_32;   // twiddles exp(-2 pi i t / T)
@@ -151,7 +158,8 @@ struct cesim_ctx_s {
   cesim::DevBuf info_dev;           // int flags
   std::vector<double> z_host_cached;
 
-  int gemm_nf = 1;                  // node fragments per wave in the mixed grid GEMM
+  int gemm_nf = 0;                  // node fragments per wave in the mixed grid GEMM (0: tuned / 1)
+  cesim::DrawShape draw_force;      // tile shape set with ce_set_param (wins over the table)
   int gemm_split = 0;               // 0: FP16 x3, 1: BF16 x3
   int draw_chunk_pairs = 0;         // pairs per draw launch (0: by a 2 GiB budget)
 
@@ -185,6 +193,13 @@ cesim_status chol_solve_batch_plan(const std::vector<cesim_ctx>& cs,
                                    GroupedSeq& seq);
 cesim_status make_plan(int T, Plan& p);
 size_t draw_pair_bytes(cesim_ctx c);
+// Launch shapes in force: explicit settings, else the tuning table, else
+// the largest shapes / one node fragment.
+DrawShape draw_shape(cesim_ctx c);
+int gemm_fragments(cesim_ctx c, int R);
+bool register_draw_path(cesim_ctx c);
+DrawShape draw_shape_limits(cesim_ctx c);   // largest shapes of the register path
+bool tune_has_entries(cesim_ctx c, int R);  // table holds this context's shapes
 int draw_chunk_pairs(cesim_ctx c, int nreal);
 cesim_status make_twiddles(int T, DevBuf& tw64, DevBuf& tw32, hipStream_t s);
 

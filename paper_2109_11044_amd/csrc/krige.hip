@@ -403,7 +403,7 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   const float2* S2 = c->obs_t32.as<float2>();
   const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
   const float fdx = (float)dx, fdy = (float)dy, fks = (float)ks;
-  const int nf = c->gemm_nf == 2 ? 2 : 1;
+  const int nf = gemm_fragments(c, R);
   dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
 #define CESIM_KS(NU, NF, H)                                                                     \
   k_krige_split3<NU, NF, H><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh), \

@@ -93,3 +93,25 @@ def test_setup_argument_errors_without_device():
     assert L.condition(None, None, 0.0, None) == 1
     assert L.cesim_status_string(2).decode().startswith("negative")
     L.ce_destroy(None)
+
+
+def test_tuning_table_save_load_round_trip(tmp_path):
+    cesim.tune_clear()
+    src = tmp_path / "in.jsonl"
+    src.write_text('{"key": "draw p1 2048x2048", "v": [4, 2, 8]}\n'
+                   '{"key": "gemm s0 nu0 M1048576 n10 R1024", "v": [2, 0, 0]}\n')
+    cesim.tune_load(str(src))
+    assert cesim.tune_entries() == 2
+    out = tmp_path / "out.jsonl"
+    cesim.tune_save(str(out))
+    assert sorted(out.read_text().splitlines()) == sorted(src.read_text().splitlines())
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"key": "draw p1 64x64", "v": [1, 1, 1]}\nnot json\n')
+    with pytest.raises(cesim.CesimError) as e:
+        cesim.tune_load(str(bad))
+    assert e.value.name == "INVALID_ARG"
+    assert cesim.tune_entries() == 3          # the line before the bad one is kept
+    with pytest.raises(cesim.CesimError):
+        cesim.tune_load(str(tmp_path / "missing.jsonl"))
+    cesim.tune_clear()
+    assert cesim.tune_entries() == 0
