@@ -306,55 +306,76 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
   return CESIM_OK;
 }
 
-// X[r][.] <- A^{-1} X[r][.] for r < R with the factor held in c->amat.
-cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
-  hipStream_t s = c->stream;
-  const int n = c->nobs;
-  const int nblk = (n + kNB - 1) / kNB;
+// The GEMMs of the forward (L Y = X) and backward (L^T X = Y) blocked
+// substitutions of one system, in order, as C(r, i) over realizations r:
+//   forward block kb:  X[r][k0+c]      <- sum_t X[r][k0+t] Linv[c][t]
+//                      X[r][k0+nbk+i]  -= sum_t X[r][k0+t] L[k0+nbk+i][k0+t]
+//   backward block kb: X[r][k0+c]      <- sum_t X[r][k0+t] Linv[t][c]
+//                      X[r][i]         -= sum_t X[r][k0+t] L[k0+t][i]   (i < k0)
+// The diagonal applications run in place: a workgroup holds all 64 columns
+// of its rows and reads them before it writes.  Forward step kb is entry
+// 2 kb (+1) of fwd, backward step kb (counted from the last block) of bwd.
+static void solve_step_lists(cesim_ctx c, double* X, int R, std::vector<std::vector<GemmArgs>>& fwd,
+                             std::vector<std::vector<GemmArgs>>& bwd) {
+  const int n = c->nobs, nblk = (n + kNB - 1) / kNB;
   const double* L = c->amat.as<double>();
   const double* D = c->dinv.as<double>();
+  fwd.assign(nblk, {});
+  bwd.assign(nblk, {});
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * kNB, nbk = std::min(kNB, n - k0), rest = n - k0 - nbk;
+    GemmArgs g;
+    g.M = R; g.N = nbk; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+    g.A = X + k0; g.sai = n; g.sak = 1;
+    g.B = D + (size_t)kb * kNB * kNB; g.sbk = 1; g.sbj = kNB;
+    g.C = X + k0; g.sci = n; g.scj = 1;
+    fwd[kb].push_back(g);
+    if (rest > 0) {
+      g.M = R; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = X + k0; g.sai = n; g.sak = 1;
+      g.B = L + (size_t)(k0 + nbk) * n + k0; g.sbk = 1; g.sbj = n;
+      g.C = X + k0 + nbk; g.sci = n; g.scj = 1;
+      fwd[kb].push_back(g);
+    }
+  }
+  for (int st = 0; st < nblk; ++st) {
+    const int kb = nblk - 1 - st, k0 = kb * kNB, nbk = std::min(kNB, n - k0);
+    GemmArgs g;
+    g.M = R; g.N = nbk; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
+    g.A = X + k0; g.sai = n; g.sak = 1;
+    g.B = D + (size_t)kb * kNB * kNB; g.sbk = kNB; g.sbj = 1;
+    g.C = X + k0; g.sci = n; g.scj = 1;
+    bwd[st].push_back(g);
+    if (k0 > 0) {
+      g.M = R; g.N = k0; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = X + k0; g.sai = n; g.sak = 1;
+      g.B = L + (size_t)k0 * n; g.sbk = n; g.sbj = 1;
+      g.C = X; g.sci = n; g.scj = 1;
+      bwd[st].push_back(g);
+    }
+  }
+}
+
+static void solve_steps(cesim_ctx c, double* X, int R, std::vector<GemmArgs>& out) {
+  std::vector<std::vector<GemmArgs>> fwd, bwd;
+  solve_step_lists(c, X, R, fwd, bwd);
+  for (auto& v : fwd) out.insert(out.end(), v.begin(), v.end());
+  for (auto& v : bwd) out.insert(out.end(), v.begin(), v.end());
+}
+
+// X[r][.] <- A^{-1} X[r][.] for r < R with the factor held in c->amat.
+// Every step is a GEMM with the realizations as its rows, so that each lane
+// of a tile writes consecutive observations of one realization (X is
+// [R][n], observation index fastest).
+cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
+  hipStream_t s = c->stream;
   const int tr = c->timer.begin(ST_SOLVE, s);
-  for (int kb = 0; kb < nblk; ++kb) {          // L Y = X
-    const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    {   // X[r][k0+c] <- sum_t Linv[c][t] X[r][k0+t]  (in place, see above)
-      GemmArgs g;
-      g.M = nbk; g.N = R; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
-      g.A = D + (size_t)kb * kNB * kNB; g.sai = kNB; g.sak = 1;
-      g.B = X + k0; g.sbk = 1; g.sbj = n;
-      g.C = X + k0; g.sci = 1; g.scj = n;
-      CESIM_TRY(gemm_f64(g, false, s));
-    }
-    const int rest = n - k0 - nbk;
-    if (rest <= 0) break;
-    GemmArgs g;
-    g.M = rest; g.N = R; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-    g.A = L + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
-    g.B = X + k0; g.sbk = 1; g.sbj = n;
-    g.C = X + k0 + nbk; g.sci = 1; g.scj = n;
-    CESIM_TRY(gemm_f64(g, false, s));
-  }
-  for (int kb = nblk - 1; kb >= 0; --kb) {     // L^T X = Y
-    const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    {   // X[r][k0+c] <- sum_t Linv[t][c] X[r][k0+t]
-      GemmArgs g;
-      g.M = nbk; g.N = R; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
-      g.A = D + (size_t)kb * kNB * kNB; g.sai = 1; g.sak = kNB;
-      g.B = X + k0; g.sbk = 1; g.sbj = n;
-      g.C = X + k0; g.sci = 1; g.scj = n;
-      CESIM_TRY(gemm_f64(g, false, s));
-    }
-    if (k0 == 0) break;
-    GemmArgs g;
-    g.M = k0; g.N = R; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-    g.A = L + (size_t)k0 * n; g.sai = 1; g.sak = n;      // (L^T)(i, k0+t) = L(k0+t, i)
-    g.B = X + k0; g.sbk = 1; g.sbj = n;
-    g.C = X; g.sci = 1; g.scj = n;
-    CESIM_TRY(gemm_f64(g, false, s));
-  }
+  std::vector<GemmArgs> steps;
+  solve_steps(c, X, R, steps);
+  for (const GemmArgs& g : steps) CESIM_TRY(gemm_f64(g, false, s));
   c->timer.end(tr, s);
   return CESIM_OK;
 }
-
 
 // ------------------------------------------------ grouped systems (batches)
 
@@ -477,64 +498,29 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
 
 // Record X_e <- A_e^{-1} X_e ([R_e][n_e], FP64) for every context with the
 // factors held in the contexts: forward steps aligned at the first block,
-// backward steps at each system's last block.  Same arithmetic per system
-// as chol_solve_device.
+// backward steps at each system's last block; each step's diagonal
+// applications of all systems form one grouped launch, their updates the
+// next.  Same GEMMs per system as chol_solve_device.
 cesim_status chol_solve_batch_plan(const std::vector<cesim_ctx>& cs,
                                    const std::vector<double*>& X, const std::vector<int>& R,
                                    GroupedSeq& seq) {
   const int ne = (int)cs.size();
+  std::vector<std::vector<std::vector<GemmArgs>>> fwd(ne), bwd(ne);
   int maxnb = 0;
-  for (cesim_ctx c : cs) maxnb = std::max(maxnb, (c->nobs + kNB - 1) / kNB);
-  for (int kb = 0; kb < maxnb; ++kb) {          // L Y = X
-    std::vector<GemmArgs> dg, up;
-    for (int e = 0; e < ne; ++e) {
-      cesim_ctx c = cs[e];
-      const int n = c->nobs, k0 = kb * kNB;
-      if (k0 >= n) continue;
-      const int nbk = std::min(kNB, n - k0), rest = n - k0 - nbk;
-      const double* L = c->amat.as<double>();
-      const double* D = c->dinv.as<double>();
-      GemmArgs g;
-      g.M = nbk; g.N = R[e]; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
-      g.A = D + (size_t)kb * kNB * kNB; g.sai = kNB; g.sak = 1;
-      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
-      g.C = X[e] + k0; g.sci = 1; g.scj = n;
-      dg.push_back(g);
-      if (rest <= 0) continue;
-      g.M = rest; g.N = R[e]; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-      g.A = L + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
-      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
-      g.C = X[e] + k0 + nbk; g.sci = 1; g.scj = n;
-      up.push_back(g);
-    }
-    seq.add_gemm(dg, false);
-    seq.add_gemm(up, false);
+  for (int e = 0; e < ne; ++e) {
+    solve_step_lists(cs[e], X[e], R[e], fwd[e], bwd[e]);
+    maxnb = std::max(maxnb, (int)fwd[e].size());
   }
-  for (int st = 0; st < maxnb; ++st) {          // L^T X = Y
-    std::vector<GemmArgs> dg, up;
-    for (int e = 0; e < ne; ++e) {
-      cesim_ctx c = cs[e];
-      const int n = c->nobs, nblk = (n + kNB - 1) / kNB, kb = nblk - 1 - st;
-      if (kb < 0) continue;
-      const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-      const double* L = c->amat.as<double>();
-      const double* D = c->dinv.as<double>();
-      GemmArgs g;
-      g.M = nbk; g.N = R[e]; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
-      g.A = D + (size_t)kb * kNB * kNB; g.sai = 1; g.sak = kNB;
-      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
-      g.C = X[e] + k0; g.sci = 1; g.scj = n;
-      dg.push_back(g);
-      if (k0 == 0) continue;
-      g.M = k0; g.N = R[e]; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-      g.A = L + (size_t)k0 * n; g.sai = 1; g.sak = n;
-      g.B = X[e] + k0; g.sbk = 1; g.sbj = n;
-      g.C = X[e]; g.sci = 1; g.scj = n;
-      up.push_back(g);
-    }
-    seq.add_gemm(dg, false);
-    seq.add_gemm(up, false);
-  }
+  for (int pass = 0; pass < 2; ++pass)
+    for (int st = 0; st < maxnb; ++st)
+      for (int part = 0; part < 2; ++part) {
+        std::vector<GemmArgs> g;
+        for (int e = 0; e < ne; ++e) {
+          const auto& lst = pass == 0 ? fwd[e] : bwd[e];
+          if (st < (int)lst.size() && part < (int)lst[st].size()) g.push_back(lst[st][part]);
+        }
+        seq.add_gemm(g, false);
+      }
   return CESIM_OK;
 }
 
