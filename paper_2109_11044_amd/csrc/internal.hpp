@@ -151,7 +151,10 @@ struct cesim_ctx_s {
   bool chol_valid = false;
   double chol_nugget = -1.0;
   cesim::DevBuf amat;               // n x n: K22 + tau^2 I, then its Cholesky factor
-  cesim::DevBuf dinv;               // inverses of the diagonal blocks
+  cesim::DevBuf dinv;               // inverses of the 64 x 64 diagonal blocks
+  cesim::DevBuf winv;               // inverses of the 256 x 256 diagonal blocks (solves)
+  cesim::DevBuf wtmp;               // products formed while building winv
+  cesim::DevBuf solve_tmp;          // [R][n]: second buffer of the substitutions
   cesim::DevBuf zdev;               // observed values
   cesim::DevBuf coef;               // [R][n] FP64: z - z*, then the coefficients
   cesim::DevBuf coef_b16;           // half-precision hi / lo coefficients + column scales (mixed)

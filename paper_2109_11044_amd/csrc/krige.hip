@@ -330,6 +330,7 @@ static void cov_map(const cesim_ctx c, double scale, double& ux, double& uxy, do
 cesim_status krige_reserve(cesim_ctx c, int R) {
   const int n = c->nobs;
   CESIM_TRY(c->coef.reserve(sizeof(double) * (size_t)n * R));
+  CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * (size_t)n * R));
   if (c->prec == CESIM_PREC_MIXED) {
     const int Rp = (R + 255) / 256 * 256;
     const int npad = (n + kKC - 1) / kKC * kKC;

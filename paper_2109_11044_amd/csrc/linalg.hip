@@ -18,7 +18,8 @@ namespace cesim {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-constexpr int kNB = 64;   // Cholesky / solve block size
+constexpr int kNB = 64;   // Cholesky block size
+constexpr int kSB = 256;  // substitution block size (4 Cholesky blocks)
 
 __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, double tau2,
                              double* __restrict__ A) {
@@ -30,132 +31,89 @@ __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, 
   A[(size_t)i * n + j] = v;
 }
 
-// Factor the nbk x nbk diagonal block at (k0, k0): 256 threads, thread t
-// holding the 4 x 4 register tile (rows 4 (t / 16) + i, columns
-// 4 (t % 16) + k).  Right-looking: at step j the pivot's owner forms
-// sqrt(d), the owners of column j scale it and publish it to LDS, and every
-// thread applies the rank-one update to its tile (two barriers per step, no
-// LDS read-modify-write).  The inverse of L is formed the same way on an
-// identity tile set.  Writes L back and the inverse to dinv (kNB x kNB,
-// row-major, zero above the diagonal; padded with the identity past nbk).
-__device__ __forceinline__ double tile_get(const double (&a)[4][4], int i, int k) {
-  double v = 0.0;
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) v = (ii == i && kk == k) ? a[ii][kk] : v;
-  return v;
+// Copies the inverse of each 64 x 64 diagonal factor block kb into its
+// place in the 256 x 256 block inverse W[kb / 4] (zeroed beforehand).
+__global__ void __launch_bounds__(256)
+k_place_diag(const double* __restrict__ D, int n, double* __restrict__ W) {
+  const int kb = blockIdx.x, big = kb / 4, i = kb % 4;
+  const int sz = min(kNB, n - kb * kNB);
+  double* w = W + (size_t)big * kSB * kSB + (size_t)(kNB * i) * kSB + kNB * i;
+  const double* d = D + (size_t)kb * kNB * kNB;
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int a = e / kNB, cc = e % kNB;
+    if (a < sz && cc < sz) w[(size_t)a * kSB + cc] = d[e];
+  }
 }
 
+// Factor the nbk x nbk diagonal block at (k0, k0) with one wave and form
+// the inverse of its factor.  Lane i holds row i in registers (every index
+// static, the loops unrolled).  Right-looking: at pivot j every lane posts
+// its column-j entry to LDS, reads the pivot and, for each k > j, the
+// broadcast entry of row k, and updates its row (no barrier beyond the two
+// that order the posts).  The inverse X = L^{-1} is then formed column by
+// column (lane c holds column c) by forward substitution on the identity
+// from an LDS copy of L.  Writes L back (lower part) and the inverse to
+// dinv (kNB x kNB, row-major, zero above the diagonal, the identity past
+// nbk); bit 2 of *info marks a non-positive pivot.
 __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, int k0, int nbk,
                                                 double* __restrict__ dinv, int* __restrict__ info) {
-  __shared__ double Lf[kNB][kNB + 1];
+  __shared__ double Ls[kNB][kNB + 1];
   __shared__ double col[kNB];
-  __shared__ double rdiag[kNB];                 // 1 / L[j][j]
-  __shared__ double pv;
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
-  const int r0 = 4 * ti, c0 = 4 * tj;
-  double a[4][4];
+  __shared__ double rinv[kNB];
+  const int i = threadIdx.x;
+  double a[kNB];
+  bool bad = false;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int k = 0; k < kNB; ++k)
+    a[k] = (i < nbk && k < nbk) ? A[(size_t)(k0 + i) * n + k0 + k] : (i == k ? 1.0 : 0.0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = r0 + i, c = c0 + k;
-      a[i][k] = (r < nbk && c < nbk) ? A[(size_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
-    }
   for (int j = 0; j < kNB; ++j) {
-    const int jt = j >> 2, jj = j & 3;
-    if (ti == jt && tj == jt) {
-      const double d = tile_get(a, jj, jj);
-      if (j < nbk && !(d > 0.0)) atomicOr(info, 2);
-      const double sq = sqrt(d);
-      pv = sq;
-      rdiag[j] = 1.0 / sq;
-    }
+    col[i] = a[j];                        // column j, not yet scaled
     __syncthreads();
-    const double piv = pv, rinv = rdiag[j];
-    if (tj == jt) {               // column j: L[r][j] = a[r][j] / piv (r > j), piv on the diagonal
+    const double d = col[j];
+    bad |= (j < nbk && !(d > 0.0));
+    const double piv = sqrt(d), r = 1.0 / piv;
+    a[j] = (i > j) ? a[j] * r : (i == j ? piv : 0.0);
+    const double lij = a[j] * r;          // L[i][j] / L[j][j]: pairs with unscaled col[k]
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = r0 + i;
-        double v = tile_get(a, i, jj);
-        v = (r == j) ? piv : (r > j ? v * rinv : 0.0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (k == jj) a[i][k] = (r >= j) ? v : a[i][k];
-        col[r] = v;
-      }
+    for (int k = j + 1; k < kNB; ++k) {   // entries k > i of row i are never read
+      a[k] = fma(-lij, col[k], a[k]);
+      if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
+    rinv[j] = r;
     __syncthreads();
-    double cr[4], cc[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      cr[i] = col[r0 + i];
-      cc[i] = col[c0 + i];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (r0 + i > j && c0 + k > j) a[i][k] -= cr[i] * cc[k];
   }
-  // publish L (lower part; zero above the diagonal)
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = r0 + i, c = c0 + k;
-      Lf[r][c] = (c <= r) ? a[i][k] : 0.0;
-      if (r < nbk && c <= r) A[(size_t)(k0 + r) * n + k0 + c] = a[i][k];
-      a[i][k] = (r == c) ? 1.0 : 0.0;          // X = I, becomes L^{-1}
-    }
+  for (int k = 0; k < kNB; ++k) {
+    Ls[i][k] = (k <= i) ? a[k] : 0.0;
+    if (i < nbk && k <= i) A[(size_t)(k0 + i) * n + k0 + k] = a[k];
+  }
   __syncthreads();
-  // right-looking: row q of X /= L[q][q]; rows r > q: X[r] -= L[r][q] X[q]
+  double x[kNB];
+#pragma unroll
+  for (int r = 0; r < kNB; ++r) x[r] = (r == i) ? 1.0 : 0.0;
+#pragma unroll
   for (int q = 0; q < kNB; ++q) {
-    const int qt = q >> 2, qq = q & 3;
-    if (ti == qt) {
-      const double inv = rdiag[q];
+    x[q] *= rinv[q];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double v = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v = (i == qq) ? a[i][k] * inv : v;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i == qq) a[i][k] = v;
-        col[c0 + k] = v;
-      }
+    for (int r = q + 1; r < kNB; ++r) {
+      x[r] = fma(-Ls[r][q], x[q], x[r]);
+      if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
-    double xr[4], lr[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) xr[k] = col[c0 + k];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) lr[i] = Lf[r0 + i][q];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (r0 + i > q) a[i][k] -= lr[i] * xr[k];
-    __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = r0 + i, c = c0 + k;
-      dinv[r * kNB + c] = (c <= r) ? a[i][k] : 0.0;
-    }
+  for (int r = 0; r < kNB; ++r) dinv[r * kNB + i] = (r >= i) ? x[r] : 0.0;
+  if (bad && i == 0) atomicOr(info, 2);
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
              int* __restrict__ info) {
   potrf_diag_body(A, n, k0, nbk, dinv, info);
 }
 
 // One diagonal block of each of several systems: workgroup q takes d[q].
-__global__ void __launch_bounds__(256) k_potrf_diag_grp(const DiagDesc* __restrict__ d) {
+__global__ void __launch_bounds__(64) k_potrf_diag_grp(const DiagDesc* __restrict__ d) {
   const DiagDesc e = d[blockIdx.x];
   potrf_diag_body(e.A, e.n, e.k0, e.nbk, e.dinv, e.info);
 }
@@ -260,6 +218,54 @@ cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s) {
   return CESIM_OK;
 }
 
+// Inverses W_B of the 256 x 256 diagonal blocks of the factor of every
+// context, for the substitutions.  With the 64-block inverses D_i on its
+// diagonal, block row i of W_B is W_{i,0:i} = -D_i (L_{i,0:i} W_{0:i,0:i})
+// (block forward substitution on the identity); rows i = 1, 2, 3 in turn,
+// each as two grouped GEMMs over all blocks of all contexts.  Synchronises.
+static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s) {
+  std::vector<std::vector<GemmArgs>> lv(6);
+  for (cesim_ctx c : cs) {
+    const int n = c->nobs, nblk = (n + kNB - 1) / kNB, nbig = (n + kSB - 1) / kSB;
+    CESIM_TRY(c->winv.reserve(sizeof(double) * (size_t)nbig * kSB * kSB));
+    CESIM_TRY(c->wtmp.reserve(sizeof(double) * (size_t)nbig * kNB * (kSB - kNB)));
+    double* W = c->winv.as<double>();
+    CESIM_HIP(hipMemsetAsync(W, 0, sizeof(double) * (size_t)nbig * kSB * kSB, s));
+    k_place_diag<<<nblk, 256, 0, s>>>(c->dinv.as<double>(), n, W);
+    CESIM_HIP(hipGetLastError());
+    const double* L = c->amat.as<double>();
+    const double* D = c->dinv.as<double>();
+    for (int B = 0; B < nbig; ++B) {
+      const int K0 = B * kSB, nb = std::min(kSB, n - K0);
+      double* WB = W + (size_t)B * kSB * kSB;
+      double* TB = c->wtmp.as<double>() + (size_t)B * kNB * (kSB - kNB);
+      for (int i = 1; i * kNB < nb; ++i) {
+        const int si = std::min(kNB, nb - kNB * i);
+        GemmArgs g;        // T = L_{i,0:i} W_{0:i,0:i}
+        g.M = si; g.N = kNB * i; g.K = kNB * i; g.alpha = 1.0; g.beta = 0.0;
+        g.A = L + (size_t)(K0 + kNB * i) * n + K0; g.sai = n; g.sak = 1;
+        g.B = WB; g.sbk = kSB; g.sbj = 1;
+        g.C = TB; g.sci = kSB - kNB; g.scj = 1;
+        lv[2 * (i - 1)].push_back(g);
+        g.M = si; g.N = kNB * i; g.K = si; g.alpha = -1.0; g.beta = 0.0;   // W_{i,0:i} = -D_i T
+        g.A = D + (size_t)(4 * B + i) * kNB * kNB; g.sai = kNB; g.sak = 1;
+        g.B = TB; g.sbk = kSB - kNB; g.sbj = 1;
+        g.C = WB + (size_t)(kNB * i) * kSB; g.sci = kSB; g.scj = 1;
+        lv[2 * (i - 1) + 1].push_back(g);
+      }
+    }
+  }
+  GroupedSeq seq;
+  for (auto& v : lv) seq.add_gemm(v, false);
+  if (!seq.launches.empty()) {
+    CESIM_TRY(seq.upload(s));
+    CESIM_TRY(seq.launch(s));
+    CESIM_HIP(hipStreamSynchronize(s));
+    seq.dev.release();
+  }
+  return CESIM_OK;
+}
+
 // Factor A = K22 + tau^2 I in place (lower triangle).  Synchronises and
 // reports NOT_POSITIVE_DEFINITE on a non-positive pivot.
 cesim_status chol_factor_device(cesim_ctx c, double tau2) {
@@ -278,7 +284,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
   CESIM_HIP(hipGetLastError());
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
+    k_potrf_diag<<<1, 64, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
     CESIM_HIP(hipGetLastError());
     const int rest = n - k0 - nbk;
     if (rest <= 0) break;
@@ -298,59 +304,67 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
     g.C = A + (size_t)(k0 + nbk) * n + (k0 + nbk); g.sci = n; g.scj = 1;
     CESIM_TRY(gemm_f64(g, true, s));
   }
-  c->timer.end(tr, s);
   int hinfo[4];
   CESIM_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   CESIM_HIP(hipStreamSynchronize(s));
-  if (hinfo[0] & 2) return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+  if (hinfo[0] & 2) {
+    c->timer.end(tr, s);
+    return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+  }
+  CESIM_TRY(build_winv({c}, s));
+  c->timer.end(tr, s);
   return CESIM_OK;
 }
 
-// The GEMMs of the forward (L Y = X) and backward (L^T X = Y) blocked
-// substitutions of one system, in order, as C(r, i) over realizations r:
-//   forward block kb:  X[r][k0+c]      <- sum_t X[r][k0+t] Linv[c][t]
-//                      X[r][k0+nbk+i]  -= sum_t X[r][k0+t] L[k0+nbk+i][k0+t]
-//   backward block kb: X[r][k0+c]      <- sum_t X[r][k0+t] Linv[t][c]
-//                      X[r][i]         -= sum_t X[r][k0+t] L[k0+t][i]   (i < k0)
-// The diagonal applications run in place: a workgroup holds all 64 columns
-// of its rows and reads them before it writes.  Forward step kb is entry
-// 2 kb (+1) of fwd, backward step kb (counted from the last block) of bwd.
+// The GEMMs of the forward (L Y = X) and backward (L^T Z = Y) blocked
+// substitutions of one system, in order, with 256-wide blocks and their
+// inverses W (winv), as C(r, i) over realizations r (X, Y: [R][n]):
+//   forward block kb:  Y[r][K0+c]    = sum_t X[r][K0+t] W[c][t]
+//                      X[r][K0+nb+i] -= sum_t Y[r][K0+t] L[K0+nb+i][K0+t]
+//   backward block kb: X[r][K0+c]    = sum_t Y[r][K0+t] W[t][c]
+//                      Y[r][i]       -= sum_t X[r][K0+t] L[K0+t][i]   (i < K0)
+// X holds the right-hand sides and ends with the solution; no GEMM writes
+// what it reads.  Forward step kb is fwd[kb], backward step st (counted from
+// the last block) bwd[st].
 static void solve_step_lists(cesim_ctx c, double* X, int R, std::vector<std::vector<GemmArgs>>& fwd,
                              std::vector<std::vector<GemmArgs>>& bwd) {
-  const int n = c->nobs, nblk = (n + kNB - 1) / kNB;
+  const int n = c->nobs, nbig = (n + kSB - 1) / kSB;
   const double* L = c->amat.as<double>();
-  const double* D = c->dinv.as<double>();
-  fwd.assign(nblk, {});
-  bwd.assign(nblk, {});
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * kNB, nbk = std::min(kNB, n - k0), rest = n - k0 - nbk;
+  const double* W = c->winv.as<double>();
+  double* Y = c->solve_tmp.as<double>();
+  fwd.assign(nbig, {});
+  bwd.assign(nbig, {});
+  for (int kb = 0; kb < nbig; ++kb) {
+    const int K0 = kb * kSB, nb = std::min(kSB, n - K0), rest = n - K0 - nb;
+    const double* WB = W + (size_t)kb * kSB * kSB;
     GemmArgs g;
-    g.M = R; g.N = nbk; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
-    g.A = X + k0; g.sai = n; g.sak = 1;
-    g.B = D + (size_t)kb * kNB * kNB; g.sbk = 1; g.sbj = kNB;
-    g.C = X + k0; g.sci = n; g.scj = 1;
+    g.M = R; g.N = nb; g.K = nb; g.alpha = 1.0; g.beta = 0.0;
+    g.A = X + K0; g.sai = n; g.sak = 1;
+    g.B = WB; g.sbk = 1; g.sbj = kSB;
+    g.C = Y + K0; g.sci = n; g.scj = 1;
     fwd[kb].push_back(g);
     if (rest > 0) {
-      g.M = R; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-      g.A = X + k0; g.sai = n; g.sak = 1;
-      g.B = L + (size_t)(k0 + nbk) * n + k0; g.sbk = 1; g.sbj = n;
-      g.C = X + k0 + nbk; g.sci = n; g.scj = 1;
+      g.M = R; g.N = rest; g.K = nb; g.alpha = -1.0; g.beta = 1.0;
+      g.A = Y + K0; g.sai = n; g.sak = 1;
+      g.B = L + (size_t)(K0 + nb) * n + K0; g.sbk = 1; g.sbj = n;
+      g.C = X + K0 + nb; g.sci = n; g.scj = 1;
       fwd[kb].push_back(g);
     }
   }
-  for (int st = 0; st < nblk; ++st) {
-    const int kb = nblk - 1 - st, k0 = kb * kNB, nbk = std::min(kNB, n - k0);
+  for (int st = 0; st < nbig; ++st) {
+    const int kb = nbig - 1 - st, K0 = kb * kSB, nb = std::min(kSB, n - K0);
+    const double* WB = W + (size_t)kb * kSB * kSB;
     GemmArgs g;
-    g.M = R; g.N = nbk; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
-    g.A = X + k0; g.sai = n; g.sak = 1;
-    g.B = D + (size_t)kb * kNB * kNB; g.sbk = kNB; g.sbj = 1;
-    g.C = X + k0; g.sci = n; g.scj = 1;
+    g.M = R; g.N = nb; g.K = nb; g.alpha = 1.0; g.beta = 0.0;
+    g.A = Y + K0; g.sai = n; g.sak = 1;
+    g.B = WB; g.sbk = kSB; g.sbj = 1;
+    g.C = X + K0; g.sci = n; g.scj = 1;
     bwd[st].push_back(g);
-    if (k0 > 0) {
-      g.M = R; g.N = k0; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-      g.A = X + k0; g.sai = n; g.sak = 1;
-      g.B = L + (size_t)k0 * n; g.sbk = n; g.sbj = 1;
-      g.C = X; g.sci = n; g.scj = 1;
+    if (K0 > 0) {
+      g.M = R; g.N = K0; g.K = nb; g.alpha = -1.0; g.beta = 1.0;
+      g.A = X + K0; g.sai = n; g.sak = 1;
+      g.B = L + (size_t)K0 * n; g.sbk = n; g.sbj = 1;
+      g.C = Y; g.sci = n; g.scj = 1;
       bwd[st].push_back(g);
     }
   }
@@ -369,6 +383,7 @@ static void solve_steps(cesim_ctx c, double* X, int R, std::vector<GemmArgs>& ou
 // [R][n], observation index fastest).
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
   hipStream_t s = c->stream;
+  CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * (size_t)c->nobs * R));
   const int tr = c->timer.begin(ST_SOLVE, s);
   std::vector<GemmArgs> steps;
   solve_steps(c, X, R, steps);
@@ -420,7 +435,7 @@ cesim_status GroupedSeq::upload(hipStream_t s) {
 cesim_status GroupedSeq::launch(hipStream_t s) const {
   for (const Launch& l : launches) {
     if (l.kind == 0)
-      k_potrf_diag_grp<<<l.blocks, 256, 0, s>>>(d_diag + l.first);
+      k_potrf_diag_grp<<<l.blocks, 64, 0, s>>>(d_diag + l.first);
     else if (l.kind == 1)
       k_gemm_f64_grp<false><<<l.blocks, 256, 0, s>>>(d_gemm + l.first, d_pfx + l.pfx, l.count);
     else
@@ -487,13 +502,15 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
     CESIM_HIP(hipMemcpyAsync(&flags[4 * e], cs[e]->info_dev.p, sizeof(int) * 4,
                              hipMemcpyDeviceToHost, s));
   CESIM_HIP(hipStreamSynchronize(s));
+  std::vector<cesim_ctx> good;
   for (int e = 0; e < ne; ++e) {
     not_pd[e] = (flags[4 * e] & 2) ? 1 : 0;
     cs[e]->chol_valid = !not_pd[e];
     cs[e]->chol_nugget = tau2[e];
+    if (!not_pd[e]) good.push_back(cs[e]);
   }
   seq.dev.release();
-  return CESIM_OK;
+  return build_winv(good, s);
 }
 
 // Record X_e <- A_e^{-1} X_e ([R_e][n_e], FP64) for every context with the
