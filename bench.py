@@ -241,14 +241,12 @@ def events_main(args, torch, cesim, workloads):
     beside it on the same events (steady state, factorisations reused)."""
     prec = "mixed" if args.precision in ("both", "mixed") else "fp64"
     table = workloads.event_table(64)
-    evs = []
-    for e, wl in enumerate(table):
-        evs.append(dict(cov=cesim.make_cov(wl.nu, wl.sigma2, wl.range, wl.aniso_ratio,
-                                           wl.aniso_angle),
-                        grid=cesim.unit_square_grid(wl.m), obs_xy=wl.obs_xy(),
-                        z=workloads.iid_values(wl.n, wl.sigma2 + wl.tau2, seed=2000 + e),
-                        nugget=wl.tau2, k=wl.k, nreal=wl.nreal, first_real=0,
-                        seed=args.seed, event_id=e))
+    evs = [dict(cov=cesim.make_cov(d["nu"], d["sigma2"], d["range"], d["aniso_ratio"],
+                                   d["aniso_angle"]),
+                grid=cesim.unit_square_grid(d["m"]), obs_xy=d["obs_xy"], z=d["z"],
+                nugget=d["nugget"], k=d["k"], nreal=d["nreal"], first_real=0, seed=args.seed,
+                event_id=d["event_id"])
+           for d in workloads.event_inputs(table)]
     R = sum(ev["nreal"] for ev in evs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

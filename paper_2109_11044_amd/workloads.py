@@ -121,3 +121,17 @@ def event_table(nevents=64, seed=SEED_EVENTS):
             aniso_angle=float(rng.uniform(0.0, np.pi)),
             extra=dict(loc_seed=1000 + e)))
     return out
+
+
+def event_inputs(table, values_seed=2000):
+    """Per-event inputs of a batch built from ``event_table``: station
+    coordinates and iid observed values (seed values_seed + e), as plain
+    dicts of parameters and arrays."""
+    out = []
+    for e, wl in enumerate(table):
+        out.append(dict(nu=wl.nu, sigma2=wl.sigma2, range=wl.range,
+                        aniso_ratio=wl.aniso_ratio, aniso_angle=wl.aniso_angle,
+                        m=wl.m, obs_xy=wl.obs_xy(),
+                        z=iid_values(wl.n, wl.sigma2 + wl.tau2, seed=values_seed + e),
+                        nugget=wl.tau2, k=wl.k, nreal=wl.nreal, event_id=e))
+    return out
