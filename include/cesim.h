@@ -168,6 +168,10 @@ cesim_status offgrid_nnkrige(cesim_ctx ctx, int nobs, const double* obs_xy_host,
  *        (block, r, event id, 1)),
  *   B_r     = (K22 + nugget I)^{-1} (z - z*_r)        (FP64 Cholesky),
  *   v_r     = y_r + K12 B_r,  K12[g, i] = C(g - s_i).
+ * MIXED evaluates v_r as y_r + yhat - K12 (K22 + nugget I)^{-1} z*_r with
+ * the prediction yhat = K12 (K22 + nugget I)^{-1} z computed once in FP64
+ * (kept while the factor and z are unchanged) and the per-realization
+ * product in the half-precision split GEMM.
  * z_host: nobs observed values, host memory, copied.  nugget >= 0.  The
  * Cholesky factor of K22 + nugget I is kept and reused while the nugget and
  * the observation set are unchanged.  Errors: BAD_STATE (no offgrid_nnkrige
@@ -216,9 +220,10 @@ const char* cesim_status_string(cesim_status s);
  * eigenvalue check, draw pass 1 (noise + row FFT), draw pass 2 (column
  * FFT, scale, inverse column FFT), draw pass 3 (inverse row FFT + crop),
  * local-Kriging setup, observation Cholesky, synthetic observations and
- * right-hand sides, observation solves, bf16 split of the coefficients,
- * cross-covariance GEMM onto the grid. */
-#define CESIM_NUM_STAGES 12
+ * right-hand sides, observation solves, half-precision split of the
+ * coefficients, cross-covariance GEMM onto the grid, FP64 prediction from the
+ * observed values (MIXED only). */
+#define CESIM_NUM_STAGES 13
 
 /* Launch-shape parameters (performance only; results do not change):
  *   CESIM_PARAM_GEMM_NODE_FRAGMENTS: 32-node fragments per wave in the mixed

@@ -37,7 +37,7 @@ PARAM_DRAW_ROWS_FWD = 5
 PARAM_DRAW_COLS = 6
 PARAM_DRAW_ROWS_INV = 7
 BATCH_AUTOTUNE = 1
-NUM_STAGES = 12
+NUM_STAGES = 13
 VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",
                 "cesim_stage_name", "cesim_release_cached_memory", "cesim_batch_destroy",
                 "cesim_tune_clear")

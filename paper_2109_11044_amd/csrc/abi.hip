@@ -237,7 +237,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
-          &c->info_dev};
+          &c->chat, &c->yhat, &c->info_dev};
 }
 
 void ce_destroy(cesim_ctx c) {
@@ -313,7 +313,8 @@ const char* cesim_stage_name(int stage) {
   static const char* names[ST_COUNT] = {
       "setup_torus_base", "setup_fft2_fp64", "setup_eigen_check", "draw_noise_rowfft",
       "draw_colfft_scale_icolfft", "draw_irowfft_crop", "offgrid_local_krige",
-      "obs_cholesky", "synth_obs_rhs", "obs_solve", "coef_split_bf16", "krige_grid_gemm"};
+      "obs_cholesky", "synth_obs_rhs", "obs_solve", "coef_split_half", "krige_grid_gemm",
+      "krige_predict_fp64"};
   return (stage >= 0 && stage < ST_COUNT) ? names[stage] : "unknown";
 }
 
@@ -404,6 +405,7 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   const auto t_start = std::chrono::steady_clock::now();
   CESIM_HIP(hipStreamSynchronize(c->stream));   // host staging below is reused
   c->chol_valid = false;
+  c->yhat_valid = false;
   c->nobs = 0;
   c->obs_host.assign(xy, xy + 2 * (size_t)nobs);
   CESIM_TRY(c->obs_xy.reserve(sizeof(double) * 2 * nobs));
@@ -458,6 +460,7 @@ cesim_status condition(cesim_ctx c, const double* z, double nugget, void* fields
       std::memcmp(c->z_host_cached.data(), z, sizeof(double) * n) != 0) {
     CESIM_HIP(hipStreamSynchronize(c->stream));   // previous upload retired
     c->z_host_cached.assign(z, z + n);
+    c->yhat_valid = false;
     CESIM_TRY(c->zdev.reserve(sizeof(double) * n));
     CESIM_HIP(hipMemcpyAsync(c->zdev.p, c->z_host_cached.data(), sizeof(double) * n,
                              hipMemcpyHostToDevice, c->stream));
@@ -517,9 +520,7 @@ cesim_status offgrid_copy_weights(cesim_ctx c, int* corners, double* w, double* 
 cesim_status condition_copy_coefficients(cesim_ctx c, double* dev_out) {
   if (!c || !dev_out) return CESIM_ERR_INVALID_ARG;
   if (c->nobs < 1 || !c->coef.p) return CESIM_ERR_BAD_STATE;
-  CESIM_HIP(hipMemcpyAsync(dev_out, c->coef.p, sizeof(double) * (size_t)c->nobs * c->nreal,
-                           hipMemcpyDeviceToDevice, c->stream));
-  return CESIM_OK;
+  return copy_coefficients_device(c, dev_out);
 }
 
 cesim_status cesim_covariance_host(const cesim_cov* cov, int n, const double* hx,

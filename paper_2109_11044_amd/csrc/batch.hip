@@ -83,7 +83,8 @@ cesim_status record_run(cesim_batch b) {
     CESIM_TRY(ce_draw_device(c, ev.nreal, ev.seed, ev.first_real, ev.fields));
   }
   for (size_t e = 0; e < b->ctx.size(); ++e)
-    CESIM_TRY(lk_synth_rhs_device(b->ctx[e], b->ev[e].fields, b->ctx[e]->coef.as<double>()));
+    CESIM_TRY(lk_synth_rhs_device(b->ctx[e], b->ev[e].fields, b->ctx[e]->coef.as<double>(),
+                                  b->prec == CESIM_PREC_FP64));
   CESIM_TRY(b->solve.launch(b->own));
   for (size_t e = 0; e < b->ctx.size(); ++e)
     CESIM_TRY(krige_grid_device(b->ctx[e], b->ctx[e]->coef.as<double>(), b->ev[e].fields));
@@ -153,6 +154,8 @@ cesim_status plan(cesim_batch b, cesim_status* status, int flags) {
     c->first_real = ev.first_real;
     c->nreal = ev.nreal;
   }
+  if (b->prec == CESIM_PREC_MIXED)
+    for (int e = 0; e < ne; ++e) CESIM_TRY(predict_device(b->ctx[e]));
   if (flags & CESIM_BATCH_AUTOTUNE)
     for (int e = 0; e < ne; ++e)
       if (!tune_has_entries(b->ctx[e], b->ev[e].nreal))

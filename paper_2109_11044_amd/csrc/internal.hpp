@@ -52,7 +52,8 @@ struct DevBuf {
 // Stages timed with HIP events when timing is enabled on a context.
 enum Stage {
   ST_SETUP_BASE = 0, ST_SETUP_FFT, ST_SETUP_EIG, ST_DRAW_PASS1, ST_DRAW_PASS2, ST_DRAW_PASS3,
-  ST_LK_SETUP, ST_CHOL, ST_SYNTH_RHS, ST_SOLVE, ST_COEF_SPLIT, ST_KRIGE_GEMM, ST_COUNT
+  ST_LK_SETUP, ST_CHOL, ST_SYNTH_RHS, ST_SOLVE, ST_COEF_SPLIT, ST_KRIGE_GEMM, ST_PREDICT,
+  ST_COUNT
 };
 
 struct StageTimer {
@@ -149,6 +150,7 @@ struct cesim_ctx_s {
 
   // conditioning
   bool chol_valid = false;
+  bool yhat_valid = false;          // mixed path: chat and yhat match the factor and z
   double chol_nugget = -1.0;
   cesim::DevBuf amat;               // n x n: K22 + tau^2 I, then its Cholesky factor
   cesim::DevBuf dinv;               // inverses of the 64 x 64 diagonal blocks
@@ -158,6 +160,8 @@ struct cesim_ctx_s {
   cesim::DevBuf zdev;               // observed values
   cesim::DevBuf coef;               // [R][n] FP64: z - z*, then the coefficients
   cesim::DevBuf coef_b16;           // half-precision hi / lo coefficients + column scales (mixed)
+  cesim::DevBuf chat;               // mixed path: A^{-1} z, FP64 [n]
+  cesim::DevBuf yhat;               // mixed path: K12 A^{-1} z on the grid, FP32 [M]
   cesim::DevBuf info_dev;           // int flags
   std::vector<double> z_host_cached;
 
@@ -186,7 +190,9 @@ cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_rea
 cesim_status lk_setup_device(cesim_ctx c);
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields);
 cesim_status lk_phi_device(cesim_ctx c, double tau2);
-cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs);
+cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, bool with_z);
+cesim_status predict_device(cesim_ctx c);
+cesim_status copy_coefficients_device(cesim_ctx c, double* out);
 cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields);
 cesim_status krige_reserve(cesim_ctx c, int R);
 cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vector<double>& tau2,

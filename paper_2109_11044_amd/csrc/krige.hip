@@ -134,6 +134,39 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
   }
 }
 
+// Kriging prediction from the observed values, yhat[g] = sum_i C(g - s_i)
+// chat_i with chat = A^{-1} z (the term K12 (K22 + tau^2 I)^{-1} z of eq. (4),
+// common to every realization), in FP64, one grid node per thread, stations
+// staged through LDS.  The mixed path adds it to every realization and runs
+// its half-precision GEMM on the per-realization part only: with data that
+// the covariance does not explain well chat is large and K12 chat cancels
+// strongly, which half-precision operands and FP32 sums would not resolve.
+__global__ void __launch_bounds__(256)
+k_predict_f64(float* __restrict__ yhat, int m1, int M, const double* __restrict__ chat, int n,
+              const double2* __restrict__ st, double ux, double uxy, double uyx, double uy,
+              double dx, double dy, int nu_code, double sigma2) {
+  __shared__ double2 S[256];
+  __shared__ double Cv[256];
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int gg = min(g, M - 1);
+  const double gx = (double)(gg % m1) * dx, gy = (double)(gg / m1) * dy;
+  const double a = ux * gx + uxy * gy, b = uyx * gx + uy * gy;
+  double acc = 0.0;
+  for (int i0 = 0; i0 < n; i0 += 256) {
+    const int i = i0 + threadIdx.x;
+    __syncthreads();
+    S[threadIdx.x] = st[min(i, n - 1)];
+    Cv[threadIdx.x] = i < n ? chat[i] : 0.0;
+    __syncthreads();
+    const int cnt = min(256, n - i0);
+    for (int j = 0; j < cnt; ++j) {
+      const double hx = a - S[j].x, hy = b - S[j].y;
+      acc = fma(matern_rho(nu_code, sqrt(hx * hx + hy * hy)), Cv[j], acc);
+    }
+  }
+  if (g < M) yhat[g] = (float)(sigma2 * acc);
+}
+
 // ----------------------------------------------------------- mixed kernel
 constexpr int kKC = 32;     // observations per k-chunk of the mixed kernel
 
@@ -204,8 +237,9 @@ template <int NU, int NF, typename H>
 __global__ void __launch_bounds__(256, 3 - NF)
 k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
                const H* __restrict__ Bh, const H* __restrict__ Bl,
-               const float* __restrict__ colscale, int n, const float2* __restrict__ st,
-               float ux, float uxy, float uyx, float uy, float dx, float dy, float kscale) {
+               const float* __restrict__ colscale, const float* __restrict__ yhat, int n,
+               const float2* __restrict__ st, float ux, float uxy, float uyx, float uy, float dx,
+               float dy, float kscale) {
   using HV = typename HalfOps<H>::V;
   constexpr int TG = 128 * NF, TR = 256;
   __shared__ __align__(16) H Sh[2][TR * kKC];
@@ -301,12 +335,13 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
   for (int f = 0; f < NF; ++f) {
     const int gg = g0 + 32 * NF * wave + 32 * f + (lane & 31);
     if (gg >= M) continue;
+    const float yh = yhat[gg];
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int r = r0 + 32 * b + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (r < R) fields[(size_t)r * M + gg] += acc[f][b][e] * colscale[r];
+        if (r < R) fields[(size_t)r * M + gg] += fmaf(acc[f][b][e], colscale[r], yh);
       }
   }
 }
@@ -350,8 +385,11 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   }
   CESIM_TRY(lk_phi_device(c, nugget));
   CESIM_TRY(krige_reserve(c, R));
+  const bool mixed = c->prec == CESIM_PREC_MIXED;
+  if (mixed) CESIM_TRY(predict_device(c));
   double* X = c->coef.as<double>();
-  CESIM_TRY(lk_synth_rhs_device(c, fields, X));
+  // FP64: X = A^{-1} (z - z*_r); mixed: X = -A^{-1} z*_r (yhat carries z)
+  CESIM_TRY(lk_synth_rhs_device(c, fields, X, !mixed));
   CESIM_TRY(chol_solve_device(c, X, R));
   return krige_grid_device(c, X, fields);
 }
@@ -402,14 +440,15 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   tr = c->timer.begin(ST_KRIGE_GEMM, s);
   float* F = static_cast<float*>(fields);
   const float2* S2 = c->obs_t32.as<float2>();
+  const float* YH = c->yhat.as<float>();
   const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
   const float fdx = (float)dx, fdy = (float)dy, fks = (float)ks;
   const int nf = gemm_fragments(c, R);
   dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
 #define CESIM_KS(NU, NF, H)                                                                     \
   k_krige_split3<NU, NF, H><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh), \
-                                                 reinterpret_cast<const H*>(Hl), colscale, n, S2, \
-                                                 a, b, cc, d, fdx, fdy, fks)
+                                                 reinterpret_cast<const H*>(Hl), colscale, YH, n, \
+                                                 S2, a, b, cc, d, fdx, fdy, fks)
 #define CESIM_KS_NU(NF, H)                  \
   switch (c->covd.nu_code) {                \
     case 0: CESIM_KS(0, NF, H); break;      \
@@ -425,6 +464,47 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
 #undef CESIM_KS
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
+  return CESIM_OK;
+}
+
+// Mixed path: chat = A^{-1} z and yhat = K12 chat (FP64, stored FP32), once
+// per factorisation and set of observed values.
+__global__ void k_coef_out(const double* __restrict__ X, const double* __restrict__ chat, int n,
+                           size_t total, double* __restrict__ out) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < total) out[q] = X[q] + (chat ? chat[q % n] : 0.0);
+}
+
+// B_r = A^{-1} (z - z*_r) of the last condition() into out ([R][n]): X
+// itself on the FP64 path, chat + X on the mixed path.
+cesim_status copy_coefficients_device(cesim_ctx c, double* out) {
+  const size_t total = (size_t)c->nobs * c->nreal;
+  const double* ch = c->prec == CESIM_PREC_MIXED ? c->chat.as<double>() : nullptr;
+  k_coef_out<<<(unsigned)((total + 255) / 256), 256, 0, c->stream>>>(c->coef.as<double>(), ch,
+                                                                     c->nobs, total, out);
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+cesim_status predict_device(cesim_ctx c) {
+  if (c->yhat_valid) return CESIM_OK;
+  hipStream_t s = c->stream;
+  const int n = c->nobs, m1 = c->grid.m1, M = c->grid.m1 * c->grid.m2;
+  CESIM_TRY(c->chat.reserve(sizeof(double) * n));
+  CESIM_TRY(c->yhat.reserve(sizeof(float) * M));
+  CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * n));
+  CESIM_HIP(hipMemcpyAsync(c->chat.p, c->zdev.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  CESIM_TRY(chol_solve_device(c, c->chat.as<double>(), 1));
+  double ux, uxy, uyx, uy;
+  cov_map(c, 1.0, ux, uxy, uyx, uy);
+  const int tr = c->timer.begin(ST_PREDICT, s);
+  k_predict_f64<<<(M + 255) / 256, 256, 0, s>>>(c->yhat.as<float>(), m1, M, c->chat.as<double>(),
+                                                 n, c->obs_t64.as<double2>(), ux, uxy, uyx, uy,
+                                                 c->grid.dx, c->grid.dy, c->covd.nu_code,
+                                                 c->covd.sigma2);
+  CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
+  c->yhat_valid = true;
   return CESIM_OK;
 }
 

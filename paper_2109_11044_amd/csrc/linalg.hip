@@ -270,6 +270,7 @@ static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s) 
 // reports NOT_POSITIVE_DEFINITE on a non-positive pivot.
 cesim_status chol_factor_device(cesim_ctx c, double tau2) {
   hipStream_t s = c->stream;
+  c->yhat_valid = false;
   const int n = c->nobs;
   const int nblk = (n + kNB - 1) / kNB;
   CESIM_TRY(c->amat.reserve(sizeof(double) * (size_t)n * n));
@@ -459,6 +460,7 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
     cesim_ctx c = cs[e];
     const int n = c->nobs, nblk = (n + kNB - 1) / kNB;
     maxnb = std::max(maxnb, nblk);
+    c->yhat_valid = false;
     CESIM_TRY(c->amat.reserve(sizeof(double) * (size_t)n * n));
     CESIM_TRY(c->dinv.reserve(sizeof(double) * (size_t)nblk * kNB * kNB));
     CESIM_HIP(hipMemsetAsync(c->info_dev.p, 0, sizeof(int) * 4, s));

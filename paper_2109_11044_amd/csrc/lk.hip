@@ -92,7 +92,7 @@ __global__ void k_phi(const double* __restrict__ gam, int n, double tau2, double
   if (i < n) phi[i] = sqrt(tau2 + gam[i]);
 }
 
-// rhs[r][i] = z_i - (w_i . y_r[window_i] + phi_i xi_{r,i})
+// rhs[r][i] = z_i - (w_i . y_r[window_i] + phi_i xi_{r,i})   (z_i = 0 when z is null)
 template <typename F>
 __global__ void __launch_bounds__(256)
 k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict__ corners,
@@ -116,7 +116,7 @@ k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict
   if (word < 2) box_muller_f64(wd.x, wd.y, z0, z1);
   else box_muller_f64(wd.z, wd.w, z0, z1);
   const double xi = (word & 1) ? z1 : z0;
-  rhs[(size_t)r * n + i] = z[i] - (acc + phi[i] * xi);
+  rhs[(size_t)r * n + i] = (z ? z[i] : 0.0) - (acc + phi[i] * xi);
 }
 
 cesim_status lk_setup_device(cesim_ctx c) {
@@ -151,7 +151,8 @@ cesim_status lk_phi_device(cesim_ctx c, double tau2) {
   return CESIM_OK;
 }
 
-cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs) {
+cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, bool with_z) {
+  const double* z = with_z ? c->zdev.as<double>() : nullptr;
   const int n = c->nobs;
   dim3 grid((n + 255) / 256, c->nreal);
   const NoiseKey key{(uint32_t)(c->seed & 0xffffffffu), (uint32_t)(c->seed >> 32), c->first_real,
@@ -161,11 +162,11 @@ cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs) {
   if (c->prec == CESIM_PREC_FP64)
     k_synth_rhs<double><<<grid, 256, 0, c->stream>>>(
         static_cast<const double*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, key, rhs);
+        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key, rhs);
   else
     k_synth_rhs<float><<<grid, 256, 0, c->stream>>>(
         static_cast<const float*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), c->zdev.as<double>(), n, c->k, w2, key, rhs);
+        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key, rhs);
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, c->stream);
   return CESIM_OK;

@@ -155,8 +155,11 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
     if (st == CESIM_OK) store(draw_key(c), pick);
   }
   if (st == CESIM_OK && c->prec == CESIM_PREC_MIXED && c->nobs > 0) {
-    // the GEMM is timed at the full realization count (its key includes it)
+    // the GEMM is timed at the full realization count (its key includes it);
+    // its epilogue reads the prediction buffer, whose contents do not matter here
     st = krige_reserve(c, nreal);
+    if (st == CESIM_OK)
+      st = c->yhat.reserve(sizeof(float) * (size_t)c->grid.m1 * c->grid.m2);
     c->nreal = nreal;
     const int stg[3] = {ST_KRIGE_GEMM, -1, -1};
     double best = 1e300;
