@@ -141,28 +141,53 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
 // its half-precision GEMM on the per-realization part only: with data that
 // the covariance does not explain well chat is large and K12 chat cancels
 // strongly, which half-precision operands and FP32 sums would not resolve.
+// Near pairs -- lag below kNear range units, where the correlation exceeds
+// 1e-4 (exp(-x) for nu = 1/2, x sqrt 2 K1(x sqrt 2) for nu = 1,
+// (1 + x sqrt 3) exp(-x sqrt 3) for nu = 3/2, each with margin) -- are
+// evaluated entirely in FP64.  Far pairs use FP32 coordinates pre-scaled by
+// kappa (as in the mixed GEMM) and the FP32 correlation: its relative error
+// (a few 1e-6, from the rounded lag) times a correlation below 1e-4 stays far
+// below the FP64 terms' rounding in the cancelling sum; they are summed per
+// chunk of 256 stations in FP32 and the chunk sums in FP64.
+template <int NU>
 __global__ void __launch_bounds__(256)
 k_predict_f64(float* __restrict__ yhat, int m1, int M, const double* __restrict__ chat, int n,
               const double2* __restrict__ st, double ux, double uxy, double uyx, double uy,
-              double dx, double dy, int nu_code, double sigma2) {
+              double dx, double dy, double sigma2) {
+  constexpr double kNear = NU == 0 ? 9.5 : (NU == 1 ? 8.0 : 7.0);
+  constexpr double kKappa = NU == 0 ? kLog2e : (NU == 1 ? kSqrt2 : kSqrt3);
+  constexpr float kNearS2 = (float)(kNear * kKappa * kNear * kKappa);
   __shared__ double2 S[256];
+  __shared__ float2 S32[256];
   __shared__ double Cv[256];
   const int g = blockIdx.x * 256 + threadIdx.x;
   const int gg = min(g, M - 1);
   const double gx = (double)(gg % m1) * dx, gy = (double)(gg / m1) * dy;
   const double a = ux * gx + uxy * gy, b = uyx * gx + uy * gy;
+  const float a32 = (float)(kKappa * a), b32 = (float)(kKappa * b);
   double acc = 0.0;
   for (int i0 = 0; i0 < n; i0 += 256) {
     const int i = i0 + threadIdx.x;
     __syncthreads();
-    S[threadIdx.x] = st[min(i, n - 1)];
+    const double2 sv = st[min(i, n - 1)];
+    S[threadIdx.x] = sv;
+    S32[threadIdx.x] = make_float2((float)(kKappa * sv.x), (float)(kKappa * sv.y));
     Cv[threadIdx.x] = i < n ? chat[i] : 0.0;
     __syncthreads();
     const int cnt = min(256, n - i0);
+    float far = 0.0f;
+#pragma unroll 4
     for (int j = 0; j < cnt; ++j) {
-      const double hx = a - S[j].x, hy = b - S[j].y;
-      acc = fma(matern_rho(nu_code, sqrt(hx * hx + hy * hy)), Cv[j], acc);
+      const float hx = a32 - S32[j].x, hy = b32 - S32[j].y;
+      const float xs2 = hx * hx + hy * hy;
+      if (xs2 < kNearS2) {
+        const double ex = a - S[j].x, ey = b - S[j].y;
+        acc = fma(matern_rho(NU, sqrt(ex * ex + ey * ey)), Cv[j], acc);
+      } else {
+        far = fmaf(rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(xs2)), (float)Cv[j], far);
+      }
     }
+    acc += (double)far;
   }
   if (g < M) yhat[g] = (float)(sigma2 * acc);
 }
@@ -374,6 +399,8 @@ cesim_status krige_reserve(cesim_ctx c, int R) {
   return CESIM_OK;
 }
 
+static cesim_status predict_from_chat(cesim_ctx c);
+
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   hipStream_t s = c->stream;
   const int n = c->nobs, R = c->nreal;
@@ -384,13 +411,24 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     c->chol_nugget = nugget;
   }
   CESIM_TRY(lk_phi_device(c, nugget));
-  CESIM_TRY(krige_reserve(c, R));
   const bool mixed = c->prec == CESIM_PREC_MIXED;
-  if (mixed) CESIM_TRY(predict_device(c));
+  // on the mixed path a stale prediction is refreshed with the same solve:
+  // z rides along as row R of the right-hand sides
+  const bool with_chat = mixed && !c->yhat_valid;
+  CESIM_TRY(krige_reserve(c, R + (with_chat ? 1 : 0)));
   double* X = c->coef.as<double>();
+  if (with_chat)
+    CESIM_HIP(hipMemcpyAsync(X + (size_t)R * n, c->zdev.p, sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, s));
   // FP64: X = A^{-1} (z - z*_r); mixed: X = -A^{-1} z*_r (yhat carries z)
   CESIM_TRY(lk_synth_rhs_device(c, fields, X, !mixed));
-  CESIM_TRY(chol_solve_device(c, X, R));
+  CESIM_TRY(chol_solve_device(c, X, R + (with_chat ? 1 : 0)));
+  if (with_chat) {
+    CESIM_TRY(c->chat.reserve(sizeof(double) * n));
+    CESIM_HIP(hipMemcpyAsync(c->chat.p, X + (size_t)R * n, sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, s));
+    CESIM_TRY(predict_from_chat(c));
+  }
   return krige_grid_device(c, X, fields);
 }
 
@@ -486,26 +524,40 @@ cesim_status copy_coefficients_device(cesim_ctx c, double* out) {
   return CESIM_OK;
 }
 
-cesim_status predict_device(cesim_ctx c) {
-  if (c->yhat_valid) return CESIM_OK;
+// yhat from c->chat (already A^{-1} z).
+static cesim_status predict_from_chat(cesim_ctx c) {
   hipStream_t s = c->stream;
   const int n = c->nobs, m1 = c->grid.m1, M = c->grid.m1 * c->grid.m2;
-  CESIM_TRY(c->chat.reserve(sizeof(double) * n));
   CESIM_TRY(c->yhat.reserve(sizeof(float) * M));
-  CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * n));
-  CESIM_HIP(hipMemcpyAsync(c->chat.p, c->zdev.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  CESIM_TRY(chol_solve_device(c, c->chat.as<double>(), 1));
   double ux, uxy, uyx, uy;
   cov_map(c, 1.0, ux, uxy, uyx, uy);
   const int tr = c->timer.begin(ST_PREDICT, s);
-  k_predict_f64<<<(M + 255) / 256, 256, 0, s>>>(c->yhat.as<float>(), m1, M, c->chat.as<double>(),
-                                                 n, c->obs_t64.as<double2>(), ux, uxy, uyx, uy,
-                                                 c->grid.dx, c->grid.dy, c->covd.nu_code,
-                                                 c->covd.sigma2);
+  const dim3 grid((M + 255) / 256);
+#define CESIM_PRED(NU)                                                                        \
+  k_predict_f64<NU><<<grid, 256, 0, s>>>(c->yhat.as<float>(), m1, M, c->chat.as<double>(), n, \
+                                         c->obs_t64.as<double2>(), ux, uxy, uyx, uy,          \
+                                         c->grid.dx, c->grid.dy, c->covd.sigma2)
+  switch (c->covd.nu_code) {
+    case 0: CESIM_PRED(0); break;
+    case 1: CESIM_PRED(1); break;
+    default: CESIM_PRED(2); break;
+  }
+#undef CESIM_PRED
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   c->yhat_valid = true;
   return CESIM_OK;
+}
+
+cesim_status predict_device(cesim_ctx c) {
+  if (c->yhat_valid) return CESIM_OK;
+  const int n = c->nobs;
+  CESIM_TRY(c->chat.reserve(sizeof(double) * n));
+  CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * n));
+  CESIM_HIP(hipMemcpyAsync(c->chat.p, c->zdev.p, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                           c->stream));
+  CESIM_TRY(chol_solve_device(c, c->chat.as<double>(), 1));
+  return predict_from_chat(c);
 }
 
 }  // namespace cesim
