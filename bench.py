@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--nreal", type=int, default=1000)
     ap.add_argument("--batch", type=int, default=0, help="realizations per call (0: all)")
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--gemm-nf", type=int, default=0, help="node fragments per wave (0: library default)")
+    ap.add_argument("--gemm-tile", type=int, default=0,
+                    help="mixed GEMM tile 1-3 (0: tuning table or library default)")
     ap.add_argument("--chunk-pairs", type=int, default=0)
     ap.add_argument("--split", choices=["fp16", "bf16"], default="fp16",
                     help="half type of the three-product split in the mixed GEMM")
@@ -95,8 +96,8 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
 
     def step():
         ctx = cesim.Context(cov, grid, prec)
-        if args.gemm_nf:
-            ctx.set_param(cesim.PARAM_GEMM_NODE_FRAGMENTS, args.gemm_nf)
+        if args.gemm_tile:
+            ctx.set_param(cesim.PARAM_GEMM_TILE, args.gemm_tile)
         if args.chunk_pairs:
             ctx.set_param(cesim.PARAM_DRAW_CHUNK_PAIRS, args.chunk_pairs)
         ctx.set_param(cesim.PARAM_GEMM_SPLIT, 0 if args.split == "fp16" else 1)

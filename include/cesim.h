@@ -226,9 +226,12 @@ const char* cesim_status_string(cesim_status s);
 #define CESIM_NUM_STAGES 13
 
 /* Launch-shape parameters (performance only; results do not change):
- *   CESIM_PARAM_GEMM_NODE_FRAGMENTS: 32-node fragments per wave in the mixed
- *     cross-covariance GEMM, 1 or 2; 0 (default) takes the tuning table's
- *     choice for the problem's shape, else 1.
+ *   CESIM_PARAM_GEMM_TILE: workgroup tile of the mixed cross-covariance GEMM,
+ *     1 = 128 grid nodes x 256 realizations (4 waves), 2 = 256 x 256 (4 waves
+ *     of two 32-node fragments), 3 = 128 x 512 (8 waves; the correlations of
+ *     each observation chunk are computed once for all 512 realizations);
+ *     0 (default) takes the tuning table's choice for the problem's shape,
+ *     else 1.
  *   CESIM_PARAM_DRAW_ROWS_FWD, CESIM_PARAM_DRAW_COLS, CESIM_PARAM_DRAW_ROWS_INV:
  *     torus rows per workgroup of draw pass 1, columns per workgroup of
  *     pass 2, rows per workgroup of pass 3 on the register-FFT path
@@ -240,7 +243,7 @@ const char* cesim_status_string(cesim_status s);
  *   CESIM_PARAM_GEMM_SPLIT (changes rounding, not the method): half type of
  *     the three-product split in the mixed GEMM, 0 = FP16 (default, about
  *     22 significant bits per operand) or 1 = BF16 (about 16 bits). */
-#define CESIM_PARAM_GEMM_NODE_FRAGMENTS 1
+#define CESIM_PARAM_GEMM_TILE 1
 #define CESIM_PARAM_DRAW_CHUNK_PAIRS 2
 #define CESIM_PARAM_GEMM_SPLIT 3
 /*   CESIM_PARAM_EVENT_ID (changes the realizations): word 2 of the Philox
@@ -256,7 +259,8 @@ cesim_status ce_set_param(cesim_ctx ctx, int param, int value);
  * ce_autotune times the candidate tile shapes of the three draw passes (on
  * the register-FFT path: the largest shape and three successively halved
  * ones, each pass timed on its own with HIP events) and, on the MIXED path
- * after offgrid_nnkrige, 1 or 2 node fragments of the grid GEMM, on
+ * after offgrid_nnkrige, the tiles of the grid GEMM (3 only for more than
+ * 256 realizations), on
  * min(nreal, 64) realizations written into fields_dev (caller-owned,
  * [nreal][m2][m1]; its contents and the coefficients of the last
  * condition() are overwritten).  The fastest shapes go into a process-wide

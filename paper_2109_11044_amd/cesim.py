@@ -29,7 +29,7 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "cesim_batch_create", "cesim_batch_run", "cesim_batch_get_info",
            "cesim_batch_destroy", "cesim_run_events", "ce_autotune",
            "cesim_tune_save", "cesim_tune_load", "cesim_tune_entries", "cesim_tune_clear"]
-PARAM_GEMM_NODE_FRAGMENTS = 1
+PARAM_GEMM_TILE = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
 PARAM_EVENT_ID = 4

@@ -255,9 +255,9 @@ void cesim_set_default_timing(int enable) { g_default_timing = enable != 0; }
 cesim_status ce_set_param(cesim_ctx c, int param, int value) {
   if (!c) return CESIM_ERR_INVALID_ARG;
   switch (param) {
-    case CESIM_PARAM_GEMM_NODE_FRAGMENTS:
-      if (value < 0 || value > 2) return CESIM_ERR_INVALID_ARG;
-      c->gemm_nf = value;
+    case CESIM_PARAM_GEMM_TILE:
+      if (value < 0 || value > 3) return CESIM_ERR_INVALID_ARG;
+      c->gemm_tile = value;
       return CESIM_OK;
     case CESIM_PARAM_DRAW_ROWS_FWD:
     case CESIM_PARAM_DRAW_ROWS_INV:

@@ -165,7 +165,7 @@ struct cesim_ctx_s {
   cesim::DevBuf info_dev;           // int flags
   std::vector<double> z_host_cached;
 
-  int gemm_nf = 0;                  // node fragments per wave in the mixed grid GEMM (0: tuned / 1)
+  int gemm_tile = 0;                // mixed grid GEMM tile, 1-3 (0: tuning table, else 1)
   cesim::DrawShape draw_force;      // tile shape set with ce_set_param (wins over the table)
   int gemm_split = 0;               // 0: FP16 x3, 1: BF16 x3
   int draw_chunk_pairs = 0;         // pairs per draw launch (0: by a 2 GiB budget)
@@ -205,7 +205,7 @@ size_t draw_pair_bytes(cesim_ctx c);
 // Launch shapes in force: explicit settings, else the tuning table, else
 // the largest shapes / one node fragment.
 DrawShape draw_shape(cesim_ctx c);
-int gemm_fragments(cesim_ctx c, int R);
+int gemm_tile(cesim_ctx c, int R);
 bool register_draw_path(cesim_ctx c);
 DrawShape draw_shape_limits(cesim_ctx c);   // largest shapes of the register path
 bool tune_has_entries(cesim_ctx c, int R);  // table holds this context's shapes

@@ -258,6 +258,54 @@ __device__ __forceinline__ void k12_frag(float gxt, float gyt, const float2* __r
   }
 }
 
+// Correlations of one k-step for the lanes of a wave: lane l holds
+// observations sv[8 (l / 32) + j], j < 8, for its NF nodes (FP32, split into
+// half-precision hi / lo; correlations scaled by ks).
+template <int NU, int NF, typename H>
+__device__ __forceinline__ void k12_step(const float2* sv, bool upper, const float (&gxt)[NF],
+                                         const float (&gyt)[NF], float ks,
+                                         typename HalfOps<H>::V (&ah)[NF],
+                                         typename HalfOps<H>::V (&al)[NF]) {
+  const float2* p = sv + (upper ? 8 : 0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float2 sj = p[j];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const float hx = gxt[f] - sj.x, hy = gyt[f] - sj.y;
+      const float c = ks * rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+      const H h = (H)c;
+      ah[f][j] = h;
+      al[f][j] = (H)(c - (float)h);
+    }
+  }
+}
+
+// Three products hi.hi + hi.lo + lo.hi of one k-step (ks = 0 or 16 within
+// the chunk) for the 8 blocks of 32 realizations whose coefficients start at
+// sh / sl (rows of 32 observations, swizzled as stored).
+template <int NF, typename H>
+__device__ __forceinline__ void mfma_step(const H* __restrict__ sh, const H* __restrict__ sl,
+                                          int ks, int lane, const typename HalfOps<H>::V (&ah)[NF],
+                                          const typename HalfOps<H>::V (&al)[NF],
+                                          floatx16 (&acc)[NF][8]) {
+  using HV = typename HalfOps<H>::V;
+  const int kb = (lane >> 5) * 8;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int rr = 32 * b + (lane & 31);
+    const int pc = ((ks + kb) >> 3) ^ ((rr >> 2) & 3);
+    const HV bh = *reinterpret_cast<const HV*>(&sh[rr * kKC + 8 * pc]);
+    const HV bl = *reinterpret_cast<const HV*>(&sl[rr * kKC + 8 * pc]);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      acc[f][b] = HalfOps<H>::mfma(bh, ah[f], acc[f][b]);
+      acc[f][b] = HalfOps<H>::mfma(bh, al[f], acc[f][b]);
+      acc[f][b] = HalfOps<H>::mfma(bl, ah[f], acc[f][b]);
+    }
+  }
+}
+
 template <int NU, int NF, typename H>
 __global__ void __launch_bounds__(256, 3 - NF)
 k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
@@ -371,6 +419,122 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
   }
 }
 
+// Same product with a workgroup of 8 waves over 128 grid nodes x 512
+// realizations: waves w and w + 4 own the same 32 nodes and realizations
+// [r0 + 256 (w / 4), + 256).  The correlations of a chunk of 32 observations
+// are computed once per workgroup: wave w / 4 = q evaluates k-step q (16
+// observations) for its nodes, keeps it in registers and posts it to LDS,
+// and reads the other k-step from its partner -- half the arithmetic per
+// matrix instruction of the 4-wave kernel.  The correlations of chunk kc + 1
+// are evaluated while chunk kc is multiplied.
+template <int NU, typename H>
+__global__ void __launch_bounds__(512, 1)
+k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
+                 const H* __restrict__ Bh, const H* __restrict__ Bl,
+                 const float* __restrict__ colscale, const float* __restrict__ yhat, int n,
+                 const float2* __restrict__ st, float ux, float uxy, float uyx, float uy,
+                 float dx, float dy, float kscale) {
+  using HV = typename HalfOps<H>::V;
+  constexpr int TG = 128, TR = 512;
+  __shared__ __align__(16) H Sh[2][TR * kKC];
+  __shared__ __align__(16) H Sl[2][TR * kKC];
+  __shared__ __align__(16) HV Kx[4][2][2][64];     // [node frag][k-step][hi, lo][lane]
+  __shared__ float2 Ss[3][kKC];
+  const int g0 = blockIdx.x * TG, r0 = blockIdx.y * TR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nf = wave & 3, q = wave >> 2;
+  const bool upper = lane >= 32;
+  float gxt[1], gyt[1];
+  {
+    const int g = min(g0 + 32 * nf + (lane & 31), M - 1);
+    const float gx = (float)(g % m1) * dx, gy = (float)(g / m1) * dy;
+    gxt[0] = ux * gx + uxy * gy;
+    gyt[0] = uyx * gx + uy * gy;
+  }
+  floatx16 acc[1][8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[0][b][e] = 0.0f;
+  const int nchunks = (n + kKC - 1) / kKC;
+  u32x4v ph[4], pl[4];
+#define CESIM_FETCHX(KC)                                                                    \
+  {                                                                                         \
+    const u32x4v* gh_ = reinterpret_cast<const u32x4v*>(Bh + ((size_t)(KC) * Rp + r0) * kKC); \
+    const u32x4v* gl_ = reinterpret_cast<const u32x4v*>(Bl + ((size_t)(KC) * Rp + r0) * kKC); \
+    ph[0] = gh_[threadIdx.x];                                                               \
+    ph[1] = gh_[threadIdx.x + 512];                                                         \
+    ph[2] = gh_[threadIdx.x + 1024];                                                        \
+    ph[3] = gh_[threadIdx.x + 1536];                                                        \
+    pl[0] = gl_[threadIdx.x];                                                               \
+    pl[1] = gl_[threadIdx.x + 512];                                                         \
+    pl[2] = gl_[threadIdx.x + 1024];                                                        \
+    pl[3] = gl_[threadIdx.x + 1536];                                                        \
+  }
+#define CESIM_ST1X(U)                                                     \
+  {                                                                       \
+    const int qq = threadIdx.x + 512 * (U), row = qq >> 2;                \
+    const int pq = (row << 2) | ((qq & 3) ^ ((row >> 2) & 3));            \
+    sh_[pq] = ph[U];                                                      \
+    sl_[pq] = pl[U];                                                      \
+  }
+#define CESIM_STASHX(BUF)                                                 \
+  {                                                                       \
+    u32x4v* sh_ = reinterpret_cast<u32x4v*>(Sh[BUF]);                     \
+    u32x4v* sl_ = reinterpret_cast<u32x4v*>(Sl[BUF]);                     \
+    CESIM_ST1X(0) CESIM_ST1X(1) CESIM_ST1X(2) CESIM_ST1X(3)               \
+  }
+  // stations rotate through three chunk buffers as in the 4-wave kernel
+  const int sl_ = threadIdx.x & (kKC - 1);
+  Ss[0][sl_] = st[min(sl_, n - 1)];
+  Ss[1][sl_] = st[min(kKC + sl_, n - 1)];
+  CESIM_FETCHX(0)
+  CESIM_STASHX(0)
+  __syncthreads();
+  HV own_h[1], own_l[1], oth_h[1], oth_l[1];
+  k12_step<NU, 1, H>(Ss[0] + 16 * q, upper, gxt, gyt, kscale, own_h, own_l);
+  Kx[nf][q][0][lane] = own_h[0];
+  Kx[nf][q][1][lane] = own_l[0];
+  __syncthreads();
+  for (int kc = 0; kc < nchunks; ++kc) {
+    const int buf = kc & 1;
+    const int sb = kc % 3, sb1 = sb == 2 ? 0 : sb + 1, sb2 = sb1 == 2 ? 0 : sb1 + 1;
+    oth_h[0] = Kx[nf][1 - q][0][lane];
+    oth_l[0] = Kx[nf][1 - q][1][lane];
+    CESIM_FETCHX(min(kc + 1, nchunks - 1))
+    const float2 ps = st[min((kc + 2) * kKC + sl_, n - 1)];
+    // k-step 0 is wave group 0's correlations, k-step 1 group 1's
+    if (q == 0) {
+      mfma_step<1, H>(Sh[buf] + 256 * q * kKC, Sl[buf] + 256 * q * kKC, 0, lane, own_h, own_l, acc);
+      mfma_step<1, H>(Sh[buf] + 256 * q * kKC, Sl[buf] + 256 * q * kKC, 16, lane, oth_h, oth_l, acc);
+    } else {
+      mfma_step<1, H>(Sh[buf] + 256 * q * kKC, Sl[buf] + 256 * q * kKC, 0, lane, oth_h, oth_l, acc);
+      mfma_step<1, H>(Sh[buf] + 256 * q * kKC, Sl[buf] + 256 * q * kKC, 16, lane, own_h, own_l, acc);
+    }
+    k12_step<NU, 1, H>(Ss[sb1] + 16 * q, upper, gxt, gyt, kscale, own_h, own_l);
+    __syncthreads();                                   // Kx and Sh/Sl[buf ^ 1] free
+    Kx[nf][q][0][lane] = own_h[0];
+    Kx[nf][q][1][lane] = own_l[0];
+    CESIM_STASHX(buf ^ 1)
+    Ss[sb2][sl_] = ps;
+    __syncthreads();
+  }
+#undef CESIM_FETCHX
+#undef CESIM_STASHX
+#undef CESIM_ST1X
+  const int gg = g0 + 32 * nf + (lane & 31);
+  if (gg >= M) return;
+  const float yh = yhat[gg];
+  const int rq = r0 + 256 * q;
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = rq + 32 * b + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      if (r < R) fields[(size_t)r * M + gg] += fmaf(acc[0][b][e], colscale[r], yh);
+    }
+}
+
 // ------------------------------------------------------------------- host
 
 cesim_status chol_factor_device(cesim_ctx c, double tau2);
@@ -392,7 +556,7 @@ cesim_status krige_reserve(cesim_ctx c, int R) {
   CESIM_TRY(c->coef.reserve(sizeof(double) * (size_t)n * R));
   CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * (size_t)n * R));
   if (c->prec == CESIM_PREC_MIXED) {
-    const int Rp = (R + 255) / 256 * 256;
+    const int Rp = (R + 511) / 512 * 512;        // covers every GEMM tile
     const int npad = (n + kKC - 1) / kKC * kKC;
     CESIM_TRY(c->coef_b16.reserve(sizeof(uint16_t) * 2 * (size_t)npad * Rp + sizeof(float) * Rp));
   }
@@ -451,7 +615,8 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
     c->timer.end(tr, s);
     return CESIM_OK;
   }
-  const int Rp = (R + 255) / 256 * 256;
+  const int tile = gemm_tile(c, R);
+  const int Rp = tile == 3 ? (R + 511) / 512 * 512 : (R + 255) / 256 * 256;
   const int npad = (n + kKC - 1) / kKC * kKC;
   const bool f16 = c->gemm_split == 0;
   // correlations enter FP16 multiplied by 2^12 (values up to 4096), which
@@ -481,8 +646,9 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   const float* YH = c->yhat.as<float>();
   const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
   const float fdx = (float)dx, fdy = (float)dy, fks = (float)ks;
-  const int nf = gemm_fragments(c, R);
+  const int nf = tile == 2 ? 2 : 1;
   dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
+  const dim3 gridx((M + 127) / 128, Rp / 512);
 #define CESIM_KS(NU, NF, H)                                                                     \
   k_krige_split3<NU, NF, H><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh), \
                                                  reinterpret_cast<const H*>(Hl), colscale, YH, n, \
@@ -493,11 +659,25 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
     case 1: CESIM_KS(1, NF, H); break;      \
     default: CESIM_KS(2, NF, H); break;     \
   }
-  if (f16) {
+#define CESIM_KX(NU, H)                                                                         \
+  k_krige_split3_x<NU, H><<<gridx, 512, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh),  \
+                                                reinterpret_cast<const H*>(Hl), colscale, YH, n,  \
+                                                S2, a, b, cc, d, fdx, fdy, fks)
+#define CESIM_KX_NU(H)                      \
+  switch (c->covd.nu_code) {                \
+    case 0: CESIM_KX(0, H); break;          \
+    case 1: CESIM_KX(1, H); break;          \
+    default: CESIM_KX(2, H); break;         \
+  }
+  if (tile == 3) {
+    if (f16) { CESIM_KX_NU(_Float16) } else { CESIM_KX_NU(__bf16) }
+  } else if (f16) {
     if (nf == 1) { CESIM_KS_NU(1, _Float16) } else { CESIM_KS_NU(2, _Float16) }
   } else {
     if (nf == 1) { CESIM_KS_NU(1, __bf16) } else { CESIM_KS_NU(2, __bf16) }
   }
+#undef CESIM_KX_NU
+#undef CESIM_KX
 #undef CESIM_KS_NU
 #undef CESIM_KS
   CESIM_HIP(hipGetLastError());

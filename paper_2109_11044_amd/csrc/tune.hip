@@ -2,14 +2,14 @@
 //
 // Tunable: the tile shapes of the three register-FFT draw passes (rows per
 // workgroup of the row passes, columns per workgroup of the column pass)
-// and the node fragments per wave of the mixed grid GEMM.  None of them
+// and the workgroup tile of the mixed grid GEMM.  None of them
 // changes a single bit of any result (each output element sees the same
 // operations in the same order), so tuning affects speed only.  The radix
 // sequence of the transforms is fixed by design and not tuned.
 //
 // Chosen shapes live in a process-wide table keyed by problem shape:
 //   "draw p<precision> <t1>x<t2>"                 -> rows1, log2 cols, rows3
-//   "gemm s<split> nu<code> M<nodes> n<n/512> R<Rp>" -> node fragments
+//   "gemm s<split> nu<code> M<nodes> n<n/512> R<Rp>" -> GEMM tile
 // and can be saved to / loaded from a JSON-lines file.
 #include <hip/hip_runtime.h>
 
@@ -82,10 +82,10 @@ DrawShape draw_shape(cesim_ctx c) {
   return d;
 }
 
-int gemm_fragments(cesim_ctx c, int R) {
-  if (c->gemm_nf == 1 || c->gemm_nf == 2) return c->gemm_nf;
+int gemm_tile(cesim_ctx c, int R) {
+  if (c->gemm_tile >= 1 && c->gemm_tile <= 3) return c->gemm_tile;
   std::array<int, 3> v;
-  if (lookup(gemm_key(c, R), v) && (v[0] == 1 || v[0] == 2)) return v[0];
+  if (lookup(gemm_key(c, R), v) && v[0] >= 1 && v[0] <= 3) return v[0];
   return 1;
 }
 
@@ -110,7 +110,7 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
   std::copy(c->timer.calls, c->timer.calls + ST_COUNT, saved_acc.calls);
   const bool saved_on = c->timer.enabled;
   const DrawShape saved_force = c->draw_force;
-  const int saved_nf = c->gemm_nf, saved_nreal = c->nreal;
+  const int saved_tile = c->gemm_tile, saved_nreal = c->nreal;
   const bool saved_have = c->have_fields;
   cesim_status st = CESIM_OK;
   c->timer.enabled = true;
@@ -164,8 +164,9 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
     const int stg[3] = {ST_KRIGE_GEMM, -1, -1};
     double best = 1e300;
     int pick = 1;
-    for (int nf = 1; nf <= 2 && st == CESIM_OK; ++nf) {
-      c->gemm_nf = nf;
+    const int ntiles = nreal > 256 ? 3 : 2;   // the 512-realization tile needs > 256
+    for (int nf = 1; nf <= ntiles && st == CESIM_OK; ++nf) {
+      c->gemm_tile = nf;
       double ms[3];
       st = timed([&] { return krige_grid_device(c, c->coef.as<double>(), fields); }, ms, stg);
       if (st == CESIM_OK && ms[0] < best) {
@@ -181,7 +182,7 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
   std::copy(saved_acc.calls, saved_acc.calls + ST_COUNT, c->timer.calls);
   c->timer.enabled = saved_on;
   c->draw_force = saved_force;
-  c->gemm_nf = saved_nf;
+  c->gemm_tile = saved_tile;
   c->nreal = saved_nreal;
   c->have_fields = saved_have;
   return st;

@@ -42,12 +42,14 @@ def test_every_draw_tile_shape_gives_identical_fields(prec, m, torus):
             assert torch.equal(y, y0) and torch.equal(v, v0), (rows, cols)
 
 
-def test_gemm_fragments_give_identical_fields():
+@pytest.mark.parametrize("nreal", [6, 300, 600])
+def test_gemm_tiles_give_identical_fields(nreal):
     import torch
     cesim.tune_clear()
-    _, v1 = run("mixed", 128, 256, [(cesim.PARAM_GEMM_NODE_FRAGMENTS, 1)])
-    _, v2 = run("mixed", 128, 256, [(cesim.PARAM_GEMM_NODE_FRAGMENTS, 2)])
-    assert torch.equal(v1, v2)
+    _, v1 = run("mixed", 128, 256, [(cesim.PARAM_GEMM_TILE, 1)], nreal=nreal)
+    for tile in (2, 3):
+        _, v = run("mixed", 128, 256, [(cesim.PARAM_GEMM_TILE, tile)], nreal=nreal)
+        assert torch.equal(v1, v), tile
 
 
 @pytest.mark.parametrize("prec,torus", [("mixed", 384), ("fp64", 256), ("mixed", 256)])
