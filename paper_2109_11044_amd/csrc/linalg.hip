@@ -45,12 +45,21 @@ k_place_diag(const double* __restrict__ D, int n, double* __restrict__ W) {
   }
 }
 
+// The diagonal factorisation runs as a single wave: its LDS accesses are
+// executed in program order, so a lane reads what another lane of the same
+// wave wrote by an earlier instruction without a barrier.  This keeps the
+// compiler from moving LDS accesses across the point (no instruction is
+// emitted).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Factor the nbk x nbk diagonal block at (k0, k0) with one wave and form
 // the inverse of its factor.  Lane i holds row i in registers (every index
 // static, the loops unrolled).  Right-looking: at pivot j every lane posts
 // its column-j entry to LDS, reads the pivot and, for each k > j, the
-// broadcast entry of row k, and updates its row (no barrier beyond the two
-// that order the posts).  The inverse X = L^{-1} is then formed column by
+// broadcast entry of row k, and updates its row.  The inverse X = L^{-1} is then formed column by
 // column (lane c holds column c) by forward substitution on the identity
 // from an LDS copy of L.  Writes L back (lower part) and the inverse to
 // dinv (kNB x kNB, row-major, zero above the diagonal, the identity past
@@ -69,7 +78,7 @@ __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, i
 #pragma unroll
   for (int j = 0; j < kNB; ++j) {
     col[i] = a[j];                        // column j, not yet scaled
-    __syncthreads();
+    wave_lds_order();
     const double d = col[j];
     bad |= (j < nbk && !(d > 0.0));
     const double piv = sqrt(d), r = 1.0 / piv;
@@ -81,14 +90,14 @@ __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, i
       if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     rinv[j] = r;
-    __syncthreads();
+    wave_lds_order();
   }
 #pragma unroll
   for (int k = 0; k < kNB; ++k) {
     Ls[i][k] = (k <= i) ? a[k] : 0.0;
     if (i < nbk && k <= i) A[(size_t)(k0 + i) * n + k0 + k] = a[k];
   }
-  __syncthreads();
+  wave_lds_order();
   double x[kNB];
 #pragma unroll
   for (int r = 0; r < kNB; ++r) x[r] = (r == i) ? 1.0 : 0.0;
