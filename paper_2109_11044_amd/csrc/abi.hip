@@ -235,7 +235,7 @@ const char* cesim_status_string(cesim_status s) {
 static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
   return {&c->tt.tw1_64, &c->tt.tw2_64, &c->tt.tw1_32, &c->tt.tw2_32, &c->s64,
           &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
-          &c->corners, &c->weights, &c->gamma, &c->phi, &c->amat, &c->dinv,
+          &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->yhat, &c->info_dev};
 }
@@ -415,11 +415,25 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   CESIM_TRY(c->weights.reserve(sizeof(double) * (size_t)nobs * k));
   CESIM_TRY(c->gamma.reserve(sizeof(double) * nobs));
   CESIM_TRY(c->phi.reserve(sizeof(double) * nobs));
+  CESIM_TRY(c->obs_order.reserve(sizeof(int) * nobs));
   // transformed coordinates: FP64 path U (s - origin); mixed path kappa U (s - origin)
   const CovDev& d = c->covd;
   const double kappa = d.nu_code == 0 ? kLog2e : (d.nu_code == 2 ? kSqrt3 : kSqrt2);
   std::vector<double2> t64(nobs);
   std::vector<float2> t32(nobs);
+  // processing order of the gathers: Morton (Z) order of the grid cell
+  std::vector<std::pair<uint64_t, int>> key(nobs);
+  for (int i = 0; i < nobs; ++i) {
+    const double fx = std::floor((xy[2 * i] - g.x0) / g.dx), fy = std::floor((xy[2 * i + 1] - g.y0) / g.dy);
+    const uint32_t cx = (uint32_t)std::min(std::max(fx, 0.0), 65535.0);
+    const uint32_t cy = (uint32_t)std::min(std::max(fy, 0.0), 65535.0);
+    uint64_t m = 0;
+    for (int b = 0; b < 16; ++b) m |= (uint64_t)((cx >> b) & 1) << (2 * b) | (uint64_t)((cy >> b) & 1) << (2 * b + 1);
+    key[i] = {m, i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> order(nobs);
+  for (int i = 0; i < nobs; ++i) order[i] = key[i].second;
   for (int i = 0; i < nobs; ++i) {
     const double hx = xy[2 * i] - g.x0, hy = xy[2 * i + 1] - g.y0;
     const double a = d.u00 * hx + d.u01 * hy, b = d.u10 * hx + d.u11 * hy;
@@ -432,6 +446,8 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   CESIM_HIP(hipMemcpyAsync(c->obs_t64.p, t64.data(), sizeof(double2) * nobs,
                            hipMemcpyHostToDevice, s));
   CESIM_HIP(hipMemcpyAsync(c->obs_t32.p, t32.data(), sizeof(float2) * nobs,
+                           hipMemcpyHostToDevice, s));
+  CESIM_HIP(hipMemcpyAsync(c->obs_order.p, order.data(), sizeof(int) * nobs,
                            hipMemcpyHostToDevice, s));
   c->nobs = nobs;
   c->k = k;

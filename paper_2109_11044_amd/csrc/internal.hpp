@@ -145,6 +145,7 @@ struct cesim_ctx_s {
   cesim::DevBuf obs_t32;            // [n] float2: transformed coordinates (mixed)
   cesim::DevBuf obs_t64;            // [n] double2: transformed coordinates (FP64)
   cesim::DevBuf corners, weights, gamma, phi;
+  cesim::DevBuf obs_order;          // [n] int: observations in Morton order of their grid cell
   double gamma_min = 0, gamma_max = 0;
   std::vector<double> obs_host;
 

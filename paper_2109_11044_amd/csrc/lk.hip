@@ -98,10 +98,13 @@ __global__ void __launch_bounds__(256)
 k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict__ corners,
             const double* __restrict__ W, const double* __restrict__ phi,
             const double* __restrict__ z, int n, int K, int w2, NoiseKey key,
-            double* __restrict__ rhs) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+            const int* __restrict__ order, double* __restrict__ rhs) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
-  if (i >= n) return;
+  if (t >= n) return;
+  // observations in spatial order: neighbouring lanes gather from
+  // neighbouring windows and share cache lines (results are per observation)
+  const int i = order[t];
   const int2 ab = corners[i];
   const F* y = fields + (size_t)r * m1 * m2 + (size_t)ab.y * m1 + ab.x;
   const double* w = W + (size_t)i * K;
@@ -162,11 +165,13 @@ cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, b
   if (c->prec == CESIM_PREC_FP64)
     k_synth_rhs<double><<<grid, 256, 0, c->stream>>>(
         static_cast<const double*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key, rhs);
+        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key,
+        c->obs_order.as<int>(), rhs);
   else
     k_synth_rhs<float><<<grid, 256, 0, c->stream>>>(
         static_cast<const float*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key, rhs);
+        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key,
+        c->obs_order.as<int>(), rhs);
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, c->stream);
   return CESIM_OK;
