@@ -59,6 +59,9 @@ def parse():
                     help="tune launch shapes before the warm-up (one-off, reported as tune_ms)")
     ap.add_argument("--no-unbatched", action="store_true",
                     help="events64: skip the one-context-per-event comparison")
+    ap.add_argument("--record-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "this benchmark with --copy-probe-mib into profiles/hbm_traffic_*.json")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB once (a "
                          "reference kernel of known traffic for hardware-counter runs)")
@@ -164,26 +167,89 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
                 finite=finite, gamma_max=info.get("gamma_max"), tune_ms=info.get("tune_ms"))
 
 
+# Stage -> (kernel name fragment, source files whose text the kernel is
+# built from) for the recorded HBM counters.
+COUNTED_STAGES = {
+    "draw_noise_rowfft": ("k_p2_rows_noise<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp", "devmath.hpp"]),
+    "draw_colfft_scale_icolfft": ("k_p2_cols<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
+    "draw_irowfft_crop": ("k_p2_rows_inv_crop<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
+    "krige_grid_gemm": ("k_krige_split3", ["krige.hip", "devmath.hpp"]),
+    "krige_predict_fp64": ("k_predict_f64", ["krige.hip", "devmath.hpp"]),
+    "synth_obs_rhs": ("k_synth_rhs<float>", ["lk.hip", "devmath.hpp"]),
+}
+
+
+def _digest(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def recorded_traffic(stage, workload):
     """HBM bytes per launch of a stage from the counter runs recorded under
-    profiles/, or None when the kernel source has changed since (its hash no
-    longer matches) or no record exists for this workload."""
+    profiles/, or None when a source of the kernel has changed since (its hash
+    no longer matches) or no record exists for this workload."""
     import glob
-    import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")):
-        with open(path) as f:
-            rec = json.load(f)
-        if rec.get("workload") != workload or stage not in rec.get("kernels", {}):
-            continue
-        src, digest = rec["sources"].get(stage, [None, None])
-        if not src:
-            continue
-        with open(os.path.join(ROOT, src), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != digest:
+        try:
+            with open(path) as f:
+                rec = json.load(f)
+            if rec.get("workload") != workload or stage not in rec.get("kernels", {}):
+                continue
+            srcs = rec["sources"].get(stage, [])
+            if not srcs or any(_digest(rel) != digest for rel, digest in srcs):
                 return None
-        k = rec["kernels"][stage]
-        return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+            k = rec["kernels"][stage]
+            return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+        except (OSError, ValueError, KeyError, TypeError):
+            continue
     return None
+
+
+def record_counters(fetch_csv, write_csv, probe_mib, workload):
+    """Turn two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) of ``bench.py --copy-probe-mib probe_mib`` into HBM bytes per
+    launch for the counted stages, each counter scaled by what it reads for
+    the device copy of known size; writes profiles/hbm_traffic_<workload>.json
+    and prints a markdown table."""
+    import csv
+    probe = probe_mib * (1 << 20)
+
+    def load(path):
+        rows = list(csv.DictReader(open(path)))
+        cp = max((r for r in rows if "copyBuffer" in r["Kernel_Name"]),
+                 key=lambda r: float(r["Counter_Value"]))
+        return rows, float(cp["Counter_Value"]) * 1024.0
+
+    frows, fprobe = load(fetch_csv)
+    wrows, wprobe = load(write_csv)
+    fs, ws = probe / fprobe, probe / wprobe
+    rec = {"workload": workload, "precision": "mixed",
+           "calibration": {"probe_bytes_each_way": probe, "fetch_scale": fs, "write_scale": ws},
+           "sources": {}, "kernels": {}}
+    lines = ["| stage | kernel | launches | FETCH_SIZE KiB/launch (raw) | WRITE_SIZE KiB/launch (raw) "
+             "| HBM read GB/launch (scaled) | HBM write GB/launch (scaled) |",
+             "|---|---|---:|---:|---:|---:|---:|"]
+    for stage, (frag, files) in COUNTED_STAGES.items():
+        fr = [float(r["Counter_Value"]) for r in frows if frag in r["Kernel_Name"]]
+        wr = [float(r["Counter_Value"]) for r in wrows if frag in r["Kernel_Name"]]
+        if not fr or not wr:
+            continue
+        name = next(r["Kernel_Name"] for r in frows if frag in r["Kernel_Name"])
+        f_kib, w_kib = sum(fr) / len(fr), sum(wr) / len(wr)
+        rec["kernels"][stage] = {"kernel": name, "launches": len(fr),
+                                 "fetch_bytes_per_launch": f_kib * 1024.0 * fs,
+                                 "write_bytes_per_launch": w_kib * 1024.0 * ws}
+        rec["sources"][stage] = [[f"paper_2109_11044_amd/csrc/{f}",
+                                  _digest(f"paper_2109_11044_amd/csrc/{f}")] for f in files]
+        lines.append(f"| {stage} | `{name.split('(')[0][:60]}` | {len(fr)} | {f_kib:.1f} | {w_kib:.1f} "
+                     f"| {f_kib * 1024 * fs / 1e9:.3f} | {w_kib * 1024 * ws / 1e9:.3f} |")
+    out = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"calibration: FETCH_SIZE x {fs:.4f}, WRITE_SIZE x {ws:.4f}")
+    print("\n".join(lines))
+    print(f"wrote {out}")
 
 
 def cpu_baseline(wl, xy, z, seed):
@@ -320,6 +386,11 @@ def events_main(args, torch, cesim, workloads):
 
 def main():
     args = parse()
+    if args.record_counters:
+        from paper_2109_11044_amd import workloads
+        record_counters(args.record_counters[0], args.record_counters[1],
+                        args.copy_probe_mib or 1024, workloads.DM.name)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
