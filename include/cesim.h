@@ -235,8 +235,8 @@ const char* cesim_status_string(cesim_status s);
  *   CESIM_PARAM_DRAW_ROWS_FWD, CESIM_PARAM_DRAW_COLS, CESIM_PARAM_DRAW_ROWS_INV:
  *     torus rows per workgroup of draw pass 1, columns per workgroup of
  *     pass 2, rows per workgroup of pass 3 on the register-FFT path
- *     (square tori of 2^a from 128 to 8192, and of 3 * 2^a from 384 to 6144
- *     in MIXED precision); powers of two, clamped to each kernel's largest
+ *     (square tori of 2^a from 128 to 8192 and of 3 * 2^a from 384 to 6144);
+ *     powers of two, clamped to each kernel's largest
  *     shape; 0 (default) takes the tuning table's choice, else the largest.
  *   CESIM_PARAM_DRAW_CHUNK_PAIRS: realization pairs per launch of the draw
  *     passes (bounds the pair buffer); 0 (default) chooses up to 2 GiB.

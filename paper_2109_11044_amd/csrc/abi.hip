@@ -237,14 +237,18 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
-          &c->chat, &c->yhat, &c->info_dev};
+          &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev};
 }
 
 void ce_destroy(cesim_ctx c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->aux) (void)hipStreamSynchronize(c->aux);
   c->timer.destroy();
   for (DevBuf* b : all_bufs(c)) b->release();
+  if (c->aux_done) (void)hipEventDestroy(c->aux_done);
+  if (c->last_use) (void)hipEventDestroy(c->last_use);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 
@@ -295,6 +299,7 @@ cesim_status ce_get_stage_times(cesim_ctx c, double* ms, long long* calls, int n
                                 int reset) {
   if (!c || nstages < 0 || nstages > ST_COUNT) return CESIM_ERR_INVALID_ARG;
   CESIM_HIP(hipStreamSynchronize(c->stream));
+  CESIM_HIP(hipStreamSynchronize(c->aux));
   c->timer.resolve();
   for (int i = 0; i < nstages; ++i) {
     if (ms) ms[i] = c->timer.ms[i];
@@ -334,7 +339,16 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
   c->prec = prec;
   c->covd = make_cov(*cov);
   c->gridd = {grid->m1, grid->m2, grid->x0, grid->y0, grid->dx, grid->dy};
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->aux_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming) != hipSuccess) {
+    ce_destroy(c);
+    return CESIM_ERR_HIP;
+  }
   for (DevBuf* b : all_bufs(c)) b->stream = c->stream;
+  for (DevBuf* b : {&c->amat, &c->dinv, &c->winv, &c->wtmp, &c->chat, &c->chat_tmp, &c->yhat,
+                    &c->zdev})
+    b->stream = c->aux;                 // written by the work condition() puts on aux
   c->timer.enabled = g_default_timing;
   cesim_status st = c->info_dev.reserve(sizeof(int) * 4);
   if (st != CESIM_OK) { ce_destroy(c); return st; }
@@ -404,6 +418,7 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   }
   const auto t_start = std::chrono::steady_clock::now();
   CESIM_HIP(hipStreamSynchronize(c->stream));   // host staging below is reused
+  CESIM_HIP(hipStreamSynchronize(c->aux));      // buffers below may be reallocated
   c->chol_valid = false;
   c->yhat_valid = false;
   c->nobs = 0;
@@ -474,12 +489,16 @@ cesim_status condition(cesim_ctx c, const double* z, double nugget, void* fields
     if (!isfin(z[i])) return CESIM_ERR_INVALID_ARG;
   if (c->z_host_cached.size() != (size_t)n ||
       std::memcmp(c->z_host_cached.data(), z, sizeof(double) * n) != 0) {
-    CESIM_HIP(hipStreamSynchronize(c->stream));   // previous upload retired
+    // the upload goes to aux (after the last kernel that read the previous
+    // values), so that it does not wait for a draw queued on the stream
+    CESIM_HIP(hipStreamSynchronize(c->aux));      // previous upload retired
     c->z_host_cached.assign(z, z + n);
     c->yhat_valid = false;
     CESIM_TRY(c->zdev.reserve(sizeof(double) * n));
+    CESIM_TRY(aux_wait_last_use(c));
     CESIM_HIP(hipMemcpyAsync(c->zdev.p, c->z_host_cached.data(), sizeof(double) * n,
-                             hipMemcpyHostToDevice, c->stream));
+                             hipMemcpyHostToDevice, c->aux));
+    c->aux_pending = true;
   }
   return condition_device(c, nugget, fields);
 }

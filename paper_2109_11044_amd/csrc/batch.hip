@@ -155,7 +155,7 @@ cesim_status plan(cesim_batch b, cesim_status* status, int flags) {
     c->nreal = ev.nreal;
   }
   if (b->prec == CESIM_PREC_MIXED)
-    for (int e = 0; e < ne; ++e) CESIM_TRY(predict_device(b->ctx[e]));
+    for (int e = 0; e < ne; ++e) CESIM_TRY(predict_device(b->ctx[e], b->own));
   if (flags & CESIM_BATCH_AUTOTUNE)
     for (int e = 0; e < ne; ++e)
       if (!tune_has_entries(b->ctx[e], b->ev[e].nreal))

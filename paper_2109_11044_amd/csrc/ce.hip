@@ -634,9 +634,8 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
   return CESIM_OK;
 }
 
-// Square tori of 2^a from 128 to 8192 take the register path, and in FP32
-// also 3 * 2^a from 384 to 6144 (48 elements per thread; in FP64 these
-// would not fit the register file and stay on the LDS path).
+// Square tori of 2^a from 128 to 8192 and of 3 * 2^a from 384 to 6144 take
+// the register path (16 or 24 elements per thread).
 template <typename real>
 bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m2, int np,
                      const cpx<real>* tw1, const cpx<real>* tw2, const real* sl,
@@ -653,11 +652,9 @@ bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m
     CESIM_P2(8192)
     default: break;
   }
-  if constexpr (sizeof(real) == 4) {
-    switch (t1) {
-      CESIM_P2(384) CESIM_P2(768) CESIM_P2(1536) CESIM_P2(3072) CESIM_P2(6144)
-      default: break;
-    }
+  switch (t1) {
+    CESIM_P2(384) CESIM_P2(768) CESIM_P2(1536) CESIM_P2(3072) CESIM_P2(6144)
+    default: break;
   }
 #undef CESIM_P2
   return false;
@@ -711,7 +708,7 @@ bool register_draw_path(cesim_ctx c) {
   if (c->t1 != c->t2) return false;
   switch (c->t1) {
     case 128: case 256: case 512: case 1024: case 2048: case 4096: case 8192: return true;
-    case 384: case 768: case 1536: case 3072: case 6144: return c->prec == CESIM_PREC_MIXED;
+    case 384: case 768: case 1536: case 3072: case 6144: return true;
     default: return false;
   }
 }
@@ -723,8 +720,6 @@ DrawShape draw_shape_limits(cesim_ctx c) {
   case TT: return f64 ? clamp_shape<double, TT, TT>(DrawShape{}) : clamp_shape<float, TT, TT>(DrawShape{});
     CESIM_LIM(128) CESIM_LIM(256) CESIM_LIM(512) CESIM_LIM(1024) CESIM_LIM(2048) CESIM_LIM(4096)
     CESIM_LIM(8192)
-#undef CESIM_LIM
-#define CESIM_LIM(TT) case TT: return clamp_shape<float, TT, TT>(DrawShape{});
     CESIM_LIM(384) CESIM_LIM(768) CESIM_LIM(1536) CESIM_LIM(3072) CESIM_LIM(6144)
 #undef CESIM_LIM
     default: return DrawShape{1, 0, 1};

@@ -1,7 +1,7 @@
 // fft_pow2.hpp -- register-resident Stockham FFT for lengths T = 2^a or
 // T = 3 * 2^a known at compile time (the draw's hot path).
 //
-// Each thread owns E elements of one transform (E = 16, or 48 when 3 | T),
+// Each thread owns E elements of one transform (E = 16, or 24 when 3 | T),
 // its "home" positions base + S h (h < E, S = T / E threads per
 // transform).  A stage of radix R (R | E) treats them as U = E / R
 // butterflies j = base + S u with inputs h = u + q U (positions j + q T / R),
@@ -9,8 +9,8 @@
 // belong at positions (j / Ns) Ns R + (j mod Ns) + q Ns; unless the stage is
 // the last one (whose outputs land on the home positions), they are
 // exchanged through LDS and every thread reloads its home positions.
-// Forward plans are [16, ..., 16, r, 3] and inverse plans the reverse
-// (r = the remaining power of two, the 3 only when 3 | T), so a forward
+// Forward plans are [16, ..., 16, r] for 2^a and [8, ..., 8, r, 3] for
+// 3 * 2^a, inverse plans the reverse (r = the remaining power of two), so a forward
 // transform followed by an inverse one needs no exchange in between:
 // pointwise scaling happens in registers.
 // Twiddles: w1 = table[k T / (Ns R)] from exp(-2 pi i t / T), higher powers
@@ -25,17 +25,18 @@ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
 // Elements per thread for length T.
 template <int T>
-constexpr int p2_elems() { return T % 3 == 0 ? 48 : 16; }
+constexpr int p2_elems() { return T % 3 == 0 ? 24 : 16; }
 
 template <int T, bool INV>
 struct P2Plan {
   static constexpr bool THREE = T % 3 == 0;
+  static constexpr int LB = THREE ? 3 : 4;           // log2 of the main radix (8 or 16)
   static constexpr int L = ilog2c(THREE ? T / 3 : T);
-  static constexpr int REM = L % 4;
-  static constexpr int N16 = L / 4;
-  static constexpr int NST = N16 + (REM ? 1 : 0) + (THREE ? 1 : 0);
+  static constexpr int REM = L % LB;
+  static constexpr int NMAIN = L / LB;
+  static constexpr int NST = NMAIN + (REM ? 1 : 0) + (THREE ? 1 : 0);
   static constexpr int fwd_radix(int s) {
-    return s < N16 ? 16 : ((s == N16 && REM) ? (1 << REM) : 3);
+    return s < NMAIN ? (1 << LB) : ((s == NMAIN && REM) ? (1 << REM) : 3);
   }
   static constexpr int radix(int s) { return INV ? fwd_radix(NST - 1 - s) : fwd_radix(s); }
   static constexpr int ns(int s) {

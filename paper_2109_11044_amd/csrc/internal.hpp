@@ -123,6 +123,14 @@ struct TorusTables {
 
 struct cesim_ctx_s {
   hipStream_t stream = nullptr;
+  // condition() runs the observation factorisation, the upload of the
+  // observed values and the FP64 prediction -- which do not need the drawn
+  // fields -- on aux, overlapping the draw queued on stream.  aux first waits
+  // for last_use (recorded on stream after the previous condition()'s last
+  // kernel); stream waits for aux_done before it uses their results.
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_done = nullptr, last_use = nullptr;
+  bool last_use_valid = false, aux_pending = false;
   cesim_cov cov{};
   cesim_grid grid{};
   cesim_precision prec = CESIM_PREC_FP64;
@@ -162,6 +170,7 @@ struct cesim_ctx_s {
   cesim::DevBuf coef;               // [R][n] FP64: z - z*, then the coefficients
   cesim::DevBuf coef_b16;           // half-precision hi / lo coefficients + column scales (mixed)
   cesim::DevBuf chat;               // mixed path: A^{-1} z, FP64 [n]
+  cesim::DevBuf chat_tmp;           // second buffer of that solve
   cesim::DevBuf yhat;               // mixed path: K12 A^{-1} z on the grid, FP32 [M]
   cesim::DevBuf info_dev;           // int flags
   std::vector<double> z_host_cached;
@@ -192,7 +201,10 @@ cesim_status lk_setup_device(cesim_ctx c);
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields);
 cesim_status lk_phi_device(cesim_ctx c, double tau2);
 cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, bool with_z);
-cesim_status predict_device(cesim_ctx c);
+cesim_status predict_device(cesim_ctx c, hipStream_t s);
+cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s);
+cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y);
+cesim_status aux_wait_last_use(cesim_ctx c);
 cesim_status copy_coefficients_device(cesim_ctx c, double* out);
 cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields);
 cesim_status krige_reserve(cesim_ctx c, int R);

@@ -537,8 +537,6 @@ k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
 
 // ------------------------------------------------------------------- host
 
-cesim_status chol_factor_device(cesim_ctx c, double tau2);
-cesim_status chol_solve_device(cesim_ctx c, double* X, int R);
 
 // Linear map U (range units) and the per-path coordinate scale.
 static void cov_map(const cesim_ctx c, double scale, double& ux, double& uxy, double& uyx,
@@ -563,37 +561,49 @@ cesim_status krige_reserve(cesim_ctx c, int R) {
   return CESIM_OK;
 }
 
-static cesim_status predict_from_chat(cesim_ctx c);
+static cesim_status predict_from_chat(cesim_ctx c, hipStream_t s);
+
+// aux waits for the last kernel of the previous condition() that read the
+// factor, the observed values or the prediction (once per condition()).
+cesim_status aux_wait_last_use(cesim_ctx c) {
+  if (c->last_use_valid) {
+    CESIM_HIP(hipStreamWaitEvent(c->aux, c->last_use, 0));
+    c->last_use_valid = false;
+  }
+  return CESIM_OK;
+}
 
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   hipStream_t s = c->stream;
   const int n = c->nobs, R = c->nreal;
-  if (!c->chol_valid || c->chol_nugget != nugget) {
-    c->chol_valid = false;
-    CESIM_TRY(chol_factor_device(c, nugget));
-    c->chol_valid = true;
-    c->chol_nugget = nugget;
+  const bool mixed = c->prec == CESIM_PREC_MIXED;
+  const bool refactor = !c->chol_valid || c->chol_nugget != nugget;
+  if (refactor || (mixed && !c->yhat_valid)) {
+    CESIM_TRY(aux_wait_last_use(c));
+    if (refactor) {
+      c->chol_valid = false;
+      CESIM_TRY(chol_factor_device(c, nugget, c->aux));
+      c->chol_valid = true;
+      c->chol_nugget = nugget;
+    }
+    if (mixed) CESIM_TRY(predict_device(c, c->aux));
+    c->aux_pending = true;
+  }
+  if (c->aux_pending) {
+    CESIM_HIP(hipEventRecord(c->aux_done, c->aux));
+    CESIM_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
+    c->aux_pending = false;
   }
   CESIM_TRY(lk_phi_device(c, nugget));
-  const bool mixed = c->prec == CESIM_PREC_MIXED;
-  // on the mixed path a stale prediction is refreshed with the same solve:
-  // z rides along as row R of the right-hand sides
-  const bool with_chat = mixed && !c->yhat_valid;
-  CESIM_TRY(krige_reserve(c, R + (with_chat ? 1 : 0)));
+  CESIM_TRY(krige_reserve(c, R));
   double* X = c->coef.as<double>();
-  if (with_chat)
-    CESIM_HIP(hipMemcpyAsync(X + (size_t)R * n, c->zdev.p, sizeof(double) * n,
-                             hipMemcpyDeviceToDevice, s));
   // FP64: X = A^{-1} (z - z*_r); mixed: X = -A^{-1} z*_r (yhat carries z)
   CESIM_TRY(lk_synth_rhs_device(c, fields, X, !mixed));
-  CESIM_TRY(chol_solve_device(c, X, R + (with_chat ? 1 : 0)));
-  if (with_chat) {
-    CESIM_TRY(c->chat.reserve(sizeof(double) * n));
-    CESIM_HIP(hipMemcpyAsync(c->chat.p, X + (size_t)R * n, sizeof(double) * n,
-                             hipMemcpyDeviceToDevice, s));
-    CESIM_TRY(predict_from_chat(c));
-  }
-  return krige_grid_device(c, X, fields);
+  CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
+  CESIM_TRY(krige_grid_device(c, X, fields));
+  CESIM_HIP(hipEventRecord(c->last_use, s));
+  c->last_use_valid = true;
+  return CESIM_OK;
 }
 
 // fields[r] += K12 X[r] for the c->nreal realizations of the last draw
@@ -704,9 +714,8 @@ cesim_status copy_coefficients_device(cesim_ctx c, double* out) {
   return CESIM_OK;
 }
 
-// yhat from c->chat (already A^{-1} z).
-static cesim_status predict_from_chat(cesim_ctx c) {
-  hipStream_t s = c->stream;
+// yhat from c->chat (already A^{-1} z), on stream s.
+static cesim_status predict_from_chat(cesim_ctx c, hipStream_t s) {
   const int n = c->nobs, m1 = c->grid.m1, M = c->grid.m1 * c->grid.m2;
   CESIM_TRY(c->yhat.reserve(sizeof(float) * M));
   double ux, uxy, uyx, uy;
@@ -729,15 +738,16 @@ static cesim_status predict_from_chat(cesim_ctx c) {
   return CESIM_OK;
 }
 
-cesim_status predict_device(cesim_ctx c) {
+// Mixed path: chat = A^{-1} z and yhat = K12 chat (FP64, stored FP32) on
+// stream s, once per factorisation and set of observed values.
+cesim_status predict_device(cesim_ctx c, hipStream_t s) {
   if (c->yhat_valid) return CESIM_OK;
   const int n = c->nobs;
   CESIM_TRY(c->chat.reserve(sizeof(double) * n));
-  CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * n));
-  CESIM_HIP(hipMemcpyAsync(c->chat.p, c->zdev.p, sizeof(double) * n, hipMemcpyDeviceToDevice,
-                           c->stream));
-  CESIM_TRY(chol_solve_device(c, c->chat.as<double>(), 1));
-  return predict_from_chat(c);
+  CESIM_TRY(c->chat_tmp.reserve(sizeof(double) * n));
+  CESIM_HIP(hipMemcpyAsync(c->chat.p, c->zdev.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  CESIM_TRY(chol_solve_device(c, c->chat.as<double>(), 1, s, c->chat_tmp.as<double>()));
+  return predict_from_chat(c, s);
 }
 
 }  // namespace cesim

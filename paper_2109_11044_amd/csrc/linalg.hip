@@ -66,7 +66,9 @@ __device__ __forceinline__ void wave_lds_order() {
 // nbk); bit 2 of *info marks a non-positive pivot.
 __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, int k0, int nbk,
                                                 double* __restrict__ dinv, int* __restrict__ info) {
-  __shared__ double Ls[kNB][kNB + 1];
+  // L packed by rows (row r at r (r + 1) / 2): 16.6 KB, small enough to
+  // share a CU with the draw kernels when condition() overlaps them
+  __shared__ double Ls[kNB * (kNB + 1) / 2];
   __shared__ double col[kNB];
   __shared__ double rinv[kNB];
   const int i = threadIdx.x;
@@ -92,9 +94,10 @@ __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, i
     rinv[j] = r;
     wave_lds_order();
   }
+  const int prow = i * (i + 1) / 2;
 #pragma unroll
   for (int k = 0; k < kNB; ++k) {
-    Ls[i][k] = (k <= i) ? a[k] : 0.0;
+    if (k <= i) Ls[prow + k] = a[k];
     if (i < nbk && k <= i) A[(size_t)(k0 + i) * n + k0 + k] = a[k];
   }
   wave_lds_order();
@@ -106,7 +109,7 @@ __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, i
     x[q] *= rinv[q];
 #pragma unroll
     for (int r = q + 1; r < kNB; ++r) {
-      x[r] = fma(-Ls[r][q], x[q], x[r]);
+      x[r] = fma(-Ls[r * (r + 1) / 2 + q], x[q], x[r]);
       if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -277,8 +280,7 @@ static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s) 
 
 // Factor A = K22 + tau^2 I in place (lower triangle).  Synchronises and
 // reports NOT_POSITIVE_DEFINITE on a non-positive pivot.
-cesim_status chol_factor_device(cesim_ctx c, double tau2) {
-  hipStream_t s = c->stream;
+cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s) {
   c->yhat_valid = false;
   const int n = c->nobs;
   const int nblk = (n + kNB - 1) / kNB;
@@ -336,12 +338,12 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2) {
 // X holds the right-hand sides and ends with the solution; no GEMM writes
 // what it reads.  Forward step kb is fwd[kb], backward step st (counted from
 // the last block) bwd[st].
-static void solve_step_lists(cesim_ctx c, double* X, int R, std::vector<std::vector<GemmArgs>>& fwd,
+static void solve_step_lists(cesim_ctx c, double* X, double* Y, int R,
+                             std::vector<std::vector<GemmArgs>>& fwd,
                              std::vector<std::vector<GemmArgs>>& bwd) {
   const int n = c->nobs, nbig = (n + kSB - 1) / kSB;
   const double* L = c->amat.as<double>();
   const double* W = c->winv.as<double>();
-  double* Y = c->solve_tmp.as<double>();
   fwd.assign(nbig, {});
   bwd.assign(nbig, {});
   for (int kb = 0; kb < nbig; ++kb) {
@@ -380,9 +382,9 @@ static void solve_step_lists(cesim_ctx c, double* X, int R, std::vector<std::vec
   }
 }
 
-static void solve_steps(cesim_ctx c, double* X, int R, std::vector<GemmArgs>& out) {
+static void solve_steps(cesim_ctx c, double* X, double* Y, int R, std::vector<GemmArgs>& out) {
   std::vector<std::vector<GemmArgs>> fwd, bwd;
-  solve_step_lists(c, X, R, fwd, bwd);
+  solve_step_lists(c, X, Y, R, fwd, bwd);
   for (auto& v : fwd) out.insert(out.end(), v.begin(), v.end());
   for (auto& v : bwd) out.insert(out.end(), v.begin(), v.end());
 }
@@ -391,12 +393,11 @@ static void solve_steps(cesim_ctx c, double* X, int R, std::vector<GemmArgs>& ou
 // Every step is a GEMM with the realizations as its rows, so that each lane
 // of a tile writes consecutive observations of one realization (X is
 // [R][n], observation index fastest).
-cesim_status chol_solve_device(cesim_ctx c, double* X, int R) {
-  hipStream_t s = c->stream;
-  CESIM_TRY(c->solve_tmp.reserve(sizeof(double) * (size_t)c->nobs * R));
+// Y: second buffer of at least R n doubles.
+cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y) {
   const int tr = c->timer.begin(ST_SOLVE, s);
   std::vector<GemmArgs> steps;
-  solve_steps(c, X, R, steps);
+  solve_steps(c, X, Y, R, steps);
   for (const GemmArgs& g : steps) CESIM_TRY(gemm_f64(g, false, s));
   c->timer.end(tr, s);
   return CESIM_OK;
@@ -536,7 +537,7 @@ cesim_status chol_solve_batch_plan(const std::vector<cesim_ctx>& cs,
   std::vector<std::vector<std::vector<GemmArgs>>> fwd(ne), bwd(ne);
   int maxnb = 0;
   for (int e = 0; e < ne; ++e) {
-    solve_step_lists(cs[e], X[e], R[e], fwd[e], bwd[e]);
+    solve_step_lists(cs[e], X[e], cs[e]->solve_tmp.as<double>(), R[e], fwd[e], bwd[e]);
     maxnb = std::max(maxnb, (int)fwd[e].size());
   }
   for (int pass = 0; pass < 2; ++pass)
