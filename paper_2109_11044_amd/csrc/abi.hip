@@ -237,7 +237,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
-          &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev};
+          &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev};
 }
 
 void ce_destroy(cesim_ctx c) {
@@ -246,8 +246,10 @@ void ce_destroy(cesim_ctx c) {
   if (c->aux) (void)hipStreamSynchronize(c->aux);
   c->timer.destroy();
   for (DevBuf* b : all_bufs(c)) b->release();
-  if (c->aux_done) (void)hipEventDestroy(c->aux_done);
-  if (c->last_use) (void)hipEventDestroy(c->last_use);
+  c->winv_stage.release();
+  if (c->chol_info_host) (void)hipHostFree(c->chol_info_host);
+  for (hipEvent_t e : {c->aux_done, c->last_use, c->factor_ready, c->z_ready})
+    if (e) (void)hipEventDestroy(e);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
@@ -341,16 +343,25 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
   c->gridd = {grid->m1, grid->m2, grid->x0, grid->y0, grid->dx, grid->dy};
   if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->aux_done, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->factor_ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->z_ready, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void**)&c->chol_info_host, sizeof(int) * 4, hipHostMallocDefault) !=
+          hipSuccess) {
+    (void)hipGetLastError();
     ce_destroy(c);
     return CESIM_ERR_HIP;
   }
+  c->chol_info_host[0] = 0;
   for (DevBuf* b : all_bufs(c)) b->stream = c->stream;
   for (DevBuf* b : {&c->amat, &c->dinv, &c->winv, &c->wtmp, &c->chat, &c->chat_tmp, &c->yhat,
-                    &c->zdev})
+                    &c->zdev, &c->chol_info, &c->winv_seq.dev})
     b->stream = c->aux;                 // written by the work condition() puts on aux
   c->timer.enabled = g_default_timing;
   cesim_status st = c->info_dev.reserve(sizeof(int) * 4);
+  if (st == CESIM_OK) st = c->chol_info.reserve(sizeof(int) * 4);
+  if (st == CESIM_OK && hipMemsetAsync(c->chol_info.p, 0, sizeof(int) * 4, c->stream) != hipSuccess)
+    st = CESIM_ERR_HIP;
   if (st != CESIM_OK) { ce_destroy(c); return st; }
   std::vector<std::pair<int, int>> cands;
   if (grid->t1 == 0 && grid->t2 == 0) {
@@ -498,6 +509,8 @@ cesim_status condition(cesim_ctx c, const double* z, double nugget, void* fields
     CESIM_TRY(aux_wait_last_use(c));
     CESIM_HIP(hipMemcpyAsync(c->zdev.p, c->z_host_cached.data(), sizeof(double) * n,
                              hipMemcpyHostToDevice, c->aux));
+    CESIM_HIP(hipEventRecord(c->z_ready, c->aux));
+    c->z_pending = true;
     c->aux_pending = true;
   }
   return condition_device(c, nugget, fields);

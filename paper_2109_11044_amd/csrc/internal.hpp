@@ -91,6 +91,18 @@ struct DiagDesc {
 // A recorded sequence of grouped launches over several independent systems
 // (diagonal factorisations and FP64 GEMMs), uploaded once and then launched
 // any number of times without host work beyond the launches themselves.
+// Pinned host staging of an asynchronous upload: the host copy stays
+// untouched until the copy recorded by `done` has run.
+struct PinnedStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  cesim_status acquire(size_t n);   // waits for the previous copy; grows to n bytes
+  cesim_status mark(hipStream_t s); // records done after a copy queued on s
+  void release();
+};
+
 struct GroupedSeq {
   struct Launch { int kind, first, count, blocks, pfx; };   // kind: 0 diag, 1 GEMM, 2 lower GEMM
   std::vector<DiagDesc> diag;
@@ -103,7 +115,9 @@ struct GroupedSeq {
   int* d_pfx = nullptr;
   void add_diag(const std::vector<DiagDesc>& v);
   void add_gemm(const std::vector<GemmArgs>& v, bool lower);   // empty problems are dropped
+  void clear();                                                // keeps the device buffer
   cesim_status upload(hipStream_t s);                          // synchronises s
+  cesim_status upload_async(hipStream_t s, PinnedStage& st);   // does not synchronise
   cesim_status launch(hipStream_t s) const;
 };
 
@@ -128,9 +142,11 @@ struct cesim_ctx_s {
   // fields -- on aux, overlapping the draw queued on stream.  aux first waits
   // for last_use (recorded on stream after the previous condition()'s last
   // kernel); stream waits for aux_done before it uses their results.
+  // factor_ready: the factor and block inverses are complete (the solves
+  // may start); z_ready: the observed values are on the device.
   hipStream_t aux = nullptr;
-  hipEvent_t aux_done = nullptr, last_use = nullptr;
-  bool last_use_valid = false, aux_pending = false;
+  hipEvent_t aux_done = nullptr, last_use = nullptr, factor_ready = nullptr, z_ready = nullptr;
+  bool last_use_valid = false, aux_pending = false, z_pending = false;
   cesim_cov cov{};
   cesim_grid grid{};
   cesim_precision prec = CESIM_PREC_FP64;
@@ -172,7 +188,12 @@ struct cesim_ctx_s {
   cesim::DevBuf chat;               // mixed path: A^{-1} z, FP64 [n]
   cesim::DevBuf chat_tmp;           // second buffer of that solve
   cesim::DevBuf yhat;               // mixed path: K12 A^{-1} z on the grid, FP32 [M]
-  cesim::DevBuf info_dev;           // int flags
+  cesim::DevBuf info_dev;           // int flags of the local-Kriging setup
+  cesim::DevBuf chol_info;          // int[4]: bit 2 of [0] marks a failed factorisation;
+                                    // the grid GEMM leaves the fields alone when it is set
+  int* chol_info_host = nullptr;    // pinned copy, valid once factor_ready has completed
+  cesim::GroupedSeq winv_seq;       // launches that build winv (kept until they have run)
+  cesim::PinnedStage winv_stage;
   std::vector<double> z_host_cached;
 
   int gemm_tile = 0;                // mixed grid GEMM tile, 1-3 (0: tuning table, else 1)

@@ -53,7 +53,8 @@ template <> struct HalfOps<_Float16> {
 __global__ void __launch_bounds__(256, 2)
 k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __restrict__ X,
             int n, const double2* __restrict__ st, double ux, double uxy, double uyx, double uy,
-            double dx, double dy, int nu_code, double sigma2) {
+            double dx, double dy, int nu_code, double sigma2, const int* __restrict__ fail) {
+  if (fail[0] & 2) return;   // failed factorisation: the fields stay as drawn
   constexpr int TG = 128, TR = 128, TK = 16;
   __shared__ double Xs[2][TK][TR + 1];
   __shared__ double2 Ss[2][TK];
@@ -312,7 +313,8 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
                const H* __restrict__ Bh, const H* __restrict__ Bl,
                const float* __restrict__ colscale, const float* __restrict__ yhat, int n,
                const float2* __restrict__ st, float ux, float uxy, float uyx, float uy, float dx,
-               float dy, float kscale) {
+               float dy, float kscale, const int* __restrict__ fail) {
+  if (fail[0] & 2) return;   // failed factorisation: the fields stay as drawn
   using HV = typename HalfOps<H>::V;
   constexpr int TG = 128 * NF, TR = 256;
   __shared__ __align__(16) H Sh[2][TR * kKC];
@@ -433,7 +435,8 @@ k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
                  const H* __restrict__ Bh, const H* __restrict__ Bl,
                  const float* __restrict__ colscale, const float* __restrict__ yhat, int n,
                  const float2* __restrict__ st, float ux, float uxy, float uyx, float uy,
-                 float dx, float dy, float kscale) {
+                 float dx, float dy, float kscale, const int* __restrict__ fail) {
+  if (fail[0] & 2) return;   // failed factorisation: the fields stay as drawn
   using HV = typename HalfOps<H>::V;
   constexpr int TG = 128, TR = 512;
   __shared__ __align__(16) H Sh[2][TR * kKC];
@@ -573,9 +576,15 @@ cesim_status aux_wait_last_use(cesim_ctx c) {
   return CESIM_OK;
 }
 
+// Everything is queued before the host waits: on aux the factorisation (when
+// the nugget or the stations changed) and the mixed path's prediction, on
+// the stream the synthetic data, the solves (after factor_ready) and the
+// grid GEMM (after aux_done).  Only then does a new factorisation's status
+// come back to the host; after a failed pivot the GEMM has left the fields
+// unchanged.
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   hipStream_t s = c->stream;
-  const int n = c->nobs, R = c->nreal;
+  const int R = c->nreal;
   const bool mixed = c->prec == CESIM_PREC_MIXED;
   const bool refactor = !c->chol_valid || c->chol_nugget != nugget;
   if (refactor || (mixed && !c->yhat_valid)) {
@@ -583,26 +592,37 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     if (refactor) {
       c->chol_valid = false;
       CESIM_TRY(chol_factor_device(c, nugget, c->aux));
-      c->chol_valid = true;
-      c->chol_nugget = nugget;
+      CESIM_HIP(hipEventRecord(c->factor_ready, c->aux));
     }
     if (mixed) CESIM_TRY(predict_device(c, c->aux));
     c->aux_pending = true;
-  }
-  if (c->aux_pending) {
-    CESIM_HIP(hipEventRecord(c->aux_done, c->aux));
-    CESIM_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
-    c->aux_pending = false;
   }
   CESIM_TRY(lk_phi_device(c, nugget));
   CESIM_TRY(krige_reserve(c, R));
   double* X = c->coef.as<double>();
   // FP64: X = A^{-1} (z - z*_r); mixed: X = -A^{-1} z*_r (yhat carries z)
+  if (!mixed && c->z_pending) CESIM_HIP(hipStreamWaitEvent(s, c->z_ready, 0));
+  c->z_pending = false;
   CESIM_TRY(lk_synth_rhs_device(c, fields, X, !mixed));
+  if (refactor) CESIM_HIP(hipStreamWaitEvent(s, c->factor_ready, 0));
   CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
+  if (c->aux_pending) {
+    CESIM_HIP(hipEventRecord(c->aux_done, c->aux));
+    CESIM_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
+    c->aux_pending = false;
+  }
   CESIM_TRY(krige_grid_device(c, X, fields));
   CESIM_HIP(hipEventRecord(c->last_use, s));
   c->last_use_valid = true;
+  if (refactor) {
+    CESIM_HIP(hipEventSynchronize(c->factor_ready));
+    if (c->chol_info_host[0] & 2) {
+      c->yhat_valid = false;
+      return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+    }
+    c->chol_valid = true;
+    c->chol_nugget = nugget;
+  }
   return CESIM_OK;
 }
 
@@ -620,7 +640,7 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
     const int tr = c->timer.begin(ST_KRIGE_GEMM, s);
     k_krige_f64<<<grid, 256, 0, s>>>(static_cast<double*>(fields), m1, M, R, X, n,
                                      c->obs_t64.as<double2>(), ux, uxy, uyx, uy, dx, dy,
-                                     c->covd.nu_code, c->covd.sigma2);
+                                     c->covd.nu_code, c->covd.sigma2, c->chol_info.as<int>());
     CESIM_HIP(hipGetLastError());
     c->timer.end(tr, s);
     return CESIM_OK;
@@ -656,13 +676,14 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   const float* YH = c->yhat.as<float>();
   const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
   const float fdx = (float)dx, fdy = (float)dy, fks = (float)ks;
+  const int* FAIL = c->chol_info.as<int>();
   const int nf = tile == 2 ? 2 : 1;
   dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
   const dim3 gridx((M + 127) / 128, Rp / 512);
 #define CESIM_KS(NU, NF, H)                                                                     \
   k_krige_split3<NU, NF, H><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh), \
                                                  reinterpret_cast<const H*>(Hl), colscale, YH, n, \
-                                                 S2, a, b, cc, d, fdx, fdy, fks)
+                                                 S2, a, b, cc, d, fdx, fdy, fks, FAIL)
 #define CESIM_KS_NU(NF, H)                  \
   switch (c->covd.nu_code) {                \
     case 0: CESIM_KS(0, NF, H); break;      \
@@ -672,7 +693,7 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
 #define CESIM_KX(NU, H)                                                                         \
   k_krige_split3_x<NU, H><<<gridx, 512, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh),  \
                                                 reinterpret_cast<const H*>(Hl), colscale, YH, n,  \
-                                                S2, a, b, cc, d, fdx, fdy, fks)
+                                                S2, a, b, cc, d, fdx, fdy, fks, FAIL)
 #define CESIM_KX_NU(H)                      \
   switch (c->covd.nu_code) {                \
     case 0: CESIM_KX(0, H); break;          \

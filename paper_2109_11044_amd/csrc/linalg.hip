@@ -10,6 +10,7 @@
 // FP64 matrix-core GEMM (v_mfma_f64_16x16x4f64, 64 x 64 tiles).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <vector>
 
 #include "internal.hpp"
@@ -137,8 +138,8 @@ __global__ void __launch_bounds__(64) k_potrf_diag_grp(const DiagDesc* __restric
 template <bool LOWER>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
   constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ double As[TK][TM + 2];
-  __shared__ double Bs[TK][TN + 2];
+  __shared__ double As[2][TK][TM + 2];
+  __shared__ double Bs[2][TK][TN + 2];
   if (LOWER && bj > bi) return;
   const int i0 = bi * TM, j0 = bj * TN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -150,28 +151,49 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
     for (int b = 0; b < 2; ++b) acc[a][b] = (doublex4){0.0, 0.0, 0.0, 0.0};
   const bool a_ifast = (g.sai == 1);
   const bool b_jfast = (g.sbj == 1);
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
+  // element u of this thread's share of a k-step: (row, k) of the A tile
+  // and (k, column) of the B tile, along the operand's contiguous index
+  int ai[4], ak[4], bj_[4], bk[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    if (a_ifast) { ai[u] = e % TM; ak[u] = e / TM; } else { ak[u] = e % TK; ai[u] = e / TK; }
+    if (b_jfast) { bj_[u] = e % TN; bk[u] = e / TN; } else { bk[u] = e % TK; bj_[u] = e / TK; }
+  }
+  double ra[4], rb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      int ii, kk;
-      if (a_ifast) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
-      const int gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < g.M && gk < g.K) ? g.A[gi * g.sai + gk * g.sak] : 0.0;
-      int jj;
-      if (b_jfast) { jj = e % TN; kk = e / TN; } else { kk = e % TK; jj = e / TK; }
-      const int gj = j0 + jj, gk2 = k0 + kk;
-      Bs[kk][jj] = (gj < g.N && gk2 < g.K) ? g.B[gk2 * g.sbk + gj * g.sbj] : 0.0;
+      const int gi = i0 + ai[u], gk = k0 + ak[u];
+      ra[u] = (gi < g.M && gk < g.K) ? g.A[gi * g.sai + gk * g.sak] : 0.0;
+      const int gj = j0 + bj_[u], gk2 = k0 + bk[u];
+      rb[u] = (gj < g.N && gk2 < g.K) ? g.B[gk2 * g.sbk + gj * g.sbj] : 0.0;
     }
-    __syncthreads();
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[buf][ak[u]][ai[u]] = ra[u];
+      Bs[buf][bk[u]][bj_[u]] = rb[u];
+    }
+  };
+  // one barrier per k-step: the next step's operands are fetched into
+  // registers during this step's products and stored into the other buffer
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    const bool more = k0 + TK < g.K;
+    if (more) fetch(k0 + TK);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
       double a[2], b[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        a[t] = As[kk][wr + 16 * t + (lane & 15)];
-        b[t] = Bs[kk][wc + 16 * t + (lane & 15)];
+        a[t] = As[buf][kk][wr + 16 * t + (lane & 15)];
+        b[t] = Bs[buf][kk][wc + 16 * t + (lane & 15)];
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
@@ -179,7 +201,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
         for (int y = 0; y < 2; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -234,8 +258,11 @@ cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s) {
 // context, for the substitutions.  With the 64-block inverses D_i on its
 // diagonal, block row i of W_B is W_{i,0:i} = -D_i (L_{i,0:i} W_{0:i,0:i})
 // (block forward substitution on the identity); rows i = 1, 2, 3 in turn,
-// each as two grouped GEMMs over all blocks of all contexts.  Synchronises.
-static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s) {
+// each as two grouped GEMMs over all blocks of all contexts.  With keep
+// (one context) the launch table is uploaded through the context's pinned
+// stage and kept there, and nothing synchronises; otherwise synchronises.
+static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s,
+                               GroupedSeq* keep = nullptr) {
   std::vector<std::vector<GemmArgs>> lv(6);
   for (cesim_ctx c : cs) {
     const int n = c->nobs, nblk = (n + kNB - 1) / kNB, nbig = (n + kSB - 1) / kSB;
@@ -267,6 +294,14 @@ static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s) 
       }
     }
   }
+  if (keep) {
+    keep->clear();
+    keep->dev.stream = s;
+    for (auto& v : lv) keep->add_gemm(v, false);
+    if (keep->launches.empty()) return CESIM_OK;
+    CESIM_TRY(keep->upload_async(s, cs[0]->winv_stage));
+    return keep->launch(s);
+  }
   GroupedSeq seq;
   for (auto& v : lv) seq.add_gemm(v, false);
   if (!seq.launches.empty()) {
@@ -278,8 +313,11 @@ static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s) 
   return CESIM_OK;
 }
 
-// Factor A = K22 + tau^2 I in place (lower triangle).  Synchronises and
-// reports NOT_POSITIVE_DEFINITE on a non-positive pivot.
+// Factor A = K22 + tau^2 I in place (lower triangle) and build the block
+// inverses of the solves, all queued on s without synchronising.  A
+// non-positive pivot sets bit 2 of c->chol_info[0] on the device; its
+// pinned copy c->chol_info_host is valid once work queued on s after this
+// call has completed.
 cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s) {
   c->yhat_valid = false;
   const int n = c->nobs;
@@ -288,7 +326,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s) {
   CESIM_TRY(c->dinv.reserve(sizeof(double) * (size_t)nblk * kNB * kNB));
   double* A = c->amat.as<double>();
   double* D = c->dinv.as<double>();
-  int* info = c->info_dev.as<int>();
+  int* info = c->chol_info.as<int>();
   CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
   const int tr = c->timer.begin(ST_CHOL, s);
   k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd, tau2,
@@ -316,14 +354,10 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s) {
     g.C = A + (size_t)(k0 + nbk) * n + (k0 + nbk); g.sci = n; g.scj = 1;
     CESIM_TRY(gemm_f64(g, true, s));
   }
-  int hinfo[4];
-  CESIM_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
-  CESIM_HIP(hipStreamSynchronize(s));
-  if (hinfo[0] & 2) {
-    c->timer.end(tr, s);
-    return CESIM_ERR_NOT_POSITIVE_DEFINITE;
-  }
-  CESIM_TRY(build_winv({c}, s));
+  CESIM_HIP(hipMemcpyAsync(c->chol_info_host, info, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+  // after a failed pivot the inverses are built from meaningless values;
+  // nothing downstream writes the fields then
+  CESIM_TRY(build_winv({c}, s, &c->winv_seq));
   c->timer.end(tr, s);
   return CESIM_OK;
 }
@@ -427,6 +461,69 @@ void GroupedSeq::add_gemm(const std::vector<GemmArgs>& v, bool lower) {
   launches.push_back(l);
 }
 
+void GroupedSeq::clear() {
+  diag.clear();
+  gemm.clear();
+  pfx.clear();
+  launches.clear();
+}
+
+cesim_status PinnedStage::acquire(size_t n) {
+  if (pending) {
+    CESIM_HIP(hipEventSynchronize(done));
+    pending = false;
+  }
+  if (!done) CESIM_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+  if (n <= bytes) return CESIM_OK;
+  if (p) CESIM_HIP(hipHostFree(p));
+  p = nullptr;
+  bytes = 0;
+  if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    return CESIM_ERR_OUT_OF_MEMORY;
+  }
+  bytes = n;
+  return CESIM_OK;
+}
+
+cesim_status PinnedStage::mark(hipStream_t s) {
+  CESIM_HIP(hipEventRecord(done, s));
+  pending = true;
+  return CESIM_OK;
+}
+
+void PinnedStage::release() {
+  if (pending) (void)hipEventSynchronize(done);
+  if (p) (void)hipHostFree(p);
+  if (done) (void)hipEventDestroy(done);
+  p = nullptr;
+  bytes = 0;
+  done = nullptr;
+  pending = false;
+}
+
+// One contiguous table (diag | GEMMs | prefix), each part 256-byte aligned.
+cesim_status GroupedSeq::upload_async(hipStream_t s, PinnedStage& st) {
+  const size_t bd = sizeof(DiagDesc) * diag.size(), bg = sizeof(GemmArgs) * gemm.size();
+  const size_t bp = sizeof(int) * pfx.size();
+  const size_t og = (bd + 255) / 256 * 256, op = og + (bg + 255) / 256 * 256;
+  const size_t total = op + bp;
+  CESIM_TRY(dev.reserve(total + 256));
+  CESIM_TRY(st.acquire(total));
+  unsigned char* h = static_cast<unsigned char*>(st.p);
+  if (bd) std::memcpy(h, diag.data(), bd);
+  if (bg) std::memcpy(h + og, gemm.data(), bg);
+  if (bp) std::memcpy(h + op, pfx.data(), bp);
+  CESIM_HIP(hipMemcpyAsync(dev.p, h, total, hipMemcpyHostToDevice, s));
+  CESIM_TRY(st.mark(s));
+  unsigned char* base = dev.as<unsigned char>();
+  d_diag = reinterpret_cast<DiagDesc*>(base);
+  d_gemm = reinterpret_cast<GemmArgs*>(base + og);
+  d_pfx = reinterpret_cast<int*>(base + op);
+  return CESIM_OK;
+}
+
 cesim_status GroupedSeq::upload(hipStream_t s) {
   const size_t bd = sizeof(DiagDesc) * diag.size(), bg = sizeof(GemmArgs) * gemm.size();
   const size_t bp = sizeof(int) * pfx.size();
@@ -473,7 +570,7 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
     c->yhat_valid = false;
     CESIM_TRY(c->amat.reserve(sizeof(double) * (size_t)n * n));
     CESIM_TRY(c->dinv.reserve(sizeof(double) * (size_t)nblk * kNB * kNB));
-    CESIM_HIP(hipMemsetAsync(c->info_dev.p, 0, sizeof(int) * 4, s));
+    CESIM_HIP(hipMemsetAsync(c->chol_info.p, 0, sizeof(int) * 4, s));
     k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd,
                                                            tau2[e], c->amat.as<double>());
     CESIM_HIP(hipGetLastError());
@@ -489,7 +586,7 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
       const int nbk = std::min(kNB, n - k0), rest = n - k0 - nbk;
       double* A = c->amat.as<double>();
       double* D = c->dinv.as<double>() + (size_t)kb * kNB * kNB;
-      dd.push_back({A, n, k0, nbk, D, c->info_dev.as<int>()});
+      dd.push_back({A, n, k0, nbk, D, c->chol_info.as<int>()});
       if (rest <= 0) continue;
       GemmArgs g;
       g.M = rest; g.N = nbk; g.K = nbk; g.alpha = 1.0; g.beta = 0.0;
@@ -511,7 +608,7 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
   CESIM_TRY(seq.launch(s));
   std::vector<int> flags(4 * ne);
   for (int e = 0; e < ne; ++e)
-    CESIM_HIP(hipMemcpyAsync(&flags[4 * e], cs[e]->info_dev.p, sizeof(int) * 4,
+    CESIM_HIP(hipMemcpyAsync(&flags[4 * e], cs[e]->chol_info.p, sizeof(int) * 4,
                              hipMemcpyDeviceToHost, s));
   CESIM_HIP(hipStreamSynchronize(s));
   std::vector<cesim_ctx> good;
