@@ -576,27 +576,22 @@ cesim_status aux_wait_last_use(cesim_ctx c) {
   return CESIM_OK;
 }
 
-// Everything is queued before the host waits: on aux the factorisation (when
-// the nugget or the stations changed) and the mixed path's prediction, on
-// the stream the synthetic data, the solves (after factor_ready) and the
-// grid GEMM (after aux_done).  Only then does a new factorisation's status
-// come back to the host; after a failed pivot the GEMM has left the fields
-// unchanged.
+// Everything is queued before the host waits, the work of the stream first
+// where it does not depend on aux (launches reach the GPU only as fast as
+// a long dependent chain on aux retires them): the synthetic data, then on
+// aux the factorisation (when the nugget or the stations changed), the
+// solves on the stream after factor_ready, the mixed path's prediction on
+// aux, and the grid GEMM after aux_done.  Only then does a new
+// factorisation's status come back to the host; after a failed pivot the
+// GEMM has left the fields unchanged.
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   hipStream_t s = c->stream;
   const int R = c->nreal;
   const bool mixed = c->prec == CESIM_PREC_MIXED;
   const bool refactor = !c->chol_valid || c->chol_nugget != nugget;
-  if (refactor || (mixed && !c->yhat_valid)) {
-    CESIM_TRY(aux_wait_last_use(c));
-    if (refactor) {
-      c->chol_valid = false;
-      CESIM_TRY(chol_factor_device(c, nugget, c->aux));
-      CESIM_HIP(hipEventRecord(c->factor_ready, c->aux));
-    }
-    if (mixed) CESIM_TRY(predict_device(c, c->aux));
-    c->aux_pending = true;
-  }
+  const bool predict = mixed && (refactor || !c->yhat_valid);
+  if (refactor) c->chol_valid = false;
+  if (predict) c->yhat_valid = false;
   CESIM_TRY(lk_phi_device(c, nugget));
   CESIM_TRY(krige_reserve(c, R));
   double* X = c->coef.as<double>();
@@ -604,8 +599,17 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   if (!mixed && c->z_pending) CESIM_HIP(hipStreamWaitEvent(s, c->z_ready, 0));
   c->z_pending = false;
   CESIM_TRY(lk_synth_rhs_device(c, fields, X, !mixed));
-  if (refactor) CESIM_HIP(hipStreamWaitEvent(s, c->factor_ready, 0));
+  if (refactor || predict) CESIM_TRY(aux_wait_last_use(c));
+  if (refactor) {
+    CESIM_TRY(chol_factor_device(c, nugget, c->aux));
+    CESIM_HIP(hipEventRecord(c->factor_ready, c->aux));
+    CESIM_HIP(hipStreamWaitEvent(s, c->factor_ready, 0));
+  }
   CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
+  if (predict) {
+    CESIM_TRY(predict_device(c, c->aux));
+    c->aux_pending = true;
+  }
   if (c->aux_pending) {
     CESIM_HIP(hipEventRecord(c->aux_done, c->aux));
     CESIM_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
