@@ -280,6 +280,31 @@ cesim_status cesim_tune_load(const char* path);
 int cesim_tune_entries(void);
 void cesim_tune_clear(void);
 
+/* ---- gradient of a linear ensemble statistic ----
+ * The adjoint of steps 1-5 of Section 2 (with the local Kriging of
+ * Section 2.1 and the Kriging system of eq. (4)) for the statistic
+ *   L = (1/R) sum_{r} sum_{g} wgt[g] v_r[g]
+ * over the conditional realizations v_r, r = first_real .. first_real +
+ * nreal - 1, that ce_simulate(ctx, nreal, seed, first_real) followed by
+ * condition(ctx, z, nugget) produces on the FP64 path (noise counters carry
+ * the context's CESIM_PARAM_EVENT_ID).  Because every v_r is affine in its
+ * noise, L and its derivatives are evaluated once on the mean noises of the
+ * R realizations; no field is drawn.  Results (host arrays, caller-owned):
+ *   out[0] = L, out[1] = dL/drange, out[2] = dL/dsigma2, out[3] = dL/dnugget,
+ *   dz[i]  = dL/dz_i for i < nobs.
+ * The range derivative moves the major- and minor-axis ranges together
+ * (fixed anisotropy ratio and angle).  wgt_dev: caller-owned device array
+ * of m1*m2 doubles, [m2][m1], x fastest; z: host [nobs].  Computes in FP64
+ * on either precision (on a MIXED context the draw itself uses FP32 noise,
+ * so its ensemble differs from the FP64 one at the 1e-7 level).  Needs
+ * offgrid_nnkrige (else BAD_STATE); refactors A when the nugget differs from
+ * the last condition().  INVALID_ARG for null pointers, nreal < 1,
+ * first_real < 0, a negative or non-finite nugget or a non-finite z;
+ * NOT_POSITIVE_DEFINITE when A's Cholesky fails.  Synchronises. */
+cesim_status ce_grad_linear(cesim_ctx ctx, const double* z, double nugget, int nreal,
+                            uint64_t seed, int first_real, const void* wgt_dev, double* out,
+                            double* dz);
+
 /* ---- batches of independent events ----
  * One event is the whole conditional simulation above (Section 2 with the
  * local Kriging of Section 2.1) for its own covariance, grid, stations,

@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcesim.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["abi.hip", "ce.hip", "lk.hip", "linalg.hip", "krige.hip", "batch.hip", "tune.hip"]
+SOURCES = ["abi.hip", "ce.hip", "lk.hip", "linalg.hip", "krige.hip", "batch.hip", "tune.hip",
+           "grad.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are not generated
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -28,7 +28,8 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "cesim_stage_name", "cesim_release_cached_memory", "ce_set_param",
            "cesim_batch_create", "cesim_batch_run", "cesim_batch_get_info",
            "cesim_batch_destroy", "cesim_run_events", "ce_autotune",
-           "cesim_tune_save", "cesim_tune_load", "cesim_tune_entries", "cesim_tune_clear"]
+           "cesim_tune_save", "cesim_tune_load", "cesim_tune_entries", "cesim_tune_clear",
+           "ce_grad_linear"]
 PARAM_GEMM_TILE = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
@@ -135,6 +136,7 @@ def lib():
     L.cesim_tune_entries.argtypes = []
     L.cesim_tune_clear.argtypes = []
     L.cesim_tune_clear.restype = None
+    L.ce_grad_linear.argtypes = [vp, dp, d, i, u64, i, vp, dp, dp]
     for name in EXPORTS:
         if name not in VOID_EXPORTS:
             getattr(L, name).restype = i
@@ -334,6 +336,25 @@ class Context:
                "offgrid_copy_weights")
         return cor, w, gm
 
+    def grad_linear(self, z, nugget, nreal, seed, weights, first_real=0):
+        """L = mean over the realizations of sum_g weights[g] v_r[g] and its
+        gradient: {"L", "d_range", "d_sigma2", "d_nugget", "d_z"} (FP64).
+        weights: CUDA float64 tensor of m2 x m1 grid weights."""
+        t = self._torch
+        z = np.ascontiguousarray(z, dtype=np.float64).ravel()
+        if z.size != self.nobs:
+            raise ValueError("z must hold one value per observation")
+        if (not weights.is_cuda or weights.dtype != t.float64 or not weights.is_contiguous()
+                or weights.numel() != self.grid.m1 * self.grid.m2):
+            raise ValueError("weights must be a contiguous CUDA float64 tensor of m2 x m1")
+        out = np.zeros(4)
+        dz = np.zeros(self.nobs)
+        _check(lib().ce_grad_linear(self._h, _dptr(z), float(nugget), int(nreal), int(seed),
+                                    int(first_real), ctypes.c_void_p(weights.data_ptr()),
+                                    _dptr(out), _dptr(dz)), "ce_grad_linear")
+        return {"L": float(out[0]), "d_range": float(out[1]), "d_sigma2": float(out[2]),
+                "d_nugget": float(out[3]), "d_z": dz}
+
     def coefficients(self):
         t = self._torch
         out = t.empty((self.nreal, self.nobs), dtype=t.float64, device="cuda")
@@ -417,3 +438,50 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+def _ensemble_linear_stat_function():
+    import torch
+
+    class EnsembleLinearStat(torch.autograd.Function):
+        """L(range, sigma2, nugget, z) = mean over realizations of the
+        weighted grid sum of the conditional fields; backward is the
+        library's hand-written adjoint (ce_grad_linear)."""
+
+        @staticmethod
+        def forward(ctx, range_, sigma2, nugget, z, spec):
+            cov = make_cov(spec["nu"], float(sigma2), float(range_), spec.get("aniso_ratio", 1.0),
+                           spec.get("aniso_angle", 0.0))
+            with Context(cov, spec["grid"], spec.get("precision", "fp64")) as c:
+                c.set_param(PARAM_EVENT_ID, spec.get("event_id", 0))
+                c.offgrid(spec["obs_xy"], spec["k"])
+                g = c.grad_linear(z.detach().cpu().numpy(), float(nugget), spec["nreal"],
+                                  spec["seed"], spec["weights"], spec.get("first_real", 0))
+            f64 = dict(dtype=torch.float64)
+            ctx.save_for_backward(torch.tensor(g["d_range"], **f64),
+                                  torch.tensor(g["d_sigma2"], **f64),
+                                  torch.tensor(g["d_nugget"], **f64),
+                                  torch.as_tensor(g["d_z"], **f64))
+            return torch.tensor(g["L"], **f64)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            dr, ds, dn, dz = ctx.saved_tensors
+            return grad_out * dr, grad_out * ds, grad_out * dn, grad_out * dz, None
+
+    return EnsembleLinearStat
+
+
+def ensemble_linear_stat(range_, sigma2, nugget, z, spec):
+    """Differentiable (torch.autograd) linear ensemble statistic; see
+    EnsembleLinearStat.  range_, sigma2, nugget: 0-d float64 tensors; z: 1-d
+    float64 tensor; spec: nu, grid, obs_xy, k, nreal, seed, weights (CUDA
+    float64 m2 x m1) and optionally aniso_ratio, aniso_angle, precision,
+    event_id, first_real."""
+    global _ELS
+    if _ELS is None:
+        _ELS = _ensemble_linear_stat_function()
+    return _ELS.apply(range_, sigma2, nugget, z, spec)
+
+
+_ELS = None

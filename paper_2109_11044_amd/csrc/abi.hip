@@ -176,6 +176,7 @@ CovDev make_cov(const cesim_cov& c) {
   d.sigma2 = c.sigma2;
   const double cs = std::cos(c.aniso_angle), sn = std::sin(c.aniso_angle);
   const double a = c.aniso_ratio, it = 1.0 / c.range;
+  d.theta = c.range;
   if (a == 1.0 && c.aniso_angle == 0.0) {
     d.u00 = it; d.u01 = 0.0; d.u10 = 0.0; d.u11 = it;
   } else {
@@ -237,7 +238,8 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
-          &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev};
+          &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
+          &c->gwork, &c->gvec};
 }
 
 void ce_destroy(cesim_ctx c) {

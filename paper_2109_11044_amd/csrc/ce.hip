@@ -40,6 +40,8 @@ __global__ void k_twiddles(int T, double2* tw64, float2* tw32) {
 
 __device__ inline int wrapped_lag(int q, int T) { return q <= T / 2 ? q : q - T; }
 
+// DTH: the theta-derivative of the base instead (same lags, same averaging).
+template <bool DTH>
 __global__ void k_torus_base(CovDev cov, double dx, double dy, int t1, int t2, double2* out) {
   const int q1 = blockIdx.x * blockDim.x + threadIdx.x;
   const int q2 = blockIdx.y;
@@ -48,13 +50,14 @@ __global__ void k_torus_base(CovDev cov, double dx, double dy, int t1, int t2, d
   const double hy = (double)wrapped_lag(q2, t2) * dy;
   const bool nyq1 = (t1 % 2 == 0) && (2 * q1 == t1);
   const bool nyq2 = (t2 % 2 == 0) && (2 * q2 == t2);
+  auto f = [&](double a, double b) { return DTH ? dcov_eval(cov, a, b) : cov_eval(cov, a, b); };
   double c;
   if (nyq1) {
-    c = 0.5 * (cov_eval(cov, hx, hy) + cov_eval(cov, -hx, hy));
+    c = 0.5 * (f(hx, hy) + f(-hx, hy));
   } else if (nyq2) {
-    c = 0.5 * (cov_eval(cov, hx, hy) + cov_eval(cov, hx, -hy));
+    c = 0.5 * (f(hx, hy) + f(hx, -hy));
   } else {
-    c = cov_eval(cov, hx, hy);
+    c = f(hx, hy);
   }
   out[(size_t)q2 * t1 + q1] = {c, 0.0};
 }
@@ -532,8 +535,8 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
   CESIM_TRY(c->work.reserve(sizeof(double2) * N));
   double2* buf = c->work.as<double2>();
   int tr = c->timer.begin(ST_SETUP_BASE, s);
-  k_torus_base<<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy, t1,
-                                                          t2, buf);
+  k_torus_base<false><<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy,
+                                                                 t1, t2, buf);
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   tr = c->timer.begin(ST_SETUP_FFT, s);
@@ -739,6 +742,54 @@ int draw_chunk_pairs(cesim_ctx c, int nreal) {
   int chunk = (int)std::max<size_t>(1, std::min<size_t>(npairs, budget / draw_pair_bytes(c)));
   if (c->draw_chunk_pairs > 0) chunk = std::min(npairs, c->draw_chunk_pairs);
   return chunk;
+}
+
+// d sqrt(lambda)/dtheta / N from dlambda = Re FFT2 of the theta-derivative of
+// the base (in buf) and s = sqrt(lambda) / N; zero where lambda <= 1e-12
+// lambda_max, where the setup clamps lambda.
+__global__ void k_dsqrt_lambda(const double2* __restrict__ dlam, const double* __restrict__ s,
+                               size_t N, double lam_floor, double* __restrict__ ds) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const double sq = s[q] * (double)N;          // sqrt(lambda)
+  ds[q] = (sq * sq > lam_floor) ? dlam[q].x / (2.0 * sq * (double)N) : 0.0;
+}
+
+__global__ void k_real_to_complex(const double* __restrict__ a, size_t N, double2* __restrict__ out) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < N) out[q] = {a[q], 0.0};
+}
+
+// Mean-noise fields of the linear-statistic gradient (FP64, general FFT
+// passes on one pair buffer): yb = crop(F^-1 diag(sqrt(lambda)) F eps_bar)
+// and dyb = crop(F^-1 diag(d sqrt(lambda)/dtheta) F eps_bar), [m2][m1].
+cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* yb, double* dyb) {
+  hipStream_t s = c->stream;
+  const int t1 = c->t1, t2 = c->t2, m1 = c->grid.m1, m2 = c->grid.m2;
+  const size_t N = (size_t)t1 * t2;
+  CESIM_TRY(c->gwork.reserve(sizeof(double2) * N + sizeof(double) * N));
+  double2* buf = c->gwork.as<double2>();
+  double* ds = reinterpret_cast<double*>(buf + N);
+  const double2* tw1 = c->tt.tw1_64.as<double2>();
+  const double2* tw2 = c->tt.tw2_64.as<double2>();
+  const unsigned nb = (unsigned)((N + 255) / 256);
+  k_torus_base<true><<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy,
+                                                                t1, t2, buf);
+  CESIM_HIP(hipGetLastError());
+  CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, c->tt.p1, tw1, NoiseKey{}, 0, 0, s)));
+  CESIM_TRY((launch_cols<double, false>(buf, t1, t2, 1, t2, c->tt.p2, tw2, nullptr, s)));
+  k_dsqrt_lambda<<<nb, 256, 0, s>>>(buf, c->s64.as<double>(), N, 1e-12 * c->lam_max, ds);
+  CESIM_HIP(hipGetLastError());
+  for (int pass = 0; pass < 2; ++pass) {
+    k_real_to_complex<<<nb, 256, 0, s>>>(eps_bar, N, buf);
+    CESIM_HIP(hipGetLastError());
+    CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, c->tt.p1, tw1, NoiseKey{}, 0, 0, s)));
+    CESIM_TRY((launch_cols<double, true>(buf, t1, t2, 1, m2, c->tt.p2, tw2,
+                                         pass == 0 ? c->s64.as<double>() : ds, s)));
+    CESIM_TRY((launch_rows_inv_crop<double>(buf, pass == 0 ? yb : dyb, t1, t2, m1, m2, 1,
+                                            c->tt.p1, tw1, 1, 0, s)));
+  }
+  return CESIM_OK;
 }
 
 cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields) {

@@ -43,6 +43,7 @@ struct CovDev {
   int nu_code;        // 0: nu = 1/2, 1: nu = 1, 2: nu = 3/2
   double sigma2;
   double u00, u01, u10, u11;
+  double theta;       // range (U is proportional to 1 / theta)
 };
 
 // t K_1(t) for t >= 0 (equals 1 at t = 0), FP64.
@@ -104,6 +105,54 @@ __host__ __device__ inline double matern_rho(int nu_code, double x) {
   return t_bessel_k1(kSqrt2 * x);
 }
 
+// t^2 K_0(t) for t >= 0 (0 at t = 0), FP64, in the three regimes of t K_1:
+//  t <= 2: ascending series (Abramowitz and Stegun 9.6.13),
+//    K_0(t) = -(ln(t/2) + gamma) I_0(t) + sum_{k>=1} H_k (t^2/4)^k / (k!)^2,
+//    I_0(t) = sum_k (t^2/4)^k / (k!)^2,  H_k = 1 + 1/2 + ... + 1/k;
+//  2 < t <= 30: the same trapezoidal rule on K_0(t) = int_0^inf exp(-t cosh u) du;
+//  t > 30: Hankel's expansion (A&S 9.7.2) with 4 nu^2 = 0.
+__host__ __device__ inline double t2_bessel_k0(double t) {
+  if (t <= 0.0) return 0.0;
+  if (t <= 2.0) {
+    const double q = 0.25 * t * t;
+    double f = 1.0, i0 = 0.0, sh = 0.0, h = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      i0 += f;
+      sh += h * f;                                 // H_k (t^2/4)^k / (k!)^2
+      f *= q / (double)((k + 1) * (k + 1));
+      h += 1.0 / (double)(k + 1);
+    }
+    return t * t * (sh - (log(0.5 * t) + kEuler) * i0);
+  }
+  if (t <= 30.0) {
+    double s = 0.5;
+#pragma unroll 4
+    for (int j = 1; j < 32; ++j) s += exp(-t * (cosh_eighth(j) - 1.0));
+    return t * t * exp(-t) * 0.125 * s;
+  }
+  double a = 1.0, s = 1.0;
+#pragma unroll
+  for (int k = 1; k < 22; ++k) {
+    const double m = (double)(2 * k - 1);
+    a *= -(m * m) / (8.0 * (double)k * t);
+    s += a;
+  }
+  return kSqrtHalfPi * t * sqrt(t) * exp(-t) * s;
+}
+
+// g(x) = -x rho_nu'(x), x = d / theta, so that dC/dtheta = sigma^2 g(x) / theta:
+// x e^-x (nu = 1/2), t^2 K_0(t) with t = sqrt(2) x (nu = 1, from
+// d/dt [t K_1(t)] = -t K_0(t), A&S 9.6.28), t^2 e^-t with t = sqrt(3) x (nu = 3/2).
+__host__ __device__ inline double matern_g(int nu_code, double x) {
+  if (nu_code == 0) return x * exp(-x);
+  if (nu_code == 2) {
+    const double t = kSqrt3 * x;
+    return t * t * exp(-t);
+  }
+  return t2_bessel_k0(kSqrt2 * x);
+}
+
 __host__ __device__ inline double lag_x(const CovDev& c, double hx, double hy) {
   const double a = c.u00 * hx + c.u01 * hy;
   const double b = c.u10 * hx + c.u11 * hy;
@@ -112,6 +161,11 @@ __host__ __device__ inline double lag_x(const CovDev& c, double hx, double hy) {
 
 __host__ __device__ inline double cov_eval(const CovDev& c, double hx, double hy) {
   return c.sigma2 * matern_rho(c.nu_code, lag_x(c, hx, hy));
+}
+
+// dC(h) / dtheta (theta the range; the lag length in range units scales as 1 / theta).
+__host__ __device__ inline double dcov_eval(const CovDev& c, double hx, double hy) {
+  return c.sigma2 * matern_g(c.nu_code, lag_x(c, hx, hy)) / c.theta;
 }
 
 // FP32 correlation from a pre-scaled lag length for the mixed-precision

@@ -1,0 +1,239 @@
+// grad.hip -- gradient of a linear ensemble statistic of the conditional
+// realizations (steps 1-5 of Section 2 with the local Kriging of
+// Section 2.1; eq. (4)), FP64:
+//   L = (1/R) sum_r sum_g w_g v_r[g]
+// with respect to the range theta, the sill sigma^2, the nugget tau^2 and the
+// observed values z.  Every v_r is affine in its noise (eps_r of the draw,
+// xi_r of the synthetic data), so L and its derivatives follow from one
+// evaluation on the mean noises eps_bar, xi_bar:
+//   ybar  = crop(F^-1 diag(sqrt(lambda)) F eps_bar),  zbar* = W1 ybar + phi xi_bar,
+//   L     = w . ybar + u . (z - zbar*),  u = A^{-1} p,  p = K21 w,  A = K22 + tau^2 I.
+// With cbar = A^{-1} (z - zbar*) and dA^{-1} = -A^{-1} dA A^{-1}:
+//   dL/dz      = u
+//   dL/dtau^2  = -u . cbar - u . t_tau
+//   dL/dsigma^2 = w . ybar / (2 sigma^2) + p . cbar / sigma^2
+//                 - (u . (z - zbar*) - tau^2 u . cbar) / sigma^2 - u . t_sigma
+//   dL/dtheta  = w . dybar + dp . cbar - u . (dK22 cbar) - u . t_theta
+// where t_* are the derivatives of zbar* (local-Kriging kernel k_lk_grad),
+// dybar the draw with d sqrt(lambda)/dtheta, dp = dK21 w and dK22 the
+// theta-derivatives of the cross- and observation covariances.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cesim {
+
+namespace {
+
+// eps_bar[q] = mean over r of the stream-0 normal of torus element q
+// (block q / 4, word q % 4), r = first .. first + R - 1.
+__global__ void k_mean_torus_noise(uint32_t k0, uint32_t k1, uint32_t event, int first, int R,
+                                   size_t N, double* __restrict__ eb) {
+  const size_t blk = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (blk * 4 >= N) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < R; ++r) {
+    double z[4];
+    normals4_f64(k0, k1, (uint32_t)blk, (uint32_t)(first + r), event, 0u, z);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) acc[w] += z[w];
+  }
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    if (blk * 4 + w < N) eb[blk * 4 + w] = acc[w] / (double)R;
+}
+
+// xi_bar[i] = mean over r of the stream-1 normal of observation i.
+__global__ void k_mean_obs_noise(uint32_t k0, uint32_t k1, uint32_t event, int first, int R,
+                                 int n, double* __restrict__ xb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int r = 0; r < R; ++r) {
+    double z[4];
+    normals4_f64(k0, k1, (uint32_t)(i >> 2), (uint32_t)(first + r), event, 1u, z);
+    acc += z[i & 3];
+  }
+  xb[i] = acc / (double)R;
+}
+
+// p_i = sum_g C(s_i - g) w_g and dp_i = sum_g dC(s_i - g)/dtheta w_g: one
+// workgroup per observation, fixed-order reduction.
+__global__ void __launch_bounds__(256)
+k_cross_gemv(const double* __restrict__ obs, GridDev g, CovDev cov, const double* __restrict__ w,
+             double* __restrict__ p, double* __restrict__ dp) {
+  __shared__ double r0[256], r1[256];
+  const int i = blockIdx.x;
+  const double sx = obs[2 * i], sy = obs[2 * i + 1];
+  const int M = g.m1 * g.m2;
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < M; q += 256) {
+    const int x = q % g.m1, y = q / g.m1;
+    const double hx = __dadd_rn(g.x0, __dmul_rn((double)x, g.dx)) - sx;
+    const double hy = __dadd_rn(g.y0, __dmul_rn((double)y, g.dy)) - sy;
+    const double wq = w[q];
+    a += cov_eval(cov, hx, hy) * wq;
+    b += dcov_eval(cov, hx, hy) * wq;
+  }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      r0[threadIdx.x] += r0[threadIdx.x + h];
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    p[i] = r0[0];
+    dp[i] = r1[0];
+  }
+}
+
+// q_i = sum_j dC(s_i - s_j)/dtheta c_j (the theta-derivative of K22 times c).
+__global__ void __launch_bounds__(256)
+k_dk22_times(const double* __restrict__ obs, int n, CovDev cov, const double* __restrict__ c,
+             double* __restrict__ q) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  const double sx = obs[2 * i], sy = obs[2 * i + 1];
+  double a = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256)
+    a += dcov_eval(cov, sx - obs[2 * j], sy - obs[2 * j + 1]) * c[j];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) q[i] = red[0];
+}
+
+// rhs rows of the solve: row 0 = p, row 1 = z - zbar* (zbar*_i = t[4 i]).
+__global__ void k_grad_rhs(const double* __restrict__ p, const double* __restrict__ z,
+                           const double* __restrict__ t, int n, double* __restrict__ X) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  X[i] = p[i];
+  X[n + i] = z[i] - t[4 * (size_t)i];
+}
+
+constexpr int kDots = 11;
+struct DotList {
+  const double* a[kDots];
+  const double* b[kDots];
+  int sb[kDots];      // element stride of b
+  int len[kDots];
+};
+
+// out[k] = sum_i a_k[i] b_k[i sb_k], one workgroup per product, fixed order.
+__global__ void __launch_bounds__(256) k_dots(DotList d, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  const double* a = d.a[k];
+  const double* b = d.b[k];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < d.len[k]; i += 256) acc += a[i] * b[(size_t)i * d.sb[k]];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = red[0];
+}
+
+}  // namespace
+}  // namespace cesim
+
+using namespace cesim;
+
+extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugget, int nreal,
+                                       uint64_t seed, int first_real, const void* wgt,
+                                       double* out, double* dz) {
+  if (!c || !z || !wgt || !out || !dz || nreal < 1 || first_real < 0) return CESIM_ERR_INVALID_ARG;
+  if ((long)first_real + nreal > 0x7fffffffL) return CESIM_ERR_INVALID_ARG;
+  if (!(std::isfinite(nugget) && nugget >= 0.0)) return CESIM_ERR_INVALID_ARG;
+  if (c->nobs < 1) return CESIM_ERR_BAD_STATE;
+  const int n = c->nobs;
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(z[i])) return CESIM_ERR_INVALID_ARG;
+  hipStream_t s = c->stream;
+  // the grid GEMM of an earlier condition() may still read the factor (aux
+  // work is ordered before it), and the solves below use the stream
+  CESIM_HIP(hipStreamSynchronize(c->aux));
+  CESIM_HIP(hipStreamSynchronize(s));
+  const int M = c->grid.m1 * c->grid.m2;
+  const size_t N = (size_t)c->t1 * c->t2;
+  // vectors: eps_bar N | ybar M | dybar M | xi_bar n | t 4n | p n | dp n | z n | X 2n | Y 2n | q n | dots
+  const size_t nv = N + 2 * (size_t)M + 14 * (size_t)n + kDots;
+  CESIM_TRY(c->gvec.reserve(sizeof(double) * nv));
+  double* eb = c->gvec.as<double>();
+  double* yb = eb + N;
+  double* dyb = yb + M;
+  double* xb = dyb + M;
+  double* t = xb + n;
+  double* p = t + 4 * (size_t)n;
+  double* dp = p + n;
+  double* zd = dp + n;
+  double* X = zd + n;
+  double* Y = X + 2 * (size_t)n;
+  double* q = Y + 2 * (size_t)n;
+  double* dots = q + n;
+  std::vector<double> zh(z, z + n);
+  CESIM_HIP(hipMemcpyAsync(zd, zh.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), ev = (uint32_t)c->event_id;
+  k_mean_torus_noise<<<(unsigned)((N / 4 + 1 + 255) / 256), 256, 0, s>>>(k0, k1, ev, first_real,
+                                                                        nreal, N, eb);
+  k_mean_obs_noise<<<(n + 255) / 256, 256, 0, s>>>(k0, k1, ev, first_real, nreal, n, xb);
+  CESIM_HIP(hipGetLastError());
+  CESIM_TRY(ce_grad_fields_device(c, eb, yb, dyb));
+  CESIM_TRY(lk_grad_device(c, nugget, yb, dyb, xb, t));
+  const double* w = static_cast<const double*>(wgt);
+  k_cross_gemv<<<n, 256, 0, s>>>(c->obs_xy.as<double>(), c->gridd, c->covd, w, p, dp);
+  k_grad_rhs<<<(n + 255) / 256, 256, 0, s>>>(p, zd, t, n, X);
+  CESIM_HIP(hipGetLastError());
+  // factor of A = K22 + tau^2 I (reused when it is current)
+  const bool refactor = !c->chol_valid || c->chol_nugget != nugget;
+  if (refactor) {
+    c->chol_valid = false;
+    CESIM_TRY(chol_factor_device(c, nugget, s));
+  }
+  CESIM_TRY(chol_solve_device(c, X, 2, s, Y));   // X = [u; cbar]
+  const double* u = X;
+  const double* cb = X + n;
+  k_dk22_times<<<n, 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd, cb, q);
+  // 0 w.ybar  1 w.dybar  2 p.cbar  3 dp.cbar  4 u.z  5 u.cbar  6 u.t_theta
+  // 7 u.t_sigma  8 u.t_tau  9 u.(dK22 cbar)  10 u.zbar*
+  DotList d{};
+  const double* A[kDots] = {w, w, p, dp, u, u, u, u, u, u, u};
+  const double* B[kDots] = {yb, dyb, cb, cb, zd, cb, t + 1, t + 2, t + 3, q, t};
+  const int SB[kDots] = {1, 1, 1, 1, 1, 1, 4, 4, 4, 1, 4};
+  for (int k = 0; k < kDots; ++k) {
+    d.a[k] = A[k];
+    d.b[k] = B[k];
+    d.sb[k] = SB[k];
+    d.len[k] = k < 2 ? M : n;
+  }
+  k_dots<<<kDots, 256, 0, s>>>(d, dots);
+  CESIM_HIP(hipGetLastError());
+  double h[kDots];
+  CESIM_HIP(hipMemcpyAsync(h, dots, sizeof(h), hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipMemcpyAsync(dz, u, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipStreamSynchronize(s));
+  if (refactor) {
+    if (c->chol_info_host[0] & 2) return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+    c->chol_valid = true;
+    c->chol_nugget = nugget;
+  }
+  const double s2 = c->covd.sigma2, ub = h[4] - h[10];     // u . (z - zbar*)
+  out[0] = h[0] + ub;
+  out[1] = h[1] + h[3] - h[9] - h[6];
+  out[2] = h[0] / (2.0 * s2) + h[2] / s2 - (ub - nugget * h[5]) / s2 - h[7];
+  out[3] = -h[5] - h[8];
+  return CESIM_OK;
+}

@@ -192,6 +192,8 @@ struct cesim_ctx_s {
   cesim::DevBuf chol_info;          // int[4]: bit 2 of [0] marks a failed factorisation;
                                     // the grid GEMM leaves the fields alone when it is set
   int* chol_info_host = nullptr;    // pinned copy, valid once factor_ready has completed
+  cesim::DevBuf gwork;              // gradient: one FP64 pair buffer + d sqrt(lambda)
+  cesim::DevBuf gvec;               // gradient: mean noises, fields and vectors
   cesim::GroupedSeq winv_seq;       // launches that build winv (kept until they have run)
   cesim::PinnedStage winv_stage;
   std::vector<double> z_host_cached;
@@ -224,6 +226,9 @@ cesim_status lk_phi_device(cesim_ctx c, double tau2);
 cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, bool with_z);
 cesim_status predict_device(cesim_ctx c, hipStream_t s);
 cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s);
+cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* yb, double* dyb);
+cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
+                            const double* xib, double* out);
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y);
 cesim_status aux_wait_last_use(cesim_ctx c);
 cesim_status copy_coefficients_device(cesim_ctx c, double* out);
