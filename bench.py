@@ -52,7 +52,7 @@ def parse():
                     help="half type of the three-product split in the mixed GEMM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default="")
-    ap.add_argument("--workload", choices=["dm", "events64"], default="dm",
+    ap.add_argument("--workload", choices=["dm", "events64", "grad512"], default="dm",
                     help="dm: the 1024^2 single-event workload; events64: 64 uneven events "
                          "run as one batch (one graph launch per step)")
     ap.add_argument("--autotune", action="store_true",
@@ -384,6 +384,95 @@ def events_main(args, torch, cesim, workloads):
             f.write(line + "\n")
 
 
+def grad_main(args, torch, cesim, workloads):
+    """Gradient of the linear ensemble statistic at the differentiation
+    workload (512^2 grid, Matern nu = 1, range 0.1, nugget 0.05, 2000
+    clustered stations, 200 realizations): a step is one new context, the
+    station set-up and ce_grad_linear (L and dL/d(range, sigma^2, nugget, z)).
+    The forward ensemble (draw + condition of the 200 realizations and the
+    weighted mean) is timed beside it."""
+    wl = workloads.C4
+    xy = wl.obs_xy()
+    z = workloads.iid_values(wl.n, wl.sigma2 + wl.tau2)
+    w = torch.as_tensor(np.random.default_rng(4).standard_normal((wl.m, wl.m)), device="cuda")
+    cov = cesim.make_cov(wl.nu, wl.sigma2, wl.range)
+    grid = cesim.unit_square_grid(wl.m)
+
+    def step():
+        with cesim.Context(cov, grid, "fp64") as ctx:
+            ctx.offgrid(xy, wl.k)
+            return ctx.grad_linear(z, wl.tau2, wl.nreal, args.seed, w)
+
+    def forward(f):
+        with cesim.Context(cov, grid, "fp64") as ctx:
+            ctx.offgrid(xy, wl.k)
+            ctx.simulate(wl.nreal, args.seed, out=f)
+            ctx.condition(z, wl.tau2, f)
+            return float((f * w).sum(dim=(1, 2)).mean())
+
+    for _ in range(args.warmup):
+        g = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = step()
+    torch.cuda.synchronize()
+    ms_step = 1000.0 * (time.perf_counter() - t0) / args.steps
+    f = torch.empty((wl.nreal, wl.m, wl.m), dtype=torch.float64, device="cuda")
+    Lf = forward(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Lf = forward(f)
+    torch.cuda.synchronize()
+    ms_fwd = 1000.0 * (time.perf_counter() - t0) / args.steps
+    del f
+    out = {
+        "metric": "gradients/sec of a linear ensemble statistic (range, sigma2, nugget, 2000 z)",
+        "value": 1000.0 / ms_step, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "grad512_matern1_n2000cl_R200", "grid": "512x512", "nu": wl.nu,
+                   "range": wl.range, "nugget": wl.tau2, "n_obs": wl.n, "k": wl.k,
+                   "realizations": wl.nreal},
+        "gradient": {"L": g["L"], "d_range": g["d_range"], "d_sigma2": g["d_sigma2"],
+                     "d_nugget": g["d_nugget"], "d_z_norm": float(np.linalg.norm(g["d_z"]))},
+        "forward_ensemble": {"ms": ms_fwd, "L": Lf,
+                             "rel_diff_L": abs(Lf - g["L"]) / max(1.0, abs(Lf))},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = grad_cpu_baseline()
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as fh:
+            fh.write(line + "\n")
+
+
+def grad_cpu_baseline():
+    """The oracle's reference adjoint on a bounded sample of the gradient
+    workload: the same covariance, nugget, window and 200 realizations on a
+    192^2 grid (384^2 torus) with 750 clustered stations."""
+    from oracle import gradient as ograd
+    from oracle.covariance import Cov as OCov
+    from oracle.pipeline import Grid as OGrid
+    from paper_2109_11044_amd import workloads
+    wl = workloads.C4
+    m, n = 192, 750
+    xy = workloads.locations("clustered", n, seed=1)
+    z = workloads.iid_values(n, wl.sigma2 + wl.tau2)
+    w = np.random.default_rng(4).standard_normal((m, m))
+    threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    ograd.linear_stat_gradient(OCov(wl.nu, wl.sigma2, wl.range), OGrid.unit_square(m), xy, z,
+                               wl.tau2, wl.k, 2, wl.nreal, w, 2 * m, 2 * m)
+    sec = time.perf_counter() - t0
+    return {"value": 1.0 / sec, "unit": "gradients/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{m}^2 grid, {2 * m}^2 torus, {n} clustered stations, same covariance, "
+                      f"nugget, window and {wl.nreal} realizations (not scaled)",
+            "seconds_measured": sec}
+
+
 def main():
     args = parse()
     if args.record_counters:
@@ -406,6 +495,8 @@ def main():
     cesim.lib()
     if args.workload == "events64":
         return events_main(args, torch, cesim, workloads)
+    if args.workload == "grad512":
+        return grad_main(args, torch, cesim, workloads)
     cesim.set_default_timing(True)
     wl = workloads.DM
     wl.m, wl.n, wl.nreal = args.m, args.n, args.nreal

@@ -168,6 +168,33 @@ __host__ __device__ inline double dcov_eval(const CovDev& c, double hx, double h
   return c.sigma2 * matern_g(c.nu_code, lag_x(c, hx, hy)) / c.theta;
 }
 
+// C(h) and dC(h)/dtheta together.  For nu = 1 in the quadrature regime the
+// two sums share their exponentials (t K_1 keeps the operation order of
+// t_bessel_k1; t^2 K_0 is rounded differently from t2_bessel_k0).
+__host__ __device__ inline void cov_dcov_eval(const CovDev& c, double hx, double hy, double& cv,
+                                              double& dv) {
+  const double x = lag_x(c, hx, hy);
+  if (c.nu_code == 1) {
+    const double t = kSqrt2 * x;
+    if (t > 2.0 && t <= 30.0) {
+      double s1 = 0.5, s0 = 0.5;
+#pragma unroll 4
+      for (int j = 1; j < 32; ++j) {
+        const double ch = cosh_eighth(j);
+        const double e = exp(-t * (ch - 1.0));
+        s1 += e * ch;
+        s0 += e;
+      }
+      const double f = t * exp(-t) * 0.125;
+      cv = c.sigma2 * (f * s1);
+      dv = c.sigma2 * (t * f * s0) / c.theta;
+      return;
+    }
+  }
+  cv = c.sigma2 * matern_rho(c.nu_code, x);
+  dv = c.sigma2 * matern_g(c.nu_code, x) / c.theta;
+}
+
 // FP32 correlation from a pre-scaled lag length for the mixed-precision
 // cross-covariance: the caller scales coordinates so that xs = kappa * x with
 // kappa = log2(e) (nu = 1/2), sqrt(3) (nu = 3/2) or sqrt(2) (nu = 1).

@@ -75,8 +75,10 @@ k_cross_gemv(const double* __restrict__ obs, GridDev g, CovDev cov, const double
     const double hx = __dadd_rn(g.x0, __dmul_rn((double)x, g.dx)) - sx;
     const double hy = __dadd_rn(g.y0, __dmul_rn((double)y, g.dy)) - sy;
     const double wq = w[q];
-    a += cov_eval(cov, hx, hy) * wq;
-    b += dcov_eval(cov, hx, hy) * wq;
+    double cv, dv;
+    cov_dcov_eval(cov, hx, hy, cv, dv);
+    a += cv * wq;
+    b += dv * wq;
   }
   r0[threadIdx.x] = a;
   r1[threadIdx.x] = b;
