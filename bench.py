@@ -55,8 +55,10 @@ def parse():
     ap.add_argument("--workload", choices=["dm", "events64", "grad512"], default="dm",
                     help="dm: the 1024^2 single-event workload; events64: 64 uneven events "
                          "run as one batch (one graph launch per step)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="tune launch shapes before the warm-up (one-off, reported as tune_ms)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the one-off tuning of launch shapes that precedes the warm-up "
+                         "(by default the library's autotuner picks the draw and GEMM tiles "
+                         "outside the timed region; results do not depend on them)")
     ap.add_argument("--no-unbatched", action="store_true",
                     help="events64: skip the one-context-per-event comparison")
     ap.add_argument("--record-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -543,6 +545,8 @@ def main():
     out["fft_passes_hbm_frac"] = {k["name"]: k["frac"] for k in head["kernels"]
                                   if k.get("bound") == "hbm"}
     out["finite"] = all(r["finite"] for r in res.values())
+    out["autotune"] = {"enabled": bool(args.autotune),
+                       "tune_ms": {p: r["tune_ms"] for p, r in res.items()}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, xy, z, args.seed)
     if args.copy_probe_mib:
