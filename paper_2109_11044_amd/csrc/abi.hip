@@ -91,6 +91,12 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+void DevBuf::release_idle() {
+  if (p) cache_free(p, bytes);
+  p = nullptr;
+  bytes = 0;
+}
+
 // ------------------------------------------------------------ stage timer
 hipEvent_t StageTimer::get() {
   if (!pool.empty()) {
@@ -242,21 +248,80 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->gwork, &c->gvec};
 }
 
+namespace {
+// HIP objects of a context that are slow to create -- the second stream, its
+// events and the pinned host words -- kept in a process-wide pool and lent to
+// new contexts (all on the device current when they were created).
+struct AuxKit {
+  hipStream_t aux = nullptr;
+  hipEvent_t ev[4] = {};
+  int* info_host = nullptr;
+  PinnedStage stage;
+};
+std::mutex g_kit_mu;
+std::vector<AuxKit> g_kits;
+
+void kit_destroy(AuxKit& k) {
+  k.stage.release();
+  if (k.info_host) (void)hipHostFree(k.info_host);
+  for (hipEvent_t e : k.ev)
+    if (e) (void)hipEventDestroy(e);
+  if (k.aux) (void)hipStreamDestroy(k.aux);
+  k = AuxKit{};
+}
+
+// A kit from the pool, or a new one.
+cesim_status kit_take(AuxKit& k) {
+  {
+    std::lock_guard<std::mutex> g(g_kit_mu);
+    if (!g_kits.empty()) {
+      k = g_kits.back();
+      g_kits.pop_back();
+      return CESIM_OK;
+    }
+  }
+  bool ok = hipStreamCreateWithFlags(&k.aux, hipStreamNonBlocking) == hipSuccess;
+  for (hipEvent_t& e : k.ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&k.info_host, sizeof(int) * 4, hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    kit_destroy(k);
+    return CESIM_ERR_HIP;
+  }
+  return CESIM_OK;
+}
+}  // namespace
+
 void ce_destroy(cesim_ctx c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   if (c->aux) (void)hipStreamSynchronize(c->aux);
   c->timer.destroy();
-  for (DevBuf* b : all_bufs(c)) b->release();
-  c->winv_stage.release();
-  if (c->chol_info_host) (void)hipHostFree(c->chol_info_host);
-  for (hipEvent_t e : {c->aux_done, c->last_use, c->factor_ready, c->z_ready})
-    if (e) (void)hipEventDestroy(e);
-  if (c->aux) (void)hipStreamDestroy(c->aux);
+  for (DevBuf* b : all_bufs(c)) b->release_idle();   // both streams drained above
+  AuxKit k;
+  k.aux = c->aux;
+  k.ev[0] = c->aux_done;
+  k.ev[1] = c->last_use;
+  k.ev[2] = c->factor_ready;
+  k.ev[3] = c->z_ready;
+  k.info_host = c->chol_info_host;
+  k.stage = c->winv_stage;
+  k.stage.pending = false;                 // its copy ran on a drained stream
+  if (k.aux && k.ev[0] && k.ev[1] && k.ev[2] && k.ev[3] && k.info_host) {
+    std::lock_guard<std::mutex> g(g_kit_mu);
+    g_kits.push_back(k);
+  } else {
+    kit_destroy(k);
+  }
   delete c;
 }
 
-void cesim_release_cached_memory(void) { cache_trim(); }
+void cesim_release_cached_memory(void) {
+  cache_trim();
+  std::lock_guard<std::mutex> g(g_kit_mu);
+  for (AuxKit& k : g_kits) kit_destroy(k);
+  g_kits.clear();
+}
 
 void cesim_set_default_timing(int enable) { g_default_timing = enable != 0; }
 
@@ -343,16 +408,19 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
   c->prec = prec;
   c->covd = make_cov(*cov);
   c->gridd = {grid->m1, grid->m2, grid->x0, grid->y0, grid->dx, grid->dy};
-  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->aux_done, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->factor_ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->z_ready, hipEventDisableTiming) != hipSuccess ||
-      hipHostMalloc((void**)&c->chol_info_host, sizeof(int) * 4, hipHostMallocDefault) !=
-          hipSuccess) {
-    (void)hipGetLastError();
-    ce_destroy(c);
-    return CESIM_ERR_HIP;
+  {
+    AuxKit k;
+    if (kit_take(k) != CESIM_OK) {
+      ce_destroy(c);
+      return CESIM_ERR_HIP;
+    }
+    c->aux = k.aux;
+    c->aux_done = k.ev[0];
+    c->last_use = k.ev[1];
+    c->factor_ready = k.ev[2];
+    c->z_ready = k.ev[3];
+    c->chol_info_host = k.info_host;
+    c->winv_stage = k.stage;
   }
   c->chol_info_host[0] = 0;
   for (DevBuf* b : all_bufs(c)) b->stream = c->stream;

@@ -46,6 +46,7 @@ struct DevBuf {
   hipStream_t stream = nullptr;     // stream whose work last used the block
   cesim_status reserve(size_t n);   // grows, never shrinks; contents lost
   void release();
+  void release_idle();              // no work that uses the block is pending
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
