@@ -27,7 +27,18 @@ Nodes are ordered (a + p, b + q), index alpha = q * 2 n_p + p.
 
 The weights solve K11 w = k_i by Cholesky; gamma_i is clamped at 0.
 
-Pins (tests/test_oracle_localkrige.py): indicator weights and gamma = 0 for
+Joint variant (Section 2.1, last paragraph; Section 3.6): observations in
+the same grid box share their window, and their synthetic values can be drawn
+jointly from the conditional law given the window,
+    z*_G = W1_G y(S^g) + L_G xi_G,  L_G L_G^T = tau^2 I + Gamma_G,
+    Gamma_G[i][j] = C(s_i - s_j) - w_i . k_j
+(k_j: covariances between the window nodes and s_j), i.e. the diagonal
+blocks of the noise matrix become Cholesky factors; a box with one
+observation keeps phi_i = sqrt(tau^2 + gamma_i).  A box is the cell
+(floor((x - x0)/dx), floor((y - y0)/dy)); members are taken in ascending
+index order and xi_G holds their own normals.
+
+Pins (tests/test_oracle_localkrige.py, tests/test_oracle_joint.py): indicator weights and gamma = 0 for
 an observation on a node; the window equals the 2 n_p nearest nodes per axis
 by brute force; weights and gamma agree with the Schur complement of the joint
 covariance; gamma decreases as n_p grows; the full-grid window reproduces the
@@ -107,3 +118,51 @@ def synthetic_obs(y, a, b, W, gamma, tau2, xi):
     vals = gather_windows(np.asarray(y), a, b, npp)       # (R, n, k)
     phi = np.sqrt(tau2 + gamma)
     return np.einsum("rnk,nk->rn", vals, W) + phi[None, :] * xi
+
+
+def box_groups(obs_xy, x0, y0, dx, dy):
+    """Observations grouped by grid box: ascending index arrays, one per box
+    that holds an observation, ordered by their first member."""
+    obs_xy = np.asarray(obs_xy, dtype=np.float64).reshape(-1, 2)
+    ix = np.floor((obs_xy[:, 0] - x0) / dx).astype(np.int64)
+    iy = np.floor((obs_xy[:, 1] - y0) / dy).astype(np.int64)
+    groups = {}
+    for i, key in enumerate(zip(ix, iy)):
+        groups.setdefault(key, []).append(i)
+    return [np.array(v) for v in groups.values()]
+
+
+def box_noise_factors(obs_xy, cov: Cov, x0, y0, dx, dy, a, b, W, tau2, groups, npp):
+    """{first member: L_G} for every box with more than one observation:
+    lower Cholesky factor of tau^2 I + Gamma_G (the conditional covariance of
+    y(s_G) given the box's window plus the nugget)."""
+    obs_xy = np.asarray(obs_xy, dtype=np.float64).reshape(-1, 2)
+    p, q = window_offsets(npp)
+    out = {}
+    for G in groups:
+        if len(G) < 2:
+            continue
+        i0 = G[0]
+        gx = x0 + (a[i0] + p) * dx
+        gy = y0 + (b[i0] + q) * dy
+        kG = np.stack([covariance(gx - obs_xy[j, 0], gy - obs_xy[j, 1], cov) for j in G])
+        S = obs_xy[G]
+        KGG = covariance(S[:, 0:1] - S[None, :, 0], S[:, 1:2] - S[None, :, 1], cov)
+        Gam = KGG - W[G] @ kG.T
+        out[int(i0)] = np.linalg.cholesky(tau2 * np.eye(len(G)) + 0.5 * (Gam + Gam.T))
+    return out
+
+
+def synthetic_obs_joint(y, a, b, W, gamma, tau2, xi, groups, factors):
+    """Step 3 with boxes sampled jointly: z*_G = W1_G y + L_G xi_G; boxes with
+    one observation as in synthetic_obs.  y: (R, m2, m1), xi: (R, n)."""
+    k = W.shape[1]
+    npp = int(round(np.sqrt(k))) // 2
+    vals = gather_windows(np.asarray(y), a, b, npp)
+    z = np.einsum("rnk,nk->rn", vals, W)
+    xi = np.asarray(xi, dtype=np.float64)
+    noise = np.sqrt(tau2 + gamma)[None, :] * xi
+    for G in groups:
+        if len(G) > 1:
+            noise[:, G] = xi[:, G] @ factors[int(G[0])].T
+    return z + noise

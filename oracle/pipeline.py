@@ -66,10 +66,23 @@ def draw_observations(obs_xy, cov: Cov, tau2, seed=0):
     return L @ xi + np.sqrt(tau2) * xi2
 
 
+def synthetic(y, obs_xy, cov: Cov, grid: Grid, a, b, W, gamma, tau2, xi, joint):
+    """Step 3 with the local Kriging of Section 2.1, each observation on its
+    own (joint=False) or boxes of several observations jointly."""
+    if not joint:
+        return localkrige.synthetic_obs(y, a, b, W, gamma, tau2, xi)
+    npp = int(round(np.sqrt(W.shape[1]))) // 2
+    groups = localkrige.box_groups(obs_xy, grid.x0, grid.y0, grid.dx, grid.dy)
+    fac = localkrige.box_noise_factors(obs_xy, cov, grid.x0, grid.y0, grid.dx, grid.dy, a, b,
+                                       W, tau2, groups, npp)
+    return localkrige.synthetic_obs_joint(y, a, b, W, gamma, tau2, xi, groups, fac)
+
+
 def conditional_simulation(cov: Cov, grid: Grid, obs_xy, z, tau2, k, seed,
-                           nreal, first_real=0, t1=None, t2=None, event=0):
+                           nreal, first_real=0, t1=None, t2=None, event=0, joint=False):
     """Run steps 1-5 for realizations first_real .. first_real + nreal - 1
-    (noise counters carry ``event`` in their third word).
+    (noise counters carry ``event`` in their third word; joint: boxes of
+    several observations sampled jointly).
 
     Returns a dict of every intermediate: torus, sqrt_lam, eps, y, window
     corners a/b, W, gamma, xi, zstar, B, v."""
@@ -79,7 +92,7 @@ def conditional_simulation(cov: Cov, grid: Grid, obs_xy, z, tau2, k, seed,
     y = ce.ce_draw(s, eps, grid.m1, grid.m2)
     a, b, W, gamma = offgrid_setup(obs_xy, cov, grid, k)
     xi = philox.offgrid_noise(seed, len(obs_xy), reals, event)
-    zstar = localkrige.synthetic_obs(y, a, b, W, gamma, tau2, xi)
+    zstar = synthetic(y, obs_xy, cov, grid, a, b, W, gamma, tau2, xi, joint)
     fac = kriging.factor(obs_xy, cov, tau2)
     B = kriging.coefficients(fac, z, zstar)
     v = kriging.condition_fields(y, B, obs_xy, cov, grid.x0, grid.y0,
@@ -102,7 +115,7 @@ def draw_matrix(sqrt_lam, m1, m2):
     return np.stack(cols, axis=1)
 
 
-def linear_map(cov: Cov, grid: Grid, obs_xy, tau2, k, t1=None, t2=None):
+def linear_map(cov: Cov, grid: Grid, obs_xy, tau2, k, t1=None, t2=None, joint=False):
     """Matrices (Me, Mx) with v - y_hat = Me eps + Mx xi for the whole
     pipeline (z enters only y_hat).  Tiny problems only."""
     t1, t2, s, _ = setup(cov, grid, t1, t2)
@@ -113,15 +126,15 @@ def linear_map(cov: Cov, grid: Grid, obs_xy, tau2, k, t1=None, t2=None):
     z0 = np.zeros(n)
     # columns for eps
     Y = Bce.T.reshape(-1, grid.m2, grid.m1)                 # (N, m2, m1)
-    zs = localkrige.synthetic_obs(Y, a, b, W, gamma, tau2,
-                                  np.zeros((Y.shape[0], n)))
+    zs = synthetic(Y, obs_xy, cov, grid, a, b, W, gamma, tau2, np.zeros((Y.shape[0], n)),
+                   joint)
     Bc = kriging.coefficients(fac, z0, zs)
     Ve = kriging.condition_fields(Y, Bc, obs_xy, cov, grid.x0, grid.y0,
                                   grid.dx, grid.dy, grid.m1, grid.m2)
     Me = Ve.reshape(Y.shape[0], -1).T
     # columns for xi
     Y0 = np.zeros((n, grid.m2, grid.m1))
-    zs = localkrige.synthetic_obs(Y0, a, b, W, gamma, tau2, np.eye(n))
+    zs = synthetic(Y0, obs_xy, cov, grid, a, b, W, gamma, tau2, np.eye(n), joint)
     Bx = kriging.coefficients(fac, z0, zs)
     Vx = kriging.condition_fields(Y0, Bx, obs_xy, cov, grid.x0, grid.y0,
                                   grid.dx, grid.dy, grid.m1, grid.m2)
