@@ -253,6 +253,20 @@ const char* cesim_status_string(cesim_status s);
 #define CESIM_PARAM_DRAW_ROWS_FWD 5
 #define CESIM_PARAM_DRAW_COLS 6
 #define CESIM_PARAM_DRAW_ROWS_INV 7
+/*   CESIM_PARAM_JOINT_BOXES (changes the method, Section 2.1 last paragraph
+ *     and Section 3.6): 1 draws the synthetic values of observations that
+ *     share a grid box (the cell floor((x - x0)/dx), floor((y - y0)/dy))
+ *     jointly from their conditional law given the box's window,
+ *     z*_G = W1_G y + L_G xi_G with L_G L_G^T = tau^2 I + Gamma_G,
+ *     Gamma_G[i][j] = C(s_i - s_j) - w_i . k_j (members in ascending index
+ *     order, xi_G their own stream-1 normals); boxes of one observation keep
+ *     phi_i xi_i.  0 (default): every observation on its own.  A box of more
+ *     than 32 observations makes condition() return INVALID_ARG; a
+ *     non-positive pivot of a box factor returns NOT_POSITIVE_DEFINITE.
+ *     Batches and ce_grad_linear use the independent sampling (ce_grad_linear
+ *     returns INVALID_ARG while joint sampling is on and some box holds
+ *     several observations). */
+#define CESIM_PARAM_JOINT_BOXES 8
 cesim_status ce_set_param(cesim_ctx ctx, int param, int value);
 
 /* ---- launch-shape autotuning ----

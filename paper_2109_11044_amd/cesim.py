@@ -37,6 +37,7 @@ PARAM_EVENT_ID = 4
 PARAM_DRAW_ROWS_FWD = 5
 PARAM_DRAW_COLS = 6
 PARAM_DRAW_ROWS_INV = 7
+PARAM_JOINT_BOXES = 8
 BATCH_AUTOTUNE = 1
 NUM_STAGES = 13
 VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",

@@ -245,7 +245,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
-          &c->gwork, &c->gvec};
+          &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac};
 }
 
 namespace {
@@ -254,7 +254,7 @@ namespace {
 // new contexts (all on the device current when they were created).
 struct AuxKit {
   hipStream_t aux = nullptr;
-  hipEvent_t ev[4] = {};
+  hipEvent_t ev[5] = {};
   int* info_host = nullptr;
   PinnedStage stage;
 };
@@ -304,10 +304,11 @@ void ce_destroy(cesim_ctx c) {
   k.ev[1] = c->last_use;
   k.ev[2] = c->factor_ready;
   k.ev[3] = c->z_ready;
+  k.ev[4] = c->box_ready;
   k.info_host = c->chol_info_host;
   k.stage = c->winv_stage;
   k.stage.pending = false;                 // its copy ran on a drained stream
-  if (k.aux && k.ev[0] && k.ev[1] && k.ev[2] && k.ev[3] && k.info_host) {
+  if (k.aux && k.ev[0] && k.ev[1] && k.ev[2] && k.ev[3] && k.ev[4] && k.info_host) {
     std::lock_guard<std::mutex> g(g_kit_mu);
     g_kits.push_back(k);
   } else {
@@ -328,6 +329,10 @@ void cesim_set_default_timing(int enable) { g_default_timing = enable != 0; }
 cesim_status ce_set_param(cesim_ctx c, int param, int value) {
   if (!c) return CESIM_ERR_INVALID_ARG;
   switch (param) {
+    case CESIM_PARAM_JOINT_BOXES:
+      if (value != 0 && value != 1) return CESIM_ERR_INVALID_ARG;
+      c->joint_boxes = value;
+      return CESIM_OK;
     case CESIM_PARAM_GEMM_TILE:
       if (value < 0 || value > 3) return CESIM_ERR_INVALID_ARG;
       c->gemm_tile = value;
@@ -419,6 +424,7 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
     c->last_use = k.ev[1];
     c->factor_ready = k.ev[2];
     c->z_ready = k.ev[3];
+    c->box_ready = k.ev[4];
     c->chol_info_host = k.info_host;
     c->winv_stage = k.stage;
   }
@@ -530,6 +536,32 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   std::sort(key.begin(), key.end());
   std::vector<int> order(nobs);
   for (int i = 0; i < nobs; ++i) order[i] = key[i].second;
+  // boxes of several observations (joint sampling): members in ascending order
+  std::vector<std::pair<std::pair<long, long>, int>> bk(nobs);
+  for (int i = 0; i < nobs; ++i)
+    bk[i] = {{(long)std::floor((xy[2 * i] - g.x0) / g.dx), (long)std::floor((xy[2 * i + 1] - g.y0) / g.dy)},
+             i};
+  std::sort(bk.begin(), bk.end());
+  std::vector<int2> box_of(nobs, make_int2(-1, 0));
+  std::vector<int4> box_desc;
+  std::vector<int> box_members;
+  int fac_total = 0, max_box = 0;
+  for (int lo = 0; lo < nobs;) {
+    int hi = lo + 1;
+    while (hi < nobs && bk[hi].first == bk[lo].first) ++hi;
+    const int sz = hi - lo;
+    if (sz > 1) {
+      const int d = (int)box_desc.size();
+      box_desc.push_back(make_int4((int)box_members.size(), sz, fac_total, 0));
+      for (int q = 0; q < sz; ++q) {
+        box_members.push_back(bk[lo + q].second);
+        box_of[bk[lo + q].second] = make_int2(d, q);
+      }
+      fac_total += sz * (sz + 1) / 2;
+      max_box = std::max(max_box, sz);
+    }
+    lo = hi;
+  }
   for (int i = 0; i < nobs; ++i) {
     const double hx = xy[2 * i] - g.x0, hy = xy[2 * i + 1] - g.y0;
     const double a = d.u00 * hx + d.u01 * hy, b = d.u10 * hx + d.u11 * hy;
@@ -545,6 +577,21 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
                            hipMemcpyHostToDevice, s));
   CESIM_HIP(hipMemcpyAsync(c->obs_order.p, order.data(), sizeof(int) * nobs,
                            hipMemcpyHostToDevice, s));
+  CESIM_TRY(c->box_of.reserve(sizeof(int2) * nobs));
+  CESIM_TRY(c->box_desc.reserve(sizeof(int4) * std::max<size_t>(1, box_desc.size())));
+  CESIM_TRY(c->box_members.reserve(sizeof(int) * std::max<size_t>(1, box_members.size())));
+  CESIM_TRY(c->box_fac.reserve(sizeof(double) * std::max(1, fac_total)));
+  CESIM_HIP(hipMemcpyAsync(c->box_of.p, box_of.data(), sizeof(int2) * nobs, hipMemcpyHostToDevice,
+                           s));
+  if (!box_desc.empty()) {
+    CESIM_HIP(hipMemcpyAsync(c->box_desc.p, box_desc.data(), sizeof(int4) * box_desc.size(),
+                             hipMemcpyHostToDevice, s));
+    CESIM_HIP(hipMemcpyAsync(c->box_members.p, box_members.data(),
+                             sizeof(int) * box_members.size(), hipMemcpyHostToDevice, s));
+  }
+  c->nboxes = (int)box_desc.size();
+  c->max_box = max_box;
+  c->box_fac_valid = false;
   c->nobs = nobs;
   c->k = k;
   c->npp = npp;

@@ -147,6 +147,7 @@ struct cesim_ctx_s {
   // may start); z_ready: the observed values are on the device.
   hipStream_t aux = nullptr;
   hipEvent_t aux_done = nullptr, last_use = nullptr, factor_ready = nullptr, z_ready = nullptr;
+  hipEvent_t box_ready = nullptr;   // box factors of the joint sampling are complete
   bool last_use_valid = false, aux_pending = false, z_pending = false;
   cesim_cov cov{};
   cesim_grid grid{};
@@ -171,6 +172,14 @@ struct cesim_ctx_s {
   cesim::DevBuf obs_t64;            // [n] double2: transformed coordinates (FP64)
   cesim::DevBuf corners, weights, gamma, phi;
   cesim::DevBuf obs_order;          // [n] int: observations in Morton order of their grid cell
+  // boxes holding several observations (joint sampling, CESIM_PARAM_JOINT_BOXES)
+  int joint_boxes = 0;              // switched on by the parameter
+  int nboxes = 0, max_box = 0;      // boxes of several observations; largest size
+  bool box_fac_valid = false;       // box_fac matches the stations and chol_nugget
+  cesim::DevBuf box_of;             // [n] int2: {box, row in box} or {-1, 0}
+  cesim::DevBuf box_desc;           // [nboxes] int4: {first member, size, factor offset, 0}
+  cesim::DevBuf box_members;        // observation indices of each box, ascending
+  cesim::DevBuf box_fac;            // packed lower factors of tau^2 I + Gamma_G
   double gamma_min = 0, gamma_max = 0;
   std::vector<double> obs_host;
 
@@ -226,7 +235,10 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields);
 cesim_status lk_phi_device(cesim_ctx c, double tau2);
 cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, bool with_z);
 cesim_status predict_device(cesim_ctx c, hipStream_t s);
-cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s);
+cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool clear_info = true);
+cesim_status box_factor_device(cesim_ctx c, double tau2, hipStream_t s);
+bool joint_active(cesim_ctx c);
+constexpr int kMaxJointBox = 32;   // observations per box of the joint sampling
 cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* yb, double* dyb);
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
                             const double* xib, double* out);

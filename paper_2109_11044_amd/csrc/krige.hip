@@ -578,30 +578,43 @@ cesim_status aux_wait_last_use(cesim_ctx c) {
 
 // Everything is queued before the host waits, the work of the stream first
 // where it does not depend on aux (launches reach the GPU only as fast as
-// a long dependent chain on aux retires them): the synthetic data, then on
-// aux the factorisation (when the nugget or the stations changed), the
-// solves on the stream after factor_ready, the mixed path's prediction on
-// aux, and the grid GEMM after aux_done.  Only then does a new
-// factorisation's status come back to the host; after a failed pivot the
-// GEMM has left the fields unchanged.
+// a long dependent chain on aux retires them): with joint sampling the box
+// factors on aux, then on the stream the synthetic data, then on aux the
+// factorisation (when the nugget or the stations changed), the solves on the
+// stream after factor_ready, the mixed path's prediction on aux, and the
+// grid GEMM after aux_done.  Only then do the factorisations' status come
+// back to the host; after a failed pivot the GEMM has left the fields
+// unchanged.
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   hipStream_t s = c->stream;
   const int R = c->nreal;
   const bool mixed = c->prec == CESIM_PREC_MIXED;
+  if (joint_active(c) && c->max_box > kMaxJointBox) return CESIM_ERR_INVALID_ARG;
   const bool refactor = !c->chol_valid || c->chol_nugget != nugget;
+  const bool boxes = joint_active(c) && (refactor || !c->box_fac_valid);
   const bool predict = mixed && (refactor || !c->yhat_valid);
   if (refactor) c->chol_valid = false;
   if (predict) c->yhat_valid = false;
+  if (refactor || boxes || predict) CESIM_TRY(aux_wait_last_use(c));
+  if (refactor || boxes) CESIM_HIP(hipMemsetAsync(c->chol_info.p, 0, sizeof(int) * 4, c->aux));
+  if (boxes) {
+    c->box_fac_valid = false;
+    CESIM_TRY(box_factor_device(c, nugget, c->aux));
+    if (!refactor)
+      CESIM_HIP(hipMemcpyAsync(c->chol_info_host, c->chol_info.p, sizeof(int) * 4,
+                               hipMemcpyDeviceToHost, c->aux));
+    CESIM_HIP(hipEventRecord(c->box_ready, c->aux));
+  }
   CESIM_TRY(lk_phi_device(c, nugget));
   CESIM_TRY(krige_reserve(c, R));
   double* X = c->coef.as<double>();
   // FP64: X = A^{-1} (z - z*_r); mixed: X = -A^{-1} z*_r (yhat carries z)
   if (!mixed && c->z_pending) CESIM_HIP(hipStreamWaitEvent(s, c->z_ready, 0));
   c->z_pending = false;
+  if (boxes) CESIM_HIP(hipStreamWaitEvent(s, c->box_ready, 0));
   CESIM_TRY(lk_synth_rhs_device(c, fields, X, !mixed));
-  if (refactor || predict) CESIM_TRY(aux_wait_last_use(c));
   if (refactor) {
-    CESIM_TRY(chol_factor_device(c, nugget, c->aux));
+    CESIM_TRY(chol_factor_device(c, nugget, c->aux, false));
     CESIM_HIP(hipEventRecord(c->factor_ready, c->aux));
     CESIM_HIP(hipStreamWaitEvent(s, c->factor_ready, 0));
   }
@@ -618,12 +631,14 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   CESIM_TRY(krige_grid_device(c, X, fields));
   CESIM_HIP(hipEventRecord(c->last_use, s));
   c->last_use_valid = true;
-  if (refactor) {
-    CESIM_HIP(hipEventSynchronize(c->factor_ready));
+  if (refactor || boxes) {
+    CESIM_HIP(hipEventSynchronize(refactor ? c->factor_ready : c->box_ready));
     if (c->chol_info_host[0] & 2) {
       c->yhat_valid = false;
+      c->chol_valid = false;
       return CESIM_ERR_NOT_POSITIVE_DEFINITE;
     }
+    if (boxes) c->box_fac_valid = true;
     c->chol_valid = true;
     c->chol_nugget = nugget;
   }

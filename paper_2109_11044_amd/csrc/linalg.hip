@@ -317,8 +317,9 @@ static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s,
 // inverses of the solves, all queued on s without synchronising.  A
 // non-positive pivot sets bit 2 of c->chol_info[0] on the device; its
 // pinned copy c->chol_info_host is valid once work queued on s after this
-// call has completed.
-cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s) {
+// call has completed.  clear_info = false keeps flags set by work queued
+// before on s (the box factors of the joint sampling).
+cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool clear_info) {
   c->yhat_valid = false;
   const int n = c->nobs;
   const int nblk = (n + kNB - 1) / kNB;
@@ -327,7 +328,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s) {
   double* A = c->amat.as<double>();
   double* D = c->dinv.as<double>();
   int* info = c->chol_info.as<int>();
-  CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
+  if (clear_info) CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
   const int tr = c->timer.begin(ST_CHOL, s);
   k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd, tau2,
                                                          A);

@@ -218,13 +218,38 @@ __global__ void k_phi(const double* __restrict__ gam, int n, double tau2, double
   if (i < n) phi[i] = sqrt(tau2 + gam[i]);
 }
 
-// rhs[r][i] = z_i - (w_i . y_r[window_i] + phi_i xi_{r,i})   (z_i = 0 when z is null)
-template <typename F>
+// xi_{r,i}: block i/4, word i%4 of Philox stream 1.
+__device__ inline double obs_normal(const NoiseKey& key, int r, int i) {
+  const u32x4 wd = philox4x32_10({(uint32_t)(i >> 2), (uint32_t)(key.base() + r), key.event, 1u},
+                                 key.k0, key.k1);
+  const int word = i & 3;
+  double z0, z1;
+  if (word < 2) box_muller_f64(wd.x, wd.y, z0, z1);
+  else box_muller_f64(wd.z, wd.w, z0, z1);
+  return (word & 1) ? z1 : z0;
+}
+
+// Boxes of several observations (joint sampling): for observation i,
+// box[i] = {descriptor index, row within the box} or {-1, 0}; descriptor d
+// = {first member in `members`, size, offset of the packed factor};
+// members: observation indices of each box in ascending order.
+struct JointBoxes {
+  const int2* box;
+  const int4* desc;
+  const int* members;
+  const double* fac;            // packed lower factors, row p at p (p + 1) / 2
+};
+
+// rhs[r][i] = z_i - (w_i . y_r[window_i] + e_{r,i})   (z_i = 0 when z is null)
+// e_{r,i} = phi_i xi_{r,i}, or with JOINT for a member of a box of several
+// observations, row p of L_G xi_{r,G}.
+constexpr int kMaxBox = kMaxJointBox;
+template <typename F, bool JOINT>
 __global__ void __launch_bounds__(256)
 k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict__ corners,
             const double* __restrict__ W, const double* __restrict__ phi,
             const double* __restrict__ z, int n, int K, int w2, NoiseKey key,
-            const int* __restrict__ order, double* __restrict__ rhs) {
+            const int* __restrict__ order, double* __restrict__ rhs, JointBoxes jb) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
   if (t >= n) return;
@@ -237,15 +262,74 @@ k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict
   double acc = 0.0;
   for (int q = 0; q < w2; ++q)
     for (int p = 0; p < w2; ++p) acc += w[q * w2 + p] * (double)y[(size_t)q * m1 + p];
-  // xi_{r,i}: block i/4, word i%4 of Philox stream 1
-  const u32x4 wd = philox4x32_10({(uint32_t)(i >> 2), (uint32_t)(key.base() + r), key.event, 1u},
-                                 key.k0, key.k1);
-  const int word = i & 3;
-  double z0, z1;
-  if (word < 2) box_muller_f64(wd.x, wd.y, z0, z1);
-  else box_muller_f64(wd.z, wd.w, z0, z1);
-  const double xi = (word & 1) ? z1 : z0;
-  rhs[(size_t)r * n + i] = (z ? z[i] : 0.0) - (acc + phi[i] * xi);
+  double e;
+  const int2 bx = JOINT ? jb.box[i] : make_int2(-1, 0);
+  if (bx.x < 0) {
+    e = phi[i] * obs_normal(key, r, i);
+  } else {
+    const int4 d = jb.desc[bx.x];
+    const double* Lrow = jb.fac + d.z + bx.y * (bx.y + 1) / 2;
+    e = 0.0;
+    for (int q = 0; q <= bx.y; ++q) e += Lrow[q] * obs_normal(key, r, jb.members[d.x + q]);
+  }
+  rhs[(size_t)r * n + i] = (z ? z[i] : 0.0) - (acc + e);
+}
+
+// Factor of every box of several observations: one workgroup per box,
+// G = size <= kMaxBox members sharing the window of the first.  Gamma_ij =
+// C(s_i - s_j) - w_i . k_j (k_j: covariances between the window nodes and
+// s_j), plus tau^2 on the diagonal; Cholesky, packed lower factor.  Bit 4 of
+// *info marks a non-positive pivot.
+template <int NPP>
+__global__ void __launch_bounds__(64)
+k_box_factor(const double* __restrict__ obs, GridDev g, CovDev cov, const int2* __restrict__ corners,
+             const double* __restrict__ W, double tau2, JointBoxes jb, double* __restrict__ fac,
+             int* __restrict__ info) {
+  constexpr int W2 = 2 * NPP;
+  constexpr int K = W2 * W2;
+  __shared__ double kc[K][kMaxBox + 1];   // column j: k_j
+  __shared__ double Gm[kMaxBox][kMaxBox + 1];
+  const int4 d = jb.desc[blockIdx.x];
+  const int G = d.y, t = threadIdx.x;
+  const int i0 = jb.members[d.x];
+  const int2 ab = corners[i0];
+  if (t < G) {
+    const int j = jb.members[d.x + t];
+    const double sx = obs[2 * j], sy = obs[2 * j + 1];
+    for (int al = 0; al < K; ++al) {
+      const double gx = __dadd_rn(g.x0, __dmul_rn((double)(ab.x + al % W2), g.dx));
+      const double gy = __dadd_rn(g.y0, __dmul_rn((double)(ab.y + al / W2), g.dy));
+      kc[al][t] = cov_eval(cov, gx - sx, gy - sy);
+    }
+  }
+  __syncthreads();
+  if (t < G) {                             // row t of Gamma (lower part)
+    const int it = jb.members[d.x + t];
+    const double* w = W + (size_t)it * K;
+    for (int jj = 0; jj <= t; ++jj) {
+      const int j = jb.members[d.x + jj];
+      double acc = 0.0;
+      for (int al = 0; al < K; ++al) acc += w[al] * kc[al][jj];
+      Gm[t][jj] = cov_eval(cov, obs[2 * it] - obs[2 * j], obs[2 * it + 1] - obs[2 * j + 1]) - acc +
+                  (jj == t ? tau2 : 0.0);
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < G; ++j) {           // right-looking Cholesky, lower triangle
+    if (t == 0) {
+      const double dj = Gm[j][j];
+      if (!(dj > 0.0)) atomicOr(info, 2);
+      Gm[j][j] = sqrt(dj);
+    }
+    __syncthreads();
+    if (t > j && t < G) Gm[t][j] /= Gm[j][j];
+    __syncthreads();
+    if (t > j && t < G)
+      for (int l = j + 1; l <= t; ++l) Gm[t][l] -= Gm[t][j] * Gm[l][j];
+    __syncthreads();
+  }
+  if (t < G)
+    for (int q = 0; q <= t; ++q) fac[d.z + t * (t + 1) / 2 + q] = Gm[t][q];
 }
 
 cesim_status lk_setup_device(cesim_ctx c) {
@@ -280,6 +364,15 @@ cesim_status lk_phi_device(cesim_ctx c, double tau2) {
   return CESIM_OK;
 }
 
+static JointBoxes joint_boxes(cesim_ctx c) {
+  return {c->box_of.as<int2>(), c->box_desc.as<int4>(), c->box_members.as<int>(),
+          c->box_fac.as<double>()};
+}
+
+// Joint sampling is in force when it is switched on and some box holds
+// several observations.
+bool joint_active(cesim_ctx c) { return c->joint_boxes && c->nboxes > 0; }
+
 cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, bool with_z) {
   const double* z = with_z ? c->zdev.as<double>() : nullptr;
   const int n = c->nobs;
@@ -287,19 +380,47 @@ cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, b
   const NoiseKey key{(uint32_t)(c->seed & 0xffffffffu), (uint32_t)(c->seed >> 32), c->first_real,
                      c->event_id, c->roff};
   const int w2 = 2 * c->npp;
+  const JointBoxes jb = joint_boxes(c);
   const int tr = c->timer.begin(ST_SYNTH_RHS, c->stream);
-  if (c->prec == CESIM_PREC_FP64)
-    k_synth_rhs<double><<<grid, 256, 0, c->stream>>>(
-        static_cast<const double*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key,
-        c->obs_order.as<int>(), rhs);
-  else
-    k_synth_rhs<float><<<grid, 256, 0, c->stream>>>(
-        static_cast<const float*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),
-        c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key,
-        c->obs_order.as<int>(), rhs);
+#define CESIM_SYNTH(F, J)                                                                          \
+  k_synth_rhs<F, J><<<grid, 256, 0, c->stream>>>(                                                  \
+      static_cast<const F*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),               \
+      c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key, c->obs_order.as<int>(), \
+      rhs, jb)
+  if (c->prec == CESIM_PREC_FP64) {
+    if (joint_active(c)) CESIM_SYNTH(double, true);
+    else CESIM_SYNTH(double, false);
+  } else {
+    if (joint_active(c)) CESIM_SYNTH(float, true);
+    else CESIM_SYNTH(float, false);
+  }
+#undef CESIM_SYNTH
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, c->stream);
+  return CESIM_OK;
+}
+
+// Factors of the boxes of several observations for nugget tau2 (joint
+// sampling), on stream s; a non-positive pivot sets bit 2 of c->chol_info[0]
+// (the flag of the observation factorisation, cleared by the caller).
+cesim_status box_factor_device(cesim_ctx c, double tau2, hipStream_t s) {
+  if (!joint_active(c)) return CESIM_OK;
+  if (c->max_box > kMaxBox) return CESIM_ERR_INVALID_ARG;
+  const JointBoxes jb = joint_boxes(c);
+  int* info = c->chol_info.as<int>();
+  const dim3 grid(c->nboxes);
+#define CESIM_BOXF(NP)                                                                         \
+  k_box_factor<NP><<<grid, 64, 0, s>>>(c->obs_xy.as<double>(), c->gridd, c->covd,             \
+                                       c->corners.as<int2>(), c->weights.as<double>(), tau2, jb, \
+                                       c->box_fac.as<double>(), info)
+  switch (c->npp) {
+    case 1: CESIM_BOXF(1); break;
+    case 2: CESIM_BOXF(2); break;
+    case 3: CESIM_BOXF(3); break;
+    default: CESIM_BOXF(4); break;
+  }
+#undef CESIM_BOXF
+  CESIM_HIP(hipGetLastError());
   return CESIM_OK;
 }
 
