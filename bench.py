@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--workload", choices=["dm", "events64", "grad512"], default="dm",
                     help="dm: the 1024^2 single-event workload; events64: 64 uneven events "
                          "run as one batch (one graph launch per step)")
+    ap.add_argument("--joint", action="store_true",
+                    help="sample the observations that share a grid box jointly "
+                         "(CESIM_PARAM_JOINT_BOXES)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the one-off tuning of launch shapes that precedes the warm-up "
                          "(by default the library's autotuner picks the draw and GEMM tiles "
@@ -106,6 +109,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
         if args.chunk_pairs:
             ctx.set_param(cesim.PARAM_DRAW_CHUNK_PAIRS, args.chunk_pairs)
         ctx.set_param(cesim.PARAM_GEMM_SPLIT, 0 if args.split == "fp16" else 1)
+        ctx.set_param(cesim.PARAM_JOINT_BOXES, 1 if args.joint else 0)
         ctx.offgrid(xy, wl.k)
         for b0 in range(0, R, batch):
             nb = min(batch, R - b0)
@@ -177,7 +181,7 @@ COUNTED_STAGES = {
     "draw_irowfft_crop": ("k_p2_rows_inv_crop<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
     "krige_grid_gemm": ("k_krige_split3", ["krige.hip", "devmath.hpp"]),
     "krige_predict_fp64": ("k_predict_f64", ["krige.hip", "devmath.hpp"]),
-    "synth_obs_rhs": ("k_synth_rhs<float>", ["lk.hip", "devmath.hpp"]),
+    "synth_obs_rhs": ("k_synth_rhs<float, false>", ["lk.hip", "devmath.hpp"]),
 }
 
 
@@ -531,11 +535,13 @@ def main():
         "dtype": (f"f32 FFT / {args.split}x3 GEMM (f64 setup, Cholesky, solves)" if "mixed" in res
                   else "f64"),
         "data": "synthetic",
-        "config": {"workload": wl.name if (args.m, args.n, args.nreal) == (1024, 5000, 1000)
-                   else f"exp{args.m}_n{args.n}cl_k36_R{args.nreal}",
+        "config": {"workload": (wl.name if (args.m, args.n, args.nreal) == (1024, 5000, 1000)
+                                else f"exp{args.m}_n{args.n}cl_k36_R{args.nreal}")
+                               + ("_joint" if args.joint else ""),
                    "grid": f"{wl.m}x{wl.m}", "torus": head["t1"], "n_obs": wl.n, "k": wl.k,
                    "covariance": "exponential sigma2=1 range=0.02", "nugget": wl.tau2,
-                   "realizations_per_step": wl.nreal, "batch": args.batch or wl.nreal},
+                   "realizations_per_step": wl.nreal, "batch": args.batch or wl.nreal,
+                   "joint_boxes": bool(args.joint)},
         "roofline": roof,
     }
     if "fp64" in res and "mixed" in res:
