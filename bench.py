@@ -281,7 +281,7 @@ def cpu_baseline(wl, xy, z, seed):
     s0 = time.perf_counter()
     fac = kriging.factor(xy, cov, wl.tau2)
     t["cholesky"] = time.perf_counter() - s0
-    nd = 4
+    nd = 24
     s0 = time.perf_counter()
     eps = philox.torus_noise(seed, t1, t2, range(nd))
     y = ce.ce_draw(s, eps, wl.m, wl.m)
@@ -292,7 +292,7 @@ def cpu_baseline(wl, xy, z, seed):
     s0 = time.perf_counter()
     B = kriging.coefficients(fac, z, zsR)
     t["solve_R"] = time.perf_counter() - s0
-    rows = np.arange(32)
+    rows = np.arange(192)
     s0 = time.perf_counter()
     kriging.krige_to_grid(B, xy, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, rows=rows, chunk_rows=8)
     t["krige_rows"] = time.perf_counter() - s0
