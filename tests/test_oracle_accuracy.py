@@ -1,0 +1,67 @@
+"""Pins of the prediction standard errors (oracle/accuracy.py): SE_E
+against the exact conditional covariance of eq. (4), SE_L against the
+covariance of the whole simulation's linear map (Section 3.1 by an
+independent route), SE_L = SE_E for observations on nodes, and a loose
+statistical comparison with the fractions printed in Table 1 (Section 3.4)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import accuracy as acc
+from oracle.covariance import Cov
+from oracle.pipeline import Grid, exact_conditional, linear_map
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_local_kriging_sig3.txt")
+
+
+@pytest.mark.parametrize("cov,tau2", [(Cov(0.5, 1.0, 0.3), 0.05), (Cov(1.5, 1.2, 0.4, 2.0, 0.6), 0.1)])
+def test_se_exact_is_the_conditional_covariance(cov, tau2):
+    g = Grid.unit_square(9)
+    xy = np.random.default_rng(1).uniform(0, 1, (7, 2))
+    _, C = exact_conditional(cov, g, xy, np.zeros(7), tau2)
+    np.testing.assert_allclose(acc.se_exact(cov, g, xy, tau2) ** 2, np.diag(C), atol=1e-13)
+
+
+@pytest.mark.parametrize("cov,k,tau2", [(Cov(0.5, 1.0, 0.35), 4, 0.05),
+                                        (Cov(1.5, 1.0, 0.3, 2.0, 0.3), 16, 0.1),
+                                        (Cov(1.0, 1.0, 0.25), 16, 0.02)])
+def test_se_local_is_the_variance_of_the_simulation(cov, k, tau2):
+    g = Grid.unit_square(6)
+    xy = np.random.default_rng(2).uniform(0, 1, (5, 2))
+    Me, Mx = linear_map(cov, g, xy, tau2, k)
+    var = np.diag(Me @ Me.T + Mx @ Mx.T)
+    np.testing.assert_allclose(acc.se_local(cov, g, xy, tau2, k) ** 2, var, atol=1e-12)
+
+
+def test_observations_on_nodes_make_local_exact():
+    g = Grid.unit_square(12)
+    xy = np.array([[2, 3], [7, 9], [10, 1], [5, 5]]) / 11.0
+    cov = Cov(0.5, 1.0, 0.2)
+    np.testing.assert_allclose(acc.se_local(cov, g, xy, 0.05, 16), acc.se_exact(cov, g, xy, 0.05),
+                               atol=1e-12)
+
+
+def test_table1_fractions_loosely():
+    """Exponential covariance, 61 x 61 grid on [0, 60]^2, 35 uniform
+    observations, tau = 0.1: mean over 8 configurations of the fraction of
+    nodes correct to three significant figures, within 0.12 of the printed
+    means for n_p = 1, 2, 3 (the windows here are clamped at the grid edge
+    where the paper pads the grid, which lowers the fractions), and
+    increasing in n_p."""
+    rows = np.loadtxt(GOLDEN)
+    g = Grid(61, 61, 0.0, 0.0, 1.0, 1.0)
+    rng = np.random.default_rng(0)
+    for th in (6.68, 23.37):
+        row = rows[(rows[:, 0] == th) & (rows[:, 1] == 0.1)][0]
+        cov = Cov(0.5, 1.0, th)
+        fr = {k: [] for k in (4, 16, 36)}
+        for _ in range(8):
+            xy = rng.uniform(0, 60, (35, 2))
+            e = acc.se_exact(cov, g, xy, 0.01)
+            for k in fr:
+                fr[k].append(acc.fraction_sig3(acc.se_local(cov, g, xy, 0.01, k), e))
+        means = [np.mean(fr[k]) for k in (4, 16, 36)]
+        assert means[0] < means[1] < means[2]
+        for got, paper in zip(means, row[[2, 4, 6]]):
+            assert abs(got - paper) < 0.12, (th, got, paper)
