@@ -319,6 +319,22 @@ cesim_status ce_grad_linear(cesim_ctx ctx, const double* z, double nugget, int n
                             uint64_t seed, int first_real, const void* wgt_dev, double* out,
                             double* dz);
 
+/* ---- prediction standard errors ----
+ * The exact Kriging standard error on the grid (Section 3, eq. (4)),
+ *   SE_E(g)^2 = C(0) - K12[g] (K22 + tau^2 I)^{-1} K21[g],
+ * and the one the local-Kriging simulation realizes (Section 3.1: the
+ * diagonal of (Lambda - I) K11 (Lambda - I)^T + W2 diag(tau^2 + gamma) W2^T,
+ * Lambda = W2 W1, W2 = K12 (K22 + tau^2 I)^{-1}), for the stations of the
+ * last offgrid_nnkrige and the given nugget (tau^2 >= 0).  Writes m1*m2
+ * doubles each ([m2][m1], x fastest) into the caller-owned device arrays
+ * se_exact_dev and se_local_dev.  FP64 on either precision; refactors the
+ * observation covariance when the nugget differs from the last condition().
+ * INVALID_ARG for null pointers or a negative or non-finite nugget,
+ * BAD_STATE before offgrid_nnkrige, NOT_POSITIVE_DEFINITE when the Cholesky
+ * fails.  Synchronises. */
+cesim_status ce_prediction_se(cesim_ctx ctx, double nugget, void* se_exact_dev,
+                              void* se_local_dev);
+
 /* ---- batches of independent events ----
  * One event is the whole conditional simulation above (Section 2 with the
  * local Kriging of Section 2.1) for its own covariance, grid, stations,

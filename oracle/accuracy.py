@@ -28,36 +28,43 @@ from . import localkrige
 from .covariance import Cov, cross_covariance
 
 
-def se_exact(cov: Cov, grid, obs_xy, tau2):
-    """SE_E on the grid (flattened, x fastest)."""
+def se_exact(cov: Cov, grid, obs_xy, tau2, rows=None):
+    """SE_E on the grid (flattened, x fastest), or on the nodes listed in rows."""
     obs_xy = np.asarray(obs_xy, dtype=np.float64).reshape(-1, 2)
     n = obs_xy.shape[0]
     A = cross_covariance(obs_xy, obs_xy, cov) + tau2 * np.eye(n)
-    K12 = cross_covariance(grid.points(), obs_xy, cov)
+    G = grid.points() if rows is None else grid.points()[np.asarray(rows)]
+    K12 = cross_covariance(G, obs_xy, cov)
     W2 = np.linalg.solve(A, K12.T).T
     return np.sqrt(cov.sigma2 - np.sum(W2 * K12, axis=1))
 
 
-def se_local(cov: Cov, grid, obs_xy, tau2, k):
-    """SE_L on the grid from the closed form of Section 3.1."""
+def se_local(cov: Cov, grid, obs_xy, tau2, k, rows=None):
+    """SE_L on the grid from the closed form of Section 3.1, or on the nodes
+    listed in rows (W1 K11 is then formed only on the columns it needs: the
+    listed nodes and the window nodes)."""
     obs_xy = np.asarray(obs_xy, dtype=np.float64).reshape(-1, 2)
     n = obs_xy.shape[0]
     G = grid.points()
+    rows = np.arange(G.shape[0]) if rows is None else np.asarray(rows)
     A = cross_covariance(obs_xy, obs_xy, cov) + tau2 * np.eye(n)
-    W2 = np.linalg.solve(A, cross_covariance(G, obs_xy, cov).T).T        # M x n
+    W2 = np.linalg.solve(A, cross_covariance(G[rows], obs_xy, cov).T).T  # rows x n
     a, b, W, gamma = localkrige.local_krige(obs_xy, cov, grid.x0, grid.y0, grid.dx, grid.dy,
                                             grid.m1, grid.m2, k)
     npp = int(round(np.sqrt(k))) // 2
     p, q = localkrige.window_offsets(npp)
-    W1K = np.zeros((n, G.shape[0]))                                      # W1 K11
     idx = np.zeros((n, k), dtype=np.int64)
     for i in range(n):
-        nodes = np.stack([grid.x0 + (a[i] + p) * grid.dx, grid.y0 + (b[i] + q) * grid.dy], axis=1)
-        W1K[i] = W[i] @ cross_covariance(nodes, G, cov)
         idx[i] = (b[i] + q) * grid.m1 + a[i] + p
-    Q = np.stack([W1K[:, idx[j]] @ W[j] for j in range(n)], axis=1)      # W1 K11 W1^T
+    cols, inv = np.unique(np.concatenate([rows, idx.ravel()]), return_inverse=True)
+    at_rows, at_idx = inv[:rows.size], inv[rows.size:].reshape(n, k)
+    W1K = np.zeros((n, cols.size))                                       # (W1 K11)[:, cols]
+    for i in range(n):
+        nodes = np.stack([grid.x0 + (a[i] + p) * grid.dx, grid.y0 + (b[i] + q) * grid.dy], axis=1)
+        W1K[i] = W[i] @ cross_covariance(nodes, G[cols], cov)
+    Q = np.stack([W1K[:, at_idx[j]] @ W[j] for j in range(n)], axis=1)   # W1 K11 W1^T
     phi2 = tau2 + gamma
-    v = (np.einsum("gi,ij,gj->g", W2, Q, W2) - 2.0 * np.sum(W2 * W1K.T, axis=1)
+    v = (np.sum((W2 @ Q) * W2, axis=1) - 2.0 * np.sum(W2 * W1K[:, at_rows].T, axis=1)
          + cov.sigma2 + (W2 * W2) @ phi2)
     return np.sqrt(np.maximum(v, 0.0))
 

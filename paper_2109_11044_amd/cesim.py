@@ -29,7 +29,7 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "cesim_batch_create", "cesim_batch_run", "cesim_batch_get_info",
            "cesim_batch_destroy", "cesim_run_events", "ce_autotune",
            "cesim_tune_save", "cesim_tune_load", "cesim_tune_entries", "cesim_tune_clear",
-           "ce_grad_linear"]
+           "ce_grad_linear", "ce_prediction_se"]
 PARAM_GEMM_TILE = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
@@ -138,6 +138,7 @@ def lib():
     L.cesim_tune_clear.argtypes = []
     L.cesim_tune_clear.restype = None
     L.ce_grad_linear.argtypes = [vp, dp, d, i, u64, i, vp, dp, dp]
+    L.ce_prediction_se.argtypes = [vp, d, vp, vp]
     for name in EXPORTS:
         if name not in VOID_EXPORTS:
             getattr(L, name).restype = i
@@ -355,6 +356,17 @@ class Context:
                                     _dptr(out), _dptr(dz)), "ce_grad_linear")
         return {"L": float(out[0]), "d_range": float(out[1]), "d_sigma2": float(out[2]),
                 "d_nugget": float(out[3]), "d_z": dz}
+
+    def prediction_se(self, nugget):
+        """(SE_E, SE_L): exact and local-Kriging prediction standard errors on
+        the grid, CUDA float64 tensors of m2 x m1."""
+        t = self._torch
+        g = self.grid
+        se_e = t.empty((g.m2, g.m1), dtype=t.float64, device="cuda")
+        se_l = t.empty((g.m2, g.m1), dtype=t.float64, device="cuda")
+        _check(lib().ce_prediction_se(self._h, float(nugget), ctypes.c_void_p(se_e.data_ptr()),
+                                      ctypes.c_void_p(se_l.data_ptr())), "ce_prediction_se")
+        return se_e, se_l
 
     def coefficients(self):
         t = self._torch

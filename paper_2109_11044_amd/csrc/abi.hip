@@ -245,7 +245,8 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
-          &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac};
+          &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
+          &c->sework};
 }
 
 namespace {

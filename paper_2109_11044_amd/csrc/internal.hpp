@@ -204,6 +204,7 @@ struct cesim_ctx_s {
   int* chol_info_host = nullptr;    // pinned copy, valid once factor_ready has completed
   cesim::DevBuf gwork;              // gradient: one FP64 pair buffer + d sqrt(lambda)
   cesim::DevBuf gvec;               // gradient: mean noises, fields and vectors
+  cesim::DevBuf sework;             // standard errors: chunk arrays and W1 K11 W1^T
   cesim::GroupedSeq winv_seq;       // launches that build winv (kept until they have run)
   cesim::PinnedStage winv_stage;
   std::vector<double> z_host_cached;
@@ -240,6 +241,7 @@ cesim_status box_factor_device(cesim_ctx c, double tau2, hipStream_t s);
 bool joint_active(cesim_ctx c);
 constexpr int kMaxJointBox = 32;   // observations per box of the joint sampling
 cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* yb, double* dyb);
+cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s);
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
                             const double* xib, double* out);
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y);

@@ -1,0 +1,195 @@
+// se.hip -- prediction standard errors on the grid, FP64 (Section 3, eq. (4);
+// Section 3.1):
+//   SE_E(g)^2 = C(0) - K12[g] A^{-1} K21[g],   A = K22 + tau^2 I,
+//   SE_L(g)^2 = W2_g Q W2_g^T - 2 W2_g (W1 K11)[:, g] + C(0) + sum_i W2_gi^2 phi_i^2,
+// the exact Kriging standard error and the one the local-Kriging simulation
+// realizes (the diagonal of (Lambda - I) K11 (Lambda - I)^T + W2 diag(phi^2)
+// W2^T with Lambda = W2 W1), where W2_g = K12[g] A^{-1}, Q = W1 K11 W1^T and
+// phi_i^2 = tau^2 + gamma_i.  Grid nodes are processed in chunks of R: the
+// cross-covariance rows K (R x n), X = W2 rows (the observation factor's
+// solve with R right-hand sides), V = (W1 K11)^T rows (R x n), T = X Q
+// (FP64 matrix-core GEMM), then one fixed-order reduction per node.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace cesim {
+namespace {
+
+__device__ inline double node_x(const GridDev& g, int gg) {
+  return __dadd_rn(g.x0, __dmul_rn((double)(gg % g.m1), g.dx));
+}
+__device__ inline double node_y(const GridDev& g, int gg) {
+  return __dadd_rn(g.y0, __dmul_rn((double)(gg / g.m1), g.dy));
+}
+
+// K[r][i] = C(g_{g0 + r} - s_i); rows past the grid are zero.
+__global__ void k_cross_chunk(const double* __restrict__ obs, int n, GridDev g, CovDev cov, int g0,
+                              int R, int M, double* __restrict__ K) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)R * n) return;
+  const int r = (int)(q / n), i = (int)(q % n), gg = g0 + r;
+  K[q] = gg < M ? cov_eval(cov, node_x(g, gg) - obs[2 * i], node_y(g, gg) - obs[2 * i + 1]) : 0.0;
+}
+
+// V[r][i] = sum_al w_i[al] C(node_{i,al} - g_{g0 + r}) = (W1 K11)[i][g].
+template <int NPP>
+__global__ void k_w1k_chunk(const int2* __restrict__ corners, const double* __restrict__ W, int n,
+                            GridDev g, CovDev cov, int g0, int R, int M, double* __restrict__ V) {
+  constexpr int W2 = 2 * NPP, K = W2 * W2;
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)R * n) return;
+  const int r = (int)(q / n), i = (int)(q % n), gg = g0 + r;
+  if (gg >= M) {
+    V[q] = 0.0;
+    return;
+  }
+  const double gx = node_x(g, gg), gy = node_y(g, gg);
+  const int2 ab = corners[i];
+  const double* w = W + (size_t)i * K;
+  double acc = 0.0;
+  for (int al = 0; al < K; ++al) {
+    const double nx = __dadd_rn(g.x0, __dmul_rn((double)(ab.x + al % W2), g.dx));
+    const double ny = __dadd_rn(g.y0, __dmul_rn((double)(ab.y + al / W2), g.dy));
+    acc += w[al] * cov_eval(cov, nx - gx, ny - gy);
+  }
+  V[q] = acc;
+}
+
+// Q[i][j] = sum_al sum_be w_i[al] w_j[be] C(node_{i,al} - node_{j,be}).
+template <int NPP>
+__global__ void k_w1k11w1(const int2* __restrict__ corners, const double* __restrict__ W, int n,
+                          GridDev g, CovDev cov, double* __restrict__ Q) {
+  constexpr int W2 = 2 * NPP, K = W2 * W2;
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)n * n) return;
+  const int i = (int)(q / n), j = (int)(q % n);
+  const int2 ai = corners[i], aj = corners[j];
+  const double* wi = W + (size_t)i * K;
+  const double* wj = W + (size_t)j * K;
+  double acc = 0.0;
+  for (int al = 0; al < K; ++al) {
+    double inner = 0.0;
+    for (int be = 0; be < K; ++be) {
+      const double hx = (double)(ai.x + al % W2 - aj.x - be % W2) * g.dx;
+      const double hy = (double)(ai.y + al / W2 - aj.y - be / W2) * g.dy;
+      inner += wj[be] * cov_eval(cov, hx, hy);
+    }
+    acc += wi[al] * inner;
+  }
+  Q[q] = acc;
+}
+
+// One workgroup per node of the chunk: the four row products and the two
+// standard errors.
+__global__ void __launch_bounds__(256)
+k_se_rows(const double* __restrict__ K, const double* __restrict__ X, const double* __restrict__ V,
+          const double* __restrict__ T, const double* __restrict__ gam, double tau2, int n, int g0,
+          int M, double sigma2, double* __restrict__ se_e, double* __restrict__ se_l) {
+  __shared__ double red[4][256];
+  const int r = blockIdx.x, gg = g0 + r;
+  if (gg >= M) return;
+  const size_t o = (size_t)r * n;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double x = X[o + i];
+    a += T[o + i] * x;
+    b += x * V[o + i];
+    c += x * x * (tau2 + gam[i]);
+    d += x * K[o + i];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  red[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int u = 0; u < 4; ++u) red[u][threadIdx.x] += red[u][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    se_e[gg] = sqrt(fmax(0.0, sigma2 - red[3][0]));
+    se_l[gg] = sqrt(fmax(0.0, red[0][0] - 2.0 * red[1][0] + sigma2 + red[2][0]));
+  }
+}
+
+}  // namespace
+}  // namespace cesim
+
+using namespace cesim;
+
+extern "C" cesim_status ce_prediction_se(cesim_ctx c, double nugget, void* se_exact,
+                                         void* se_local) {
+  if (!c || !se_exact || !se_local) return CESIM_ERR_INVALID_ARG;
+  if (!(std::isfinite(nugget) && nugget >= 0.0)) return CESIM_ERR_INVALID_ARG;
+  if (c->nobs < 1) return CESIM_ERR_BAD_STATE;
+  hipStream_t s = c->stream;
+  CESIM_HIP(hipStreamSynchronize(c->aux));       // earlier aux work may use the factor
+  CESIM_HIP(hipStreamSynchronize(s));
+  const int n = c->nobs, M = c->grid.m1 * c->grid.m2;
+  // chunk of grid nodes: five R x n arrays within about 1 GiB
+  const size_t per_row = 5 * (size_t)n * sizeof(double);
+  const int R = (int)std::max<size_t>(64, std::min<size_t>((size_t)M, ((size_t)1 << 30) / per_row));
+  CESIM_TRY(c->sework.reserve(per_row * R + sizeof(double) * (size_t)n * n));
+  double* K = c->sework.as<double>();
+  double* X = K + (size_t)R * n;
+  double* Y = X + (size_t)R * n;
+  double* V = Y + (size_t)R * n;
+  double* T = V + (size_t)R * n;
+  double* Q = T + (size_t)R * n;
+  const bool refactor = !c->chol_valid || c->chol_nugget != nugget;
+  if (refactor) {
+    c->chol_valid = false;
+    CESIM_TRY(chol_factor_device(c, nugget, s));
+  }
+  const double* obs = c->obs_xy.as<double>();
+  const int2* cor = c->corners.as<int2>();
+  const double* W = c->weights.as<double>();
+  const unsigned nq = (unsigned)(((size_t)n * n + 255) / 256);
+#define CESIM_NP(NP, CALL) \
+  case NP: CALL; break;
+  switch (c->npp) {
+    CESIM_NP(1, (k_w1k11w1<1><<<nq, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, Q)))
+    CESIM_NP(2, (k_w1k11w1<2><<<nq, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, Q)))
+    CESIM_NP(3, (k_w1k11w1<3><<<nq, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, Q)))
+    default: k_w1k11w1<4><<<nq, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, Q); break;
+  }
+  CESIM_HIP(hipGetLastError());
+  const unsigned nr = (unsigned)(((size_t)R * n + 255) / 256);
+  for (int g0 = 0; g0 < M; g0 += R) {
+    k_cross_chunk<<<nr, 256, 0, s>>>(obs, n, c->gridd, c->covd, g0, R, M, K);
+    CESIM_HIP(hipGetLastError());
+    CESIM_HIP(hipMemcpyAsync(X, K, sizeof(double) * (size_t)R * n, hipMemcpyDeviceToDevice, s));
+    CESIM_TRY(chol_solve_device(c, X, R, s, Y));              // X = K A^{-1} (rows of W2)
+    switch (c->npp) {
+      CESIM_NP(1, (k_w1k_chunk<1><<<nr, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, g0, R, M, V)))
+      CESIM_NP(2, (k_w1k_chunk<2><<<nr, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, g0, R, M, V)))
+      CESIM_NP(3, (k_w1k_chunk<3><<<nr, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, g0, R, M, V)))
+      default: k_w1k_chunk<4><<<nr, 256, 0, s>>>(cor, W, n, c->gridd, c->covd, g0, R, M, V); break;
+    }
+    CESIM_HIP(hipGetLastError());
+    GemmArgs gm;                                               // T = X Q
+    gm.M = R; gm.N = n; gm.K = n; gm.alpha = 1.0; gm.beta = 0.0;
+    gm.A = X; gm.sai = n; gm.sak = 1;
+    gm.B = Q; gm.sbk = n; gm.sbj = 1;
+    gm.C = T; gm.sci = n; gm.scj = 1;
+    CESIM_TRY(gemm_f64(gm, false, s));
+    k_se_rows<<<std::min(R, M - g0), 256, 0, s>>>(K, X, V, T, c->gamma.as<double>(), nugget, n, g0,
+                                                   M, c->covd.sigma2,
+                                                   static_cast<double*>(se_exact),
+                                                   static_cast<double*>(se_local));
+    CESIM_HIP(hipGetLastError());
+  }
+#undef CESIM_NP
+  CESIM_HIP(hipStreamSynchronize(s));
+  if (refactor) {
+    if (c->chol_info_host[0] & 2) return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+    c->chol_valid = true;
+    c->chol_nugget = nugget;
+  }
+  return CESIM_OK;
+}

@@ -1,0 +1,116 @@
+"""Prediction standard errors through the C ABI (ce_prediction_se): the exact
+Kriging standard error of eq. (4) and the local-Kriging one of Section 3.1,
+FP64 on both precisions, against the oracle element by element; the chunked
+path (more grid nodes than one chunk holds); SE_L = SE_E for stations on
+nodes; the Table 1 setting of Section 3.4; error statuses."""
+import numpy as np
+import pytest
+
+from oracle import accuracy as acc
+from oracle.covariance import Cov as OCov
+from oracle.pipeline import Grid as OGrid
+from paper_2109_11044_amd import cesim, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10          # FP64 against FP64, relative to sigma
+
+
+def run(cov, grid, xy, k, tau2, prec="fp64"):
+    with cesim.Context(cesim.make_cov(*cov), grid, prec) as ctx:
+        ctx.offgrid(xy, k)
+        e, l = ctx.prediction_se(tau2)
+        return e.cpu().numpy().reshape(-1), l.cpu().numpy().reshape(-1)
+
+
+def ogrid(g):
+    return OGrid(g.m1, g.m2, g.x0, g.y0, g.dx, g.dy)
+
+
+CASES = [  # cov (nu, sigma2, range, ratio, angle), m, n, k, tau2, prec
+    ((0.5, 1.0, 0.2), 24, 30, 4, 0.05, "fp64"),
+    ((0.5, 1.3, 0.15), 40, 65, 16, 0.1, "mixed"),
+    ((1.0, 1.0, 0.12), 33, 80, 36, 0.02, "fp64"),
+    ((1.5, 0.8, 0.2, 2.0, 0.6), 28, 47, 64, 0.05, "fp64"),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_standard_errors_match_oracle(case):
+    cov, m, n, k, tau2, prec = case
+    xy = workloads.locations("clustered", n, seed=21)
+    g = cesim.unit_square_grid(m)
+    se_e, se_l = run(cov, g, xy, k, tau2, prec)
+    oc = OCov(*cov)
+    ref_e = acc.se_exact(oc, ogrid(g), xy, tau2)
+    ref_l = acc.se_local(oc, ogrid(g), xy, tau2, k)
+    s = np.sqrt(cov[1])
+    np.testing.assert_allclose(se_e, ref_e, rtol=0, atol=TOL * s)
+    np.testing.assert_allclose(se_l, ref_l, rtol=0, atol=TOL * s)
+
+
+def test_many_chunks_and_a_ragged_last_chunk():
+    """3000 stations make a chunk of 1 GiB / (5 * 3000 * 8) = 8947 nodes, so a
+    131 x 97 grid (12707 nodes) takes two chunks, the second one ragged;
+    sampled nodes, the chunk boundary among them, against the oracle."""
+    n, k, tau2 = 3000, 16, 0.05
+    cov = (0.5, 1.0, 0.1)
+    xy = workloads.locations("clustered", n, seed=5)
+    g = cesim.Grid(131, 97, 0.0, 0.0, 1.0 / 130, 1.0 / 96, 0, 0)
+    se_e, se_l = run(cov, g, xy, k, tau2)
+    oc, og = OCov(*cov), ogrid(g)
+    rows = np.random.default_rng(3).choice(g.m1 * g.m2, 200, replace=False)
+    rows = np.unique(np.concatenate([rows, [0, 8946, 8947, g.m1 * g.m2 - 1]]))
+    np.testing.assert_allclose(se_e[rows], acc.se_exact(oc, og, xy, tau2, rows), rtol=0, atol=TOL)
+    np.testing.assert_allclose(se_l[rows], acc.se_local(oc, og, xy, tau2, k, rows), rtol=0,
+                               atol=TOL)
+
+
+def test_stations_on_nodes_make_local_exact():
+    m = 21
+    xy = np.array([[2, 3], [7, 9], [10, 1], [5, 5], [20, 20], [0, 14]]) / (m - 1.0)
+    se_e, se_l = run((0.5, 1.0, 0.2), cesim.unit_square_grid(m), xy, 16, 0.05)
+    np.testing.assert_allclose(se_l, se_e, rtol=0, atol=1e-10)
+
+
+def test_table1_setting():
+    """Exponential covariance, theta = 15.02, 61 x 61 grid on [0, 60]^2, 35
+    uniform observations, tau = 0.1: both standard errors equal the oracle's,
+    and the fractions correct to three significant figures computed from them
+    equal the oracle's fractions and increase with n_p."""
+    g = cesim.Grid(61, 61, 0.0, 0.0, 1.0, 1.0, 0, 0)
+    cov = (0.5, 1.0, 15.02)
+    xy = np.random.default_rng(4).uniform(0, 60, (35, 2))
+    fr = []
+    ref_e = acc.se_exact(OCov(*cov), ogrid(g), xy, 0.01)
+    for k in (4, 16, 36):
+        se_e, se_l = run(cov, g, xy, k, 0.01)
+        ref_l = acc.se_local(OCov(*cov), ogrid(g), xy, 0.01, k)
+        np.testing.assert_allclose(se_e, ref_e, rtol=0, atol=TOL)
+        np.testing.assert_allclose(se_l, ref_l, rtol=0, atol=TOL)
+        # a node whose two values straddle a rounding boundary could flip; allow one
+        f, f_ref = acc.fraction_sig3(se_l, se_e), acc.fraction_sig3(ref_l, ref_e)
+        assert abs(f - f_ref) <= 1.0 / (61 * 61) + 1e-15, (k, f, f_ref)
+        fr.append(f)
+    assert fr[0] < fr[1] < fr[2]
+
+
+def test_error_statuses():
+    with cesim.Context(cesim.make_cov(0.5, 1.0, 0.2), cesim.unit_square_grid(16)) as ctx:
+        with pytest.raises(cesim.CesimError) as e:
+            ctx.prediction_se(0.1)
+        assert e.value.name == "BAD_STATE"
+        xy = workloads.uniform_locations(6, seed=3)
+        ctx.offgrid(xy, 4)
+        for bad in (-1.0, float("nan"), float("inf")):
+            with pytest.raises(cesim.CesimError) as e:
+                ctx.prediction_se(bad)
+            assert e.value.name == "INVALID_ARG"
+        xy2 = xy.copy()
+        xy2[1] = xy2[0]
+        ctx.offgrid(xy2, 4)
+        with pytest.raises(cesim.CesimError) as e:
+            ctx.prediction_se(0.0)
+        assert e.value.name == "NOT_POSITIVE_DEFINITE"
+        se_e, se_l = ctx.prediction_se(0.1)                  # recovers
+        assert bool((se_e >= 0).all()) and bool((se_l >= 0).all())

@@ -42,6 +42,17 @@ def test_observations_on_nodes_make_local_exact():
                                atol=1e-12)
 
 
+def test_listed_nodes_equal_the_full_grid():
+    g = Grid(10, 7, 0.2, -0.1, 0.11, 0.13)
+    xy = np.random.default_rng(5).uniform(0, 1, (9, 2))
+    cov = Cov(1.0, 1.1, 0.3)
+    rows = np.array([69, 0, 33, 34, 5])
+    np.testing.assert_allclose(acc.se_exact(cov, g, xy, 0.05, rows),
+                               acc.se_exact(cov, g, xy, 0.05)[rows], atol=1e-14)
+    np.testing.assert_allclose(acc.se_local(cov, g, xy, 0.05, 16, rows),
+                               acc.se_local(cov, g, xy, 0.05, 16)[rows], atol=1e-13)
+
+
 def test_table1_fractions_loosely():
     """Exponential covariance, 61 x 61 grid on [0, 60]^2, 35 uniform
     observations, tau = 0.1: mean over 8 configurations of the fraction of
