@@ -52,7 +52,12 @@ def parse():
                     help="half type of the three-product split in the mixed GEMM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default="")
-    ap.add_argument("--workload", choices=["dm", "events64", "grad512"], default="dm",
+    ap.add_argument("--se-chunk", type=int, default=0,
+                    help="se1024: grid nodes per chunk (0: the library's choice)")
+    ap.add_argument("--configs", type=int, default=100,
+                    help="accuracy61: random station configurations per case")
+    ap.add_argument("--workload", choices=["dm", "events64", "grad512", "accuracy61", "se1024"],
+                    default="dm",
                     help="dm: the 1024^2 single-event workload; events64: 64 uneven events "
                          "run as one batch (one graph launch per step)")
     ap.add_argument("--joint", action="store_true",
@@ -479,6 +484,203 @@ def grad_cpu_baseline():
             "seconds_measured": sec}
 
 
+def _sig3(x):
+    """Values rounded to three significant figures (x > 0), on the device."""
+    import torch
+    s = torch.pow(10.0, torch.floor(torch.log10(x)) - 2.0)
+    return torch.round(x / s) * s
+
+
+def accuracy_main(args, torch, cesim, workloads):
+    """Accuracy study of Sections 3.3-3.4 on the GPU: for each of the 18
+    cases and each random configuration of 35 stations, the exact and the
+    local-Kriging prediction standard errors on the 61 x 61 grid for
+    n_p = 1..4 (ce_prediction_se, FP64).  Reports the fraction of nodes
+    correct to three significant figures (Table 1's score) and the 95th
+    percentile over the grid of E_L = 100 (SE_L - SE_E) / SE_E (the quantity
+    behind the 1 % claim), mean and spread over configurations.  The timed
+    region is the whole study: 18 contexts, and per configuration and n_p one
+    station set-up and one standard-error map pair."""
+    m1, m2, x0, y0, dx, dy = workloads.STUDY_GRID
+    grid = cesim.Grid(m1, m2, x0, y0, dx, dy, 0, 0)
+    cases = workloads.study_cases()
+    C = args.configs
+    ks = [(2 * p) ** 2 for p in workloads.STUDY_NP]
+    locs = [workloads.study_locations(c) for c in range(C)]
+
+    def study(ncases, nconf):
+        frac = torch.zeros((ncases, len(ks), nconf), dtype=torch.float64, device="cuda")
+        p95 = torch.zeros_like(frac)
+        for ci, case in enumerate(cases[:ncases]):
+            with cesim.Context(cesim.make_cov(case["nu"], 1.0, case["theta"]), grid,
+                               "fp64") as ctx:
+                for c in range(nconf):
+                    for ki, k in enumerate(ks):
+                        ctx.offgrid(locs[c], k)
+                        e, l = ctx.prediction_se(case["tau"] ** 2)
+                        frac[ci, ki, c] = (_sig3(l) == _sig3(e)).double().mean()
+                        p95[ci, ki, c] = torch.quantile(100.0 * (l - e) / e, 0.95)
+        return frac.cpu().numpy(), p95.cpu().numpy()
+
+    study(1, 2)                                        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    frac, p95 = study(len(cases), C)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    maps = len(cases) * C * len(ks)
+    rows = []
+    for ci, case in enumerate(cases):
+        rows.append({"nu": case["nu"], "theta": round(float(case["theta"]), 4), "tau": case["tau"],
+                     "frac_sig3_mean": [float(v) for v in frac[ci].mean(axis=1)],
+                     "frac_sig3_sd": [float(v) for v in frac[ci].std(axis=1, ddof=1)],
+                     "p95_EL_pct_median": [float(v) for v in np.median(p95[ci], axis=1)],
+                     "p95_EL_pct_max": [float(v) for v in p95[ci].max(axis=1)],
+                     "configs_p95_under_1pct": [float(v) for v in (p95[ci] < 1.0).mean(axis=1)]})
+    paper = {}
+    golden = os.path.join(ROOT, "tests", "golden", "table1_local_kriging_sig3.txt")
+    if os.path.exists(golden):
+        for r in np.loadtxt(golden):
+            paper[f"theta={r[0]:g},tau={r[1]:g}"] = [float(r[2]), float(r[4]), float(r[6])]
+    out = {
+        "metric": "prediction-SE map pairs/s (exact + local Kriging) over the 18-case accuracy "
+                  "study, 61x61 grid, 35 uniform stations",
+        "value": maps / sec, "unit": "SE map pairs/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": 1000.0 * sec, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"accuracy61_18cases_C{C}_np1-4", "grid": "61x61 on [0,60]^2",
+                   "n_obs": workloads.STUDY_NOBS, "configs_per_case": C, "n_p": list(workloads.STUDY_NP),
+                   "maps": maps},
+        "roofline": None,
+        "roofline_note": "35 stations and 3721 nodes per map: launch and latency bound; the "
+                         "standard-error kernels are measured against their roofline at scale by "
+                         "--workload se1024",
+        "cases": rows,
+        "table1_paper_np1-3_means": paper,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = accuracy_cpu_baseline(workloads)
+    _emit(out, args)
+
+
+def accuracy_cpu_baseline(workloads):
+    """The oracle's se_exact and se_local on a bounded sample of the study:
+    the first case, 120 configurations, n_p = 1..4."""
+    from oracle import accuracy as acc
+    from oracle.covariance import Cov as OCov
+    from oracle.pipeline import Grid as OGrid
+    og = OGrid(*workloads.STUDY_GRID)
+    case = workloads.study_cases()[0]
+    cov = OCov(case["nu"], 1.0, case["theta"])
+    threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    nmaps = 0
+    for c in range(120):
+        xy = workloads.study_locations(c)
+        for p in workloads.STUDY_NP:
+            acc.se_exact(cov, og, xy, case["tau"] ** 2)
+            acc.se_local(cov, og, xy, case["tau"] ** 2, (2 * p) ** 2)
+            nmaps += 1
+    sec = time.perf_counter() - t0
+    return {"value": nmaps / sec, "unit": "SE map pairs/s", "cores": int(threads),
+            "kind": "oracle", "sample": f"{nmaps} map pairs: first case (nu 1/2, theta 6.68, "
+                                        "tau 0.1), 120 configurations, n_p = 1..4",
+            "seconds_measured": sec}
+
+
+def se_main(args, torch, cesim, workloads):
+    """Prediction standard-error maps at scale: the 1024^2 headline workload
+    (exponential, range 0.02, nugget 0.02, 5000 clustered stations, 6 x 6
+    windows); a step is one ce_prediction_se call (both maps, every grid
+    node).  Roofline of the GEMM of the solved rows with W1 K11 W1^T
+    (2 M n^2 flops per map, FP64 matrix cores) and of the observation solves
+    (2 M n^2 flops: two triangular solves per node)."""
+    wl = workloads.DM
+    xy = wl.obs_xy()
+    grid = cesim.unit_square_grid(wl.m)
+    M, n = wl.m * wl.m, wl.n
+    with cesim.Context(cesim.make_cov(wl.nu, wl.sigma2, wl.range), grid, "fp64") as ctx:
+        ctx.offgrid(xy, wl.k)
+        ctx.set_param(cesim.PARAM_SE_CHUNK_NODES, args.se_chunk)
+        ctx.set_timing(True)
+        for _ in range(args.warmup):
+            e, l = ctx.prediction_se(wl.tau2)
+        ctx.stage_times(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            # a different nugget each step would refactor; the same one reuses
+            # the observation factor, as repeated maps for one event do
+            e, l = ctx.prediction_se(wl.tau2)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        st = ctx.stage_times(reset=True)
+    finite = bool(torch.isfinite(e).all().item() and torch.isfinite(l).all().item())
+    ratio = float((l / e).median())
+    kern = []
+    for name, (ms, calls) in st.items():
+        if calls == 0:
+            continue
+        k = {"name": name, "ms_per_step": ms / args.steps,
+             "launches_per_step": calls / args.steps, "avg_launch_ms": ms / calls}
+        if name in ("se_gemm_xq", "obs_solve"):
+            fl = 2.0 * M * n * n
+            tf = fl / (ms / args.steps / 1000.0) / 1e12
+            k.update(bound="mfma", achieved=tf, unit="TFLOP/s", peak=PEAK_TFLOPS["fp64"],
+                     frac=tf / PEAK_TFLOPS["fp64"],
+                     algorithmic_flops_per_launch=fl / (calls / args.steps))
+        kern.append(k)
+    kern.sort(key=lambda k: -k["ms_per_step"])
+    dom = next(k for k in kern if k["name"] == "se_gemm_xq")
+    out = {
+        "metric": "prediction-SE map pairs/s (exact + local Kriging, every node) at 1024^2",
+        "value": 1.0 / sec, "unit": "SE map pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * sec, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "se_" + wl.name.replace("_R1000", ""), "grid": f"{wl.m}x{wl.m}",
+                   "n_obs": n, "k": wl.k, "covariance": "exponential sigma2=1 range=0.02",
+                   "nugget": wl.tau2},
+        "roofline": {"bound": "mfma", "kernel": dom["name"], "achieved": dom["achieved"],
+                     "peak": dom["peak"], "unit": "TFLOP/s", "frac": dom["frac"],
+                     "traffic": None, "avg_launch_ms": dom["avg_launch_ms"]},
+        "kernels": kern, "finite": finite, "median_se_local_over_exact": ratio,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = se_cpu_baseline(workloads)
+    _emit(out, args)
+
+
+def se_cpu_baseline(workloads):
+    """The oracle's se_exact and se_local on a bounded sample of the 1024^2
+    map: 1100 clustered stations (the oracle's W1 K11 W1^T at 5000 stations
+    alone is hours of host work) and 4096 sampled grid nodes."""
+    from oracle import accuracy as acc
+    from oracle.covariance import Cov as OCov
+    from oracle.pipeline import Grid as OGrid
+    wl = workloads.DM
+    n, nodes = 1100, 8192
+    xy = workloads.locations("clustered", n, seed=1)
+    rows = np.random.default_rng(0).choice(wl.m * wl.m, nodes, replace=False)
+    cov = OCov(wl.nu, wl.sigma2, wl.range)
+    threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    acc.se_exact(cov, OGrid.unit_square(wl.m), xy, wl.tau2, rows)
+    acc.se_local(cov, OGrid.unit_square(wl.m), xy, wl.tau2, wl.k, rows)
+    sec = time.perf_counter() - t0
+    return {"value": nodes / sec / (wl.m * wl.m), "unit": "SE map pairs/s", "cores": int(threads),
+            "kind": "oracle", "sample": f"{nodes} sampled nodes of the 1024^2 grid with {n} "
+                                        "clustered stations (not 5000), scaled to whole maps",
+            "seconds_measured": sec}
+
+
+def _emit(out, args):
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as fh:
+            fh.write(line + "\n")
+
+
 def main():
     args = parse()
     if args.record_counters:
@@ -503,6 +705,10 @@ def main():
         return events_main(args, torch, cesim, workloads)
     if args.workload == "grad512":
         return grad_main(args, torch, cesim, workloads)
+    if args.workload == "accuracy61":
+        return accuracy_main(args, torch, cesim, workloads)
+    if args.workload == "se1024":
+        return se_main(args, torch, cesim, workloads)
     cesim.set_default_timing(True)
     wl = workloads.DM
     wl.m, wl.n, wl.nreal = args.m, args.n, args.nreal

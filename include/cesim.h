@@ -222,8 +222,10 @@ const char* cesim_status_string(cesim_status s);
  * local-Kriging setup, observation Cholesky, synthetic observations and
  * right-hand sides, observation solves, half-precision split of the
  * coefficients, cross-covariance GEMM onto the grid, FP64 prediction from the
- * observed values (MIXED only). */
-#define CESIM_NUM_STAGES 13
+ * observed values (MIXED only); for ce_prediction_se: W1 K11 W1^T, the
+ * covariance rows of a chunk of grid nodes (K12 and (W1 K11)^T), the GEMM of
+ * the solved rows with W1 K11 W1^T, and the per-node reduction. */
+#define CESIM_NUM_STAGES 17
 
 /* Launch-shape parameters (performance only; results do not change):
  *   CESIM_PARAM_GEMM_TILE: workgroup tile of the mixed cross-covariance GEMM,
@@ -267,6 +269,10 @@ const char* cesim_status_string(cesim_status s);
  *     returns INVALID_ARG while joint sampling is on and some box holds
  *     several observations). */
 #define CESIM_PARAM_JOINT_BOXES 8
+/*   CESIM_PARAM_SE_CHUNK_NODES (performance and memory only): grid nodes per
+ *     chunk of ce_prediction_se, >= 0; 0 (default) takes as many as fit in
+ *     16 GiB of work arrays (5 x nodes x stations doubles), at least 64. */
+#define CESIM_PARAM_SE_CHUNK_NODES 9
 cesim_status ce_set_param(cesim_ctx ctx, int param, int value);
 
 /* ---- launch-shape autotuning ----

@@ -334,6 +334,10 @@ cesim_status ce_set_param(cesim_ctx c, int param, int value) {
       if (value != 0 && value != 1) return CESIM_ERR_INVALID_ARG;
       c->joint_boxes = value;
       return CESIM_OK;
+    case CESIM_PARAM_SE_CHUNK_NODES:
+      if (value < 0) return CESIM_ERR_INVALID_ARG;
+      c->se_chunk = value;
+      return CESIM_OK;
     case CESIM_PARAM_GEMM_TILE:
       if (value < 0 || value > 3) return CESIM_ERR_INVALID_ARG;
       c->gemm_tile = value;
@@ -394,7 +398,7 @@ const char* cesim_stage_name(int stage) {
       "setup_torus_base", "setup_fft2_fp64", "setup_eigen_check", "draw_noise_rowfft",
       "draw_colfft_scale_icolfft", "draw_irowfft_crop", "offgrid_local_krige",
       "obs_cholesky", "synth_obs_rhs", "obs_solve", "coef_split_half", "krige_grid_gemm",
-      "krige_predict_fp64"};
+      "krige_predict_fp64", "se_w1k11w1", "se_cov_rows", "se_gemm_xq", "se_reduce"};
   return (stage >= 0 && stage < ST_COUNT) ? names[stage] : "unknown";
 }
 

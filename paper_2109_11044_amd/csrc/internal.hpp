@@ -50,10 +50,15 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Width of the diagonal blocks of the observation factor whose inverses
+// (winv) the blocked substitutions apply.
+constexpr int kSolveBlock = 256;
+
 // Stages timed with HIP events when timing is enabled on a context.
 enum Stage {
   ST_SETUP_BASE = 0, ST_SETUP_FFT, ST_SETUP_EIG, ST_DRAW_PASS1, ST_DRAW_PASS2, ST_DRAW_PASS3,
   ST_LK_SETUP, ST_CHOL, ST_SYNTH_RHS, ST_SOLVE, ST_COEF_SPLIT, ST_KRIGE_GEMM, ST_PREDICT,
+  ST_SE_Q, ST_SE_COV_ROWS, ST_SE_GEMM, ST_SE_REDUCE,
   ST_COUNT
 };
 
@@ -174,6 +179,7 @@ struct cesim_ctx_s {
   cesim::DevBuf obs_order;          // [n] int: observations in Morton order of their grid cell
   // boxes holding several observations (joint sampling, CESIM_PARAM_JOINT_BOXES)
   int joint_boxes = 0;              // switched on by the parameter
+  int se_chunk = 0;                 // grid nodes per standard-error chunk (0: auto)
   int nboxes = 0, max_box = 0;      // boxes of several observations; largest size
   bool box_fac_valid = false;       // box_fac matches the stations and chol_nugget
   cesim::DevBuf box_of;             // [n] int2: {box, row in box} or {-1, 0}
@@ -189,7 +195,7 @@ struct cesim_ctx_s {
   double chol_nugget = -1.0;
   cesim::DevBuf amat;               // n x n: K22 + tau^2 I, then its Cholesky factor
   cesim::DevBuf dinv;               // inverses of the 64 x 64 diagonal blocks
-  cesim::DevBuf winv;               // inverses of the 256 x 256 diagonal blocks (solves)
+  cesim::DevBuf winv;               // inverses of the kSolveBlock-wide diagonal blocks
   cesim::DevBuf wtmp;               // products formed while building winv
   cesim::DevBuf solve_tmp;          // [R][n]: second buffer of the substitutions
   cesim::DevBuf zdev;               // observed values

@@ -20,7 +20,7 @@ namespace cesim {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNB = 64;   // Cholesky block size
-constexpr int kSB = 256;  // substitution block size (4 Cholesky blocks)
+constexpr int kSB = kSolveBlock;  // substitution block size (4 Cholesky blocks)
 
 __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, double tau2,
                              double* __restrict__ A) {

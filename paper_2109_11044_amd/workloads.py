@@ -135,3 +135,51 @@ def event_inputs(table, values_seed=2000):
                         z=iid_values(wl.n, wl.sigma2 + wl.tau2, seed=values_seed + e),
                         nugget=wl.tau2, k=wl.k, nreal=wl.nreal, event_id=e))
     return out
+
+
+# Accuracy study of Section 3.3: [0, 60]^2 domain with a 61 x 61 grid (unit
+# spacing), 35 observations uniform on the domain, sigma^2 = 1, nuggets
+# tau = 0.1, 0.2, 0.3, smoothness nu = 1/2 and 3/2, and ranges at which the
+# correlation falls to 5 % at 20, 45 and 70 units: 18 cases, each over many
+# random configurations, with local-Kriging windows n_p = 1..4.
+STUDY_GRID = (61, 61, 0.0, 0.0, 1.0, 1.0)
+STUDY_NOBS = 35
+STUDY_TAUS = (0.1, 0.2, 0.3)
+STUDY_NUS = (0.5, 1.5)
+STUDY_DISTANCES = (20.0, 45.0, 70.0)
+STUDY_NP = (1, 2, 3, 4)
+
+
+def _root_five_percent_matern32():
+    """t > 0 with (1 + t) exp(-t) = 0.05 (bisection; the left side falls
+    monotonically from 1)."""
+    lo, hi = 1.0, 10.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (1.0 + mid) * np.exp(-mid) > 0.05:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def study_range(nu, distance):
+    """Range theta at which the Matern correlation (argument sqrt(2 nu) d /
+    theta) is 5 % at the given distance: d / ln 20 for nu = 1/2, sqrt(3) d / t
+    with (1 + t) e^{-t} = 0.05 for nu = 3/2."""
+    if nu == 0.5:
+        return distance / np.log(20.0)
+    if nu == 1.5:
+        return np.sqrt(3.0) * distance / _root_five_percent_matern32()
+    raise ValueError("the study uses nu = 1/2 and 3/2")
+
+
+def study_cases():
+    """The 18 cases (nu, distance, theta, tau) in the order nu, distance, tau."""
+    return [dict(nu=nu, distance=d, theta=study_range(nu, d), tau=tau)
+            for nu in STUDY_NUS for d in STUDY_DISTANCES for tau in STUDY_TAUS]
+
+
+def study_locations(config, n=STUDY_NOBS):
+    """Configuration ``config``: n points uniform on [0, 60]^2 (seed 1000 + config)."""
+    return np.random.default_rng(1000 + config).uniform(0.0, 60.0, size=(n, 2))

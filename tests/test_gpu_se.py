@@ -49,18 +49,24 @@ def test_standard_errors_match_oracle(case):
     np.testing.assert_allclose(se_l, ref_l, rtol=0, atol=TOL * s)
 
 
-def test_many_chunks_and_a_ragged_last_chunk():
-    """3000 stations make a chunk of 1 GiB / (5 * 3000 * 8) = 8947 nodes, so a
-    131 x 97 grid (12707 nodes) takes two chunks, the second one ragged;
-    sampled nodes, the chunk boundary among them, against the oracle."""
+@pytest.mark.parametrize("chunk", [0, 1000, 4099])
+def test_chunks_and_a_ragged_last_chunk(chunk):
+    """3000 stations on a 131 x 97 grid (12707 nodes): one chunk by default
+    (16 GiB holds 143165 nodes), 13 chunks of 1000 and 4 of 4099, the last
+    one ragged; sampled nodes, the chunk boundaries among them, against the
+    oracle."""
     n, k, tau2 = 3000, 16, 0.05
     cov = (0.5, 1.0, 0.1)
     xy = workloads.locations("clustered", n, seed=5)
     g = cesim.Grid(131, 97, 0.0, 0.0, 1.0 / 130, 1.0 / 96, 0, 0)
-    se_e, se_l = run(cov, g, xy, k, tau2)
+    with cesim.Context(cesim.make_cov(*cov), g, "fp64") as ctx:
+        ctx.set_param(cesim.PARAM_SE_CHUNK_NODES, chunk)
+        ctx.offgrid(xy, k)
+        se_e, se_l = (t.cpu().numpy().reshape(-1) for t in ctx.prediction_se(tau2))
     oc, og = OCov(*cov), ogrid(g)
     rows = np.random.default_rng(3).choice(g.m1 * g.m2, 200, replace=False)
-    rows = np.unique(np.concatenate([rows, [0, 8946, 8947, g.m1 * g.m2 - 1]]))
+    rows = np.unique(np.concatenate([rows, [0, 999, 1000, 4098, 4099, 12295, 12296,
+                                            g.m1 * g.m2 - 1]]))
     np.testing.assert_allclose(se_e[rows], acc.se_exact(oc, og, xy, tau2, rows), rtol=0, atol=TOL)
     np.testing.assert_allclose(se_l[rows], acc.se_local(oc, og, xy, tau2, k, rows), rtol=0,
                                atol=TOL)
@@ -109,6 +115,9 @@ def test_error_statuses():
         xy2 = xy.copy()
         xy2[1] = xy2[0]
         ctx.offgrid(xy2, 4)
+        with pytest.raises(cesim.CesimError) as e:
+            ctx.set_param(cesim.PARAM_SE_CHUNK_NODES, -1)
+        assert e.value.name == "INVALID_ARG"
         with pytest.raises(cesim.CesimError) as e:
             ctx.prediction_se(0.0)
         assert e.value.name == "NOT_POSITIVE_DEFINITE"

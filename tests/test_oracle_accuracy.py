@@ -76,3 +76,19 @@ def test_table1_fractions_loosely():
         assert means[0] < means[1] < means[2]
         for got, paper in zip(means, row[[2, 4, 6]]):
             assert abs(got - paper) < 0.12, (th, got, paper)
+
+
+def test_study_ranges_give_five_percent_and_table1_thetas():
+    """The study's ranges (Section 3.3): the correlation is 5 % at 20, 45
+    and 70 units for both smoothness values, and for the exponential they
+    round to the ranges printed in Table 1."""
+    from paper_2109_11044_amd import workloads
+    from oracle.covariance import cross_covariance
+    for c in workloads.study_cases():
+        cov = Cov(c["nu"], 1.0, c["theta"])
+        r = cross_covariance(np.array([[0.0, 0.0]]), np.array([[c["distance"], 0.0]]), cov)
+        assert abs(r[0, 0] - 0.05) < 1e-12, c
+    printed = sorted(set(np.loadtxt(GOLDEN)[:, 0]))
+    got = [round(workloads.study_range(0.5, d), 2) for d in workloads.STUDY_DISTANCES]
+    assert got == printed
+    assert len(workloads.study_cases()) == 18
