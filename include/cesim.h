@@ -341,6 +341,33 @@ cesim_status ce_grad_linear(cesim_ctx ctx, const double* z, double nugget, int n
 cesim_status ce_prediction_se(cesim_ctx ctx, double nugget, void* se_exact_dev,
                               void* se_local_dev);
 
+/* ---- nearest-neighbour Kriging ----
+ * The variant of Section 2.2 (variances in Section 3.2): replaces the nobs
+ * observations at obs_xy (host, [nobs][2]) with values z (host) by surrogate
+ * observations at the grid nodes of their k-node neighbourhoods (the
+ * local-Kriging windows of offgrid_nnkrige, k = 4, 16, 36 or 64; overlapping
+ * neighbourhoods merged; sites in ascending node index, x fastest).  For the
+ * nugget tau^2 >= 0 and A = K22 + tau^2 I, each site j gets the value
+ * z_N[j] = K_j2 A^{-1} z and the error variance sigma_N[j]^2 = C(0) -
+ * K_j2 A^{-1} K_2j (clamped at 0).  The sites then become the context's
+ * stations: each one its own window node, synthetic values y(site) +
+ * sqrt(tau^2 + sigma_N^2) xi (xi: the stream-1 normal of the site index), and
+ * the observation system K_NN + tau^2 I + diag(sigma_N^2).  Afterwards
+ * condition(ctx, z_site, tau^2, fields) draws nearest-neighbour conditional
+ * fields and ce_prediction_se(ctx, tau^2, ...) returns the nearest-neighbour
+ * standard error SE_N in both maps; offgrid_nnkrige ends the mode, and
+ * ce_grad_linear rejects it (INVALID_ARG).
+ * Writes the site count to *nsites, the coordinates to site_xy (host,
+ * [capacity][2]) and the values to z_site (host, [capacity]); capacity
+ * >= nobs * k always suffices.  INVALID_ARG for null pointers, a bad k, a
+ * negative or non-finite nugget or value, more sites than capacity or than
+ * 65535; the offgrid_nnkrige statuses for the observations;
+ * NOT_POSITIVE_DEFINITE when A is not.  On an error the context holds the
+ * observations as after offgrid_nnkrige, or none.  Synchronises. */
+cesim_status nn_surrogate(cesim_ctx ctx, int nobs, const double* obs_xy, const double* z,
+                          double nugget, int k, int capacity, double* site_xy, double* z_site,
+                          int* nsites);
+
 /* ---- batches of independent events ----
  * One event is the whole conditional simulation above (Section 2 with the
  * local Kriging of Section 2.1) for its own covariance, grid, stations,

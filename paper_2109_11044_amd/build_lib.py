@@ -11,7 +11,7 @@ OUT = os.path.join(HERE, "libcesim.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["abi.hip", "ce.hip", "lk.hip", "linalg.hip", "krige.hip", "batch.hip", "tune.hip",
-           "grad.hip", "se.hip"]
+           "grad.hip", "se.hip", "nn.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are not generated
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -29,7 +29,7 @@ EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
            "cesim_batch_create", "cesim_batch_run", "cesim_batch_get_info",
            "cesim_batch_destroy", "cesim_run_events", "ce_autotune",
            "cesim_tune_save", "cesim_tune_load", "cesim_tune_entries", "cesim_tune_clear",
-           "ce_grad_linear", "ce_prediction_se"]
+           "ce_grad_linear", "ce_prediction_se", "nn_surrogate"]
 PARAM_GEMM_TILE = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
@@ -140,6 +140,7 @@ def lib():
     L.cesim_tune_clear.restype = None
     L.ce_grad_linear.argtypes = [vp, dp, d, i, u64, i, vp, dp, dp]
     L.ce_prediction_se.argtypes = [vp, d, vp, vp]
+    L.nn_surrogate.argtypes = [vp, i, dp, dp, d, i, i, dp, dp, ctypes.POINTER(ctypes.c_int)]
     for name in EXPORTS:
         if name not in VOID_EXPORTS:
             getattr(L, name).restype = i
@@ -357,6 +358,24 @@ class Context:
                                     _dptr(out), _dptr(dz)), "ce_grad_linear")
         return {"L": float(out[0]), "d_range": float(out[1]), "d_sigma2": float(out[2]),
                 "d_nugget": float(out[3]), "d_z": dz}
+
+    def nn_surrogate(self, obs_xy, z, nugget, k):
+        """Nearest-neighbour Kriging: install the surrogate sites of the
+        observations as the stations; returns (site_xy, z_site) as numpy
+        arrays (sites in ascending node index)."""
+        xy = np.ascontiguousarray(obs_xy, dtype=np.float64).reshape(-1, 2)
+        z = np.ascontiguousarray(z, dtype=np.float64).ravel()
+        if z.size != xy.shape[0]:
+            raise ValueError("z must hold one value per observation")
+        cap = xy.shape[0] * int(k)
+        sxy = np.empty((cap, 2))
+        zs = np.empty(cap)
+        ns = ctypes.c_int(0)
+        self.nobs = 0
+        _check(lib().nn_surrogate(self._h, xy.shape[0], _dptr(xy), _dptr(z), float(nugget), int(k),
+                                  cap, _dptr(sxy), _dptr(zs), ctypes.byref(ns)), "nn_surrogate")
+        self.nobs, self.k = ns.value, 4
+        return sxy[:ns.value].copy(), zs[:ns.value].copy()
 
     def prediction_se(self, nugget):
         """(SE_E, SE_L): exact and local-Kriging prediction standard errors on

@@ -246,7 +246,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
           &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
-          &c->sework};
+          &c->sework, &c->nn_extra, &c->nn_work};
 }
 
 namespace {
@@ -513,6 +513,7 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   CESIM_HIP(hipStreamSynchronize(c->aux));      // buffers below may be reallocated
   c->chol_valid = false;
   c->yhat_valid = false;
+  c->nn_active = false;
   c->nobs = 0;
   c->obs_host.assign(xy, xy + 2 * (size_t)nobs);
   CESIM_TRY(c->obs_xy.reserve(sizeof(double) * 2 * nobs));

@@ -162,6 +162,7 @@ extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugg
   if (!(std::isfinite(nugget) && nugget >= 0.0)) return CESIM_ERR_INVALID_ARG;
   if (c->nobs < 1) return CESIM_ERR_BAD_STATE;
   if (joint_active(c)) return CESIM_ERR_INVALID_ARG;   // the adjoint is of the independent sampling
+  if (c->nn_active) return CESIM_ERR_INVALID_ARG;     // and of local Kriging
   const int n = c->nobs;
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(z[i])) return CESIM_ERR_INVALID_ARG;

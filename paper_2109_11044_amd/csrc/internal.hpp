@@ -180,6 +180,11 @@ struct cesim_ctx_s {
   // boxes holding several observations (joint sampling, CESIM_PARAM_JOINT_BOXES)
   int joint_boxes = 0;              // switched on by the parameter
   int se_chunk = 0;                 // grid nodes per standard-error chunk (0: auto)
+  // nearest-neighbour Kriging: the stations are surrogate grid sites whose
+  // nugget is tau^2 + nn_extra[i] (set by nn_surrogate, cleared by offgrid_nnkrige)
+  bool nn_active = false;
+  cesim::DevBuf nn_extra;
+  cesim::DevBuf nn_work;
   int nboxes = 0, max_box = 0;      // boxes of several observations; largest size
   bool box_fac_valid = false;       // box_fac matches the stations and chol_nugget
   cesim::DevBuf box_of;             // [n] int2: {box, row in box} or {-1, 0}

@@ -22,13 +22,15 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int kNB = 64;   // Cholesky block size
 constexpr int kSB = kSolveBlock;  // substitution block size (4 Cholesky blocks)
 
+// A = K22 + tau^2 I (+ diag(extra) for the surrogate sites of
+// nearest-neighbour Kriging, whose nugget is inflated site by site).
 __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, double tau2,
-                             double* __restrict__ A) {
+                             const double* __restrict__ extra, double* __restrict__ A) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= n) return;
   double v = cov_eval(cov, obs[2 * i] - obs[2 * j], obs[2 * i + 1] - obs[2 * j + 1]);
-  if (i == j) v += tau2;
+  if (i == j) v += extra ? tau2 + extra[i] : tau2;
   A[(size_t)i * n + j] = v;
 }
 
@@ -330,8 +332,9 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool cl
   int* info = c->chol_info.as<int>();
   if (clear_info) CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
   const int tr = c->timer.begin(ST_CHOL, s);
-  k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd, tau2,
-                                                         A);
+  k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(
+      c->obs_xy.as<double>(), n, c->covd, tau2, c->nn_active ? c->nn_extra.as<double>() : nullptr,
+      A);
   CESIM_HIP(hipGetLastError());
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
@@ -573,7 +576,7 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
     CESIM_TRY(c->dinv.reserve(sizeof(double) * (size_t)nblk * kNB * kNB));
     CESIM_HIP(hipMemsetAsync(c->chol_info.p, 0, sizeof(int) * 4, s));
     k_assemble_a<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd,
-                                                           tau2[e], c->amat.as<double>());
+                                                           tau2[e], nullptr, c->amat.as<double>());
     CESIM_HIP(hipGetLastError());
   }
   GroupedSeq seq;

@@ -1,0 +1,94 @@
+"""Pins of nearest-neighbour Kriging in the oracle (oracle/nnkrige.py,
+Sections 2.2 and 3.2): SE_N^2 against the covariance of the composed linear
+map of the whole nearest-neighbour simulation; the surrogate sites against a
+brute-force search; site values and variances in closed form for one
+observation and for noise-free observations on nodes; the simulation's
+Monte Carlo variance; listed nodes against the full grid."""
+import numpy as np
+import pytest
+
+from oracle import nnkrige as nn
+from oracle.covariance import Cov, covariance
+from oracle.pipeline import Grid
+
+
+@pytest.mark.parametrize("cov,k,tau2", [(Cov(0.5, 1.0, 0.35), 4, 0.05),
+                                        (Cov(1.5, 1.0, 0.3, 2.0, 0.3), 16, 0.1),
+                                        (Cov(1.0, 1.2, 0.25), 4, 0.02)])
+def test_se_nn_is_the_variance_of_the_simulation(cov, k, tau2):
+    g = Grid.unit_square(7)
+    xy = np.random.default_rng(2).uniform(0, 1, (4, 2))
+    Me, Mx = nn.linear_map_nn(cov, g, xy, tau2, k)
+    var = np.diag(Me @ Me.T + Mx @ Mx.T)
+    np.testing.assert_allclose(nn.se_nn(cov, g, xy, tau2, k) ** 2, var, atol=1e-12)
+
+
+def test_sites_are_the_merged_nearest_neighbourhoods():
+    """Brute force: for every observation, the 2 n_p nodes nearest along each
+    axis (ties to the lower index, shifted inside the grid); the union."""
+    g = Grid(13, 9, 0.0, 0.0, 0.1, 0.125)
+    xy = np.random.default_rng(4).uniform(0, 1, (6, 2)) * [1.2, 1.0]
+    for k in (4, 16, 36):
+        w = int(round(np.sqrt(k)))
+        want = set()
+        for x, y in xy:
+            ax = sorted(range(g.m1), key=lambda i: (abs(g.x0 + i * g.dx - x), i))[:w]
+            ay = sorted(range(g.m2), key=lambda j: (abs(g.y0 + j * g.dy - y), j))[:w]
+            # a contiguous run of w nodes: the nearest ones are contiguous
+            assert max(ax) - min(ax) == w - 1 and max(ay) - min(ay) == w - 1
+            want |= {j * g.m1 + i for i in ax for j in ay}
+        got = nn.surrogate_sites(xy, g, k)
+        assert list(got) == sorted(want)
+
+
+def test_far_apart_observations_give_n_times_k_sites():
+    g = Grid.unit_square(41)
+    xy = np.array([[0.1, 0.1], [0.9, 0.12], [0.5, 0.5], [0.13, 0.88], [0.86, 0.91]])
+    for k in (4, 16, 36, 64):
+        assert nn.surrogate_sites(xy, g, k).size == 5 * k
+
+
+def test_one_observation_closed_form():
+    g = Grid.unit_square(11)
+    cov, tau2 = Cov(0.5, 1.3, 0.2), 0.07
+    s = np.array([[0.43, 0.58]])
+    out = nn.surrogate(cov, g, s, np.array([0.9]), tau2, 16)
+    c = covariance(out["xy"][:, 0] - s[0, 0], out["xy"][:, 1] - s[0, 1], cov)
+    np.testing.assert_allclose(out["zN"], c * 0.9 / (1.3 + tau2), rtol=1e-14)
+    np.testing.assert_allclose(out["sigmaN2"], 1.3 - c * c / (1.3 + tau2), rtol=1e-14)
+
+
+def test_noise_free_observations_on_nodes():
+    """With tau^2 = 0, a site on an observed node gets the observed value and
+    zero error variance."""
+    g = Grid.unit_square(17)
+    nodes = np.array([[3, 4], [10, 12], [14, 2]])
+    xy = nodes / 16.0
+    z = np.array([0.4, -1.1, 2.0])
+    out = nn.surrogate(Cov(0.5, 1.0, 0.2), g, xy, z, 0.0, 16)
+    at = np.searchsorted(out["idx"], nodes[:, 1] * 17 + nodes[:, 0])
+    np.testing.assert_allclose(out["zN"][at], z, atol=1e-12)
+    np.testing.assert_allclose(out["sigmaN2"][at], 0.0, atol=1e-12)
+
+
+def test_monte_carlo_variance_of_the_simulation():
+    """The nearest-neighbour conditional fields' variance over 4000
+    realizations matches SE_N^2 (chi-square scale 3 sqrt(2/R))."""
+    g = Grid.unit_square(9)
+    cov, tau2 = Cov(0.5, 1.0, 0.3), 0.05
+    xy = np.random.default_rng(6).uniform(0, 1, (5, 2))
+    z = np.random.default_rng(7).normal(size=5)
+    out = nn.conditional_simulation_nn(cov, g, xy, z, tau2, 4, seed=3, nreal=4000)
+    v = out["v"].reshape(4000, -1)
+    se2 = nn.se_nn(cov, g, xy, tau2, 4) ** 2
+    rel = v.var(axis=0) / se2
+    assert np.all(np.abs(rel - 1.0) < 3 * np.sqrt(2.0 / 4000) + 0.02), rel.min()
+
+
+def test_listed_nodes_equal_the_full_grid():
+    g = Grid(10, 7, 0.2, -0.1, 0.11, 0.13)
+    xy = np.random.default_rng(5).uniform(0, 1, (6, 2)) * [0.9, 0.7] + [0.2, -0.1]
+    cov = Cov(1.0, 1.1, 0.3)
+    rows = np.array([69, 0, 33, 34, 5])
+    np.testing.assert_allclose(nn.se_nn(cov, g, xy, 0.05, 16, rows),
+                               nn.se_nn(cov, g, xy, 0.05, 16)[rows], atol=1e-14)
