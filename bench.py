@@ -56,7 +56,8 @@ def parse():
                     help="se1024: grid nodes per chunk (0: the library's choice)")
     ap.add_argument("--configs", type=int, default=100,
                     help="accuracy61: random station configurations per case")
-    ap.add_argument("--workload", choices=["dm", "events64", "grad512", "accuracy61", "se1024"],
+    ap.add_argument("--workload", choices=["dm", "events64", "grad512", "accuracy61", "se1024",
+                                           "nn1024"],
                     default="dm",
                     help="dm: the 1024^2 single-event workload; events64: 64 uneven events "
                          "run as one batch (one graph launch per step)")
@@ -78,7 +79,7 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_units(name, wl, R, t1, t2, bytes_per_real):
+def algorithmic_units(name, wl, R, t1, t2, bytes_per_real, nobs=None):
     """Algorithmic bytes (or flops) of one step for a stage, by its I/O
     contract: pair buffer traffic of the draw passes (sqrt(lambda) reads are
     amortised and not counted), 2 M n R flops for the grid GEMM."""
@@ -94,7 +95,7 @@ def algorithmic_units(name, wl, R, t1, t2, bytes_per_real):
     if name in per_real:
         return per_real[name] * R, "bytes"
     if name == "krige_grid_gemm":
-        return 2.0 * M * wl.n * R, "flops"
+        return 2.0 * M * (nobs or wl.n) * R, "flops"
     return None, None
 
 
@@ -106,6 +107,15 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
     cov = cesim.make_cov(wl.nu, wl.sigma2, wl.range)
     grid = cesim.unit_square_grid(wl.m)
     info = {}
+    nn = args.workload == "nn1024"
+
+    def stations(ctx):
+        """Local Kriging of the stations, or the nearest-neighbour surrogate
+        sites; the values to condition on."""
+        if nn:
+            return ctx.nn_surrogate(xy, z, wl.tau2, wl.k)[1]
+        ctx.offgrid(xy, wl.k)
+        return z
 
     def step():
         ctx = cesim.Context(cov, grid, prec)
@@ -115,12 +125,12 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
             ctx.set_param(cesim.PARAM_DRAW_CHUNK_PAIRS, args.chunk_pairs)
         ctx.set_param(cesim.PARAM_GEMM_SPLIT, 0 if args.split == "fp16" else 1)
         ctx.set_param(cesim.PARAM_JOINT_BOXES, 1 if args.joint else 0)
-        ctx.offgrid(xy, wl.k)
+        zc = stations(ctx)
         for b0 in range(0, R, batch):
             nb = min(batch, R - b0)
             f = fields[b0:b0 + nb]
             ctx.simulate(nb, args.seed, b0, out=f)
-            ctx.condition(z, wl.tau2, f)
+            ctx.condition(zc, wl.tau2, f)
         st = ctx.stage_times(reset=True)
         info.update(ctx.info())
         ctx.close()
@@ -130,7 +140,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
         t0 = time.perf_counter()
         with cesim.Context(cov, grid, prec) as ctx:
             ctx.set_param(cesim.PARAM_GEMM_SPLIT, 0 if args.split == "fp16" else 1)
-            ctx.offgrid(xy, wl.k)
+            stations(ctx)
             ctx.autotune(batch, fields[:batch])
         info["tune_ms"] = 1000.0 * (time.perf_counter() - t0)
     for _ in range(args.warmup):
@@ -159,7 +169,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
     for name, (ms, calls) in stages.items():
         if calls == 0:
             continue
-        units, kind = algorithmic_units(name, wl, R, info["t1"], info["t2"], bpr)
+        units, kind = algorithmic_units(name, wl, R, info["t1"], info["t2"], bpr, info["nobs"])
         k = {"name": name, "ms_per_step": ms / args.steps, "launches_per_step": calls / args.steps,
              "avg_launch_ms": ms / calls}
         if kind == "bytes":
@@ -175,6 +185,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
     kernels.sort(key=lambda k: -k["ms_per_step"])
     return dict(ms_per_step=ms_step, value=R / (ms_step / 1000.0), kernels=kernels,
                 event_ms_per_step=ev0.elapsed_time(ev1) / args.steps, t1=info["t1"],
+                nobs=info["nobs"],
                 finite=finite, gamma_max=info.get("gamma_max"), tune_ms=info.get("tune_ms"))
 
 
@@ -263,10 +274,12 @@ def record_counters(fetch_csv, write_csv, probe_mib, workload):
     print(f"wrote {out}")
 
 
-def cpu_baseline(wl, xy, z, seed):
+def cpu_baseline(wl, xy, z, seed, nn=False):
     """The oracle timed on a bounded sample of the same workload, scaled to
-    one step of R realizations."""
+    one step of R realizations (nn: the nearest-neighbour variant)."""
     from oracle import ce, kriging, localkrige, philox
+    from oracle import nnkrige as onn
+    from oracle.pipeline import Grid as OGrid
     from oracle.covariance import Cov
     try:
         from threadpoolctl import threadpool_info
@@ -281,17 +294,27 @@ def cpu_baseline(wl, xy, z, seed):
     t1, t2, s, _ = ce.ce_setup(cov, dx, dx, wl.m, wl.m)
     t["setup"] = time.perf_counter() - s0
     s0 = time.perf_counter()
-    a, b, W, gamma = localkrige.local_krige(xy, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, wl.k)
+    if nn:
+        sur = onn.surrogate(cov, OGrid.unit_square(wl.m), xy, z, wl.tau2, wl.k)
+        sites, z = sur["xy"], sur["zN"]
+    else:
+        a, b, W, gamma = localkrige.local_krige(xy, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, wl.k)
+        sites = xy
     t["offgrid"] = time.perf_counter() - s0
     s0 = time.perf_counter()
-    fac = kriging.factor(xy, cov, wl.tau2)
+    fac = (onn.surrogate_factor(cov, sites, wl.tau2, sur["sigmaN2"]) if nn
+           else kriging.factor(xy, cov, wl.tau2))
     t["cholesky"] = time.perf_counter() - s0
     nd = 24
     s0 = time.perf_counter()
     eps = philox.torus_noise(seed, t1, t2, range(nd))
     y = ce.ce_draw(s, eps, wl.m, wl.m)
-    xi = philox.offgrid_noise(seed, len(xy), range(nd))
-    zs = localkrige.synthetic_obs(y, a, b, W, gamma, wl.tau2, xi)
+    xi = philox.offgrid_noise(seed, len(sites), range(nd))
+    if nn:
+        zs = (y.reshape(nd, -1)[:, sur["idx"]]
+              + np.sqrt(wl.tau2 + sur["sigmaN2"])[None, :] * xi)
+    else:
+        zs = localkrige.synthetic_obs(y, a, b, W, gamma, wl.tau2, xi)
     t["per_real_draw_synth"] = (time.perf_counter() - s0) / nd
     zsR = np.repeat(zs, R // nd + 1, axis=0)[:R]
     s0 = time.perf_counter()
@@ -299,13 +322,14 @@ def cpu_baseline(wl, xy, z, seed):
     t["solve_R"] = time.perf_counter() - s0
     rows = np.arange(192)
     s0 = time.perf_counter()
-    kriging.krige_to_grid(B, xy, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, rows=rows, chunk_rows=8)
+    kriging.krige_to_grid(B, sites, cov, 0.0, 0.0, dx, dx, wl.m, wl.m, rows=rows, chunk_rows=8)
     t["krige_rows"] = time.perf_counter() - s0
     step = (t["setup"] + t["offgrid"] + t["cholesky"] + R * t["per_real_draw_synth"]
             + t["solve_R"] + t["krige_rows"] * wl.m / rows.size)
     return {"value": R / step, "unit": "conditional realizations/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": (f"full setup, local Kriging and Cholesky; {nd} of {R} CE draws and "
+            "sample": (f"full setup, {'surrogate sites' if nn else 'local Kriging'} and "
+                       f"Cholesky; {nd} of {R} CE draws and "
                        f"synthetic data; solves for all {R}; {rows.size} of {wl.m} grid rows "
                        f"of the K12 product; scaled to one step of {R} realizations"),
             "seconds_measured": sum(t.values()), "host_cpus": len(os.sched_getaffinity(0))}
@@ -508,26 +532,33 @@ def accuracy_main(args, torch, cesim, workloads):
     ks = [(2 * p) ** 2 for p in workloads.STUDY_NP]
     locs = [workloads.study_locations(c) for c in range(C)]
 
+    zero = np.zeros(workloads.STUDY_NOBS)
+
     def study(ncases, nconf):
-        frac = torch.zeros((ncases, len(ks), nconf), dtype=torch.float64, device="cuda")
+        frac = torch.zeros((2, ncases, len(ks), nconf), dtype=torch.float64, device="cuda")
         p95 = torch.zeros_like(frac)
         for ci, case in enumerate(cases[:ncases]):
+            tau2 = case["tau"] ** 2
             with cesim.Context(cesim.make_cov(case["nu"], 1.0, case["theta"]), grid,
                                "fp64") as ctx:
                 for c in range(nconf):
                     for ki, k in enumerate(ks):
                         ctx.offgrid(locs[c], k)
-                        e, l = ctx.prediction_se(case["tau"] ** 2)
-                        frac[ci, ki, c] = (_sig3(l) == _sig3(e)).double().mean()
-                        p95[ci, ki, c] = torch.quantile(100.0 * (l - e) / e, 0.95)
+                        e, l = ctx.prediction_se(tau2)
+                        ctx.nn_surrogate(locs[c], zero, tau2, k)
+                        nn_e, _ = ctx.prediction_se(tau2)
+                        for mi, a in enumerate((l, nn_e)):
+                            frac[mi, ci, ki, c] = (_sig3(a) == _sig3(e)).double().mean()
+                            p95[mi, ci, ki, c] = torch.quantile(100.0 * (a - e) / e, 0.95)
         return frac.cpu().numpy(), p95.cpu().numpy()
 
     study(1, 2)                                        # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    frac, p95 = study(len(cases), C)
+    fr2, p2 = study(len(cases), C)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
+    frac, p95 = fr2[0], p2[0]
     maps = len(cases) * C * len(ks)
     rows = []
     for ci, case in enumerate(cases):
@@ -536,16 +567,22 @@ def accuracy_main(args, torch, cesim, workloads):
                      "frac_sig3_sd": [float(v) for v in frac[ci].std(axis=1, ddof=1)],
                      "p95_EL_pct_median": [float(v) for v in np.median(p95[ci], axis=1)],
                      "p95_EL_pct_max": [float(v) for v in p95[ci].max(axis=1)],
-                     "configs_p95_under_1pct": [float(v) for v in (p95[ci] < 1.0).mean(axis=1)]})
-    paper = {}
-    golden = os.path.join(ROOT, "tests", "golden", "table1_local_kriging_sig3.txt")
-    if os.path.exists(golden):
-        for r in np.loadtxt(golden):
-            paper[f"theta={r[0]:g},tau={r[1]:g}"] = [float(r[2]), float(r[4]), float(r[6])]
+                     "configs_p95_under_1pct": [float(v) for v in (p95[ci] < 1.0).mean(axis=1)],
+                     "nn_frac_sig3_mean": [float(v) for v in fr2[1, ci].mean(axis=1)],
+                     "nn_p95_EN_pct_median": [float(v) for v in np.median(p2[1, ci], axis=1)],
+                     "nn_configs_p95_abs_under_1pct": [float(v) for v in
+                                                       (np.abs(p2[1, ci]) < 1.0).mean(axis=1)]})
+    paper, paper_nn = {}, {}
+    for name, dest in (("table1_local_kriging_sig3.txt", paper), ("table2_nn_kriging_sig3.txt",
+                                                                   paper_nn)):
+        golden = os.path.join(ROOT, "tests", "golden", name)
+        if os.path.exists(golden):
+            for r in np.loadtxt(golden):
+                dest[f"theta={r[0]:g},tau={r[1]:g}"] = [float(r[2]), float(r[4]), float(r[6])]
     out = {
-        "metric": "prediction-SE map pairs/s (exact + local Kriging) over the 18-case accuracy "
-                  "study, 61x61 grid, 35 uniform stations",
-        "value": maps / sec, "unit": "SE map pairs/s", "n_gpus": 1, "steps": 1,
+        "metric": "prediction-SE map triples/s (exact, local and nearest-neighbour Kriging) over "
+                  "the 18-case accuracy study, 61x61 grid, 35 uniform stations",
+        "value": maps / sec, "unit": "SE map triples/s", "n_gpus": 1, "steps": 1,
         "warmup": 1, "ms_per_step": 1000.0 * sec, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"accuracy61_18cases_C{C}_np1-4", "grid": "61x61 on [0,60]^2",
@@ -557,16 +594,18 @@ def accuracy_main(args, torch, cesim, workloads):
                          "--workload se1024",
         "cases": rows,
         "table1_paper_np1-3_means": paper,
+        "table2_paper_np1-3_means": paper_nn,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = accuracy_cpu_baseline(workloads)
     _emit(out, args)
 
 
-def accuracy_cpu_baseline(workloads):
-    """The oracle's se_exact and se_local on a bounded sample of the study:
-    the first case, 120 configurations, n_p = 1..4."""
+def accuracy_cpu_baseline(workloads, nconf=24):
+    """The oracle's se_exact, se_local and se_nn on a bounded sample of the
+    study: the first case, 24 configurations, n_p = 1..4."""
     from oracle import accuracy as acc
+    from oracle import nnkrige as onn
     from oracle.covariance import Cov as OCov
     from oracle.pipeline import Grid as OGrid
     og = OGrid(*workloads.STUDY_GRID)
@@ -575,16 +614,17 @@ def accuracy_cpu_baseline(workloads):
     threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
     t0 = time.perf_counter()
     nmaps = 0
-    for c in range(120):
+    for c in range(nconf):
         xy = workloads.study_locations(c)
         for p in workloads.STUDY_NP:
             acc.se_exact(cov, og, xy, case["tau"] ** 2)
             acc.se_local(cov, og, xy, case["tau"] ** 2, (2 * p) ** 2)
+            onn.se_nn(cov, og, xy, case["tau"] ** 2, (2 * p) ** 2)
             nmaps += 1
     sec = time.perf_counter() - t0
-    return {"value": nmaps / sec, "unit": "SE map pairs/s", "cores": int(threads),
-            "kind": "oracle", "sample": f"{nmaps} map pairs: first case (nu 1/2, theta 6.68, "
-                                        "tau 0.1), 120 configurations, n_p = 1..4",
+    return {"value": nmaps / sec, "unit": "SE map triples/s", "cores": int(threads),
+            "kind": "oracle", "sample": f"{nmaps} map triples: first case (nu 1/2, theta 6.68, "
+                                        f"tau 0.1), {nconf} configurations, n_p = 1..4",
             "seconds_measured": sec}
 
 
@@ -710,8 +750,12 @@ def main():
     if args.workload == "se1024":
         return se_main(args, torch, cesim, workloads)
     cesim.set_default_timing(True)
-    wl = workloads.DM
-    wl.m, wl.n, wl.nreal = args.m, args.n, args.nreal
+    nn = args.workload == "nn1024"
+    if nn:
+        wl = workloads.NN
+    else:
+        wl = workloads.DM
+        wl.m, wl.n, wl.nreal = args.m, args.n, args.nreal
     xy = wl.obs_xy()
     z = workloads.iid_values(wl.n, wl.sigma2 + wl.tau2)
     res = {}
@@ -721,10 +765,11 @@ def main():
     dom = head["kernels"][0]
     gemm = [k for k in head["kernels"] if k.get("bound")]
     dom_k = max(gemm, key=lambda k: k["ms_per_step"]) if gemm else dom
-    wname = wl.name if (args.m, args.n, args.nreal) == (1024, 5000, 1000) else "custom"
+    default_size = nn or (args.m, args.n, args.nreal) == (1024, 5000, 1000)
+    wname = wl.name if default_size else "custom"
     head_prec = "mixed" if "mixed" in res else "fp64"
     for k in head["kernels"]:
-        if head_prec == "mixed" and not args.batch and args.split == "fp16":
+        if head_prec == "mixed" and not args.batch and args.split == "fp16" and not nn:
             k["hbm_traffic_bytes_per_launch"] = recorded_traffic(k["name"], wname)
     roof = {"bound": dom_k.get("bound"), "kernel": dom_k["name"],
             "achieved": dom_k.get("achieved"), "peak": dom_k.get("peak"),
@@ -732,7 +777,8 @@ def main():
             "traffic": dom_k.get("hbm_traffic_bytes_per_launch"),
             "avg_launch_ms": dom_k["avg_launch_ms"]}
     out = {
-        "metric": "conditional realizations/sec at 1024^2 grid (mixed vs FP64 path); HBM GB/s %",
+        "metric": ("nearest-neighbour " if nn else "")
+                  + "conditional realizations/sec at 1024^2 grid (mixed vs FP64 path); HBM GB/s %",
         "value": head["value"],
         "unit": "conditional realizations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -741,10 +787,12 @@ def main():
         "dtype": (f"f32 FFT / {args.split}x3 GEMM (f64 setup, Cholesky, solves)" if "mixed" in res
                   else "f64"),
         "data": "synthetic",
-        "config": {"workload": (wl.name if (args.m, args.n, args.nreal) == (1024, 5000, 1000)
+        "config": {"workload": (wl.name if default_size
                                 else f"exp{args.m}_n{args.n}cl_k36_R{args.nreal}")
                                + ("_joint" if args.joint else ""),
                    "grid": f"{wl.m}x{wl.m}", "torus": head["t1"], "n_obs": wl.n, "k": wl.k,
+                   "method": "nearest-neighbour Kriging" if nn else "local Kriging",
+                   "stations_conditioned_on": head["nobs"],
                    "covariance": "exponential sigma2=1 range=0.02", "nugget": wl.tau2,
                    "realizations_per_step": wl.nreal, "batch": args.batch or wl.nreal,
                    "joint_boxes": bool(args.joint)},
@@ -760,7 +808,7 @@ def main():
     out["autotune"] = {"enabled": bool(args.autotune),
                        "tune_ms": {p: r["tune_ms"] for p, r in res.items()}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, xy, z, args.seed)
+        out["cpu_baseline"] = cpu_baseline(wl, xy, z, args.seed, nn)
     if args.copy_probe_mib:
         nel = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")

@@ -29,7 +29,9 @@ Pins (tests/test_oracle_nnkrige.py): SE_N^2 against the diagonal of the
 covariance of the composed linear map of the whole nearest-neighbour
 simulation; the surrogate sites against a brute-force nearest-node search;
 z_N and sigma_N^2 reduce to the data and tau^2-free zeros for noise-free
-observations on nodes; listed nodes against the full grid.
+observations on nodes; the Monte Carlo variance of the simulation; listed
+nodes against the full grid; mse_nn at least SE_E (optimality of exact
+Kriging).
 """
 
 import numpy as np
@@ -129,3 +131,22 @@ def linear_map_nn(cov: Cov, grid, obs_xy, tau2, k, t1=None, t2=None):
     Me = Bce - P @ J @ Bce
     Mx = -P * np.sqrt(tau2 + s["sigmaN2"])[None, :]
     return Me, Mx
+
+
+def mse_nn(cov: Cov, grid, obs_xy, tau2, k):
+    """Root mean-square error of the nearest-neighbour Kriging predictor
+    K_gN F^{-1} z_N (F = K_NN + tau^2 I + Sigma_N, z_N = K_N2 A^{-1} z) as a
+    predictor of y(g) from the real data: with u_g = K_2N F^{-1} K_Ng,
+        MSE(g) = C(0) - 2 u_g . A^{-1} K_2g + u_g . A^{-1} u_g.
+    Not the variance the simulation realizes (se_nn): an alternative reading
+    of what Table 2 scores, kept for the comparison of readings."""
+    obs_xy = np.asarray(obs_xy, dtype=np.float64).reshape(-1, 2)
+    s = surrogate(cov, grid, obs_xy, np.zeros(len(obs_xy)), tau2, k)
+    fac = surrogate_factor(cov, s["xy"], tau2, s["sigmaN2"])
+    G = grid.points()
+    U = cho_solve(fac, cross_covariance(s["xy"], G, cov)).T @ cross_covariance(s["xy"], obs_xy, cov)
+    A = kriging.obs_matrix(obs_xy, cov, tau2)
+    Kg2 = cross_covariance(G, obs_xy, cov)
+    AiU = np.linalg.solve(A, U.T).T
+    v = cov.sigma2 - 2.0 * np.sum(AiU * Kg2, axis=1) + np.sum(AiU * U, axis=1)
+    return np.sqrt(np.maximum(v, 0.0))

@@ -102,6 +102,12 @@ DM = Workload("exp1024_n5000cl_k36_R1000", m=1024, nu=0.5, sigma2=1.0,
               range=0.02, n=5000, locs="clustered", k=36, tau2=0.02,
               nreal=1000, batch=1000)
 
+# Nearest-neighbour Kriging at the same grid: fine grid, sparse stations
+# (the setting Section 2.2 suits), 2 x 2 neighbourhoods.
+NN = Workload("nn_exp1024_n500cl_k4_R1000", m=1024, nu=0.5, sigma2=1.0,
+              range=0.02, n=500, locs="clustered", k=4, tau2=0.02,
+              nreal=1000, batch=1000)
+
 
 def event_table(nevents=64, seed=SEED_EVENTS):
     """Uneven batched events: grids from {128, 256, 512}^2, Matern

@@ -112,3 +112,46 @@ def test_error_statuses():
         with pytest.raises(cesim.CesimError) as e:
             ctx.grad_linear(zs, 0.1, 2, 1, w)
         assert e.value.name == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-4), ("fp64", 1e-10)])
+def test_nn_workload_1024_sampled(prec, tol):
+    """The nearest-neighbour workload in the benchmark's launch
+    configuration: 1024^2 grid, 2048 torus, 500 clustered stations, 2 x 2
+    neighbourhoods, 1000 realizations in one call; 3 realizations compared
+    with the oracle at 4096 sampled nodes."""
+    import torch
+    from oracle import ce as oce
+    from oracle import kriging, philox
+    from oracle.covariance import cross_covariance
+    from oracle.pipeline import setup
+    wl = workloads.NN
+    xy = wl.obs_xy()
+    z = workloads.iid_values(wl.n, wl.sigma2 + wl.tau2)
+    R = 1000
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    reals = [0, 517, 999]
+    nodes = np.random.default_rng(12).choice(wl.m * wl.m, 4096, replace=False)
+    print(f"nn 1024 workload, {prec}", flush=True)
+    with cesim.Context(cesim.make_cov(wl.nu, wl.sigma2, wl.range),
+                       cesim.unit_square_grid(wl.m), prec) as ctx:
+        sxy, zs = ctx.nn_surrogate(xy, z, wl.tau2, wl.k)
+        f = torch.empty((R, wl.m, wl.m), dtype=dt, device="cuda")
+        ctx.simulate(R, 2, out=f)
+        ctx.condition(zs, wl.tau2, f)
+        t = ctx.info()["t1"]
+        got = f.view(R, -1)[reals][:, torch.as_tensor(nodes, device="cuda")].cpu().numpy()
+        del f
+    oc, og = OCov(wl.nu, wl.sigma2, wl.range), OGrid.unit_square(wl.m)
+    sur = onn.surrogate(oc, og, xy, z, wl.tau2, wl.k)
+    np.testing.assert_array_equal(sxy, sur["xy"])
+    _, _, s, _ = setup(oc, og, t, t)
+    y = oce.ce_draw(s, philox.torus_noise(2, t, t, reals), wl.m, wl.m)
+    xi = philox.offgrid_noise(2, sur["idx"].size, reals)
+    zstar = y.reshape(len(reals), -1)[:, sur["idx"]] + np.sqrt(wl.tau2 + sur["sigmaN2"]) * xi
+    B = kriging.coefficients(onn.surrogate_factor(oc, sur["xy"], wl.tau2, sur["sigmaN2"]),
+                             sur["zN"], zstar)
+    ref = y.reshape(len(reals), -1)[:, nodes] + (cross_covariance(og.points()[nodes], sur["xy"],
+                                                                  oc) @ B).T
+    err = rel_rms(got, ref)
+    assert np.all(err < tol), err
