@@ -335,9 +335,11 @@ cesim_status ce_grad_linear(cesim_ctx ctx, const double* z, double nugget, int n
  * doubles each ([m2][m1], x fastest) into the caller-owned device arrays
  * se_exact_dev and se_local_dev.  FP64 on either precision; refactors the
  * observation covariance when the nugget differs from the last condition().
- * INVALID_ARG for null pointers or a negative or non-finite nugget,
- * BAD_STATE before offgrid_nnkrige, NOT_POSITIVE_DEFINITE when the Cholesky
- * fails.  Synchronises. */
+ * INVALID_ARG for null pointers or a negative or non-finite nugget, and
+ * while joint sampling is on and some box holds several observations (the
+ * closed form is that of the independent sampling); BAD_STATE before
+ * offgrid_nnkrige, NOT_POSITIVE_DEFINITE when the Cholesky fails.
+ * Synchronises. */
 cesim_status ce_prediction_se(cesim_ctx ctx, double nugget, void* se_exact_dev,
                               void* se_local_dev);
 
@@ -355,7 +357,8 @@ cesim_status ce_prediction_se(cesim_ctx ctx, double nugget, void* se_exact_dev,
  * the observation system K_NN + tau^2 I + diag(sigma_N^2).  Afterwards
  * condition(ctx, z_site, tau^2, fields) draws nearest-neighbour conditional
  * fields and ce_prediction_se(ctx, tau^2, ...) returns the nearest-neighbour
- * standard error SE_N in both maps; offgrid_nnkrige ends the mode, and
+ * standard error SE_N in both maps, both with the same tau^2 as here (the
+ * site variances were computed with it); offgrid_nnkrige ends the mode, and
  * ce_grad_linear rejects it (INVALID_ARG).
  * Writes the site count to *nsites, the coordinates to site_xy (host,
  * [capacity][2]) and the values to z_site (host, [capacity]); capacity

@@ -255,7 +255,7 @@ namespace {
 // new contexts (all on the device current when they were created).
 struct AuxKit {
   hipStream_t aux = nullptr;
-  hipEvent_t ev[5] = {};
+  hipEvent_t ev[6] = {};
   int* info_host = nullptr;
   PinnedStage stage;
 };
@@ -306,10 +306,11 @@ void ce_destroy(cesim_ctx c) {
   k.ev[2] = c->factor_ready;
   k.ev[3] = c->z_ready;
   k.ev[4] = c->box_ready;
+  k.ev[5] = c->coef_ready;
   k.info_host = c->chol_info_host;
   k.stage = c->winv_stage;
   k.stage.pending = false;                 // its copy ran on a drained stream
-  if (k.aux && k.ev[0] && k.ev[1] && k.ev[2] && k.ev[3] && k.ev[4] && k.info_host) {
+  if (k.aux && k.ev[0] && k.ev[1] && k.ev[2] && k.ev[3] && k.ev[4] && k.ev[5] && k.info_host) {
     std::lock_guard<std::mutex> g(g_kit_mu);
     g_kits.push_back(k);
   } else {
@@ -430,6 +431,7 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
     c->factor_ready = k.ev[2];
     c->z_ready = k.ev[3];
     c->box_ready = k.ev[4];
+    c->coef_ready = k.ev[5];
     c->chol_info_host = k.info_host;
     c->winv_stage = k.stage;
   }

@@ -153,6 +153,7 @@ struct cesim_ctx_s {
   hipStream_t aux = nullptr;
   hipEvent_t aux_done = nullptr, last_use = nullptr, factor_ready = nullptr, z_ready = nullptr;
   hipEvent_t box_ready = nullptr;   // box factors of the joint sampling are complete
+  hipEvent_t coef_ready = nullptr;  // the stream's solve (with A^{-1} z as its last row) is done
   bool last_use_valid = false, aux_pending = false, z_pending = false;
   cesim_cov cov{};
   cesim_grid grid{};

@@ -205,6 +205,7 @@ extern "C" cesim_status ce_prediction_se(cesim_ctx c, double nugget, void* se_ex
   if (!c || !se_exact || !se_local) return CESIM_ERR_INVALID_ARG;
   if (!(std::isfinite(nugget) && nugget >= 0.0)) return CESIM_ERR_INVALID_ARG;
   if (c->nobs < 1) return CESIM_ERR_BAD_STATE;
+  if (joint_active(c)) return CESIM_ERR_INVALID_ARG;   // the closed form is of independent sampling
   hipStream_t s = c->stream;
   CESIM_HIP(hipStreamSynchronize(c->aux));       // earlier aux work may use the factor
   CESIM_HIP(hipStreamSynchronize(s));

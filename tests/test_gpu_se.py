@@ -123,3 +123,10 @@ def test_error_statuses():
         assert e.value.name == "NOT_POSITIVE_DEFINITE"
         se_e, se_l = ctx.prediction_se(0.1)                  # recovers
         assert bool((se_e >= 0).all()) and bool((se_l >= 0).all())
+        ctx.set_param(cesim.PARAM_JOINT_BOXES, 1)
+        ctx.offgrid(np.array([[0.31, 0.52], [0.315, 0.525], [0.8, 0.1]]), 4)  # two share a box
+        with pytest.raises(cesim.CesimError) as e:
+            ctx.prediction_se(0.1)
+        assert e.value.name == "INVALID_ARG"
+        ctx.set_param(cesim.PARAM_JOINT_BOXES, 0)
+        ctx.prediction_se(0.1)
