@@ -35,9 +35,13 @@
  *     host input arrays (copied before the call returns) and the device
  *     field buffers it passes in.
  *   - Work is enqueued on the HIP stream given to ce_setup (NULL = the
- *     default stream).  ce_setup, ce_get_info and a condition() call that
- *     (re)factorises the observation covariance synchronise that stream;
- *     everything else is asynchronous.
+ *     default stream).  ce_simulate, and condition() when the factor of
+ *     the observation covariance is current, return once their work is
+ *     queued; a condition() call that (re)factorises waits for the
+ *     factorisation (not for the grid product) to return its status.  The
+ *     calls documented below as synchronising (ce_setup, offgrid_nnkrige,
+ *     ce_get_info, ce_grad_linear, ce_prediction_se, nn_surrogate, the
+ *     batch and tuning calls, the stage times) wait for their work.
  *   - Use a context from one host thread at a time.
  *   - Fields are stored [r][j][i]: realization, grid row (y), grid column
  *     (x, fastest).  Grid node (i, j) sits at (x0 + i dx, y0 + j dy).
@@ -156,7 +160,8 @@ cesim_status ce_simulate(cesim_ctx ctx, int nreal, uint64_t seed,
  * [x0, x0 + (m1-1) dx] x [y0, y0 + (m2-1) dy], widened by 1e-12 of the
  * extent for rounding, or not finite),
  * NOT_POSITIVE_DEFINITE (K11), OUT_OF_MEMORY, HIP.  Invalidates the
- * factorisation held for condition(). */
+ * factorisation held for condition() and ends the nearest-neighbour mode
+ * of nn_surrogate.  Synchronises. */
 cesim_status offgrid_nnkrige(cesim_ctx ctx, int nobs, const double* obs_xy_host,
                              int k);
 
