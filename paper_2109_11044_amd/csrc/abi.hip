@@ -241,7 +241,7 @@ const char* cesim_status_string(cesim_status s) {
 
 static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
   return {&c->tt.tw1_64, &c->tt.tw2_64, &c->tt.tw1_32, &c->tt.tw2_32, &c->s64,
-          &c->s32, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
+          &c->s32, &c->slb, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev,

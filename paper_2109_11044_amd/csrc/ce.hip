@@ -244,12 +244,13 @@ k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict
 }
 
 // Pass 2: CP columns per workgroup, loaded straight into registers; forward
-// FFT along y, sqrt(lambda)/N in registers, inverse FFT, rows < rows_out
-// stored.
+// FFT along y, sqrt(lambda)/N in registers (from the copy blocked by 8
+// columns, so that a wave reads 8 rows of 8 columns contiguously), inverse
+// FFT, rows < rows_out stored.
 template <typename real, int T>
 __global__ void __launch_bounds__((P2Cols<real, T>::NTHR))
 k_p2_cols(cpx<real>* __restrict__ buf, int t1, int rows_out, const cpx<real>* __restrict__ tw,
-          const real* __restrict__ sl, int lcp) {
+          const real* __restrict__ slb, int lcp) {
   using C = cpx<real>;
   using G = P2Cols<real, T>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -272,7 +273,7 @@ k_p2_cols(cpx<real>* __restrict__ buf, int t1, int rows_out, const cpx<real>* __
   p2_fft<real, T, false>(x, base, tw, cl);
 #pragma unroll
   for (int h = 0; h < G::E; ++h) {
-    const real m = ok ? sl[(size_t)(base + G::S * h) * t1 + col] : (real)0;
+    const real m = ok ? slb[((size_t)(col >> 3) * T + base + G::S * h) * 8 + (col & 7)] : (real)0;
     x[h] = {x[h].x * m, x[h].y * m};
   }
   p2_fft<real, T, true>(x, base, tw, cl);
@@ -379,6 +380,18 @@ __global__ void k_sqrt_lambda(const double2* lam, size_t N, double inv_n, double
   const double v = sqrt(fmax(lam[q].x, 0.0)) * inv_n;
   s64[q] = v;
   if (s32) s32[q] = (float)v;
+}
+
+// sqrt(lambda) / N of the register draw path, in the path's precision and
+// blocked by 8 columns: element (row r, column q) at ((q / 8) t2 + r) 8 + q % 8
+// (t1 is a multiple of 8 on that path).
+template <typename real>
+__global__ void k_block_lambda(const double* __restrict__ s64, int t1, int t2,
+                               real* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)t1 * t2) return;
+  const int r = (int)(e / t1), q = (int)(e % t1);
+  out[((size_t)(q >> 3) * t2 + r) * 8 + (q & 7)] = (real)s64[e];
 }
 
 // ------------------------------------------------------------------- host
@@ -572,6 +585,17 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
   k_sqrt_lambda<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(buf, N, 1.0 / (double)N,
                                                             c->s64.as<double>(), s32);
   CESIM_HIP(hipGetLastError());
+  if (register_draw_torus(t1, t2)) {       // c->t1, c->t2 are set after acceptance
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    if (c->prec == CESIM_PREC_MIXED) {
+      CESIM_TRY(c->slb.reserve(sizeof(float) * N));
+      k_block_lambda<float><<<nb, 256, 0, s>>>(c->s64.as<double>(), t1, t2, c->slb.as<float>());
+    } else {
+      CESIM_TRY(c->slb.reserve(sizeof(double) * N));
+      k_block_lambda<double><<<nb, 256, 0, s>>>(c->s64.as<double>(), t1, t2, c->slb.as<double>());
+    }
+    CESIM_HIP(hipGetLastError());
+  }
   c->timer.end(tr, s);
   return CESIM_OK;
 }
@@ -599,7 +623,7 @@ DrawShape clamp_shape(DrawShape d) {
 
 template <typename real, int T1, int T2>
 cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np, const cpx<real>* tw1,
-                           const cpx<real>* tw2, const real* sl, const NoiseKey& key, int nreal,
+                           const cpx<real>* tw2, const real* slb, const NoiseKey& key, int nreal,
                            int pair0, const DrawShape& shape, StageTimer& tm, hipStream_t s) {
   using GR = P2Rows<T1>;
   using GC = P2Cols<real, T2>;
@@ -621,7 +645,7 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
   {
     auto k = k_p2_cols<real, T2>;
     allow_lds(k, sizeof(cpx<real>) * GC::CP * GC::LD);
-    k<<<dim3((T1 + cp - 1) / cp, np), cp * GC::S, lc, s>>>(buf, T1, m2, tw2, sl, d.lcp2);
+    k<<<dim3((T1 + cp - 1) / cp, np), cp * GC::S, lc, s>>>(buf, T1, m2, tw2, slb, d.lcp2);
     CESIM_HIP(hipGetLastError());
   }
   tm.end(tr, s);
@@ -641,14 +665,14 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
 // the register path (16 or 24 elements per thread).
 template <typename real>
 bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m2, int np,
-                     const cpx<real>* tw1, const cpx<real>* tw2, const real* sl,
+                     const cpx<real>* tw1, const cpx<real>* tw2, const real* slb,
                      const NoiseKey& key, int nreal, int pair0, const DrawShape& shape,
                      StageTimer& tm, hipStream_t s, cesim_status& st) {
   if (t1 != t2) return false;
   switch (t1) {
 #define CESIM_P2(TT)                                                                        \
   case TT:                                                                                  \
-    st = draw_chunk_p2<real, TT, TT>(buf, fields, m1, m2, np, tw1, tw2, sl, key, nreal, pair0, \
+    st = draw_chunk_p2<real, TT, TT>(buf, fields, m1, m2, np, tw1, tw2, slb, key, nreal, pair0, \
                                      shape, tm, s);                                         \
     return true;
     CESIM_P2(128) CESIM_P2(256) CESIM_P2(512) CESIM_P2(1024) CESIM_P2(2048) CESIM_P2(4096)
@@ -665,7 +689,8 @@ bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m
 
 template <typename real>
 cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, real* fields,
-                        const cpx<real>* tw1, const cpx<real>* tw2, const real* sl) {
+                        const cpx<real>* tw1, const cpx<real>* tw2, const real* sl,
+                        const real* slb) {
   hipStream_t s = c->stream;
   const int t1 = c->t1, t2 = c->t2, m1 = c->grid.m1, m2 = c->grid.m2;
   const size_t pair_bytes = sizeof(cpx<real>) * (size_t)t1 * t2;
@@ -683,10 +708,11 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
   const NoiseKey key{(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), first_real,
                      c->event_id, c->roff};
   const DrawShape shape = draw_shape(c);
+  if (register_draw_torus(t1, t2) && slb == nullptr) return CESIM_ERR_BAD_STATE;
   for (int pair0 = 0; pair0 < npairs; pair0 += chunk) {
     const int np = std::min(chunk, npairs - pair0);
     cesim_status st = CESIM_OK;
-    if (draw_chunk_pow2<real>(t1, t2, buf, fields, m1, m2, np, tw1, tw2, sl, key, nreal, pair0,
+    if (draw_chunk_pow2<real>(t1, t2, buf, fields, m1, m2, np, tw1, tw2, slb, key, nreal, pair0,
                               shape, c->timer, s, st)) {
       CESIM_TRY(st);
       continue;
@@ -707,14 +733,16 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
 
 }  // namespace
 
-bool register_draw_path(cesim_ctx c) {
-  if (c->t1 != c->t2) return false;
-  switch (c->t1) {
+bool register_draw_torus(int t1, int t2) {
+  if (t1 != t2) return false;
+  switch (t1) {
     case 128: case 256: case 512: case 1024: case 2048: case 4096: case 8192: return true;
     case 384: case 768: case 1536: case 3072: case 6144: return true;
     default: return false;
   }
 }
+
+bool register_draw_path(cesim_ctx c) { return register_draw_torus(c->t1, c->t2); }
 
 DrawShape draw_shape_limits(cesim_ctx c) {
   const bool f64 = c->prec == CESIM_PREC_FP64;
@@ -796,10 +824,10 @@ cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_rea
   if (c->prec == CESIM_PREC_FP64)
     return draw_typed<double>(c, nreal, seed, first_real, static_cast<double*>(fields),
                               c->tt.tw1_64.as<double2>(), c->tt.tw2_64.as<double2>(),
-                              c->s64.as<double>());
+                              c->s64.as<double>(), c->slb.as<double>());
   return draw_typed<float>(c, nreal, seed, first_real, static_cast<float*>(fields),
                            c->tt.tw1_32.as<float2>(), c->tt.tw2_32.as<float2>(),
-                           c->s32.as<float>());
+                           c->s32.as<float>(), c->slb.as<float>());
 }
 
 }  // namespace cesim

@@ -168,6 +168,9 @@ struct cesim_ctx_s {
   cesim::TorusTables tt;
   cesim::StageTimer timer;
   cesim::DevBuf s64, s32;           // sqrt(lambda) / (t1 t2), [t2][t1]
+  // the same for the register draw path, in its precision and blocked by 8
+  // columns, [t1 / 8][t2][8], so that the column pass reads it contiguously
+  cesim::DevBuf slb;
   cesim::DevBuf work;               // pair buffers of the draw / setup FFT
   cesim::DevBuf scratch;            // small reductions
 
@@ -273,6 +276,7 @@ size_t draw_pair_bytes(cesim_ctx c);
 DrawShape draw_shape(cesim_ctx c);
 int gemm_tile(cesim_ctx c, int R);
 bool register_draw_path(cesim_ctx c);
+bool register_draw_torus(int t1, int t2);
 DrawShape draw_shape_limits(cesim_ctx c);   // largest shapes of the register path
 bool tune_has_entries(cesim_ctx c, int R);  // table holds this context's shapes
 int draw_chunk_pairs(cesim_ctx c, int nreal);
