@@ -371,9 +371,12 @@ class Context:
         sxy = np.empty((cap, 2))
         zs = np.empty(cap)
         ns = ctypes.c_int(0)
-        self.nobs = 0
-        _check(lib().nn_surrogate(self._h, xy.shape[0], _dptr(xy), _dptr(z), float(nugget), int(k),
-                                  cap, _dptr(sxy), _dptr(zs), ctypes.byref(ns)), "nn_surrogate")
+        st = lib().nn_surrogate(self._h, xy.shape[0], _dptr(xy), _dptr(z), float(nugget), int(k),
+                                cap, _dptr(sxy), _dptr(zs), ctypes.byref(ns))
+        if st != OK:                    # the context holds the observations, or none
+            inf = self.info()
+            self.nobs, self.k = inf["nobs"], inf["k"]
+            _check(st, "nn_surrogate")
         self.nobs, self.k = ns.value, 4
         return sxy[:ns.value].copy(), zs[:ns.value].copy()
 

@@ -155,3 +155,14 @@ def test_nn_workload_1024_sampled(prec, tol):
                                                                   oc) @ B).T
     err = rel_rms(got, ref)
     assert np.all(err < tol), err
+
+
+def test_too_many_sites():
+    """More than 65535 merged sites: INVALID_ARG before any site work, and
+    the context keeps the observations as after offgrid_nnkrige."""
+    xy = workloads.uniform_locations(2000, seed=21)
+    with cesim.Context(cesim.make_cov(0.5, 1.0, 0.02), cesim.unit_square_grid(1024)) as ctx:
+        with pytest.raises(cesim.CesimError) as e:
+            ctx.nn_surrogate(xy, np.zeros(2000), 0.02, 64)
+        assert e.value.name == "INVALID_ARG"
+        assert ctx.info()["nobs"] == 2000 and ctx.info()["k"] == 64

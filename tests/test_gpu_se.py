@@ -130,3 +130,29 @@ def test_error_statuses():
         assert e.value.name == "INVALID_ARG"
         ctx.set_param(cesim.PARAM_JOINT_BOXES, 0)
         ctx.prediction_se(0.1)
+
+
+def test_se_workload_1024_sampled():
+    """The standard-error workload in the benchmark's launch configuration:
+    1024^2 grid, 5000 clustered stations, 6 x 6 windows, nugget 0.02, the
+    default chunks.  SE_E at 256 sampled nodes (and the first and last node)
+    against the oracle; SE_L (whose oracle needs W1 K11 W1^T over 180000
+    window nodes) by properties that hold at any size: finite, inside
+    (0, sigma], and the 95th percentile of |SE_L / SE_E - 1| over the grid
+    below 1 % (the statistic of the claim in Section 3.4; single nodes next
+    to clustered stations, where SE_E is small, differ by several per cent)."""
+    wl = workloads.DM
+    xy = wl.obs_xy()
+    print("se 1024 workload", flush=True)
+    with cesim.Context(cesim.make_cov(wl.nu, wl.sigma2, wl.range), cesim.unit_square_grid(wl.m),
+                       "fp64") as ctx:
+        ctx.offgrid(xy, wl.k)
+        se_e, se_l = (t.cpu().numpy().reshape(-1) for t in ctx.prediction_se(wl.tau2))
+    M = wl.m * wl.m
+    rows = np.unique(np.concatenate([np.random.default_rng(9).choice(M, 256, replace=False),
+                                     [0, M - 1]]))
+    ref = acc.se_exact(OCov(wl.nu, wl.sigma2, wl.range), OGrid.unit_square(wl.m), xy, wl.tau2,
+                       rows)
+    np.testing.assert_allclose(se_e[rows], ref, rtol=0, atol=TOL)
+    assert np.all(np.isfinite(se_l)) and np.all(se_l > 0) and np.all(se_l <= np.sqrt(wl.sigma2))
+    assert np.percentile(np.abs(se_l / se_e - 1.0), 95) < 0.01
