@@ -37,7 +37,7 @@ PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp64": 78.6}   # dense matrix-co
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--m", type=int, default=1024)
@@ -151,8 +151,11 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
+    step_ms = []
     for _ in range(args.steps):
-        st = step()
+        ts = time.perf_counter()
+        st = step()                      # ends with the context's streams drained
+        step_ms.append(1000.0 * (time.perf_counter() - ts))
         for k, (ms, calls) in st.items():
             a = stages.setdefault(k, [0.0, 0])
             a[0] += ms
@@ -184,6 +187,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
         kernels.append(k)
     kernels.sort(key=lambda k: -k["ms_per_step"])
     return dict(ms_per_step=ms_step, value=R / (ms_step / 1000.0), kernels=kernels,
+                step_ms=step_ms, median_ms_per_step=float(np.median(step_ms)),
                 event_ms_per_step=ev0.elapsed_time(ev1) / args.steps, t1=info["t1"],
                 nobs=info["nobs"],
                 finite=finite, gamma_max=info.get("gamma_max"), tune_ms=info.get("tune_ms"))
@@ -798,6 +802,8 @@ def main():
                    "joint_boxes": bool(args.joint)},
         "roofline": roof,
     }
+    out["step_ms"] = {p: r["step_ms"] for p, r in res.items()}
+    out["median_ms_per_step"] = {p: r["median_ms_per_step"] for p, r in res.items()}
     if "fp64" in res and "mixed" in res:
         out["fp64_path"] = {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"]}
         out["mixed_over_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]

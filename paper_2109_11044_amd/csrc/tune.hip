@@ -71,6 +71,9 @@ void reset_timer(StageTimer& t) {
 
 namespace cesim {
 
+// A narrower pass-2 column tile must beat the widest by this factor.
+constexpr double kPass2Margin = 0.85;
+
 DrawShape draw_shape(cesim_ctx c) {
   DrawShape d = c->draw_force;
   std::array<int, 3> v;
@@ -146,11 +149,18 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
       st = timed([&] { return ce_draw_device(c, nt, 0, 0, fields); }, ms, st3);
       if (st != CESIM_OK) break;
       const int v[3] = {d.rows1, d.lcp2, d.rows3};
-      for (int q = 0; q < 3; ++q)
-        if (ms[q] < best[q]) {
+      for (int q = 0; q < 3; ++q) {
+        // Pass 2 with the widest column tile holds one workgroup per CU and
+        // leaves LDS for the diagonal factorization kernel, which
+        // condition() runs beside the draw; narrower tiles fill the LDS with
+        // two workgroups and stall that chain.  Timed alone they can be a
+        // few per cent faster, so they are taken only when clearly so.
+        const double need = (q == 1 && best[q] < 1e300) ? kPass2Margin * best[q] : best[q];
+        if (ms[q] < need) {
           best[q] = ms[q];
           pick[q] = v[q];
         }
+      }
     }
     if (st == CESIM_OK) store(draw_key(c), pick);
   }
