@@ -166,3 +166,27 @@ def test_too_many_sites():
             ctx.nn_surrogate(xy, np.zeros(2000), 0.02, 64)
         assert e.value.name == "INVALID_ARG"
         assert ctx.info()["nobs"] == 2000 and ctx.info()["k"] == 64
+
+
+def test_one_station_on_a_small_grid():
+    """One station, 2 x 2 neighbourhood on an 8 x 8 grid, one realization:
+    four sites, their values, the conditional field and SE_N against the
+    oracle."""
+    xy = np.array([[0.93, 0.05]])                       # next to a corner
+    cov, tau2, m = (0.5, 1.0, 0.3), 0.05, 8
+    oc, og = OCov(*cov), OGrid.unit_square(m)
+    z = np.array([0.7])
+    with cesim.Context(cesim.make_cov(*cov), cesim.unit_square_grid(m), "fp64") as ctx:
+        sxy, zs = ctx.nn_surrogate(xy, z, tau2, 4)
+        f = ctx.simulate(1, 3)
+        ctx.condition(zs, tau2, f)
+        t = ctx.info()["t1"]
+        got = f.cpu().numpy()
+        se_e, _ = ctx.prediction_se(tau2)
+    ref = onn.conditional_simulation_nn(oc, og, xy, z, tau2, 4, 3, 1, 0, t, t)
+    assert sxy.shape == (4, 2)
+    np.testing.assert_array_equal(sxy, ref["xy"])
+    np.testing.assert_allclose(zs, ref["zN"], rtol=0, atol=1e-12)
+    assert np.all(rel_rms(got, ref["v"]) < 1e-10)
+    np.testing.assert_allclose(se_e.cpu().numpy().reshape(-1), onn.se_nn(oc, og, xy, tau2, 4),
+                               rtol=0, atol=1e-10)

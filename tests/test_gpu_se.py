@@ -156,3 +156,14 @@ def test_se_workload_1024_sampled():
     np.testing.assert_allclose(se_e[rows], ref, rtol=0, atol=TOL)
     assert np.all(np.isfinite(se_l)) and np.all(se_l > 0) and np.all(se_l <= np.sqrt(wl.sigma2))
     assert np.percentile(np.abs(se_l / se_e - 1.0), 95) < 0.01
+
+
+@pytest.mark.parametrize("k", [4, 64])
+def test_one_station(k):
+    """A single station (n = 1): both maps against the oracle."""
+    xy = np.array([[0.413, 0.77]])
+    g = cesim.unit_square_grid(20)
+    se_e, se_l = run((1.0, 1.2, 0.3), g, xy, k, 0.05)
+    oc = OCov(1.0, 1.2, 0.3)
+    np.testing.assert_allclose(se_e, acc.se_exact(oc, ogrid(g), xy, 0.05), rtol=0, atol=TOL)
+    np.testing.assert_allclose(se_l, acc.se_local(oc, ogrid(g), xy, 0.05, k), rtol=0, atol=TOL)
