@@ -19,7 +19,8 @@ three significant figures are equal.
 Pins (tests/test_oracle_accuracy.py): SE_E^2 against the diagonal of the
 exact conditional covariance; SE_L^2 against the diagonal of the covariance
 of the whole simulation's linear map (an independent route through steps
-1-5); SE_L = SE_E for observations on grid nodes.
+1-5); SE_L = SE_E for observations on grid nodes; the rounding to three
+significant figures against Python's decimal formatting.
 """
 
 import numpy as np

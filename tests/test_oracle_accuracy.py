@@ -92,3 +92,16 @@ def test_study_ranges_give_five_percent_and_table1_thetas():
     got = [round(workloads.study_range(0.5, d), 2) for d in workloads.STUDY_DISTANCES]
     assert got == printed
     assert len(workloads.study_cases()) == 18
+
+
+def test_three_significant_figures_against_decimal_formatting():
+    """round_sig against Python's correctly rounded decimal formatting
+    (values drawn away from rounding ties), and fraction_sig3 on a hand
+    example."""
+    x = np.random.default_rng(8).uniform(0.05, 3.0, 2000)
+    ref = np.array([float(f"{v:.2e}") for v in x])
+    assert np.allclose(acc.round_sig(x), ref, rtol=1e-14, atol=0)
+    np.testing.assert_array_equal(acc.round_sig(np.array([0.123449, 0.98765, 12.3449, 0.00012351])),
+                                  np.array([0.123, 0.988, 12.3, 0.000124]))
+    assert acc.fraction_sig3(np.array([0.5004, 0.5006, 1.2345]),
+                             np.array([0.5001, 0.5001, 1.2351])) == pytest.approx(1.0 / 3.0)
