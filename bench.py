@@ -17,7 +17,7 @@ synthetic data already resident on the device when the timed region starts
 would).  The headline value is the mixed-precision path; the plain FP64 path
 is measured beside it for the speed ratio.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 import argparse
 import json
@@ -734,7 +734,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
+        print("bench.py: the library runs on one GPU; multi-GPU runs are not supported "
               "(realizations would shard across GPUs with no per-realization exchange).",
               file=sys.stderr)
         sys.exit(2)
