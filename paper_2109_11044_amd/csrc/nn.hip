@@ -83,6 +83,27 @@ __global__ void k_nn_install(const int* __restrict__ node, int ns, int m1,
   W[(size_t)j * 4 + q * 2 + p] = 1.0;
 }
 
+// The ns sites (coordinates sxy on the host; node indices nd, variances s2
+// on the device) become the context's stations.
+cesim_status install_sites(cesim_ctx c, int ns, const double* sxy, const int* nd,
+                           const double* s2) {
+  hipStream_t s = c->stream;
+  CESIM_TRY(offgrid_nnkrige(c, ns, sxy, 4));
+  CESIM_TRY(c->nn_extra.reserve(sizeof(double) * ns));
+  CESIM_HIP(hipMemcpyAsync(c->nn_extra.p, s2, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
+  int* info = c->info_dev.as<int>();
+  CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
+  k_nn_install<<<(ns + 255) / 256, 256, 0, s>>>(nd, ns, c->grid.m1, c->corners.as<int2>(),
+                                                 c->nn_extra.as<double>(), c->weights.as<double>(),
+                                                 c->gamma.as<double>(), info);
+  CESIM_HIP(hipGetLastError());
+  int hinfo[4];
+  CESIM_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipStreamSynchronize(s));
+  if (hinfo[0] & 4) return CESIM_ERR_BAD_STATE;
+  return CESIM_OK;
+}
+
 }  // namespace
 }  // namespace cesim
 
@@ -148,20 +169,13 @@ extern "C" cesim_status nn_surrogate(cesim_ctx c, int nobs, const double* xy, co
   CESIM_HIP(hipStreamSynchronize(s));   // also retires the staging vectors
   if (c->chol_info_host[0] & 2) return CESIM_ERR_NOT_POSITIVE_DEFINITE;
   std::copy(sxy.begin(), sxy.end(), site_xy);
-  // the sites become the stations
-  CESIM_TRY(offgrid_nnkrige(c, ns, sxy.data(), 4));
-  CESIM_TRY(c->nn_extra.reserve(sizeof(double) * ns));
-  CESIM_HIP(hipMemcpyAsync(c->nn_extra.p, s2, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
-  int* info = c->info_dev.as<int>();
-  CESIM_HIP(hipMemsetAsync(info, 0, sizeof(int) * 4, s));
-  k_nn_install<<<(ns + 255) / 256, 256, 0, s>>>(nd, ns, m1, c->corners.as<int2>(),
-                                                 c->nn_extra.as<double>(), c->weights.as<double>(),
-                                                 c->gamma.as<double>(), info);
-  CESIM_HIP(hipGetLastError());
-  int hinfo[4];
-  CESIM_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
-  CESIM_HIP(hipStreamSynchronize(s));
-  if (hinfo[0] & 4) return CESIM_ERR_BAD_STATE;
+  // the sites become the stations; a failure from here on leaves none, so
+  // that condition() cannot run the sites as plain local-Kriging stations
+  const cesim_status ist = install_sites(c, ns, sxy.data(), nd, s2);
+  if (ist != CESIM_OK) {
+    c->nobs = 0;
+    return ist;
+  }
   c->nboxes = 0;                        // every site is its own grid node
   c->max_box = 0;
   c->nn_active = true;
