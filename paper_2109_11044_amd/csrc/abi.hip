@@ -254,8 +254,8 @@ namespace {
 // events and the pinned host words -- kept in a process-wide pool and lent to
 // new contexts (all on the device current when they were created).
 struct AuxKit {
-  hipStream_t aux = nullptr;
-  hipEvent_t ev[6] = {};
+  hipStream_t aux = nullptr, look = nullptr;
+  hipEvent_t ev[8] = {};
   int* info_host = nullptr;
   PinnedStage stage;
 };
@@ -268,6 +268,7 @@ void kit_destroy(AuxKit& k) {
   for (hipEvent_t e : k.ev)
     if (e) (void)hipEventDestroy(e);
   if (k.aux) (void)hipStreamDestroy(k.aux);
+  if (k.look) (void)hipStreamDestroy(k.look);
   k = AuxKit{};
 }
 
@@ -282,6 +283,7 @@ cesim_status kit_take(AuxKit& k) {
     }
   }
   bool ok = hipStreamCreateWithFlags(&k.aux, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&k.look, hipStreamNonBlocking) == hipSuccess;
   for (hipEvent_t& e : k.ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&k.info_host, sizeof(int) * 4, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
@@ -297,20 +299,26 @@ void ce_destroy(cesim_ctx c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   if (c->aux) (void)hipStreamSynchronize(c->aux);
+  if (c->look) (void)hipStreamSynchronize(c->look);
   c->timer.destroy();
-  for (DevBuf* b : all_bufs(c)) b->release_idle();   // both streams drained above
+  for (DevBuf* b : all_bufs(c)) b->release_idle();   // the streams drained above
   AuxKit k;
   k.aux = c->aux;
+  k.look = c->look;
   k.ev[0] = c->aux_done;
   k.ev[1] = c->last_use;
   k.ev[2] = c->factor_ready;
   k.ev[3] = c->z_ready;
   k.ev[4] = c->box_ready;
   k.ev[5] = c->coef_ready;
+  k.ev[6] = c->la_panel;
+  k.ev[7] = c->la_update;
   k.info_host = c->chol_info_host;
   k.stage = c->winv_stage;
   k.stage.pending = false;                 // its copy ran on a drained stream
-  if (k.aux && k.ev[0] && k.ev[1] && k.ev[2] && k.ev[3] && k.ev[4] && k.ev[5] && k.info_host) {
+  bool whole = k.aux && k.look && k.info_host;
+  for (hipEvent_t e : k.ev) whole = whole && e;
+  if (whole) {
     std::lock_guard<std::mutex> g(g_kit_mu);
     g_kits.push_back(k);
   } else {
@@ -432,6 +440,9 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
     c->z_ready = k.ev[3];
     c->box_ready = k.ev[4];
     c->coef_ready = k.ev[5];
+    c->la_panel = k.ev[6];
+    c->la_update = k.ev[7];
+    c->look = k.look;
     c->chol_info_host = k.info_host;
     c->winv_stage = k.stage;
   }

@@ -154,6 +154,12 @@ struct cesim_ctx_s {
   hipEvent_t aux_done = nullptr, last_use = nullptr, factor_ready = nullptr, z_ready = nullptr;
   hipEvent_t box_ready = nullptr;   // box factors of the joint sampling are complete
   hipEvent_t coef_ready = nullptr;  // the stream's solve (with A^{-1} z as its last row) is done
+  // Look-ahead of the factorization: the trailing updates beyond the next
+  // block column run on `look` while the next diagonal block is factored;
+  // la_panel: a panel and its next-column update are done; la_update: the
+  // look stream's trailing update is done.
+  hipStream_t look = nullptr;
+  hipEvent_t la_panel = nullptr, la_update = nullptr;
   bool last_use_valid = false, aux_pending = false, z_pending = false;
   cesim_cov cov{};
   cesim_grid grid{};

@@ -336,6 +336,13 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool cl
       c->obs_xy.as<double>(), n, c->covd, tau2, c->nn_active ? c->nn_extra.as<double>() : nullptr,
       A);
   CESIM_HIP(hipGetLastError());
+  // Right-looking, with look-ahead: after the panel of block kb, s updates
+  // block column kb+1 alone and goes on to factor it, while the look stream
+  // applies the rest of block kb's trailing update (the columns from kb+2
+  // on).  The 64 x 64 tiles and each element's products are those of one
+  // lower-triangular trailing update per block, so the factor is the same.
+  hipStream_t la = c->look;
+  bool la_pending = false;            // la_update marks look work s has not joined
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
     k_potrf_diag<<<1, 64, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
@@ -351,13 +358,42 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool cl
       g.C = A + (size_t)(k0 + nbk) * n + k0; g.sci = n; g.scj = 1;
       CESIM_TRY(gemm_f64(g, false, s));
     }
-    GemmArgs g;
-    g.M = rest; g.N = rest; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
-    g.A = A + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
-    g.B = A + (size_t)(k0 + nbk) * n + k0; g.sbk = 1; g.sbj = n;
-    g.C = A + (size_t)(k0 + nbk) * n + (k0 + nbk); g.sci = n; g.scj = 1;
-    CESIM_TRY(gemm_f64(g, true, s));
+    // trailing update A[i][j] -= sum_t P[i][t] P[j][t] (P: the panel) of
+    // the rows and columns from c0, on the tiles of the lower triangle
+    const int k1 = k0 + nbk;
+    auto update = [&](int c0, int ncols, bool lower, hipStream_t st) {
+      GemmArgs g;
+      g.M = n - c0; g.N = ncols; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = A + (size_t)c0 * n + k0; g.sai = n; g.sak = 1;
+      g.B = A + (size_t)c0 * n + k0; g.sbk = 1; g.sbj = n;
+      g.C = A + (size_t)c0 * n + c0; g.sci = n; g.scj = 1;
+      return gemm_f64(g, lower, st);
+    };
+    const int nb1 = std::min(kNB, rest), rest2 = rest - nb1;
+    if (!la || rest2 <= 0) {
+      if (la_pending) CESIM_HIP(hipStreamWaitEvent(s, c->la_update, 0));
+      la_pending = false;
+      CESIM_TRY(update(k1, rest, true, s));
+      continue;
+    }
+    // block column kb+1 (all its rows): the look stream's update of the
+    // previous step wrote it too
+    if (la_pending) CESIM_HIP(hipStreamWaitEvent(s, c->la_update, 0));
+    {
+      GemmArgs g;
+      g.M = rest; g.N = nb1; g.K = nbk; g.alpha = -1.0; g.beta = 1.0;
+      g.A = A + (size_t)k1 * n + k0; g.sai = n; g.sak = 1;
+      g.B = A + (size_t)k1 * n + k0; g.sbk = 1; g.sbj = n;
+      g.C = A + (size_t)k1 * n + k1; g.sci = n; g.scj = 1;
+      CESIM_TRY(gemm_f64(g, false, s));
+    }
+    CESIM_HIP(hipEventRecord(c->la_panel, s));
+    CESIM_HIP(hipStreamWaitEvent(la, c->la_panel, 0));
+    CESIM_TRY(update(k1 + nb1, rest2, true, la));
+    CESIM_HIP(hipEventRecord(c->la_update, la));
+    la_pending = true;
   }
+  if (la_pending) CESIM_HIP(hipStreamWaitEvent(s, c->la_update, 0));
   CESIM_HIP(hipMemcpyAsync(c->chol_info_host, info, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
   // after a failed pivot the inverses are built from meaningless values;
   // nothing downstream writes the fields then
