@@ -41,7 +41,9 @@
  *     factorisation (not for the grid product) to return its status.  The
  *     calls documented below as synchronising (ce_setup, offgrid_nnkrige,
  *     ce_get_info, ce_grad_linear, ce_prediction_se, nn_surrogate, the
- *     batch and tuning calls, the stage times) wait for their work.
+ *     batch and tuning calls, the stage times) wait for their work.  A
+ *     context also owns two internal streams (default priority), ordered
+ *     with the given stream by events; ce_destroy drains them.
  *   - Use a context from one host thread at a time.
  *   - Fields are stored [r][j][i]: realization, grid row (y), grid column
  *     (x, fastest).  Grid node (i, j) sits at (x0 + i dx, y0 + j dy).
