@@ -229,7 +229,8 @@ const char* cesim_status_string(cesim_status s);
  * local-Kriging setup, observation Cholesky, synthetic observations and
  * right-hand sides, observation solves, half-precision split of the
  * coefficients, cross-covariance GEMM onto the grid, FP64 prediction from the
- * observed values (MIXED only); for ce_prediction_se: W1 K11 W1^T, the
+ * observed values (MIXED only; with its one-vector solve A^{-1} z); for
+ * ce_prediction_se: W1 K11 W1^T, the
  * covariance rows of a chunk of grid nodes (K12 and (W1 K11)^T), the GEMM of
  * the solved rows with W1 K11 W1^T, and the per-node reduction. */
 #define CESIM_NUM_STAGES 17

@@ -255,7 +255,7 @@ namespace {
 // new contexts (all on the device current when they were created).
 struct AuxKit {
   hipStream_t aux = nullptr, look = nullptr;
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[7] = {};
   int* info_host = nullptr;
   PinnedStage stage;
 };
@@ -310,9 +310,8 @@ void ce_destroy(cesim_ctx c) {
   k.ev[2] = c->factor_ready;
   k.ev[3] = c->z_ready;
   k.ev[4] = c->box_ready;
-  k.ev[5] = c->coef_ready;
-  k.ev[6] = c->la_panel;
-  k.ev[7] = c->la_update;
+  k.ev[5] = c->la_panel;
+  k.ev[6] = c->la_update;
   k.info_host = c->chol_info_host;
   k.stage = c->winv_stage;
   k.stage.pending = false;                 // its copy ran on a drained stream
@@ -439,9 +438,8 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
     c->factor_ready = k.ev[2];
     c->z_ready = k.ev[3];
     c->box_ready = k.ev[4];
-    c->coef_ready = k.ev[5];
-    c->la_panel = k.ev[6];
-    c->la_update = k.ev[7];
+    c->la_panel = k.ev[5];
+    c->la_update = k.ev[6];
     c->look = k.look;
     c->chol_info_host = k.info_host;
     c->winv_stage = k.stage;

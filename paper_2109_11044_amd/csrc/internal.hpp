@@ -153,7 +153,6 @@ struct cesim_ctx_s {
   hipStream_t aux = nullptr;
   hipEvent_t aux_done = nullptr, last_use = nullptr, factor_ready = nullptr, z_ready = nullptr;
   hipEvent_t box_ready = nullptr;   // box factors of the joint sampling are complete
-  hipEvent_t coef_ready = nullptr;  // the stream's solve (with A^{-1} z as its last row) is done
   // Look-ahead of the factorization: the trailing updates beyond the next
   // block column run on `look` while the next diagonal block is factored;
   // la_panel: a panel and its next-column update are done; la_update: the
@@ -265,7 +264,8 @@ cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* y
 cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s);
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
                             const double* xib, double* out);
-cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y);
+cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y,
+                               int stage = ST_SOLVE);
 cesim_status aux_wait_last_use(cesim_ctx c);
 cesim_status copy_coefficients_device(cesim_ctx c, double* out);
 cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields);

@@ -582,12 +582,11 @@ cesim_status aux_wait_last_use(cesim_ctx c) {
 // factors on aux, then on the stream the synthetic data, then on aux the
 // factorisation (when the nugget or the stations changed), the solves on the
 // stream after factor_ready, the mixed path's prediction on aux, and the
-// grid GEMM after aux_done.  When the mixed path needs a new prediction,
-// chat = A^{-1} z rides along as row R of the realizations' solve (the same
-// row tiles; one substitution chain instead of two competing ones) and aux
-// takes it from there after coef_ready.  Only then do the factorisations'
-// status come back to the host; after a failed pivot the GEMM has left the
-// fields unchanged.
+// grid GEMM after aux_done.  A new prediction (chat = A^{-1} z by its own
+// one-vector solve, then yhat) follows the factorisation on aux, so that it
+// runs beside the end of the draw and the synthetic data rather than beside
+// the grid GEMM.  Only then do the factorisations' status come back to the
+// host; after a failed pivot the GEMM has left the fields unchanged.
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   hipStream_t s = c->stream;
   const int R = c->nreal;
@@ -609,31 +608,21 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     CESIM_HIP(hipEventRecord(c->box_ready, c->aux));
   }
   CESIM_TRY(lk_phi_device(c, nugget));
-  const int n = c->nobs, Rs = R + (predict ? 1 : 0);
-  CESIM_TRY(krige_reserve(c, Rs));
+  CESIM_TRY(krige_reserve(c, R));
   double* X = c->coef.as<double>();
   // FP64: X = A^{-1} (z - z*_r); mixed: X = -A^{-1} z*_r (yhat carries z)
-  // and, for a new prediction, X[R] = A^{-1} z
-  if ((!mixed || predict) && c->z_pending) CESIM_HIP(hipStreamWaitEvent(s, c->z_ready, 0));
+  if (!mixed && c->z_pending) CESIM_HIP(hipStreamWaitEvent(s, c->z_ready, 0));
   c->z_pending = false;
   if (boxes) CESIM_HIP(hipStreamWaitEvent(s, c->box_ready, 0));
   CESIM_TRY(lk_synth_rhs_device(c, fields, X, !mixed));
-  if (predict)
-    CESIM_HIP(hipMemcpyAsync(X + (size_t)R * n, c->zdev.p, sizeof(double) * n,
-                             hipMemcpyDeviceToDevice, s));
   if (refactor) {
     CESIM_TRY(chol_factor_device(c, nugget, c->aux, false));
     CESIM_HIP(hipEventRecord(c->factor_ready, c->aux));
     CESIM_HIP(hipStreamWaitEvent(s, c->factor_ready, 0));
   }
-  CESIM_TRY(chol_solve_device(c, X, Rs, s, c->solve_tmp.as<double>()));
+  CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
   if (predict) {
-    CESIM_HIP(hipEventRecord(c->coef_ready, s));
-    CESIM_HIP(hipStreamWaitEvent(c->aux, c->coef_ready, 0));
-    CESIM_TRY(c->chat.reserve(sizeof(double) * n));
-    CESIM_HIP(hipMemcpyAsync(c->chat.p, X + (size_t)R * n, sizeof(double) * n,
-                             hipMemcpyDeviceToDevice, c->aux));
-    CESIM_TRY(predict_from_chat(c, c->aux));
+    CESIM_TRY(predict_device(c, c->aux));
     c->aux_pending = true;
   }
   if (c->aux_pending) {
@@ -799,7 +788,7 @@ cesim_status predict_device(cesim_ctx c, hipStream_t s) {
   CESIM_TRY(c->chat.reserve(sizeof(double) * n));
   CESIM_TRY(c->chat_tmp.reserve(sizeof(double) * n));
   CESIM_HIP(hipMemcpyAsync(c->chat.p, c->zdev.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  CESIM_TRY(chol_solve_device(c, c->chat.as<double>(), 1, s, c->chat_tmp.as<double>()));
+  CESIM_TRY(chol_solve_device(c, c->chat.as<double>(), 1, s, c->chat_tmp.as<double>(), ST_PREDICT));
   return predict_from_chat(c, s);
 }
 

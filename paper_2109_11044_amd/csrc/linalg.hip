@@ -467,9 +467,10 @@ static void solve_steps(cesim_ctx c, double* X, double* Y, int R, std::vector<Ge
 // Every step is a GEMM with the realizations as its rows, so that each lane
 // of a tile writes consecutive observations of one realization (X is
 // [R][n], observation index fastest).
-// Y: second buffer of at least R n doubles.
-cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y) {
-  const int tr = c->timer.begin(ST_SOLVE, s);
+// Y: second buffer of at least R n doubles; stage: the timer stage it counts in.
+cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y,
+                               int stage) {
+  const int tr = c->timer.begin(stage, s);
   std::vector<GemmArgs> steps;
   solve_steps(c, X, Y, R, steps);
   for (const GemmArgs& g : steps) CESIM_TRY(gemm_f64(g, false, s));
