@@ -478,6 +478,85 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, dou
   return CESIM_OK;
 }
 
+// ------------------------------------------- one right-hand side (GEMV form)
+// The same blocked substitutions for a single vector, with dot products in
+// place of GEMM tiles (a 64 x 64 tile would carry one useful row): the
+// forward steps take one wave per output row (the row's entries are
+// contiguous), the backward steps one lane per output column and four
+// waves splitting the block's rows, reduced through LDS.
+
+__device__ __forceinline__ double wave_sum(double a) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  return a;
+}
+
+// y[i] = sum_t M[i][t] v[t] (t < nt; M rows ld apart), rows i < rows; with
+// sub, y[i] -= that sum instead.
+__global__ void __launch_bounds__(256)
+k_gemv_rows(const double* __restrict__ M, size_t ld, const double* __restrict__ v, int nt,
+            double* __restrict__ y, int rows, bool sub) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (i >= rows) return;                  // whole waves
+  const double* row = M + (size_t)i * ld;
+  double a = 0.0;
+  for (int t = l; t < nt; t += 64) a = fma(row[t], v[t], a);
+  a = wave_sum(a);
+  if (l == 0) y[i] = sub ? y[i] - a : a;
+}
+
+// y[i] = sum_t M[t][i] v[t] (t < nt; M rows ld apart), columns i < cols;
+// with sub, y[i] -= that sum instead.  64 columns per workgroup.
+__global__ void __launch_bounds__(256)
+k_gemv_cols(const double* __restrict__ M, size_t ld, const double* __restrict__ v, int nt,
+            double* __restrict__ y, int cols, bool sub) {
+  __shared__ double part[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int i = blockIdx.x * 64 + l;
+  double a = 0.0;
+  if (i < cols)
+    for (int t = w; t < nt; t += 4) a = fma(M[(size_t)t * ld + i], v[t], a);
+  part[w][l] = a;
+  __syncthreads();
+  if (w == 0 && i < cols) {
+    const double r = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+    y[i] = sub ? y[i] - r : r;
+  }
+}
+
+// x <- A^{-1} x for one vector with the factor in c->amat and the 256-block
+// inverses in c->winv; y: n doubles of scratch.  Same steps as
+// chol_solve_device with R = 1.
+cesim_status chol_solve_vec_device(cesim_ctx c, double* x, hipStream_t s, double* y, int stage) {
+  const int n = c->nobs, nbig = (n + kSB - 1) / kSB;
+  const double* L = c->amat.as<double>();
+  const double* W = c->winv.as<double>();
+  const int tr = c->timer.begin(stage, s);
+  for (int kb = 0; kb < nbig; ++kb) {             // L y = x
+    const int K0 = kb * kSB, nb = std::min(kSB, n - K0), rest = n - K0 - nb;
+    k_gemv_rows<<<(nb + 3) / 4, 256, 0, s>>>(W + (size_t)kb * kSB * kSB, kSB, x + K0, nb, y + K0,
+                                             nb, false);
+    CESIM_HIP(hipGetLastError());
+    if (rest > 0) {
+      k_gemv_rows<<<(rest + 3) / 4, 256, 0, s>>>(L + (size_t)(K0 + nb) * n + K0, n, y + K0, nb,
+                                                 x + K0 + nb, rest, true);
+      CESIM_HIP(hipGetLastError());
+    }
+  }
+  for (int kb = nbig - 1; kb >= 0; --kb) {        // L^T x = y
+    const int K0 = kb * kSB, nb = std::min(kSB, n - K0);
+    k_gemv_cols<<<(nb + 63) / 64, 256, 0, s>>>(W + (size_t)kb * kSB * kSB, kSB, y + K0, nb, x + K0,
+                                               nb, false);
+    CESIM_HIP(hipGetLastError());
+    if (K0 > 0) {
+      k_gemv_cols<<<(K0 + 63) / 64, 256, 0, s>>>(L + (size_t)K0 * n, n, x + K0, nb, y, K0, true);
+      CESIM_HIP(hipGetLastError());
+    }
+  }
+  c->timer.end(tr, s);
+  return CESIM_OK;
+}
+
 // ------------------------------------------------ grouped systems (batches)
 
 void GroupedSeq::add_diag(const std::vector<DiagDesc>& v) {
