@@ -266,7 +266,8 @@ cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const do
                             const double* xib, double* out);
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y,
                                int stage = ST_SOLVE);
-cesim_status chol_solve_vec_device(cesim_ctx c, double* x, hipStream_t s, double* y, int stage);
+cesim_status chol_solve_vec_device(cesim_ctx c, const double* b, double* x, hipStream_t s,
+                                   double* y, int stage);
 cesim_status aux_wait_last_use(cesim_ctx c);
 cesim_status copy_coefficients_device(cesim_ctx c, double* out);
 cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields);

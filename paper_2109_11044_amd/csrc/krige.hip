@@ -787,8 +787,8 @@ cesim_status predict_device(cesim_ctx c, hipStream_t s) {
   const int n = c->nobs;
   CESIM_TRY(c->chat.reserve(sizeof(double) * n));
   CESIM_TRY(c->chat_tmp.reserve(sizeof(double) * n));
-  CESIM_HIP(hipMemcpyAsync(c->chat.p, c->zdev.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  CESIM_TRY(chol_solve_vec_device(c, c->chat.as<double>(), s, c->chat_tmp.as<double>(), ST_PREDICT));
+  CESIM_TRY(chol_solve_vec_device(c, c->zdev.as<double>(), c->chat.as<double>(), s,
+                                  c->chat_tmp.as<double>(), ST_PREDICT));
   return predict_from_chat(c, s);
 }
 

@@ -492,17 +492,17 @@ __device__ __forceinline__ double wave_sum(double a) {
 }
 
 // y[i] = sum_t M[i][t] v[t] (t < nt; M rows ld apart), rows i < rows; with
-// sub, y[i] -= that sum instead.
+// sub, y[i] = u[i] - that sum instead (u may be y).
 __global__ void __launch_bounds__(256)
 k_gemv_rows(const double* __restrict__ M, size_t ld, const double* __restrict__ v, int nt,
-            double* __restrict__ y, int rows, bool sub) {
+            double* y, int rows, bool sub, const double* u) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (i >= rows) return;                  // whole waves
   const double* row = M + (size_t)i * ld;
   double a = 0.0;
   for (int t = l; t < nt; t += 64) a = fma(row[t], v[t], a);
   a = wave_sum(a);
-  if (l == 0) y[i] = sub ? y[i] - a : a;
+  if (l == 0) y[i] = sub ? u[i] - a : a;
 }
 
 // y[i] = sum_t M[t][i] v[t] (t < nt; M rows ld apart), columns i < cols;
@@ -524,22 +524,25 @@ k_gemv_cols(const double* __restrict__ M, size_t ld, const double* __restrict__ 
   }
 }
 
-// x <- A^{-1} x for one vector with the factor in c->amat and the 256-block
-// inverses in c->winv; y: n doubles of scratch.  Same steps as
-// chol_solve_device with R = 1.
-cesim_status chol_solve_vec_device(cesim_ctx c, double* x, hipStream_t s, double* y, int stage) {
+// x = A^{-1} b for one vector (b is not written) with the factor in
+// c->amat and the 256-block inverses in c->winv; y: n doubles of scratch.
+// Same steps as chol_solve_device with R = 1; the first forward step reads
+// b, so that no copy of b precedes the chain.
+cesim_status chol_solve_vec_device(cesim_ctx c, const double* b, double* x, hipStream_t s,
+                                   double* y, int stage) {
   const int n = c->nobs, nbig = (n + kSB - 1) / kSB;
   const double* L = c->amat.as<double>();
   const double* W = c->winv.as<double>();
   const int tr = c->timer.begin(stage, s);
-  for (int kb = 0; kb < nbig; ++kb) {             // L y = x
+  for (int kb = 0; kb < nbig; ++kb) {             // L y = b, x holding b's updated tail
     const int K0 = kb * kSB, nb = std::min(kSB, n - K0), rest = n - K0 - nb;
-    k_gemv_rows<<<(nb + 3) / 4, 256, 0, s>>>(W + (size_t)kb * kSB * kSB, kSB, x + K0, nb, y + K0,
-                                             nb, false);
+    const double* src = kb == 0 ? b : x;
+    k_gemv_rows<<<(nb + 3) / 4, 256, 0, s>>>(W + (size_t)kb * kSB * kSB, kSB, src + K0, nb,
+                                             y + K0, nb, false, nullptr);
     CESIM_HIP(hipGetLastError());
     if (rest > 0) {
       k_gemv_rows<<<(rest + 3) / 4, 256, 0, s>>>(L + (size_t)(K0 + nb) * n + K0, n, y + K0, nb,
-                                                 x + K0 + nb, rest, true);
+                                                 x + K0 + nb, rest, true, src + K0 + nb);
       CESIM_HIP(hipGetLastError());
     }
   }
