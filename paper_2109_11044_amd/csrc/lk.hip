@@ -242,13 +242,14 @@ struct JointBoxes {
 
 // rhs[r][i] = z_i - (w_i . y_r[window_i] + e_{r,i})   (z_i = 0 when z is null)
 // e_{r,i} = phi_i xi_{r,i}, or with JOINT for a member of a box of several
-// observations, row p of L_G xi_{r,G}.
+// observations, row p of L_G xi_{r,G}.  W2: the window width 2 n_p, fixed
+// at compile time so that all W2^2 gathers of a thread are in flight at once.
 constexpr int kMaxBox = kMaxJointBox;
-template <typename F, bool JOINT>
+template <typename F, bool JOINT, int W2>
 __global__ void __launch_bounds__(256)
 k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict__ corners,
             const double* __restrict__ W, const double* __restrict__ phi,
-            const double* __restrict__ z, int n, int K, int w2, NoiseKey key,
+            const double* __restrict__ z, int n, NoiseKey key,
             const int* __restrict__ order, double* __restrict__ rhs, JointBoxes jb) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
@@ -258,10 +259,15 @@ k_synth_rhs(const F* __restrict__ fields, int m1, int m2, const int2* __restrict
   const int i = order[t];
   const int2 ab = corners[i];
   const F* y = fields + (size_t)r * m1 * m2 + (size_t)ab.y * m1 + ab.x;
-  const double* w = W + (size_t)i * K;
+  const double* w = W + (size_t)i * (W2 * W2);
+  F v[W2 * W2];
+#pragma unroll
+  for (int q = 0; q < W2; ++q)
+#pragma unroll
+    for (int p = 0; p < W2; ++p) v[q * W2 + p] = y[(size_t)q * m1 + p];
   double acc = 0.0;
-  for (int q = 0; q < w2; ++q)
-    for (int p = 0; p < w2; ++p) acc += w[q * w2 + p] * (double)y[(size_t)q * m1 + p];
+#pragma unroll
+  for (int a = 0; a < W2 * W2; ++a) acc += w[a] * (double)v[a];
   double e;
   const int2 bx = JOINT ? jb.box[i] : make_int2(-1, 0);
   if (bx.x < 0) {
@@ -379,22 +385,28 @@ cesim_status lk_synth_rhs_device(cesim_ctx c, const void* fields, double* rhs, b
   dim3 grid((n + 255) / 256, c->nreal);
   const NoiseKey key{(uint32_t)(c->seed & 0xffffffffu), (uint32_t)(c->seed >> 32), c->first_real,
                      c->event_id, c->roff};
-  const int w2 = 2 * c->npp;
   const JointBoxes jb = joint_boxes(c);
   const int tr = c->timer.begin(ST_SYNTH_RHS, c->stream);
-#define CESIM_SYNTH(F, J)                                                                          \
-  k_synth_rhs<F, J><<<grid, 256, 0, c->stream>>>(                                                  \
-      static_cast<const F*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),               \
-      c->weights.as<double>(), c->phi.as<double>(), z, n, c->k, w2, key, c->obs_order.as<int>(), \
-      rhs, jb)
+#define CESIM_SYNTH_W(F, J, W2)                                                                     \
+  k_synth_rhs<F, J, W2><<<grid, 256, 0, c->stream>>>(                                               \
+      static_cast<const F*>(fields), c->grid.m1, c->grid.m2, c->corners.as<int2>(),                \
+      c->weights.as<double>(), c->phi.as<double>(), z, n, key, c->obs_order.as<int>(), rhs, jb)
+#define CESIM_SYNTH(F, J)                                 \
+  switch (c->npp) {                                       \
+    case 1: CESIM_SYNTH_W(F, J, 2); break;                \
+    case 2: CESIM_SYNTH_W(F, J, 4); break;                \
+    case 3: CESIM_SYNTH_W(F, J, 6); break;                \
+    default: CESIM_SYNTH_W(F, J, 8); break;               \
+  }
   if (c->prec == CESIM_PREC_FP64) {
-    if (joint_active(c)) CESIM_SYNTH(double, true);
-    else CESIM_SYNTH(double, false);
+    if (joint_active(c)) { CESIM_SYNTH(double, true) }
+    else { CESIM_SYNTH(double, false) }
   } else {
-    if (joint_active(c)) CESIM_SYNTH(float, true);
-    else CESIM_SYNTH(float, false);
+    if (joint_active(c)) { CESIM_SYNTH(float, true) }
+    else { CESIM_SYNTH(float, false) }
   }
 #undef CESIM_SYNTH
+#undef CESIM_SYNTH_W
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, c->stream);
   return CESIM_OK;
