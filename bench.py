@@ -201,7 +201,7 @@ COUNTED_STAGES = {
     "draw_irowfft_crop": ("k_p2_rows_inv_crop<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
     "krige_grid_gemm": ("k_krige_split3", ["krige.hip", "devmath.hpp"]),
     "krige_predict_fp64": ("k_predict_f64", ["krige.hip", "devmath.hpp"]),
-    "synth_obs_rhs": ("k_synth_rhs<float, false>", ["lk.hip", "devmath.hpp"]),
+    "synth_obs_rhs": ("k_synth_rhs<float, false,", ["lk.hip", "devmath.hpp"]),
 }
 
 
