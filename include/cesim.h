@@ -181,8 +181,12 @@ cesim_status offgrid_nnkrige(cesim_ctx ctx, int nobs, const double* obs_xy_host,
  * product in the half-precision split GEMM.
  * z_host: nobs observed values, host memory, copied.  nugget >= 0.  The
  * Cholesky factor of K22 + nugget I is kept and reused while the nugget and
- * the observation set are unchanged.  Errors: BAD_STATE (no offgrid_nnkrige
- * or no ce_simulate before), INVALID_ARG, NOT_POSITIVE_DEFINITE,
+ * the observation set are unchanged.  A batch is conditioned once: after a
+ * successful call the next condition() needs a new ce_simulate (the fields
+ * are conditional now).  After NOT_POSITIVE_DEFINITE the fields are
+ * unchanged and the batch may be conditioned again (e.g. with another
+ * nugget).  Errors: BAD_STATE (no offgrid_nnkrige, or no ce_simulate since
+ * the last successful condition), INVALID_ARG, NOT_POSITIVE_DEFINITE,
  * OUT_OF_MEMORY, HIP. */
 cesim_status condition(cesim_ctx ctx, const double* z_host, double nugget,
                        void* fields_dev);
@@ -327,8 +331,12 @@ void cesim_tune_clear(void);
  * so its ensemble differs from the FP64 one at the 1e-7 level).  Needs
  * offgrid_nnkrige (else BAD_STATE); refactors A when the nugget differs from
  * the last condition().  INVALID_ARG for null pointers, nreal < 1,
- * first_real < 0, a negative or non-finite nugget or a non-finite z;
- * NOT_POSITIVE_DEFINITE when A's Cholesky fails.  Synchronises. */
+ * first_real < 0, a negative or non-finite nugget or a non-finite z, and
+ * for nugget = 0 when some observation has gamma_i = 0 (on a grid node;
+ * taken as gamma_i <= 1e-12 sigma2, the round-off level of that zero):
+ * phi_i = sqrt(nugget + gamma_i) then has an unbounded nugget derivative,
+ * so dL/dnugget does not exist; NOT_POSITIVE_DEFINITE when A's Cholesky
+ * fails.  Synchronises. */
 cesim_status ce_grad_linear(cesim_ctx ctx, const double* z, double nugget, int nreal,
                             uint64_t seed, int first_real, const void* wgt_dev, double* out,
                             double* dz);

@@ -17,8 +17,9 @@ the textbook construction it cites (Wood and Chan; Chan and Wood):
   used inside the m x m crop never reach T/2, so the crop covariance is
   unaffected.
 * Eigenvalues: lambda = Re FFT2(c) (unnormalised).  The embedding is accepted
-  when min(lambda) >= -1e-12 max(lambda); remaining tiny negatives are
-  clamped to 0.  Otherwise the next torus size on the ladder is tried:
+  when min(lambda) >= -1e-12 max(lambda), the imaginary parts are round-off
+  (at most 1e-12 max(lambda)) and sum(lambda) = N C(0) to 1e-9 relative;
+  remaining tiny negatives are clamped to 0.  Otherwise the next torus size on the ladder is tried:
   T = S(f m) for f in (2, 3, 4, 6, 8), where S(n) is the smallest integer
   >= n whose only prime factors are 2, 3 and 5 (the sizes the FFT handles).
 * Draw: y = Re(IFFT2(sqrt(lambda) * FFT2(eps)))[0:m2, 0:m1] with eps a
@@ -100,12 +101,22 @@ def eigenvalues(c):
     lam = f.real.copy()
     info = dict(lam_min=float(lam.min()), lam_max=float(lam.max()),
                 lam_sum=float(lam.sum()),
-                max_imag=float(np.abs(f.imag).max()))
+                max_imag=float(np.abs(f.imag).max()),
+                trace=float(c.size * c[0, 0]))
     return lam, info
 
 
+TRACE_TOL = 1e-9
+
+
 def accept(info):
-    return info["lam_min"] >= -NEG_TOL * info["lam_max"]
+    """The spectrum of a valid embedding: lambda_min >= -1e-12 lambda_max;
+    real up to round-off (max |Im| <= 1e-12 lambda_max, the base being
+    even); and the trace identity sum(lambda) = N c[0, 0] = N C(0) to 1e-9
+    relative."""
+    return (info["lam_min"] >= -NEG_TOL * info["lam_max"]
+            and info["max_imag"] <= NEG_TOL * info["lam_max"]
+            and abs(info["lam_sum"] - info["trace"]) <= TRACE_TOL * abs(info["trace"]))
 
 
 class NegativeEigenvalue(ValueError):

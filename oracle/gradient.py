@@ -163,6 +163,10 @@ def linear_stat_gradient(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, weight
     # local Kriging and the mean synthetic data
     a, b, W, gamma, dW, dgamma = local_krige_dtheta(obs_xy, cov, grid, k)
     phi = np.sqrt(tau2 + gamma)
+    if tau2 == 0.0 and np.any(gamma <= 1e-12 * cov.sigma2):
+        # tau^2 = 0 and gamma_i = 0 (a station on a grid node, where gamma_i
+        # is 0 up to round-off): dphi_i/dtau^2 = 1 / (2 phi_i) is unbounded
+        raise ValueError("dL/dtau^2 does not exist: zero nugget and a station with gamma_i = 0")
     wy = np.einsum("nk,nk->n", localkrige.gather_windows(ybar, a, b, npp), W)
     dwy = np.einsum("nk,nk->n", localkrige.gather_windows(ybar, a, b, npp), dW)
     wdy = np.einsum("nk,nk->n", localkrige.gather_windows(dybar, a, b, npp), W)

@@ -647,7 +647,11 @@ cesim_status condition(cesim_ctx c, const double* z, double nugget, void* fields
     c->z_pending = true;
     c->aux_pending = true;
   }
-  return condition_device(c, nugget, fields);
+  const cesim_status st = condition_device(c, nugget, fields);
+  // the batch is conditional now: conditioning it again would add the
+  // Kriging correction twice, so a further condition() needs a new draw
+  if (st == CESIM_OK) c->have_fields = false;
+  return st;
 }
 
 cesim_status ce_get_info(cesim_ctx c, cesim_info* info) {

@@ -573,7 +573,14 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
   c->lam_max = st[1];
   c->lam_sum = st[2];
   c->max_imag = st[3];
-  accepted = std::isfinite(st[0]) && std::isfinite(st[1]) && st[0] >= -1e-12 * st[1];
+  // The spectrum of a valid embedding: non-negative up to round-off
+  // (lambda_min >= -1e-12 lambda_max), real (the base is even, so any
+  // imaginary part is round-off: max |Im| <= 1e-12 lambda_max), and with the
+  // trace identity sum(lambda) = N c[0][0] = N C(0) to 1e-9 relative.
+  const double trace = (double)N * c->covd.sigma2;
+  accepted = std::isfinite(st[0]) && std::isfinite(st[1]) && std::isfinite(st[2]) &&
+             std::isfinite(st[3]) && st[0] >= -1e-12 * st[1] && st[3] <= 1e-12 * st[1] &&
+             std::fabs(st[2] - trace) <= 1e-9 * trace;
   if (!accepted) return CESIM_OK;
   CESIM_TRY(c->s64.reserve(sizeof(double) * N));
   float* s32 = nullptr;

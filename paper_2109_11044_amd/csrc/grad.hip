@@ -171,6 +171,16 @@ extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugg
   // work is ordered before it), and the solves below use the stream
   CESIM_HIP(hipStreamSynchronize(c->aux));
   CESIM_HIP(hipStreamSynchronize(s));
+  if (nugget == 0.0) {
+    // phi_i = sqrt(tau^2 + gamma_i): with tau^2 = 0 a station with
+    // gamma_i = 0 (on a grid node, where gamma_i is 0 up to round-off,
+    // taken as <= 1e-12 sigma^2) has dphi_i / dtau^2 = 1 / (2 phi_i)
+    // unbounded, so dL/dtau^2 does not exist there
+    std::vector<double> gm(n);
+    CESIM_HIP(hipMemcpy(gm.data(), c->gamma.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i)
+      if (!(gm[i] > 1e-12 * c->covd.sigma2)) return CESIM_ERR_INVALID_ARG;
+  }
   const int M = c->grid.m1 * c->grid.m2;
   const size_t N = (size_t)c->t1 * c->t2;
   // vectors: eps_bar N | ybar M | dybar M | xi_bar n | t 4n | p n | dp n | z n | X 2n | Y 2n | q n | dots

@@ -184,10 +184,14 @@ k_lk_grad(const double* __restrict__ obs, int n, GridDev g, CovDev cov, double t
     dwy += u[al * LD] * yb[node];
   }
   const double phi = sqrt(tau2 + gam), xi = xib[i], s2 = cov.sigma2;
+  // phi = 0 only with tau^2 = 0 and gamma_i = 0 (the host refuses that
+  // case for the nugget derivative); gamma and its derivative vanish there,
+  // so the noise terms of the range and sigma^2 derivatives are 0
+  const double hphi = phi > 0.0 ? 0.5 / phi : 0.0;
   out[4 * (size_t)i] = wy + phi * xi;
-  out[4 * (size_t)i + 1] = dwy + wdy + xi * dgam / (2.0 * phi);
-  out[4 * (size_t)i + 2] = wy / (2.0 * s2) + xi * gam / (2.0 * s2 * phi);
-  out[4 * (size_t)i + 3] = xi / (2.0 * phi);
+  out[4 * (size_t)i + 1] = dwy + wdy + xi * dgam * hphi;
+  out[4 * (size_t)i + 2] = wy / (2.0 * s2) + xi * gam * hphi / s2;
+  out[4 * (size_t)i + 3] = xi * hphi;
 }
 
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,

@@ -49,6 +49,10 @@ def test_out_of_order_calls_and_recovery():
         assert status_of(ctx.condition, np.array([0.0, np.nan]), 0.1, f) == "INVALID_ARG"
         ctx.condition(np.array([0.5, 0.5]), 0.1, f)                            # recovers
         assert torch.isfinite(f).all()
+        # a conditioned batch is not conditioned twice; a new draw re-arms it
+        assert status_of(ctx.condition, np.array([0.5, 0.5]), 0.1, f) == "BAD_STATE"
+        ctx.simulate(2, 1, out=f)
+        ctx.condition(np.array([0.5, 0.5]), 0.1, f)
     L = cesim.lib()
     assert L.ce_simulate(None, 1, 0, 0, None) == 1
 

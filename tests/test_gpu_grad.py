@@ -164,3 +164,35 @@ def test_gradient_error_statuses():
         assert e.value.name == "NOT_POSITIVE_DEFINITE"
         g = ctx.grad_linear(np.ones(5), 0.1, 2, 1, w)      # recovers
         assert np.isfinite(g["d_range"])
+
+
+def test_zero_nugget():
+    """nugget 0: with every station off the grid nodes (gamma_i > 0) the
+    adjoint matches the oracle's; a station on a node (gamma_i = 0) makes
+    dL/dnugget unbounded, reported as INVALID_ARG by both."""
+    import torch
+    m, t, n, k, R = 32, 64, 30, 16, 3
+    ocov = OCov(0.5, 1.0, 0.12)
+    xy = workloads.uniform_locations(n, seed=23)
+    z = draw_observations(xy, ocov, 0.0, seed=0)
+    w = np.random.default_rng(9).standard_normal((m, m))
+    ref = ograd.linear_stat_gradient(ocov, OGrid.unit_square(m), xy, z, 0.0, k, 5, R, w, t, t)
+    with cesim.Context(cesim.make_cov(0.5, 1.0, 0.12), cesim.unit_square_grid(m, t),
+                       "fp64") as ctx:
+        ctx.offgrid(xy, k)
+        g = ctx.grad_linear(z, 0.0, R, 5, torch.as_tensor(w, device="cuda"))
+        scale = abs(ref["L"]) + 1e-3
+        for a, b in (("L", "L"), ("d_range", "d_range"), ("d_sigma2", "d_sigma2"),
+                     ("d_nugget", "d_tau2")):
+            assert np.isfinite(g[a])
+            close(g[a], ref[b], 1e-8, scale / (0.12 if a == "d_range" else 1.0))
+        xy_node = xy.copy()
+        xy_node[3] = (10 / (m - 1), 17 / (m - 1))        # grid node (10, 17)
+        ctx.offgrid(xy_node, k)
+        with pytest.raises(cesim.CesimError) as e:
+            ctx.grad_linear(z, 0.0, R, 5, torch.as_tensor(w, device="cuda"))
+        assert e.value.name == "INVALID_ARG"
+        g = ctx.grad_linear(z, 0.05, R, 5, torch.as_tensor(w, device="cuda"))
+        assert all(np.isfinite(g[a]) for a in ("L", "d_range", "d_sigma2", "d_nugget"))
+    with pytest.raises(ValueError):
+        ograd.linear_stat_gradient(ocov, OGrid.unit_square(m), xy_node, z, 0.0, k, 5, R, w, t, t)

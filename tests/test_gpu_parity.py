@@ -44,6 +44,9 @@ def test_spectrum_matches_oracle(nu, theta, m, torus, aniso):
     assert np.max(np.abs(s * N - sref)) < 1e-12 * sref.max()
     assert info["lam_min"] == pytest.approx(oinfo["lam_min"], abs=1e-11 * oinfo["lam_max"])
     assert info["lam_sum"] == pytest.approx(N * 1.0, rel=1e-10)
+    # the setup's acceptance checks: real spectrum and the trace identity
+    assert info["max_imag"] <= 1e-12 * info["lam_max"]
+    assert info["max_imag"] == pytest.approx(oinfo["max_imag"], abs=1e-13 * oinfo["lam_max"])
 
 
 def test_ladder_moves_past_negative_torus():

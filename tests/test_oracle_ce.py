@@ -86,6 +86,28 @@ def test_negative_eigenvalues_detected_and_ladder_moves_on():
     assert t1 > 64 and info["lam_min"] >= -1e-12 * info["lam_max"]
 
 
+def test_acceptance_checks_reality_and_trace():
+    """A valid spectrum passes all three checks; a base that is not even (an
+    FFT or base bug) has a non-real spectrum and is refused; so is a spectrum
+    whose sum misses the trace identity sum(lambda) = N C(0)."""
+    cov = Cov(0.5, 1.0, 0.1)
+    g = Grid.unit_square(16)
+    c = ce.torus_base(cov, g.dx, g.dy, 32, 32)
+    lam, info = ce.eigenvalues(c)
+    assert ce.accept(info)
+    assert info["trace"] == 32 * 32 * 1.0
+    assert abs(info["lam_sum"] - info["trace"]) < 1e-12 * info["trace"]
+    assert info["max_imag"] < 1e-13 * info["lam_max"]
+    odd = c.copy()
+    odd[0, 1] += 1e-3                     # breaks c[q] = c[-q]
+    _, oinfo = ce.eigenvalues(odd)
+    assert oinfo["lam_min"] >= -1e-12 * oinfo["lam_max"]
+    assert oinfo["max_imag"] > 1e-12 * oinfo["lam_max"] and not ce.accept(oinfo)
+    bad = dict(info, lam_sum=info["trace"] * (1 + 2e-9))
+    assert not ce.accept(bad)
+    assert ce.accept(dict(info, lam_sum=info["trace"] * (1 + 5e-10)))
+
+
 def test_matern1_range015_needs_padding():
     """nu = 1, theta = 0.15 on a 256^2 unit-square grid: the 512 torus has a
     negative spectrum, 768 is the first accepted size."""
