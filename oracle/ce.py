@@ -22,20 +22,29 @@ the textbook construction it cites (Wood and Chan; Chan and Wood):
   remaining tiny negatives are clamped to 0.  Otherwise the next torus size on the ladder is tried:
   T = S(f m) for f in (2, 3, 4, 6, 8), where S(n) is the smallest integer
   >= n whose only prime factors are 2, 3 and 5 (the sizes the FFT handles).
-* Draw: y = Re(IFFT2(sqrt(lambda) * FFT2(eps)))[0:m2, 0:m1] with eps a
-  T2 x T1 field of iid N(0, 1) (Philox stream 0) and IFFT2 including
-  1 / (T1 T2).  Because lambda is real and even, the map eps -> y is real;
-  two realizations may therefore share one complex transform (real and
-  imaginary parts), which the HIP path does and this oracle does not need.
+* Draw, two realizations per transform (the complex form of the CE draw:
+  Dietrich and Newsam, SIAM J. Sci. Comput. 18, 1997; Wood and Chan
+  generate the transformed noise directly in the same way).  Realizations
+  2P and 2P + 1 form pair P.  With eps_{2P}, eps_{2P+1} two T2 x T1 fields
+  of iid N(0, 1) (Philox stream 0) and zeta_P = eps_{2P} + i eps_{2P+1},
+      W_P = FFT2(sqrt(lambda / N) * zeta_P),     N = T1 T2,
+  (unnormalised forward transform) and y_{2P} = Re W_P, y_{2P+1} = Im W_P,
+  each cropped to [0:m2, 0:m1].  Why this is exact: with F the DFT matrix,
+  E[W W^*] = (2/N) F diag(lambda) F^* = 2 C_torus (lambda real and even) and
+  E[W W^T] = 0 because E[zeta zeta^T] = I - I = 0; so Re W and Im W each
+  have covariance C_torus, whose crop is [C(g - g')], and they are
+  uncorrelated, hence independent.  One 2D FFT serves two realizations.
 
 Pins (tests/test_oracle_ce.py): brute-force DFT on tiny tori, trace
 sum(lambda) = N C(0), evenness, and the exactness of the draw: the explicit
-linear map B of the draw satisfies B B^T = [C(g - g')] on small grids,
-including padded and anisotropic cases.
+linear maps B_re, B_im from the pair's noise (eps_{2P}, eps_{2P+1}) to its
+two fields satisfy B_re B_re^T = B_im B_im^T = [C(g - g')] and
+B_re B_im^T = 0 on small grids, including padded and anisotropic cases.
 """
 
 import numpy as np
 
+from . import philox
 from .covariance import Cov, covariance
 
 LADDER_FACTORS = (2, 3, 4, 6, 8)
@@ -138,16 +147,28 @@ def ce_setup(cov: Cov, dx, dy, m1, m2, t1=None, t2=None):
     raise NegativeEigenvalue(f"no torus on the ladder is non-negative: {last}")
 
 
-def ce_draw(sqrt_lam, eps, m1, m2):
-    """Unconditional fields y_r = Re(IFFT2(s * FFT2(eps_r)))[:m2, :m1].
+def ce_draw_pair(sqrt_lam, eps_even, eps_odd, m1, m2):
+    """Both fields of one pair: W = FFT2(sqrt(lambda / N) (eps_even + i
+    eps_odd)) cropped to the grid; returns (Re W, Im W), each (m2, m1)."""
+    t2, t1 = sqrt_lam.shape
+    w = np.fft.fft2((sqrt_lam / np.sqrt(t1 * t2)) * (np.asarray(eps_even, dtype=np.float64)
+                                                    + 1j * np.asarray(eps_odd, dtype=np.float64)))
+    return w.real[:m2, :m1].copy(), w.imag[:m2, :m1].copy()
 
-    eps: (R, T2, T1) real noise; returns (R, m2, m1)."""
-    eps = np.asarray(eps, dtype=np.float64)
-    single = eps.ndim == 2
-    if single:
-        eps = eps[None]
-    out = np.empty((eps.shape[0], m2, m1))
-    for r in range(eps.shape[0]):
-        f = np.fft.ifft2(sqrt_lam * np.fft.fft2(eps[r]))
-        out[r] = f.real[:m2, :m1]
-    return out[0] if single else out
+
+def ce_draw(sqrt_lam, seed, reals, m1, m2, event=0):
+    """Unconditional fields y_r, shape (len(reals), m2, m1), for the absolute
+    realization indices ``reals``: y_r = Re W_P (r even) or Im W_P (r odd)
+    of pair P = r // 2, whose noise is eps_{2P} + i eps_{2P+1} (Philox
+    stream 0, counter word 2 = event)."""
+    t2, t1 = sqrt_lam.shape
+    reals = [int(r) for r in reals]
+    out = np.empty((len(reals), m2, m1))
+    pair, fields = None, None
+    for i, r in enumerate(reals):
+        P = r // 2
+        if P != pair:
+            eps = philox.torus_noise(seed, t1, t2, [2 * P, 2 * P + 1], event)
+            pair, fields = P, ce_draw_pair(sqrt_lam, eps[0], eps[1], m1, m2)
+        out[i] = fields[r % 2]
+    return out

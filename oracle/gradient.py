@@ -6,10 +6,13 @@ The statistic is
     L = (1/R) sum_r sum_g w_g v_r[g]
 over the conditional fields v_r of Section 2 (steps 1-5, with the local
 Kriging of Section 2.1 for steps 2-4) and fixed grid weights w.  Each v_r is
-affine in its noise (eps_r for the circulant-embedding draw, xi_r for the
-nugget of the synthetic data), so L equals the same expression evaluated
-once on the mean noises eps_bar = mean_r eps_r and xi_bar = mean_r xi_r:
-    ybar   = crop(F^-1 diag(sqrt(lambda)) F eps_bar)       (Section 2, step 2)
+affine in its noise (the pair noise zeta_P = eps_{2P} + i eps_{2P+1} of the
+circulant-embedding draw, P = r // 2, and xi_r for the nugget of the
+synthetic data): y_r = Re(c_r W_P) with W_P = FFT2(sqrt(lambda / N) zeta_P),
+c_r = 1 for even r and -i for odd r.  So L equals the same expression
+evaluated once on the mean noises zeta_bar = mean_r c_r zeta_{r // 2}
+(complex) and xi_bar = mean_r xi_r:
+    ybar   = crop(Re FFT2(sqrt(lambda / N) zeta_bar))      (Section 2, step 2)
     zbar*  = W1 ybar + phi * xi_bar                        (Section 2.1 (b)-(c))
     L      = w . ybar + u . (z - zbar*),  u = A^{-1} K21 w (steps 1, 4, 5; eq. (4))
 with A = K22 + tau^2 I and phi_i = sqrt(tau^2 + gamma_i).
@@ -104,14 +107,19 @@ def torus_base_dtheta(cov: Cov, dx, dy, t1, t2):
 
 
 def mean_noises(seed, t1, t2, n, reals, event=0, chunk=16):
-    """eps_bar (t2, t1) and xi_bar (n,) over the realizations ``reals``."""
-    reals = list(reals)
-    eb = np.zeros((t2, t1))
+    """zeta_bar (t2, t1), complex, and xi_bar (n,) over the realizations
+    ``reals``: zeta_bar = mean_r c_r (eps_{2P} + i eps_{2P+1}), P = r // 2,
+    c_r = 1 (r even) or -i (r odd)."""
+    reals = [int(r) for r in reals]
+    eb = np.zeros((t2, t1), dtype=np.complex128)
     xb = np.zeros(n)
+    for r in reals:
+        P = r // 2
+        eps = philox.torus_noise(seed, t1, t2, [2 * P, 2 * P + 1], event)
+        zeta = eps[0] + 1j * eps[1]
+        eb += zeta if r % 2 == 0 else -1j * zeta
     for i in range(0, len(reals), chunk):
-        rr = reals[i:i + chunk]
-        eb += philox.torus_noise(seed, t1, t2, rr, event).sum(axis=0)
-        xb += philox.offgrid_noise(seed, n, rr, event).sum(axis=0)
+        xb += philox.offgrid_noise(seed, n, reals[i:i + chunk], event).sum(axis=0)
     return eb / len(reals), xb / len(reals)
 
 
@@ -157,9 +165,9 @@ def linear_stat_gradient(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, weight
     keep = lam > 1e-12 * lam.max()
     ds = np.where(keep, dlam / (2.0 * np.where(keep, s, 1.0)), 0.0)
     eb, xb = mean_noises(seed, t1, t2, n, range(first_real, first_real + nreal), event)
-    fe = np.fft.fft2(eb)
-    ybar = np.fft.ifft2(s * fe).real[:grid.m2, :grid.m1]
-    dybar = np.fft.ifft2(ds * fe).real[:grid.m2, :grid.m1]
+    rn = 1.0 / np.sqrt(t1 * t2)
+    ybar = np.fft.fft2(rn * s * eb).real[:grid.m2, :grid.m1]
+    dybar = np.fft.fft2(rn * ds * eb).real[:grid.m2, :grid.m1]
     # local Kriging and the mean synthetic data
     a, b, W, gamma, dW, dgamma = local_krige_dtheta(obs_xy, cov, grid, k)
     phi = np.sqrt(tau2 + gamma)
@@ -193,7 +201,7 @@ def linear_stat_gradient(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, weight
                     - np.sum(u * (dwy + wdy + xb * dgamma / (2.0 * phi))))
     return dict(L=L, d_range=d_theta, d_sigma2=d_sigma2, d_tau2=d_tau2, d_z=u,
                 ybar=ybar, dybar=dybar, zbar=zbar, u=u, cbar=cbar, p=p, dp=dp,
-                eps_bar=eb, xi_bar=xb)
+                zeta_bar=eb, xi_bar=xb)
 
 
 def ensemble_stat(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, weights, t1, t2,

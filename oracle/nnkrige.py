@@ -103,8 +103,7 @@ def conditional_simulation_nn(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, f
     s = surrogate(cov, grid, obs_xy, z, tau2, k)
     t1, t2, sl, info = setup(cov, grid, t1, t2)
     reals = np.arange(first_real, first_real + nreal)
-    eps = philox.torus_noise(seed, t1, t2, reals, event)
-    y = ce.ce_draw(sl, eps, grid.m1, grid.m2)
+    y = ce.ce_draw(sl, seed, reals, grid.m1, grid.m2, event)
     nN = s["idx"].size
     xi = philox.offgrid_noise(seed, nN, reals, event)
     zstar = y.reshape(nreal, -1)[:, s["idx"]] + np.sqrt(tau2 + s["sigmaN2"])[None, :] * xi
@@ -116,12 +115,13 @@ def conditional_simulation_nn(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, f
 
 
 def linear_map_nn(cov: Cov, grid, obs_xy, tau2, k, t1=None, t2=None):
-    """(Me, Mx) with v - E v = Me eps + Mx xi for the nearest-neighbour
-    simulation (the data enter only the mean).  Tiny problems only."""
+    """(Me, Mx) with v - E v = Me [eps_{2P}; eps_{2P+1}] + Mx xi for the
+    nearest-neighbour simulation, realization 2P of a pair (the data enter
+    only the mean).  Tiny problems only."""
     from .pipeline import draw_matrix, setup
     s = surrogate(cov, grid, obs_xy, np.zeros(len(obs_xy)), tau2, k)
     t1, t2, sl, _ = setup(cov, grid, t1, t2)
-    Bce = draw_matrix(sl, grid.m1, grid.m2)                      # (M, N)
+    Bce = draw_matrix(sl, grid.m1, grid.m2)                      # (M, 2N)
     fac = surrogate_factor(cov, s["xy"], tau2, s["sigmaN2"])
     nN = s["idx"].size
     K1N = cross_covariance(grid.points(), s["xy"], cov)

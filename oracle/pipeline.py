@@ -10,11 +10,14 @@ local-Kriging approximation of steps 2-4:
   (d) the grid prediction uses tau^2 alone.
 
 Random inputs: eps_r from Philox stream 0 and xi_r from stream 1, both keyed
-by the seed, the absolute realization index r and the event index.
+by the seed, the absolute realization index r and the event index; the CE
+draw of realization r uses the torus noise of both members of its pair
+(eps_{2P}, eps_{2P+1}, P = r // 2).
 
 Test-only helpers build, for tiny problems, the explicit linear map of the
-pipeline from (eps, xi) to v - y_hat, the paper's closed-form covariance of
-that map (Section 3.1) and the exact conditional law (eq. (4), Section 3).
+pipeline from (eps_{2P}, eps_{2P+1}, xi) to v - y_hat, the paper's
+closed-form covariance of that map (Section 3.1) and the exact conditional
+law (eq. (4), Section 3).
 """
 
 from dataclasses import dataclass
@@ -84,12 +87,11 @@ def conditional_simulation(cov: Cov, grid: Grid, obs_xy, z, tau2, k, seed,
     (noise counters carry ``event`` in their third word; joint: boxes of
     several observations sampled jointly).
 
-    Returns a dict of every intermediate: torus, sqrt_lam, eps, y, window
+    Returns a dict of every intermediate: torus, sqrt_lam, y, window
     corners a/b, W, gamma, xi, zstar, B, v."""
     t1, t2, s, info = setup(cov, grid, t1, t2)
     reals = np.arange(first_real, first_real + nreal)
-    eps = philox.torus_noise(seed, t1, t2, reals, event)
-    y = ce.ce_draw(s, eps, grid.m1, grid.m2)
+    y = ce.ce_draw(s, seed, reals, grid.m1, grid.m2, event)
     a, b, W, gamma = offgrid_setup(obs_xy, cov, grid, k)
     xi = philox.offgrid_noise(seed, len(obs_xy), reals, event)
     zstar = synthetic(y, obs_xy, cov, grid, a, b, W, gamma, tau2, xi, joint)
@@ -97,35 +99,42 @@ def conditional_simulation(cov: Cov, grid: Grid, obs_xy, z, tau2, k, seed,
     B = kriging.coefficients(fac, z, zstar)
     v = kriging.condition_fields(y, B, obs_xy, cov, grid.x0, grid.y0,
                                  grid.dx, grid.dy, grid.m1, grid.m2)
-    return dict(t1=t1, t2=t2, info=info, sqrt_lam=s, eps=eps, y=y, a=a, b=b,
+    return dict(t1=t1, t2=t2, info=info, sqrt_lam=s, y=y, a=a, b=b,
                 W=W, gamma=gamma, xi=xi, zstar=zstar, B=B, v=v)
 
 
 # ---------------------------------------------------------------- test only
 
-def draw_matrix(sqrt_lam, m1, m2):
-    """Explicit matrix of the CE draw eps (T2*T1) -> y (m2*m1)."""
+def draw_matrix(sqrt_lam, m1, m2, part=0):
+    """Explicit matrix (M, 2N) of the CE draw of one member of a pair, from
+    the pair's noise [eps_{2P}; eps_{2P+1}] (each T2*T1) to y (m2*m1):
+    part 0 is realization 2P (Re W), part 1 realization 2P + 1 (Im W)."""
     t2, t1 = sqrt_lam.shape
     N = t1 * t2
     cols = []
-    for q in range(N):
-        e = np.zeros(N)
-        e[q] = 1.0
-        cols.append(ce.ce_draw(sqrt_lam, e.reshape(t2, t1), m1, m2).reshape(-1))
+    for half in (0, 1):
+        for q in range(N):
+            e = np.zeros(N)
+            e[q] = 1.0
+            z = np.zeros(N)
+            pair = (e, z) if half == 0 else (z, e)
+            f = ce.ce_draw_pair(sqrt_lam, pair[0].reshape(t2, t1), pair[1].reshape(t2, t1), m1, m2)
+            cols.append(f[part].reshape(-1))
     return np.stack(cols, axis=1)
 
 
 def linear_map(cov: Cov, grid: Grid, obs_xy, tau2, k, t1=None, t2=None, joint=False):
-    """Matrices (Me, Mx) with v - y_hat = Me eps + Mx xi for the whole
-    pipeline (z enters only y_hat).  Tiny problems only."""
+    """Matrices (Me, Mx) with v - y_hat = Me [eps_{2P}; eps_{2P+1}] + Mx xi
+    for the whole pipeline, realization 2P of a pair (z enters only y_hat;
+    realization 2P + 1 has the same covariance).  Tiny problems only."""
     t1, t2, s, _ = setup(cov, grid, t1, t2)
-    Bce = draw_matrix(s, grid.m1, grid.m2)                  # (M, N)
+    Bce = draw_matrix(s, grid.m1, grid.m2)                  # (M, 2N)
     a, b, W, gamma = offgrid_setup(obs_xy, cov, grid, k)
     n = len(obs_xy)
     fac = kriging.factor(obs_xy, cov, tau2)
     z0 = np.zeros(n)
     # columns for eps
-    Y = Bce.T.reshape(-1, grid.m2, grid.m1)                 # (N, m2, m1)
+    Y = Bce.T.reshape(-1, grid.m2, grid.m1)                 # (2N, m2, m1)
     zs = synthetic(Y, obs_xy, cov, grid, a, b, W, gamma, tau2, np.zeros((Y.shape[0], n)),
                    joint)
     Bc = kriging.coefficients(fac, z0, zs)

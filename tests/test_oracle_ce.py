@@ -70,10 +70,14 @@ def test_draw_is_exact(cov, m, t):
     g = Grid.unit_square(m)
     t1, t2, s, info = setup(cov, g, t, t)
     assert info["lam_min"] >= 0.0
-    B = draw_matrix(s, m, m)
+    Bre = draw_matrix(s, m, m, 0)        # realization 2P from (eps_2P, eps_2P+1)
+    Bim = draw_matrix(s, m, m, 1)        # realization 2P + 1
     P = g.points()
     K = cross_covariance(P, P, cov)
-    assert np.max(np.abs(B @ B.T - K)) < 1e-12 * cov.sigma2
+    assert np.max(np.abs(Bre @ Bre.T - K)) < 1e-12 * cov.sigma2
+    assert np.max(np.abs(Bim @ Bim.T - K)) < 1e-12 * cov.sigma2
+    # the two members of a pair are uncorrelated (jointly Gaussian: independent)
+    assert np.max(np.abs(Bre @ Bim.T)) < 1e-12 * cov.sigma2
 
 
 def test_negative_eigenvalues_detected_and_ladder_moves_on():
@@ -126,8 +130,7 @@ def test_unconditional_moments_monte_carlo():
     g = Grid.unit_square(m)
     t1, t2, s, _ = setup(cov, g)
     R = 4000
-    eps = philox.torus_noise(21, t1, t2, range(R))
-    y = ce.ce_draw(s, eps, m, m).reshape(R, -1)
+    y = ce.ce_draw(s, 21, range(R), m, m).reshape(R, -1)
     P = g.points()
     K = cross_covariance(P, P, cov)
     for (i, j) in [(0, 0), (0, 1), (9, 27), (5, 60), (63, 63), (0, 63)]:
@@ -135,3 +138,21 @@ def test_unconditional_moments_monte_carlo():
         zsc = (prod.mean() - K[i, j]) / (prod.std() / np.sqrt(R))
         assert abs(zsc) < 4, (i, j, zsc)
     assert abs(y.mean()) < 4 / np.sqrt(R)
+    # the members of a pair (2P, 2P + 1) are uncorrelated at every lag
+    ye, yo = y[0::2], y[1::2]
+    for (i, j) in [(0, 0), (9, 27), (63, 0), (20, 21)]:
+        prod = ye[:, i] * yo[:, j]
+        zsc = prod.mean() / (prod.std() / np.sqrt(ye.shape[0]))
+        assert abs(zsc) < 4, (i, j, zsc)
+
+
+def test_realization_depends_only_on_its_index():
+    """Pairs are absolute (P = r // 2), so any batching gives the same fields,
+    including calls that start or end inside a pair."""
+    cov = Cov(1.5, 1.0, 0.2)
+    g = Grid.unit_square(6)
+    t1, t2, s, _ = setup(cov, g)
+    full = ce.ce_draw(s, 5, range(7), 6, 6, event=2)
+    for lo, hi in [(1, 4), (3, 4), (4, 7), (0, 1), (5, 6)]:
+        assert np.array_equal(ce.ce_draw(s, 5, range(lo, hi), 6, 6, event=2), full[lo:hi])
+    assert not np.allclose(ce.ce_draw(s, 5, range(2), 6, 6, event=3), full[:2])
