@@ -81,16 +81,16 @@ def parse():
 
 def algorithmic_units(name, wl, R, t1, t2, bytes_per_real, nobs=None):
     """Algorithmic bytes (or flops) of one step for a stage, by its I/O
-    contract: pair buffer traffic of the draw passes (sqrt(lambda) reads are
-    amortised and not counted), 2 M n R flops for the grid GEMM."""
-    N = t1 * t2
+    contract: traffic of the pair buffer between the two draw passes and of
+    the fields (the noise is generated in registers; sqrt(lambda) is read
+    once per call in principle and not counted), 2 M n R flops for the grid
+    GEMM."""
     M = wl.m * wl.m
-    frac = wl.m / t2                      # rows the crop keeps
+    kept = t1 * wl.m                      # complex entries per pair kept after pass A
     b = bytes_per_real                    # 4 (FP32) or 8 (FP64) per real value
-    per_real = {
-        "draw_noise_rowfft": b * N,                 # writes the pair buffer: 2 b N per pair
-        "draw_colfft_scale_icolfft": (2 * b * N + 2 * b * N * frac) / 2,
-        "draw_irowfft_crop": (2 * b * N * frac + 2 * b * M) / 2,
+    per_real = {                          # per realization = half a pair
+        "draw_noise_colfft": (2 * b * kept) / 2,               # writes the kept rows
+        "draw_rowfft_crop": (2 * b * kept + 2 * b * M) / 2,    # reads them, writes 2 fields
     }
     if name in per_real:
         return per_real[name] * R, "bytes"
@@ -196,9 +196,8 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
 # Stage -> (kernel name fragment, source files whose text the kernel is
 # built from) for the recorded HBM counters.
 COUNTED_STAGES = {
-    "draw_noise_rowfft": ("k_p2_rows_noise<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp", "devmath.hpp"]),
-    "draw_colfft_scale_icolfft": ("k_p2_cols<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
-    "draw_irowfft_crop": ("k_p2_rows_inv_crop<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
+    "draw_noise_colfft": ("k_p2_cols_noise<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp", "devmath.hpp"]),
+    "draw_rowfft_crop": ("k_p2_rows_crop<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
     "krige_grid_gemm": ("k_krige_split3", ["krige.hip", "devmath.hpp"]),
     "krige_predict_fp64": ("k_predict_f64", ["krige.hip", "devmath.hpp"]),
     "synth_obs_rhs": ("k_synth_rhs<float, false,", ["lk.hip", "devmath.hpp"]),
@@ -311,8 +310,7 @@ def cpu_baseline(wl, xy, z, seed, nn=False):
     t["cholesky"] = time.perf_counter() - s0
     nd = 24
     s0 = time.perf_counter()
-    eps = philox.torus_noise(seed, t1, t2, range(nd))
-    y = ce.ce_draw(s, eps, wl.m, wl.m)
+    y = ce.ce_draw(s, seed, range(nd), wl.m, wl.m)
     xi = philox.offgrid_noise(seed, len(sites), range(nd))
     if nn:
         zs = (y.reshape(nd, -1)[:, sur["idx"]]

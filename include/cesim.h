@@ -139,11 +139,16 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid,
                       cesim_ctx* out);
 
 /* Unconditional draw of nreal realizations, absolute indices first_real ..
- * first_real + nreal - 1 (step 2 of Section 2; Section 2.1 item (a)):
- *   y_r = Re(IFFT2(sqrt(lambda) FFT2(eps_r)))[0:m2, 0:m1],
+ * first_real + nreal - 1 (step 2 of Section 2; Section 2.1 item (a)), two
+ * per transform: realizations 2P and 2P + 1 form pair P and
+ *   W_P = FFT2(sqrt(lambda / N) (eps_{2P} + i eps_{2P+1})),  N = t1 t2,
+ *   y_{2P} = Re W_P[0:m2, 0:m1],  y_{2P+1} = Im W_P[0:m2, 0:m1],
  * eps_r the t2 x t1 torus noise of Philox stream 0 (element q = j t1 + i:
- * block q/4, word q%4, counter (block, r, event id, 0), Box-Muller).  Two
- * realizations share one complex transform.  fields_dev: caller-owned
+ * block q/4, word q%4, counter (block, r, event id, 0), Box-Muller).  The
+ * real and imaginary parts are independent fields of covariance C
+ * (lambda is real and even).  Pairs are absolute, so y_r depends only on
+ * (seed, r); a call that starts or ends inside a pair transforms the whole
+ * pair and writes its own member.  fields_dev: caller-owned
  * device buffer of nreal*m2*m1 doubles (FP64) or floats (MIXED), written
  * asynchronously.  Records (seed, first_real, nreal) for condition().
  * Errors: INVALID_ARG (nreal < 1, first_real < 0, NULL), OUT_OF_MEMORY,
@@ -194,7 +199,7 @@ cesim_status condition(cesim_ctx ctx, const double* z_host, double nugget,
 /* Statistics of the context; synchronises the stream. */
 cesim_status ce_get_info(cesim_ctx ctx, cesim_info* info);
 
-/* Copies sqrt(lambda) / (t1 t2) (FP64, t2 x t1, row-major) -- the spectral
+/* Copies sqrt(lambda / (t1 t2)) (FP64, t2 x t1, row-major) -- the spectral
  * multiplier the draw applies -- into a caller-owned device buffer. */
 cesim_status ce_copy_spectrum(cesim_ctx ctx, double* dev_out);
 
@@ -228,8 +233,8 @@ const char* cesim_status_string(cesim_status s);
  * the context's stream around each stage it launches (per launch or per
  * chunk of launches); times accumulate until read with reset != 0.
  * Stages, in order (CESIM_NUM_STAGES of them): torus base, setup FFT,
- * eigenvalue check, draw pass 1 (noise + row FFT), draw pass 2 (column
- * FFT, scale, inverse column FFT), draw pass 3 (inverse row FFT + crop),
+ * eigenvalue check, draw pass A (pair noise, scaling, column FFT), draw
+ * pass B (row FFT + crop),
  * local-Kriging setup, observation Cholesky, synthetic observations and
  * right-hand sides, observation solves, half-precision split of the
  * coefficients, cross-covariance GEMM onto the grid, FP64 prediction from the
@@ -237,7 +242,7 @@ const char* cesim_status_string(cesim_status s);
  * ce_prediction_se: W1 K11 W1^T, the
  * covariance rows of a chunk of grid nodes (K12 and (W1 K11)^T), the GEMM of
  * the solved rows with W1 K11 W1^T, and the per-node reduction. */
-#define CESIM_NUM_STAGES 17
+#define CESIM_NUM_STAGES 16
 
 /* Launch-shape parameters (performance only; results do not change):
  *   CESIM_PARAM_GEMM_TILE: workgroup tile of the mixed cross-covariance GEMM,
@@ -246,11 +251,10 @@ const char* cesim_status_string(cesim_status s);
  *     each observation chunk are computed once for all 512 realizations);
  *     0 (default) takes the tuning table's choice for the problem's shape,
  *     else 1.
- *   CESIM_PARAM_DRAW_ROWS_FWD, CESIM_PARAM_DRAW_COLS, CESIM_PARAM_DRAW_ROWS_INV:
- *     torus rows per workgroup of draw pass 1, columns per workgroup of
- *     pass 2, rows per workgroup of pass 3 on the register-FFT path
- *     (square tori of 2^a from 128 to 8192 and of 3 * 2^a from 384 to 6144);
- *     powers of two, clamped to each kernel's largest
+ *   CESIM_PARAM_DRAW_COLS, CESIM_PARAM_DRAW_ROWS: torus columns per
+ *     workgroup of draw pass A and grid rows per workgroup of pass B on the
+ *     register-FFT path (square tori of 2^a from 128 to 8192 and of 3 * 2^a
+ *     from 384 to 6144); powers of two, clamped to each kernel's largest
  *     shape; 0 (default) takes the tuning table's choice, else the largest.
  *   CESIM_PARAM_DRAW_CHUNK_PAIRS: realization pairs per launch of the draw
  *     passes (bounds the pair buffer); 0 (default) chooses up to 2 GiB.
@@ -264,9 +268,8 @@ const char* cesim_status_string(cesim_status s);
  *     counter of the torus noise and of xi, >= 0 (default 0); a context with
  *     event id e draws exactly what event e of a batch draws. */
 #define CESIM_PARAM_EVENT_ID 4
-#define CESIM_PARAM_DRAW_ROWS_FWD 5
 #define CESIM_PARAM_DRAW_COLS 6
-#define CESIM_PARAM_DRAW_ROWS_INV 7
+#define CESIM_PARAM_DRAW_ROWS 7
 /*   CESIM_PARAM_JOINT_BOXES (changes the method, Section 2.1 last paragraph
  *     and Section 3.6): 1 draws the synthetic values of observations that
  *     share a grid box (the cell floor((x - x0)/dx), floor((y - y0)/dy))

@@ -34,13 +34,12 @@ PARAM_GEMM_TILE = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
 PARAM_EVENT_ID = 4
-PARAM_DRAW_ROWS_FWD = 5
 PARAM_DRAW_COLS = 6
-PARAM_DRAW_ROWS_INV = 7
+PARAM_DRAW_ROWS = 7
 PARAM_JOINT_BOXES = 8
 PARAM_SE_CHUNK_NODES = 9
 BATCH_AUTOTUNE = 1
-NUM_STAGES = 17
+NUM_STAGES = 16
 VOID_EXPORTS = ("cesim_status_string", "ce_destroy", "cesim_set_default_timing",
                 "cesim_stage_name", "cesim_release_cached_memory", "cesim_batch_destroy",
                 "cesim_tune_clear")

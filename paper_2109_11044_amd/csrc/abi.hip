@@ -350,14 +350,13 @@ cesim_status ce_set_param(cesim_ctx c, int param, int value) {
       if (value < 0 || value > 3) return CESIM_ERR_INVALID_ARG;
       c->gemm_tile = value;
       return CESIM_OK;
-    case CESIM_PARAM_DRAW_ROWS_FWD:
-    case CESIM_PARAM_DRAW_ROWS_INV:
+    case CESIM_PARAM_DRAW_ROWS:
       if (value < 0 || (value & (value - 1))) return CESIM_ERR_INVALID_ARG;
-      (param == CESIM_PARAM_DRAW_ROWS_FWD ? c->draw_force.rows1 : c->draw_force.rows3) = value;
+      c->draw_force.rows = value;
       return CESIM_OK;
     case CESIM_PARAM_DRAW_COLS:
       if (value < 0 || (value & (value - 1))) return CESIM_ERR_INVALID_ARG;
-      c->draw_force.lcp2 = value == 0 ? -1 : __builtin_ctz((unsigned)value);
+      c->draw_force.lcp = value == 0 ? -1 : __builtin_ctz((unsigned)value);
       return CESIM_OK;
     case CESIM_PARAM_GEMM_SPLIT:
       if (value != 0 && value != 1) return CESIM_ERR_INVALID_ARG;
@@ -403,8 +402,8 @@ cesim_status ce_get_stage_times(cesim_ctx c, double* ms, long long* calls, int n
 
 const char* cesim_stage_name(int stage) {
   static const char* names[ST_COUNT] = {
-      "setup_torus_base", "setup_fft2_fp64", "setup_eigen_check", "draw_noise_rowfft",
-      "draw_colfft_scale_icolfft", "draw_irowfft_crop", "offgrid_local_krige",
+      "setup_torus_base", "setup_fft2_fp64", "setup_eigen_check", "draw_noise_colfft",
+      "draw_rowfft_crop", "offgrid_local_krige",
       "obs_cholesky", "synth_obs_rhs", "obs_solve", "coef_split_half", "krige_grid_gemm",
       "krige_predict_fp64", "se_w1k11w1", "se_cov_rows", "se_gemm_xq", "se_reduce"};
   return (stage >= 0 && stage < ST_COUNT) ? names[stage] : "unknown";

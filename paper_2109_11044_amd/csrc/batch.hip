@@ -129,13 +129,16 @@ cesim_status plan(cesim_batch b, cesim_status* status, int flags) {
       if (first == CESIM_OK) first = CESIM_ERR_NOT_POSITIVE_DEFINITE;
     }
   if (first != CESIM_OK) return first;
-  // shared pair buffers, realization offset, solve launches
+  // realization offset (the draw sizes its pairs for offsets of either
+  // parity), shared pair buffers, solve launches
+  CESIM_TRY(b->roff.reserve(sizeof(int)));
+  for (int e = 0; e < ne; ++e) b->ctx[e]->roff = b->roff.as<int>();
   size_t wbytes = 0;
   for (int e = 0; e < ne; ++e)
     wbytes = std::max(wbytes, draw_pair_bytes(b->ctx[e]) *
-                                  (size_t)draw_chunk_pairs(b->ctx[e], b->ev[e].nreal));
+                                  (size_t)draw_chunk_pairs(b->ctx[e], b->ev[e].nreal,
+                                                           b->ev[e].first_real));
   CESIM_TRY(b->work.reserve(wbytes));
-  CESIM_TRY(b->roff.reserve(sizeof(int)));
   k_set_int<<<1, 1, 0, b->own>>>(b->roff.as<int>(), 0);
   CESIM_HIP(hipGetLastError());
   std::vector<double*> X(ne);

@@ -73,251 +73,255 @@ __device__ inline const cpx<real>* stage_twiddles(cpx<real>* dst, const cpx<real
   return dst;
 }
 
-// Noise for torus rows [j0, j0 + nrows) of pair p into LDS as
-// eps_{r0} + i eps_{r1}; element q = j t1 + i uses block q / 4, word q % 4.
-template <typename real, int NTHR>
-__device__ void noise_rows(cpx<real>* lds, int t1, int j0, int nrows, const NoiseKey& key,
-                           int r0, bool has_r1) {
-  const uint32_t k0 = key.k0, k1 = key.k1, ev = key.event;
-  const long q_lo = (long)j0 * t1;
-  const long q_hi = q_lo + (long)nrows * t1;
-  const long b_lo = q_lo >> 2, b_hi = (q_hi - 1) >> 2;
-  for (long b = b_lo + threadIdx.x; b <= b_hi; b += NTHR) {
-    real za[4], zb[4] = {0, 0, 0, 0};
-    if constexpr (sizeof(real) == 8) {
-      normals4_f64(k0, k1, (uint32_t)b, (uint32_t)r0, ev, 0u, za);
-      if (has_r1) normals4_f64(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), ev, 0u, zb);
-    } else {
-      normals4_f32(k0, k1, (uint32_t)b, (uint32_t)r0, ev, 0u, za);
-      if (has_r1) normals4_f32(k0, k1, (uint32_t)b, (uint32_t)(r0 + 1), ev, 0u, zb);
-    }
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const long q = 4 * b + w;
-      if (q >= q_lo && q < q_hi) lds[q - q_lo] = {za[w], zb[w]};
-    }
+// Absolute pair of workgroup row p of a draw launch: pairs are (2P, 2P + 1)
+// in absolute realization numbers, so a call starting at an odd realization
+// begins with the second member of a pair.  Returns realization 2P, or -1
+// for a spare pair beyond the call (graphs replayed at an offset of either
+// parity are captured with one spare pair).
+__device__ __forceinline__ int pair_first_real(const NoiseKey& key, int nreal, int pair0, int p) {
+  const int first = key.base();
+  const int r0 = 2 * ((first >> 1) + pair0 + p);
+  return r0 < first + nreal ? r0 : -1;
+}
+
+// Four normals of Philox block blk for each member of the pair (2P, 2P + 1).
+template <typename real>
+__device__ __forceinline__ void pair_normals(const NoiseKey& key, uint32_t blk, int r0, real za[4],
+                                             real zb[4]) {
+  if constexpr (sizeof(real) == 8) {
+    normals4_f64(key.k0, key.k1, blk, (uint32_t)r0, key.event, 0u, za);
+    normals4_f64(key.k0, key.k1, blk, (uint32_t)(r0 + 1), key.event, 0u, zb);
+  } else {
+    normals4_f32(key.k0, key.k1, blk, (uint32_t)r0, key.event, 0u, za);
+    normals4_f32(key.k0, key.k1, blk, (uint32_t)(r0 + 1), key.event, 0u, zb);
   }
 }
 
-// Forward FFT of nb torus rows per workgroup.  NOISE: the input is the pair
-// noise; otherwise it is read from buf.  Output overwrites buf.
-template <typename real, int NTHR, int E, bool NOISE>
+// Crop of one transformed row j of pair (2P, 2P + 1): the first m1 entries
+// give realization 2P (real part) and 2P + 1 (imaginary part), each written
+// when it belongs to the call (fields[r - first]).
+template <typename real>
+struct CropRow {
+  real* re = nullptr;
+  real* im = nullptr;
+  __device__ CropRow(real* fields, const NoiseKey& key, int nreal, int r0, int m1, int m2, int j) {
+    const long f0 = (long)r0 - key.base();          // -1 .. nreal - 1
+    const size_t M = (size_t)m1 * m2;
+    if (f0 >= 0) re = fields + (size_t)f0 * M + (size_t)j * m1;
+    if (f0 + 1 < nreal) im = fields + (size_t)(f0 + 1) * M + (size_t)j * m1;
+  }
+  template <typename C>
+  __device__ __forceinline__ void put(int x, C v) const {
+    if (re) re[x] = v.x;
+    if (im) im[x] = v.y;
+  }
+};
+
+// Forward FFT of nb rows per workgroup, in place (the setup's 2D FFT and
+// the gradient's draw of the mean noise).
+template <typename real, int NTHR, int E>
 __global__ void __launch_bounds__(NTHR)
 k_rows_fwd(cpx<real>* __restrict__ buf, int t1, int t2, int nb, Plan plan,
-           const cpx<real>* __restrict__ tw, bool tw_lds, NoiseKey key, int nreal, int pair0) {
+           const cpx<real>* __restrict__ tw, bool tw_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
-  const int p = blockIdx.y;
   const int j0 = blockIdx.x * nb;
   const int nr = min(nb, t2 - j0);
-  cpx<real>* base = buf + ((size_t)p * t2 + j0) * t1;
+  cpx<real>* base = buf + (size_t)j0 * t1;
   const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + nb * t1, tw, t1, tw_lds);
-  if constexpr (NOISE) {
-    const int pg = pair0 + p;               // pair index within this call
-    const int r0 = key.base() + 2 * pg;
-    noise_rows<real, NTHR>(lds, t1, j0, nr, key, r0, 2 * pg + 1 < nreal);
-  } else {
-    for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
-  }
+  for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
   __syncthreads();
   fft_lds<false, NTHR, E, false, real>(lds, plan, nr, 1, t1, twl);
   for (int e = threadIdx.x; e < nr * t1; e += NTHR) base[e] = lds[e];
 }
 
-// Column panel of cp columns of every pair: forward FFT along y; with SCALE
-// also multiply by s[ky][kx] and inverse FFT along y, writing rows < rows_out.
-template <typename real, int NTHR, int E, bool SCALE>
+// Forward FFT of a panel of cp columns, in place, all rows.
+template <typename real, int NTHR, int E>
 __global__ void __launch_bounds__(NTHR)
-k_cols(cpx<real>* __restrict__ buf, int t1, int t2, int cp, int rows_out, Plan plan,
-       const cpx<real>* __restrict__ tw, bool tw_lds, const real* __restrict__ s) {
+k_cols(cpx<real>* __restrict__ buf, int t1, int t2, int cp, Plan plan,
+       const cpx<real>* __restrict__ tw, bool tw_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
   const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + cp * t2, tw, t2, tw_lds);
-  const int p = blockIdx.y;
   const int c0 = blockIdx.x * cp;
   const int cw = min(cp, t1 - c0);
-  cpx<real>* base = buf + (size_t)p * t2 * t1 + c0;
+  cpx<real>* base = buf + c0;
   for (int e = threadIdx.x; e < t2 * cp; e += NTHR) {
     const int row = e / cp, c = e - row * cp;
     lds[e] = c < cw ? base[(size_t)row * t1 + c] : cpx<real>{0, 0};
   }
   __syncthreads();
   fft_lds<false, NTHR, E, true, real>(lds, plan, cp, cp, 1, twl);
-  if constexpr (SCALE) {
-    for (int e = threadIdx.x; e < t2 * cp; e += NTHR) {
-      const int row = e / cp, c = e - row * cp;
-      if (c < cw) {
-        const real m = s[(size_t)row * t1 + c0 + c];
-        lds[e] = {lds[e].x * m, lds[e].y * m};
-      }
-    }
-    __syncthreads();
-    fft_lds<true, NTHR, E, true, real>(lds, plan, cp, cp, 1, twl);
-  }
-  for (int e = threadIdx.x; e < rows_out * cp; e += NTHR) {
+  for (int e = threadIdx.x; e < t2 * cp; e += NTHR) {
     const int row = e / cp, c = e - row * cp;
     if (c < cw) base[(size_t)row * t1 + c] = lds[e];
   }
 }
 
-// Inverse FFT along x of nb kept rows (y < m2) and the crop: the first m1
-// outputs of the row of pair p become fields 2p (real) and 2p+1 (imag).
+// Draw pass A, any torus: a panel of cp columns of pair p.  The pair noise
+// eps_{2P} + i eps_{2P+1} (element q = j t1 + i: Philox block q / 4, word
+// q % 4) times s = sqrt(lambda / N), forward FFT along y, rows < m2 stored
+// as buf[p][row][col] (row stride t1).
 template <typename real, int NTHR, int E>
 __global__ void __launch_bounds__(NTHR)
-k_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, int t1, int t2,
-                int m1, int m2, int nb, Plan plan, const cpx<real>* __restrict__ tw, bool tw_lds,
-                int nreal, int pair0) {
+k_cols_noise(cpx<real>* __restrict__ buf, int t1, int t2, int cp, int m2, Plan plan,
+             const cpx<real>* __restrict__ tw, bool tw_lds, const real* __restrict__ s,
+             NoiseKey key, int nreal, int pair0) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
-  const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + nb * t1, tw, t1, tw_lds);
   const int p = blockIdx.y;
+  const int r0 = pair_first_real(key, nreal, pair0, p);
+  if (r0 < 0) return;
+  const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + cp * t2, tw, t2, tw_lds);
+  const int c0 = blockIdx.x * cp;
+  const int cw = min(cp, t1 - c0);
+  // blocks covering elements j t1 + c0 .. j t1 + c0 + cw - 1 of each row
+  const int bpr = (cw + 3) / 4 + 1;
+  for (int e = threadIdx.x; e < t2 * bpr; e += NTHR) {
+    const int row = e / bpr, g = e - row * bpr;
+    const long q_lo = (long)row * t1 + c0;
+    const long b = (q_lo >> 2) + g;
+    if (4 * b >= q_lo + cw) continue;
+    real za[4], zb[4];
+    pair_normals<real>(key, (uint32_t)b, r0, za, zb);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const long q = 4 * b + w;
+      if (q >= q_lo && q < q_lo + cw) {
+        const int c = (int)(q - q_lo);
+        const real m = s[q];
+        lds[row * cp + c] = {za[w] * m, zb[w] * m};
+      }
+    }
+  }
+  for (int e = threadIdx.x; e < t2 * cp; e += NTHR)     // ragged last panel
+    if (e % cp >= cw) lds[e] = cpx<real>{0, 0};
+  __syncthreads();
+  fft_lds<false, NTHR, E, true, real>(lds, plan, cp, cp, 1, twl);
+  cpx<real>* out = buf + (size_t)p * m2 * t1 + c0;
+  for (int e = threadIdx.x; e < m2 * cp; e += NTHR) {
+    const int row = e / cp, c = e - row * cp;
+    if (c < cw) out[(size_t)row * t1 + c] = lds[e];
+  }
+}
+
+// Draw pass B, any torus: forward FFT along x of nb kept rows (y < m2) of
+// pair p and the crop into realizations 2P (real part) and 2P + 1
+// (imaginary part).
+template <typename real, int NTHR, int E>
+__global__ void __launch_bounds__(NTHR)
+k_rows_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, int t1, int m1, int m2,
+            int nb, Plan plan, const cpx<real>* __restrict__ tw, bool tw_lds, NoiseKey key,
+            int nreal, int pair0) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<real>* lds = reinterpret_cast<cpx<real>*>(smem);
+  const int p = blockIdx.y;
+  const int r0 = pair_first_real(key, nreal, pair0, p);
+  if (r0 < 0) return;
+  const cpx<real>* twl = stage_twiddles<real, NTHR>(lds + nb * t1, tw, t1, tw_lds);
   const int j0 = blockIdx.x * nb;
   const int nr = min(nb, m2 - j0);
-  const cpx<real>* base = buf + ((size_t)p * t2 + j0) * t1;
+  const cpx<real>* base = buf + ((size_t)p * m2 + j0) * t1;
   for (int e = threadIdx.x; e < nr * t1; e += NTHR) lds[e] = base[e];
   __syncthreads();
-  fft_lds<true, NTHR, E, false, real>(lds, plan, nr, 1, t1, twl);
-  const int pg = pair0 + p;
-  const size_t M = (size_t)m1 * m2;
-  real* f0 = fields + (size_t)(2 * pg) * M + (size_t)j0 * m1;
-  const bool has1 = 2 * pg + 1 < nreal;
+  fft_lds<false, NTHR, E, false, real>(lds, plan, nr, 1, t1, twl);
   for (int e = threadIdx.x; e < nr * m1; e += NTHR) {
     const int row = e / m1, x = e - row * m1;
-    const cpx<real> v = lds[row * t1 + x];
-    f0[(size_t)row * m1 + x] = v.x;
-    if (has1) f0[M + (size_t)row * m1 + x] = v.y;
+    const CropRow<real> cr(fields, key, nreal, r0, m1, m2, j0 + row);
+    cr.put(x, lds[row * t1 + x]);
   }
 }
 
 // ------------------------------------------- power-of-two draw kernels
-// Same three passes as above with the transform length fixed at compile
-// time and the data held in registers (see fft_pow2.hpp).
+// The same two passes with the transform length fixed at compile time and
+// the data held in registers (see fft_pow2.hpp).
 
-// Pass 1: noise of ROWS torus rows (natural order into LDS), forward row
-// FFT, result written from registers.
-template <typename real, int T>
-__global__ void __launch_bounds__(P2Rows<T>::NTHR)
-k_p2_rows_noise(cpx<real>* __restrict__ buf, int t2, const cpx<real>* __restrict__ tw, NoiseKey key,
-                int nreal, int pair0) {
-  using C = cpx<real>;
-  using G = P2Rows<T>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* lds = reinterpret_cast<C*>(smem);
-  const int p = blockIdx.y;
-  const int rows = blockDim.x / G::S;
-  const int j0 = blockIdx.x * rows;
-  const int pg = pair0 + p;
-  const int r0 = key.base() + 2 * pg;
-  const bool has1 = 2 * pg + 1 < nreal;
-  const uint32_t k0 = key.k0, k1 = key.k1, ev = key.event;
-  // Philox blocks of 4 consecutive elements; T is a multiple of 4, so a
-  // block never straddles two rows.
-  constexpr int BPR = T / 4;
-  for (int blk = threadIdx.x; blk < rows * BPR; blk += blockDim.x) {
-    const int b = blk / BPR, i0 = (blk % BPR) * 4;
-    if (j0 + b >= t2) continue;
-    const uint32_t gb = (uint32_t)((((long)(j0 + b)) * T + i0) >> 2);
-    real za[4], zb[4] = {0, 0, 0, 0};
-    if constexpr (sizeof(real) == 8) {
-      normals4_f64(k0, k1, gb, (uint32_t)r0, ev, 0u, za);
-      if (has1) normals4_f64(k0, k1, gb, (uint32_t)(r0 + 1), ev, 0u, zb);
-    } else {
-      normals4_f32(k0, k1, gb, (uint32_t)r0, ev, 0u, za);
-      if (has1) normals4_f32(k0, k1, gb, (uint32_t)(r0 + 1), ev, 0u, zb);
-    }
-    const RowLds<C> rl{lds + b * G::LD};
-#pragma unroll
-    for (int w = 0; w < 4; ++w) rl.store(i0 + w, C{za[w], zb[w]});
-  }
-  __syncthreads();
-  const int b = threadIdx.x / G::S, base = threadIdx.x % G::S;
-  const RowLds<C> rl{lds + b * G::LD};
-  C x[G::E];
-#pragma unroll
-  for (int h = 0; h < G::E; ++h) x[h] = rl.load(base + G::S * h);
-  p2_fft<real, T, false>(x, base, tw, rl);
-  if (j0 + b < t2) {
-    C* out = buf + ((size_t)p * t2 + j0 + b) * T;
-#pragma unroll
-    for (int h = 0; h < G::E; ++h) out[base + G::S * h] = x[h];
-  }
-}
-
-// Pass 2: CP columns per workgroup, loaded straight into registers; forward
-// FFT along y, sqrt(lambda)/N in registers (from the copy blocked by 8
-// columns, so that a wave reads 8 rows of 8 columns contiguously), inverse
-// FFT, rows < rows_out stored.
+// Pass A: CP columns per workgroup.  The pair noise of the panel goes into
+// LDS (a Philox block holds 4 adjacent columns of one row), each element is
+// scaled by s = sqrt(lambda / N) read from the copy blocked by 8 columns (a
+// wave reads 8 rows of 8 columns contiguously), the forward FFT along y runs
+// in registers and rows < m2 are stored as buf[p][row][col].
 template <typename real, int T>
 __global__ void __launch_bounds__((P2Cols<real, T>::NTHR))
-k_p2_cols(cpx<real>* __restrict__ buf, int t1, int rows_out, const cpx<real>* __restrict__ tw,
-          const real* __restrict__ slb, int lcp) {
+k_p2_cols_noise(cpx<real>* __restrict__ buf, int m2, const cpx<real>* __restrict__ tw,
+                const real* __restrict__ slb, int lcp, NoiseKey key, int nreal, int pair0) {
   using C = cpx<real>;
   using G = P2Cols<real, T>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int p = blockIdx.y;
+  const int r0 = pair_first_real(key, nreal, pair0, p);
+  if (r0 < 0) return;
   const int cp = 1 << lcp;
-  const int c = threadIdx.x & (cp - 1), base = threadIdx.x >> lcp;
   // Workgroups are dealt to the 8 XCDs round-robin; when the panel count is
   // a multiple of 8, panels are renumbered so that one XCD takes adjacent
   // panels in turn and the halves of each cache line meet in its L2.
   int panel = blockIdx.x;
   if ((gridDim.x & 7) == 0) panel = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-  const int col = panel * cp + c;
-  const bool ok = col < t1;
-  C* colp = buf + (size_t)p * T * t1 + col;
+  const int col0 = panel * cp;
+  const int bpr = cp >= 4 ? cp >> 2 : 1;             // Philox blocks per row of the panel
+  const int i00 = col0 & ~3;
+  for (int e = threadIdx.x; e < T * bpr; e += blockDim.x) {
+    const int row = e >> (lcp >= 2 ? lcp - 2 : 0);
+    const int i0 = i00 + 4 * (e - row * bpr);
+    real za[4], zb[4];
+    pair_normals<real>(key, (uint32_t)(((long)row * T + i0) >> 2), r0, za, zb);
+    const int pr = (row + (row >> 4)) << lcp;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int c = i0 + w - col0;
+      if (c >= 0 && c < cp) lds[pr + c] = C{za[w], zb[w]};
+    }
+  }
+  __syncthreads();
+  const int c = threadIdx.x & (cp - 1), hb = threadIdx.x >> lcp;
+  const int col = col0 + c;
+  const ColLds<C> cl{lds, c, lcp};
   C x[G::E];
 #pragma unroll
-  for (int h = 0; h < G::E; ++h) x[h] = ok ? colp[(size_t)(base + G::S * h) * t1] : C{0, 0};
-  const ColLds<C> cl{lds, c, lcp};
-  p2_fft<real, T, false>(x, base, tw, cl);
+  for (int h = 0; h < G::E; ++h) {
+    const int row = hb + G::S * h;
+    const C v = cl.load(row);
+    const real m = slb[((size_t)(col >> 3) * T + row) * 8 + (col & 7)];
+    x[h] = {v.x * m, v.y * m};
+  }
+  p2_fft<real, T, false>(x, hb, tw, cl);
+  C* colp = buf + (size_t)p * m2 * T + col;
 #pragma unroll
   for (int h = 0; h < G::E; ++h) {
-    const real m = ok ? slb[((size_t)(col >> 3) * T + base + G::S * h) * 8 + (col & 7)] : (real)0;
-    x[h] = {x[h].x * m, x[h].y * m};
-  }
-  p2_fft<real, T, true>(x, base, tw, cl);
-  if (ok) {
-#pragma unroll
-    for (int h = 0; h < G::E; ++h) {
-      const int row = base + G::S * h;
-      if (row < rows_out) colp[(size_t)row * t1] = x[h];
-    }
+    const int row = hb + G::S * h;
+    if (row < m2) colp[(size_t)row * T] = x[h];
   }
 }
 
-// Pass 3: ROWS kept rows per workgroup: inverse row FFT and the crop into
-// fields 2p (real part) and 2p+1 (imaginary part).
+// Pass B: ROWS kept rows per workgroup: forward row FFT and the crop into
+// realizations 2P (real part) and 2P + 1 (imaginary part).
 template <typename real, int T>
 __global__ void __launch_bounds__(P2Rows<T>::NTHR)
-k_p2_rows_inv_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, int t2, int m1,
-                   int m2, const cpx<real>* __restrict__ tw, int nreal, int pair0) {
+k_p2_rows_crop(const cpx<real>* __restrict__ buf, real* __restrict__ fields, int m1, int m2,
+               const cpx<real>* __restrict__ tw, NoiseKey key, int nreal, int pair0) {
   using C = cpx<real>;
   using G = P2Rows<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int p = blockIdx.y;
-  const int b = threadIdx.x / G::S, base = threadIdx.x % G::S;
+  const int r0 = pair_first_real(key, nreal, pair0, p);
+  if (r0 < 0) return;
+  const int b = threadIdx.x / G::S, hb = threadIdx.x % G::S;
   const int j = blockIdx.x * (blockDim.x / G::S) + b;
   const bool ok = j < m2;
-  const C* in = buf + ((size_t)p * t2 + (ok ? j : 0)) * T;
+  const C* in = buf + ((size_t)p * m2 + (ok ? j : 0)) * T;
   C x[G::E];
 #pragma unroll
-  for (int h = 0; h < G::E; ++h) x[h] = ok ? in[base + G::S * h] : C{0, 0};
+  for (int h = 0; h < G::E; ++h) x[h] = ok ? in[hb + G::S * h] : C{0, 0};
   const RowLds<C> rl{lds + b * G::LD};
-  p2_fft<real, T, true>(x, base, tw, rl);
+  p2_fft<real, T, false>(x, hb, tw, rl);
   if (!ok) return;
-  const int pg = pair0 + p;
-  const size_t M = (size_t)m1 * m2;
-  real* f0 = fields + (size_t)(2 * pg) * M + (size_t)j * m1;
-  const bool has1 = 2 * pg + 1 < nreal;
+  const CropRow<real> cr(fields, key, nreal, r0, m1, m2, j);
 #pragma unroll
   for (int h = 0; h < G::E; ++h) {
-    const int xcol = base + G::S * h;
-    if (xcol < m1) {
-      f0[xcol] = x[h].x;
-      if (has1) f0[M + xcol] = x[h].y;
-    }
+    const int xcol = hb + G::S * h;
+    if (xcol < m1) cr.put(xcol, x[h]);
   }
 }
 
@@ -374,15 +378,17 @@ __global__ void __launch_bounds__(512) k_eig_final(const double* part, int npart
   }
 }
 
-__global__ void k_sqrt_lambda(const double2* lam, size_t N, double inv_n, double* s64, float* s32) {
+// s = sqrt(lambda / N), the multiplier of the draw (lambda clamped at 0).
+__global__ void k_sqrt_lambda(const double2* lam, size_t N, double rsqrt_n, double* s64,
+                              float* s32) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N) return;
-  const double v = sqrt(fmax(lam[q].x, 0.0)) * inv_n;
+  const double v = sqrt(fmax(lam[q].x, 0.0)) * rsqrt_n;
   s64[q] = v;
   if (s32) s32[q] = (float)v;
 }
 
-// sqrt(lambda) / N of the register draw path, in the path's precision and
+// sqrt(lambda / N) of the register draw path, in the path's precision and
 // blocked by 8 columns: element (row r, column q) at ((q / 8) t2 + r) 8 + q % 8
 // (t1 is a multiple of 8 on that path).
 template <typename real>
@@ -462,73 +468,66 @@ void allow_lds(K kernel, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename real, bool NOISE>
-cesim_status launch_rows_fwd(cpx<real>* buf, int t1, int t2, int npairs, const Plan& plan,
-                             const cpx<real>* tw, const NoiseKey& key, int nreal, int pair0,
-                             hipStream_t s) {
-  int nb, E;
+// Forward 2D FFT of one t2 x t1 complex array in place (rows, then columns).
+template <typename real>
+cesim_status fft2_forward(cpx<real>* buf, int t1, int t2, const Plan& p1, const Plan& p2,
+                          const cpx<real>* tw1, const cpx<real>* tw2, hipStream_t s) {
+  int nb, E, cp;
   bool twl;
   size_t lds;
   row_config<real>(t1, nb, E, twl, lds);
-  dim3 grid((t2 + nb - 1) / nb, npairs);
-  if (E == 16) {
-    auto k = k_rows_fwd<real, kRowThreads, 16, NOISE>;
+  {
+    const dim3 grid((t2 + nb - 1) / nb);
+    auto k = E == 16 ? k_rows_fwd<real, kRowThreads, 16> : k_rows_fwd<real, kRowThreads, 32>;
     allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, key, nreal, pair0);
-  } else {
-    auto k = k_rows_fwd<real, kRowThreads, 32, NOISE>;
-    allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, plan, tw, twl, key, nreal, pair0);
+    k<<<grid, kRowThreads, lds, s>>>(buf, t1, t2, nb, p1, tw1, twl);
+    CESIM_HIP(hipGetLastError());
   }
-  CESIM_HIP(hipGetLastError());
+  col_config<real>(t2, t1, cp, E, twl, lds);
+  {
+    const dim3 grid((t1 + cp - 1) / cp);
+    auto k = E == 4 ? k_cols<real, kColThreads, 4>
+           : E == 8 ? k_cols<real, kColThreads, 8>
+           : E == 16 ? k_cols<real, kColThreads, 16> : k_cols<real, kColThreads, 32>;
+    allow_lds(k, lds);
+    k<<<grid, kColThreads, lds, s>>>(buf, t1, t2, cp, p2, tw2, twl);
+    CESIM_HIP(hipGetLastError());
+  }
   return CESIM_OK;
 }
 
-template <typename real, bool SCALE>
-cesim_status launch_cols(cpx<real>* buf, int t1, int t2, int npairs, int rows_out, const Plan& plan,
-                         const cpx<real>* tw, const real* sl, hipStream_t s) {
+// Draw pass A on any torus (LDS Stockham).
+template <typename real>
+cesim_status launch_cols_noise(cpx<real>* buf, int t1, int t2, int m2, int npairs,
+                               const Plan& plan, const cpx<real>* tw, const real* s,
+                               const NoiseKey& key, int nreal, int pair0, hipStream_t st) {
   int cp, E;
   bool twl;
   size_t lds;
   col_config<real>(t2, t1, cp, E, twl, lds);
-  dim3 grid((t1 + cp - 1) / cp, npairs);
-#define CESIM_COLS(EE)                                                            \
-  {                                                                               \
-    auto k = k_cols<real, kColThreads, EE, SCALE>;                                \
-    allow_lds(k, lds);                                                            \
-    k<<<grid, kColThreads, lds, s>>>(buf, t1, t2, cp, rows_out, plan, tw, twl, sl); \
-  }
-  switch (E) {
-    case 4: CESIM_COLS(4) break;
-    case 8: CESIM_COLS(8) break;
-    case 16: CESIM_COLS(16) break;
-    default: CESIM_COLS(32) break;
-  }
-#undef CESIM_COLS
+  const dim3 grid((t1 + cp - 1) / cp, npairs);
+  auto k = E == 4 ? k_cols_noise<real, kColThreads, 4>
+         : E == 8 ? k_cols_noise<real, kColThreads, 8>
+         : E == 16 ? k_cols_noise<real, kColThreads, 16> : k_cols_noise<real, kColThreads, 32>;
+  allow_lds(k, lds);
+  k<<<grid, kColThreads, lds, st>>>(buf, t1, t2, cp, m2, plan, tw, twl, s, key, nreal, pair0);
   CESIM_HIP(hipGetLastError());
   return CESIM_OK;
 }
 
+// Draw pass B on any torus (LDS Stockham).
 template <typename real>
-cesim_status launch_rows_inv_crop(const cpx<real>* buf, real* fields, int t1, int t2, int m1,
-                                  int m2, int npairs, const Plan& plan, const cpx<real>* tw,
-                                  int nreal, int pair0, hipStream_t s) {
+cesim_status launch_rows_crop(const cpx<real>* buf, real* fields, int t1, int m1, int m2,
+                              int npairs, const Plan& plan, const cpx<real>* tw,
+                              const NoiseKey& key, int nreal, int pair0, hipStream_t s) {
   int nb, E;
   bool twl;
   size_t lds;
   row_config<real>(t1, nb, E, twl, lds);
-  dim3 grid((m2 + nb - 1) / nb, npairs);
-  if (E == 16) {
-    auto k = k_rows_inv_crop<real, kRowThreads, 16>;
-    allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, twl, nreal,
-                                     pair0);
-  } else {
-    auto k = k_rows_inv_crop<real, kRowThreads, 32>;
-    allow_lds(k, lds);
-    k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, t2, m1, m2, nb, plan, tw, twl, nreal,
-                                     pair0);
-  }
+  const dim3 grid((m2 + nb - 1) / nb, npairs);
+  auto k = E == 16 ? k_rows_crop<real, kRowThreads, 16> : k_rows_crop<real, kRowThreads, 32>;
+  allow_lds(k, lds);
+  k<<<grid, kRowThreads, lds, s>>>(buf, fields, t1, m1, m2, nb, plan, tw, twl, key, nreal, pair0);
   CESIM_HIP(hipGetLastError());
   return CESIM_OK;
 }
@@ -553,10 +552,8 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   tr = c->timer.begin(ST_SETUP_FFT, s);
-  CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, p1, c->tt.tw1_64.as<double2>(),
-                                            NoiseKey{}, 0, 0, s)));
-  CESIM_TRY((launch_cols<double, false>(buf, t1, t2, 1, t2, p2, c->tt.tw2_64.as<double2>(),
-                                        nullptr, s)));
+  CESIM_TRY(fft2_forward<double>(buf, t1, t2, p1, p2, c->tt.tw1_64.as<double2>(),
+                                 c->tt.tw2_64.as<double2>(), s));
   c->timer.end(tr, s);
   const int nparts = 512;
   CESIM_TRY(c->scratch.reserve(sizeof(double) * (4 * nparts + 8)));
@@ -589,7 +586,7 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
     s32 = c->s32.as<float>();
   }
   tr = c->timer.begin(ST_SETUP_EIG, s);
-  k_sqrt_lambda<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(buf, N, 1.0 / (double)N,
+  k_sqrt_lambda<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(buf, N, 1.0 / std::sqrt((double)N),
                                                             c->s64.as<double>(), s32);
   CESIM_HIP(hipGetLastError());
   if (register_draw_torus(t1, t2)) {       // c->t1, c->t2 are set after acceptance
@@ -609,22 +606,18 @@ cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted) {
 
 namespace {
 
-// Tile shape of the register path: rows per workgroup of passes 1 and 3 and
-// log2 of the columns per workgroup of pass 2, clamped to each kernel's
+// Tile shape of the register path: log2 of the columns per workgroup of
+// pass A and the rows per workgroup of pass B, clamped to each kernel's
 // maximum (results do not depend on it).
 template <typename real, int T1, int T2>
 DrawShape clamp_shape(DrawShape d) {
   using GR = P2Rows<T1>;
   using GC = P2Cols<real, T2>;
-  auto fix_rows = [](int r) {
-    int v = GR::ROWS;
-    if (r > 0) while (v > 1 && v > r) v >>= 1;
-    return v;
-  };
-  d.rows1 = fix_rows(d.rows1);
-  d.rows3 = fix_rows(d.rows3);
+  int v = GR::ROWS;
+  if (d.rows > 0) while (v > 1 && v > d.rows) v >>= 1;
+  d.rows = v;
   const int lmax = ilog2c(GC::CP);
-  d.lcp2 = (d.lcp2 < 0 || d.lcp2 > lmax) ? lmax : d.lcp2;
+  d.lcp = (d.lcp < 0 || d.lcp > lmax) ? lmax : d.lcp;
   return d;
 }
 
@@ -635,33 +628,24 @@ cesim_status draw_chunk_p2(cpx<real>* buf, real* fields, int m1, int m2, int np,
   using GR = P2Rows<T1>;
   using GC = P2Cols<real, T2>;
   const DrawShape d = clamp_shape<real, T1, T2>(shape);
-  const int cp = 1 << d.lcp2;
-  const size_t lr1 = sizeof(cpx<real>) * d.rows1 * GR::LD;
-  const size_t lr3 = sizeof(cpx<real>) * d.rows3 * GR::LD;
+  const int cp = 1 << d.lcp;
   const size_t lc = sizeof(cpx<real>) * cp * GC::LD;
-  int tr = tm.begin(ST_DRAW_PASS1, s);
+  const size_t lr = sizeof(cpx<real>) * d.rows * GR::LD;
+  int tr = tm.begin(ST_DRAW_PASS_A, s);
   {
-    auto k = k_p2_rows_noise<real, T1>;
-    allow_lds(k, sizeof(cpx<real>) * GR::ROWS * GR::LD);
-    k<<<dim3((T2 + d.rows1 - 1) / d.rows1, np), d.rows1 * GR::S, lr1, s>>>(buf, T2, tw1, key,
-                                                                           nreal, pair0);
-    CESIM_HIP(hipGetLastError());
-  }
-  tm.end(tr, s);
-  tr = tm.begin(ST_DRAW_PASS2, s);
-  {
-    auto k = k_p2_cols<real, T2>;
+    auto k = k_p2_cols_noise<real, T2>;
     allow_lds(k, sizeof(cpx<real>) * GC::CP * GC::LD);
-    k<<<dim3((T1 + cp - 1) / cp, np), cp * GC::S, lc, s>>>(buf, T1, m2, tw2, slb, d.lcp2);
+    k<<<dim3((T1 + cp - 1) / cp, np), cp * GC::S, lc, s>>>(buf, m2, tw2, slb, d.lcp, key, nreal,
+                                                           pair0);
     CESIM_HIP(hipGetLastError());
   }
   tm.end(tr, s);
-  tr = tm.begin(ST_DRAW_PASS3, s);
+  tr = tm.begin(ST_DRAW_PASS_B, s);
   {
-    auto k = k_p2_rows_inv_crop<real, T1>;
+    auto k = k_p2_rows_crop<real, T1>;
     allow_lds(k, sizeof(cpx<real>) * GR::ROWS * GR::LD);
-    k<<<dim3((m2 + d.rows3 - 1) / d.rows3, np), d.rows3 * GR::S, lr3, s>>>(buf, fields, T2, m1,
-                                                                           m2, tw1, nreal, pair0);
+    k<<<dim3((m2 + d.rows - 1) / d.rows, np), d.rows * GR::S, lr, s>>>(buf, fields, m1, m2, tw1,
+                                                                       key, nreal, pair0);
     CESIM_HIP(hipGetLastError());
   }
   tm.end(tr, s);
@@ -697,17 +681,17 @@ bool draw_chunk_pow2(int t1, int t2, cpx<real>* buf, real* fields, int m1, int m
 template <typename real>
 cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, real* fields,
                         const cpx<real>* tw1, const cpx<real>* tw2, const real* sl,
-                        const real* slb) {
+                        const real* slb, void* work, size_t work_bytes) {
   hipStream_t s = c->stream;
   const int t1 = c->t1, t2 = c->t2, m1 = c->grid.m1, m2 = c->grid.m2;
-  const size_t pair_bytes = sizeof(cpx<real>) * (size_t)t1 * t2;
-  const int npairs = (nreal + 1) / 2;
-  int chunk = draw_chunk_pairs(c, nreal);
+  const size_t pair_bytes = draw_pair_bytes(c);
+  const int npairs = draw_npairs(c, nreal, first_real);
+  int chunk = draw_chunk_pairs(c, nreal, first_real);
   cpx<real>* buf;
-  if (c->ext_work) {                // pair buffers lent by a batch
-    chunk = std::min<size_t>(chunk, c->ext_work_bytes / pair_bytes);
+  if (work) {                       // pair buffers lent by the caller
+    chunk = std::min<size_t>(chunk, work_bytes / pair_bytes);
     if (chunk < 1) return CESIM_ERR_INVALID_ARG;
-    buf = static_cast<cpx<real>*>(c->ext_work);
+    buf = static_cast<cpx<real>*>(work);
   } else {
     CESIM_TRY(c->work.reserve(pair_bytes * chunk));
     buf = c->work.as<cpx<real>>();
@@ -724,15 +708,13 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
       CESIM_TRY(st);
       continue;
     }
-    int tr = c->timer.begin(ST_DRAW_PASS1, s);
-    CESIM_TRY((launch_rows_fwd<real, true>(buf, t1, t2, np, c->tt.p1, tw1, key, nreal, pair0, s)));
+    int tr = c->timer.begin(ST_DRAW_PASS_A, s);
+    CESIM_TRY((launch_cols_noise<real>(buf, t1, t2, m2, np, c->tt.p2, tw2, sl, key, nreal, pair0,
+                                       s)));
     c->timer.end(tr, s);
-    tr = c->timer.begin(ST_DRAW_PASS2, s);
-    CESIM_TRY((launch_cols<real, true>(buf, t1, t2, np, m2, c->tt.p2, tw2, sl, s)));
-    c->timer.end(tr, s);
-    tr = c->timer.begin(ST_DRAW_PASS3, s);
-    CESIM_TRY((launch_rows_inv_crop<real>(buf, fields, t1, t2, m1, m2, np, c->tt.p1, tw1, nreal,
-                                          pair0, s)));
+    tr = c->timer.begin(ST_DRAW_PASS_B, s);
+    CESIM_TRY((launch_rows_crop<real>(buf, fields, t1, m1, m2, np, c->tt.p1, tw1, key, nreal,
+                                      pair0, s)));
     c->timer.end(tr, s);
   }
   return CESIM_OK;
@@ -760,45 +742,66 @@ DrawShape draw_shape_limits(cesim_ctx c) {
     CESIM_LIM(8192)
     CESIM_LIM(384) CESIM_LIM(768) CESIM_LIM(1536) CESIM_LIM(3072) CESIM_LIM(6144)
 #undef CESIM_LIM
-    default: return DrawShape{1, 0, 1};
+    default: return DrawShape{0, 1};
   }
 }
 
+// Bytes of one pair's buffer between the passes: the m2 kept rows of the
+// column transform, complex, in the path's precision.
 size_t draw_pair_bytes(cesim_ctx c) {
   const size_t el = c->prec == CESIM_PREC_FP64 ? sizeof(double2) : sizeof(float2);
-  return el * (size_t)c->t1 * c->t2;
+  return el * (size_t)c->t1 * c->grid.m2;
+}
+
+// Pairs a call of nreal realizations from first_real touches: absolute
+// pairs floor(first / 2) .. floor((first + nreal - 1) / 2).  A context whose
+// realization offset is read on the device (a captured batch, replayed at
+// offsets of either parity) takes nreal / 2 + 1, one of which may be spare.
+int draw_npairs(cesim_ctx c, int nreal, int first_real) {
+  if (c->roff) return nreal / 2 + 1;
+  return ((first_real + nreal - 1) >> 1) - (first_real >> 1) + 1;
 }
 
 // Pairs per draw launch: all of them within a 2 GiB buffer, or the count
 // set with CESIM_PARAM_DRAW_CHUNK_PAIRS.
-int draw_chunk_pairs(cesim_ctx c, int nreal) {
-  const int npairs = (nreal + 1) / 2;
+int draw_chunk_pairs(cesim_ctx c, int nreal, int first_real) {
+  const int npairs = draw_npairs(c, nreal, first_real);
   const size_t budget = (size_t)2 << 30;
   int chunk = (int)std::max<size_t>(1, std::min<size_t>(npairs, budget / draw_pair_bytes(c)));
   if (c->draw_chunk_pairs > 0) chunk = std::min(npairs, c->draw_chunk_pairs);
   return chunk;
 }
 
-// d sqrt(lambda)/dtheta / N from dlambda = Re FFT2 of the theta-derivative of
-// the base (in buf) and s = sqrt(lambda) / N; zero where lambda <= 1e-12
+// d sqrt(lambda / N) / dtheta from dlambda = Re FFT2 of the theta-derivative
+// of the base (in buf) and s = sqrt(lambda / N); zero where lambda <= 1e-12
 // lambda_max, where the setup clamps lambda.
 __global__ void k_dsqrt_lambda(const double2* __restrict__ dlam, const double* __restrict__ s,
                                size_t N, double lam_floor, double* __restrict__ ds) {
   const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= N) return;
-  const double sq = s[q] * (double)N;          // sqrt(lambda)
-  ds[q] = (sq * sq > lam_floor) ? dlam[q].x / (2.0 * sq * (double)N) : 0.0;
+  const double lam = s[q] * s[q] * (double)N;
+  ds[q] = lam > lam_floor ? dlam[q].x / (2.0 * s[q] * (double)N) : 0.0;
 }
 
-__global__ void k_real_to_complex(const double* __restrict__ a, size_t N, double2* __restrict__ out) {
+__global__ void k_scale_complex(const double2* __restrict__ a, const double* __restrict__ m,
+                                size_t N, double2* __restrict__ out) {
   const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (q < N) out[q] = {a[q], 0.0};
+  if (q < N) out[q] = {a[q].x * m[q], a[q].y * m[q]};
+}
+
+__global__ void k_crop_real(const double2* __restrict__ a, int t1, int m1, int m2,
+                            double* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)m1 * m2) return;
+  const int j = (int)(e / m1), i = (int)(e % m1);
+  out[e] = a[(size_t)j * t1 + i].x;
 }
 
 // Mean-noise fields of the linear-statistic gradient (FP64, general FFT
-// passes on one pair buffer): yb = crop(F^-1 diag(sqrt(lambda)) F eps_bar)
-// and dyb = crop(F^-1 diag(d sqrt(lambda)/dtheta) F eps_bar), [m2][m1].
-cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* yb, double* dyb) {
+// passes on one buffer): with the complex mean noise zeta_bar,
+// yb = crop(Re FFT2(s zeta_bar)) and dyb = crop(Re FFT2(ds zeta_bar)),
+// [m2][m1], s = sqrt(lambda / N) and ds its theta-derivative.
+cesim_status ce_grad_fields_device(cesim_ctx c, const double2* zeta_bar, double* yb, double* dyb) {
   hipStream_t s = c->stream;
   const int t1 = c->t1, t2 = c->t2, m1 = c->grid.m1, m2 = c->grid.m2;
   const size_t N = (size_t)t1 * t2;
@@ -811,30 +814,33 @@ cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* y
   k_torus_base<true><<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy,
                                                                 t1, t2, buf);
   CESIM_HIP(hipGetLastError());
-  CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, c->tt.p1, tw1, NoiseKey{}, 0, 0, s)));
-  CESIM_TRY((launch_cols<double, false>(buf, t1, t2, 1, t2, c->tt.p2, tw2, nullptr, s)));
+  CESIM_TRY(fft2_forward<double>(buf, t1, t2, c->tt.p1, c->tt.p2, tw1, tw2, s));
   k_dsqrt_lambda<<<nb, 256, 0, s>>>(buf, c->s64.as<double>(), N, 1e-12 * c->lam_max, ds);
   CESIM_HIP(hipGetLastError());
+  const unsigned nm = (unsigned)(((size_t)m1 * m2 + 255) / 256);
   for (int pass = 0; pass < 2; ++pass) {
-    k_real_to_complex<<<nb, 256, 0, s>>>(eps_bar, N, buf);
+    k_scale_complex<<<nb, 256, 0, s>>>(zeta_bar, pass == 0 ? c->s64.as<double>() : ds, N, buf);
     CESIM_HIP(hipGetLastError());
-    CESIM_TRY((launch_rows_fwd<double, false>(buf, t1, t2, 1, c->tt.p1, tw1, NoiseKey{}, 0, 0, s)));
-    CESIM_TRY((launch_cols<double, true>(buf, t1, t2, 1, m2, c->tt.p2, tw2,
-                                         pass == 0 ? c->s64.as<double>() : ds, s)));
-    CESIM_TRY((launch_rows_inv_crop<double>(buf, pass == 0 ? yb : dyb, t1, t2, m1, m2, 1,
-                                            c->tt.p1, tw1, 1, 0, s)));
+    CESIM_TRY(fft2_forward<double>(buf, t1, t2, c->tt.p1, c->tt.p2, tw1, tw2, s));
+    k_crop_real<<<nm, 256, 0, s>>>(buf, t1, m1, m2, pass == 0 ? yb : dyb);
+    CESIM_HIP(hipGetLastError());
   }
   return CESIM_OK;
 }
 
-cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields) {
+cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields,
+                            void* work, size_t work_bytes) {
+  if (c->ext_work && !work) {       // pair buffers lent by a batch
+    work = c->ext_work;
+    work_bytes = c->ext_work_bytes;
+  }
   if (c->prec == CESIM_PREC_FP64)
     return draw_typed<double>(c, nreal, seed, first_real, static_cast<double*>(fields),
                               c->tt.tw1_64.as<double2>(), c->tt.tw2_64.as<double2>(),
-                              c->s64.as<double>(), c->slb.as<double>());
+                              c->s64.as<double>(), c->slb.as<double>(), work, work_bytes);
   return draw_typed<float>(c, nreal, seed, first_real, static_cast<float*>(fields),
                            c->tt.tw1_32.as<float2>(), c->tt.tw2_32.as<float2>(),
-                           c->s32.as<float>(), c->slb.as<float>());
+                           c->s32.as<float>(), c->slb.as<float>(), work, work_bytes);
 }
 
 }  // namespace cesim

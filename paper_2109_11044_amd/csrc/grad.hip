@@ -3,10 +3,11 @@
 // Section 2.1; eq. (4)), FP64:
 //   L = (1/R) sum_r sum_g w_g v_r[g]
 // with respect to the range theta, the sill sigma^2, the nugget tau^2 and the
-// observed values z.  Every v_r is affine in its noise (eps_r of the draw,
-// xi_r of the synthetic data), so L and its derivatives follow from one
-// evaluation on the mean noises eps_bar, xi_bar:
-//   ybar  = crop(F^-1 diag(sqrt(lambda)) F eps_bar),  zbar* = W1 ybar + phi xi_bar,
+// observed values z.  Every v_r is affine in its noise (the pair noise
+// zeta_{r/2} of the draw, y_r = Re(c_r FFT2(sqrt(lambda / N) zeta_{r/2})) with
+// c_r = 1 or -i, and xi_r of the synthetic data), so L and its derivatives
+// follow from one evaluation on the mean noises zeta_bar, xi_bar:
+//   ybar  = crop(Re FFT2(sqrt(lambda / N) zeta_bar)),  zbar* = W1 ybar + phi xi_bar,
 //   L     = w . ybar + u . (z - zbar*),  u = A^{-1} p,  p = K21 w,  A = K22 + tau^2 I.
 // With cbar = A^{-1} (z - zbar*) and dA^{-1} = -A^{-1} dA A^{-1}:
 //   dL/dz      = u
@@ -28,22 +29,30 @@ namespace cesim {
 
 namespace {
 
-// eps_bar[q] = mean over r of the stream-0 normal of torus element q
-// (block q / 4, word q % 4), r = first .. first + R - 1.
-__global__ void k_mean_torus_noise(uint32_t k0, uint32_t k1, uint32_t event, int first, int R,
-                                   size_t N, double* __restrict__ eb) {
+// zeta_bar[q] = mean over r of c_r zeta_{r/2}[q]: zeta_P = eps_{2P} + i
+// eps_{2P+1} is the pair noise of torus element q (stream 0: block q / 4,
+// word q % 4) and c_r = 1 (r even) or -i (r odd), so that y_r = Re(c_r W_P),
+// r = first .. first + R - 1.
+__global__ void k_mean_pair_noise(uint32_t k0, uint32_t k1, uint32_t event, int first, int R,
+                                  size_t N, double2* __restrict__ zb) {
   const size_t blk = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (blk * 4 >= N) return;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int r = 0; r < R; ++r) {
-    double z[4];
-    normals4_f64(k0, k1, (uint32_t)blk, (uint32_t)(first + r), event, 0u, z);
+  double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+  const int last = first + R - 1;
+  for (int P = first >> 1; P <= last >> 1; ++P) {
+    double za[4], zo[4];
+    normals4_f64(k0, k1, (uint32_t)blk, (uint32_t)(2 * P), event, 0u, za);
+    normals4_f64(k0, k1, (uint32_t)blk, (uint32_t)(2 * P + 1), event, 0u, zo);
+    const bool even = 2 * P >= first, odd = 2 * P + 1 <= last;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) acc[w] += z[w];
+    for (int w = 0; w < 4; ++w) {
+      if (even) { ar[w] += za[w]; ai[w] += zo[w]; }
+      if (odd) { ar[w] += zo[w]; ai[w] -= za[w]; }
+    }
   }
 #pragma unroll
   for (int w = 0; w < 4; ++w)
-    if (blk * 4 + w < N) eb[blk * 4 + w] = acc[w] / (double)R;
+    if (blk * 4 + w < N) zb[blk * 4 + w] = {ar[w] / (double)R, ai[w] / (double)R};
 }
 
 // xi_bar[i] = mean over r of the stream-1 normal of observation i.
@@ -183,11 +192,11 @@ extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugg
   }
   const int M = c->grid.m1 * c->grid.m2;
   const size_t N = (size_t)c->t1 * c->t2;
-  // vectors: eps_bar N | ybar M | dybar M | xi_bar n | t 4n | p n | dp n | z n | X 2n | Y 2n | q n | dots
-  const size_t nv = N + 2 * (size_t)M + 14 * (size_t)n + kDots;
+  // vectors: zeta_bar 2N | ybar M | dybar M | xi_bar n | t 4n | p n | dp n | z n | X 2n | Y 2n | q n | dots
+  const size_t nv = 2 * N + 2 * (size_t)M + 14 * (size_t)n + kDots;
   CESIM_TRY(c->gvec.reserve(sizeof(double) * nv));
   double* eb = c->gvec.as<double>();
-  double* yb = eb + N;
+  double* yb = eb + 2 * N;
   double* dyb = yb + M;
   double* xb = dyb + M;
   double* t = xb + n;
@@ -201,11 +210,11 @@ extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugg
   std::vector<double> zh(z, z + n);
   CESIM_HIP(hipMemcpyAsync(zd, zh.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), ev = (uint32_t)c->event_id;
-  k_mean_torus_noise<<<(unsigned)((N / 4 + 1 + 255) / 256), 256, 0, s>>>(k0, k1, ev, first_real,
-                                                                        nreal, N, eb);
+  k_mean_pair_noise<<<(unsigned)((N / 4 + 1 + 255) / 256), 256, 0, s>>>(
+      k0, k1, ev, first_real, nreal, N, reinterpret_cast<double2*>(eb));
   k_mean_obs_noise<<<(n + 255) / 256, 256, 0, s>>>(k0, k1, ev, first_real, nreal, n, xb);
   CESIM_HIP(hipGetLastError());
-  CESIM_TRY(ce_grad_fields_device(c, eb, yb, dyb));
+  CESIM_TRY(ce_grad_fields_device(c, reinterpret_cast<const double2*>(eb), yb, dyb));
   CESIM_TRY(lk_grad_device(c, nugget, yb, dyb, xb, t));
   const double* w = static_cast<const double*>(wgt);
   k_cross_gemv<<<n, 256, 0, s>>>(c->obs_xy.as<double>(), c->gridd, c->covd, w, p, dp);

@@ -56,7 +56,7 @@ constexpr int kSolveBlock = 256;
 
 // Stages timed with HIP events when timing is enabled on a context.
 enum Stage {
-  ST_SETUP_BASE = 0, ST_SETUP_FFT, ST_SETUP_EIG, ST_DRAW_PASS1, ST_DRAW_PASS2, ST_DRAW_PASS3,
+  ST_SETUP_BASE = 0, ST_SETUP_FFT, ST_SETUP_EIG, ST_DRAW_PASS_A, ST_DRAW_PASS_B,
   ST_LK_SETUP, ST_CHOL, ST_SYNTH_RHS, ST_SOLVE, ST_COEF_SPLIT, ST_KRIGE_GEMM, ST_PREDICT,
   ST_SE_Q, ST_SE_COV_ROWS, ST_SE_GEMM, ST_SE_REDUCE,
   ST_COUNT
@@ -127,11 +127,11 @@ struct GroupedSeq {
   cesim_status launch(hipStream_t s) const;
 };
 
-// Tile shape of the register-FFT draw passes: rows per workgroup of passes
-// 1 and 3 (0: largest) and log2 of the columns per workgroup of pass 2
-// (-1: largest).  Results do not depend on it.
+// Tile shape of the register-FFT draw passes: log2 of the columns per
+// workgroup of pass A (-1: largest) and the rows per workgroup of pass B
+// (0: largest).  Results do not depend on it.
 struct DrawShape {
-  int rows1 = 0, lcp2 = -1, rows3 = 0;
+  int lcp = -1, rows = 0;
 };
 
 struct TorusTables {
@@ -250,7 +250,10 @@ namespace cesim {
 
 // Kernels launched from the ABI layer (defined in the .hip files).
 cesim_status ce_setup_device(cesim_ctx c, int t1, int t2, bool& accepted);
-cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields);
+// work / work_bytes: pair buffers lent by the caller (nullptr: the
+// context's own, or a batch's).
+cesim_status ce_draw_device(cesim_ctx c, int nreal, uint64_t seed, int first_real, void* fields,
+                            void* work = nullptr, size_t work_bytes = 0);
 cesim_status lk_setup_device(cesim_ctx c);
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields);
 cesim_status lk_phi_device(cesim_ctx c, double tau2);
@@ -260,7 +263,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool cl
 cesim_status box_factor_device(cesim_ctx c, double tau2, hipStream_t s);
 bool joint_active(cesim_ctx c);
 constexpr int kMaxJointBox = 32;   // observations per box of the joint sampling
-cesim_status ce_grad_fields_device(cesim_ctx c, const double* eps_bar, double* yb, double* dyb);
+cesim_status ce_grad_fields_device(cesim_ctx c, const double2* zeta_bar, double* yb, double* dyb);
 cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s);
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
                             const double* xib, double* out);
@@ -287,7 +290,8 @@ bool register_draw_path(cesim_ctx c);
 bool register_draw_torus(int t1, int t2);
 DrawShape draw_shape_limits(cesim_ctx c);   // largest shapes of the register path
 bool tune_has_entries(cesim_ctx c, int R);  // table holds this context's shapes
-int draw_chunk_pairs(cesim_ctx c, int nreal);
+int draw_npairs(cesim_ctx c, int nreal, int first_real);
+int draw_chunk_pairs(cesim_ctx c, int nreal, int first_real);
 cesim_status make_twiddles(int T, DevBuf& tw64, DevBuf& tw32, hipStream_t s);
 
 }  // namespace cesim

@@ -1,14 +1,14 @@
 // tune.hip -- launch-shape autotuning.
 //
-// Tunable: the tile shapes of the three register-FFT draw passes (rows per
-// workgroup of the row passes, columns per workgroup of the column pass)
+// Tunable: the tile shapes of the two register-FFT draw passes (columns per
+// workgroup of the column pass A, rows per workgroup of the row pass B)
 // and the workgroup tile of the mixed grid GEMM.  None of them
 // changes a single bit of any result (each output element sees the same
 // operations in the same order), so tuning affects speed only.  The radix
 // sequence of the transforms is fixed by design and not tuned.
 //
 // Chosen shapes live in a process-wide table keyed by problem shape:
-//   "draw p<precision> <t1>x<t2>"                 -> rows1, log2 cols, rows3
+//   "drawAB p<precision> <t1>x<t2>"               -> log2 cols (A), rows (B), 0
 //   "gemm s<split> nu<code> M<nodes> n<n/512> R<Rp>" -> GEMM tile
 // and can be saved to / loaded from a JSON-lines file.
 #include <hip/hip_runtime.h>
@@ -33,7 +33,7 @@ std::map<std::string, std::array<int, 3>> g_table;
 
 std::string draw_key(cesim_ctx c) {
   char b[64];
-  std::snprintf(b, sizeof(b), "draw p%d %dx%d", (int)c->prec, c->t1, c->t2);
+  std::snprintf(b, sizeof(b), "drawAB p%d %dx%d", (int)c->prec, c->t1, c->t2);
   return b;
 }
 
@@ -71,16 +71,15 @@ void reset_timer(StageTimer& t) {
 
 namespace cesim {
 
-// A narrower pass-2 column tile must beat the widest by this factor.
-constexpr double kPass2Margin = 0.85;
+// A narrower pass-A column tile must beat the widest by this factor.
+constexpr double kPassAMargin = 0.85;
 
 DrawShape draw_shape(cesim_ctx c) {
   DrawShape d = c->draw_force;
   std::array<int, 3> v;
   if (lookup(draw_key(c), v)) {
-    if (d.rows1 == 0) d.rows1 = v[0];
-    if (d.lcp2 < 0) d.lcp2 = v[1];
-    if (d.rows3 == 0) d.rows3 = v[2];
+    if (d.lcp < 0) d.lcp = v[0];
+    if (d.rows == 0) d.rows = v[1];
   }
   return d;
 }
@@ -131,16 +130,13 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
   if (register_draw_path(c)) {
     c->draw_force = DrawShape{};
     const DrawShape mx = draw_shape_limits(c);
-    const int st3[3] = {ST_DRAW_PASS1, ST_DRAW_PASS2, ST_DRAW_PASS3};
-    double best[3] = {1e300, 1e300, 1e300};
-    std::array<int, 3> pick{mx.rows1, mx.lcp2, mx.rows3};
+    const int st3[3] = {ST_DRAW_PASS_A, ST_DRAW_PASS_B, -1};
+    double best[2] = {1e300, 1e300};
+    std::array<int, 3> pick{mx.lcp, mx.rows, 0};
     std::vector<DrawShape> cands;
     for (int i = 0; i < 4; ++i) {
-      const DrawShape d{std::max(1, mx.rows1 >> i), std::max(0, mx.lcp2 - i),
-                        std::max(1, mx.rows3 >> i)};
-      if (!cands.empty() && cands.back().rows1 == d.rows1 && cands.back().lcp2 == d.lcp2 &&
-          cands.back().rows3 == d.rows3)
-        break;
+      const DrawShape d{std::max(0, mx.lcp - i), std::max(1, mx.rows >> i)};
+      if (!cands.empty() && cands.back().lcp == d.lcp && cands.back().rows == d.rows) break;
       cands.push_back(d);
     }
     for (const DrawShape& d : cands) {
@@ -148,14 +144,14 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
       double ms[3];
       st = timed([&] { return ce_draw_device(c, nt, 0, 0, fields); }, ms, st3);
       if (st != CESIM_OK) break;
-      const int v[3] = {d.rows1, d.lcp2, d.rows3};
-      for (int q = 0; q < 3; ++q) {
-        // Pass 2 with the widest column tile holds one workgroup per CU and
+      const int v[2] = {d.lcp, d.rows};
+      for (int q = 0; q < 2; ++q) {
+        // Pass A with the widest column tile holds one workgroup per CU and
         // leaves LDS for the diagonal factorization kernel, which
         // condition() runs beside the draw; narrower tiles fill the LDS with
         // two workgroups and stall that chain.  Timed alone they can be a
         // few per cent faster, so they are taken only when clearly so.
-        const double need = (q == 1 && best[q] < 1e300) ? kPass2Margin * best[q] : best[q];
+        const double need = (q == 0 && best[q] < 1e300) ? kPassAMargin * best[q] : best[q];
         if (ms[q] < need) {
           best[q] = ms[q];
           pick[q] = v[q];
@@ -233,7 +229,7 @@ cesim_status cesim_tune_load(const char* path) {
     char key[128];
     int a, b, c;
     if (std::sscanf(line, " {\"key\": \"%127[^\"]\", \"v\": [%d, %d, %d]}", key, &a, &b, &c) != 4 ||
-        (std::strncmp(key, "draw ", 5) != 0 && std::strncmp(key, "gemm ", 5) != 0)) {
+        (std::strncmp(key, "drawAB ", 7) != 0 && std::strncmp(key, "gemm ", 5) != 0)) {
       st = CESIM_ERR_INVALID_ARG;
       break;
     }

@@ -98,7 +98,7 @@ def test_setup_argument_errors_without_device():
 def test_tuning_table_save_load_round_trip(tmp_path):
     cesim.tune_clear()
     src = tmp_path / "in.jsonl"
-    src.write_text('{"key": "draw p1 2048x2048", "v": [4, 2, 8]}\n'
+    src.write_text('{"key": "drawAB p1 2048x2048", "v": [2, 8, 0]}\n'
                    '{"key": "gemm s0 nu0 M1048576 n10 R1024", "v": [2, 0, 0]}\n')
     cesim.tune_load(str(src))
     assert cesim.tune_entries() == 2
@@ -106,7 +106,7 @@ def test_tuning_table_save_load_round_trip(tmp_path):
     cesim.tune_save(str(out))
     assert sorted(out.read_text().splitlines()) == sorted(src.read_text().splitlines())
     bad = tmp_path / "bad.jsonl"
-    bad.write_text('{"key": "draw p1 64x64", "v": [1, 1, 1]}\nnot json\n')
+    bad.write_text('{"key": "drawAB p1 64x64", "v": [1, 1, 0]}\nnot json\n')
     with pytest.raises(cesim.CesimError) as e:
         cesim.tune_load(str(bad))
     assert e.value.name == "INVALID_ARG"

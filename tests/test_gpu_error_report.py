@@ -55,7 +55,7 @@ def test_error_of_every_intermediate(prec):
     A = kriging.obs_matrix(xy, ocov, wl.tau2)
     zstar = z[None, :] - alpha @ A                          # A symmetric
     err = dict(
-        lam=float(np.max(np.abs(s * t * t - sref)) / sref.max()),
+        lam=float(np.max(np.abs(s * t - sref)) / sref.max()),      # s = sqrt(lambda / t^2)
         w=float(np.max(np.abs(w - ref["W"])) / np.abs(ref["W"]).max()),
         gamma=float(np.max(np.abs(gm - ref["gamma"]))),
         y=rel_rms(y, ref["y"]),

@@ -30,9 +30,7 @@ def sampled_reference(ocov, m, xy, z, tau2, k, reals, t, nodes, seed, event=0, f
     realizations ``reals`` (steps 1-5 of Section 2; Section 2.1 (a)-(d))."""
     g = OGrid.unit_square(m)
     _, _, s, _ = setup(ocov, g, t, t)
-    eps = philox.torus_noise(seed, t, t, reals, event)
-    y = oce.ce_draw(s, eps, m, m)
-    del eps
+    y = oce.ce_draw(s, seed, reals, m, m, event)
     a, b, W, gamma = offgrid_setup(xy, ocov, g, k)
     xi = philox.offgrid_noise(seed, len(xy), reals, event)
     zs = localkrige.synthetic_obs(y, a, b, W, gamma, tau2, xi)

@@ -146,7 +146,7 @@ def test_nn_workload_1024_sampled(prec, tol):
     sur = onn.surrogate(oc, og, xy, z, wl.tau2, wl.k)
     np.testing.assert_array_equal(sxy, sur["xy"])
     _, _, s, _ = setup(oc, og, t, t)
-    y = oce.ce_draw(s, philox.torus_noise(2, t, t, reals), wl.m, wl.m)
+    y = oce.ce_draw(s, 2, reals, wl.m, wl.m)
     xi = philox.offgrid_noise(2, sur["idx"].size, reals)
     zstar = y.reshape(len(reals), -1)[:, sur["idx"]] + np.sqrt(wl.tau2 + sur["sigmaN2"]) * xi
     B = kriging.coefficients(onn.surrogate_factor(oc, sur["xy"], wl.tau2, sur["sigmaN2"]),

@@ -93,8 +93,7 @@ def sampled_reference(wl, xy, z, reals, t, nodes, seed=2):
     ocov = OCov(wl.nu, wl.sigma2, wl.range)
     g = OGrid.unit_square(wl.m)
     _, _, s, _ = setup(ocov, g, t, t)
-    eps = philox.torus_noise(seed, t, t, reals)
-    y = oce.ce_draw(s, eps, wl.m, wl.m)
+    y = oce.ce_draw(s, seed, reals, wl.m, wl.m)
     a, b, W, gamma = offgrid_setup(xy, ocov, g, wl.k)
     xi = philox.offgrid_noise(seed, len(xy), reals)
     zs = localkrige.synthetic_obs(y, a, b, W, gamma, wl.tau2, xi)
