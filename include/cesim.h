@@ -156,6 +156,23 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid,
 cesim_status ce_simulate(cesim_ctx ctx, int nreal, uint64_t seed,
                          int first_real, void* fields_dev);
 
+/* ce_simulate for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same draw, bit for bit, with its pair buffers in a static device array of
+ * 64 MiB instead of memory the context allocates.  The library holds one
+ * such array on every device it runs on, until the process ends; its
+ * address is looked up once per device by ce_setup.  Pairs are processed in
+ * chunks that fit it (the buffer of one pair is 8 t1 m2 bytes on MIXED,
+ * 16 t1 m2 on FP64).  Every call on a device shares that device's array:
+ * calls that overlap on one device (on different streams or contexts) race
+ * and must be ordered by the caller.  The call allocates nothing and calls
+ * no allocating routine; stage timing is off for it.  Arguments, fields_dev
+ * ownership and the record kept for condition() as for ce_simulate.
+ * Errors: INVALID_ARG (as ce_simulate, or one pair's buffer larger than
+ * 64 MiB), BAD_STATE (no array address), HIP. */
+cesim_status ce_simulate_noalloc(cesim_ctx ctx, int nreal, uint64_t seed,
+                                 int first_real, void* fields_dev);
+
 /* Local-Kriging setup (Section 2.1; Section 3.1; Section 3.6).
  * obs_xy_host: nobs (x, y) pairs, host memory, copied.  k = (2 n_p)^2 in
  * {4, 16, 36, 64} and 2 n_p <= min(m1, m2).  Window of s: lower-left node

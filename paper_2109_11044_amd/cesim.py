@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "NEGATIVE_EIGENVALUE",
                 5: "OUT_OF_MEMORY", 6: "HIP", 7: "BAD_STATE"}
 PREC = {"fp64": 0, "mixed": 1}
 
-EXPORTS = ["ce_setup", "ce_simulate", "offgrid_nnkrige", "condition",
+EXPORTS = ["ce_setup", "ce_simulate", "ce_simulate_noalloc", "offgrid_nnkrige", "condition",
            "ce_get_info", "ce_copy_spectrum", "offgrid_copy_weights",
            "condition_copy_coefficients", "cesim_covariance_host",
            "cesim_philox_host", "cesim_status_string", "ce_destroy",
@@ -100,6 +100,7 @@ def lib():
     L.ce_setup.argtypes = [ctypes.POINTER(Cov), ctypes.POINTER(Grid), i, vp,
                            ctypes.POINTER(vp)]
     L.ce_simulate.argtypes = [vp, i, u64, i, vp]
+    L.ce_simulate_noalloc.argtypes = [vp, i, u64, i, vp]
     L.offgrid_nnkrige.argtypes = [vp, i, dp, i]
     L.condition.argtypes = [vp, dp, d, vp]
     L.ce_get_info.argtypes = [vp, ctypes.POINTER(Info)]

@@ -449,7 +449,8 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
                     &c->zdev, &c->chol_info, &c->winv_seq.dev})
     b->stream = c->aux;                 // written by the work condition() puts on aux
   c->timer.enabled = g_default_timing;
-  cesim_status st = c->info_dev.reserve(sizeof(int) * 4);
+  cesim_status st = draw_scratch_address(&c->draw_scratch);
+  if (st == CESIM_OK) st = c->info_dev.reserve(sizeof(int) * 4);
   if (st == CESIM_OK) st = c->chol_info.reserve(sizeof(int) * 4);
   if (st == CESIM_OK && hipMemsetAsync(c->chol_info.p, 0, sizeof(int) * 4, c->stream) != hipSuccess)
     st = CESIM_ERR_HIP;
@@ -489,6 +490,27 @@ cesim_status ce_simulate(cesim_ctx c, int nreal, uint64_t seed, int first_real, 
   if (!c || !fields || nreal < 1 || first_real < 0) return CESIM_ERR_INVALID_ARG;
   if ((long)first_real + nreal > 0x7fffffffL) return CESIM_ERR_INVALID_ARG;
   CESIM_TRY(ce_draw_device(c, nreal, seed, first_real, fields));
+  c->have_fields = true;
+  c->seed = seed;
+  c->first_real = first_real;
+  c->nreal = nreal;
+  return CESIM_OK;
+}
+
+cesim_status ce_simulate_noalloc(cesim_ctx c, int nreal, uint64_t seed, int first_real,
+                                 void* fields) {
+  if (!c || !fields || nreal < 1 || first_real < 0) return CESIM_ERR_INVALID_ARG;
+  if ((long)first_real + nreal > 0x7fffffffL) return CESIM_ERR_INVALID_ARG;
+  if (!c->draw_scratch) return CESIM_ERR_BAD_STATE;
+  if (draw_pair_bytes(c) > kDrawScratchBytes) return CESIM_ERR_INVALID_ARG;   // one pair must fit
+  // same kernels as ce_simulate, pairs in chunks that fit the static array;
+  // the stage timer (which records events) is off for the call
+  const bool timing = c->timer.enabled;
+  c->timer.enabled = false;
+  const cesim_status st =
+      ce_draw_device(c, nreal, seed, first_real, fields, c->draw_scratch, kDrawScratchBytes);
+  c->timer.enabled = timing;
+  CESIM_TRY(st);
   c->have_fields = true;
   c->seed = seed;
   c->first_real = first_real;

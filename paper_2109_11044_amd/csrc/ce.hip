@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "internal.hpp"
 #include "fft_pow2.hpp"
@@ -825,6 +827,30 @@ cesim_status ce_grad_fields_device(cesim_ctx c, const double2* zeta_bar, double*
     k_crop_real<<<nm, 256, 0, s>>>(buf, t1, m1, m2, pass == 0 ? yb : dyb);
     CESIM_HIP(hipGetLastError());
   }
+  return CESIM_OK;
+}
+
+// ------------------------------------------- pair buffers without allocation
+// The pair buffers of ce_simulate_noalloc: one array per device that runs
+// the library, held until the process ends and shared by every such call on
+// that device.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, looked up once per device
+// with that device current (ce_setup) and cached.
+static __device__ __align__(256) unsigned char scratch[kDrawScratchBytes];
+
+cesim_status draw_scratch_address(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;             // per device ordinal
+  int dev = 0;
+  CESIM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    CESIM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
   return CESIM_OK;
 }
 

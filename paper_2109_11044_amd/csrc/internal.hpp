@@ -239,6 +239,9 @@ struct cesim_ctx_s {
   const int* roff = nullptr;
   void* ext_work = nullptr;
   size_t ext_work_bytes = 0;
+  // device address of this device's static pair-buffer array (the draw of
+  // ce_simulate_noalloc), looked up at set-up
+  void* draw_scratch = nullptr;
 
   // last simulate
   bool have_fields = false;
@@ -293,5 +296,9 @@ bool tune_has_entries(cesim_ctx c, int R);  // table holds this context's shapes
 int draw_npairs(cesim_ctx c, int nreal, int first_real);
 int draw_chunk_pairs(cesim_ctx c, int nreal, int first_real);
 cesim_status make_twiddles(int T, DevBuf& tw64, DevBuf& tw32, hipStream_t s);
+// Size of the static pair-buffer array of ce_simulate_noalloc (one per
+// device) and the current device's address of it.
+constexpr size_t kDrawScratchBytes = (size_t)64 << 20;
+cesim_status draw_scratch_address(void** out);
 
 }  // namespace cesim
