@@ -267,7 +267,9 @@ const char* cesim_status_string(cesim_status s);
  *     of two 32-node fragments), 3 = 128 x 512 (8 waves; the correlations of
  *     each observation chunk are computed once for all 512 realizations);
  *     0 (default) takes the tuning table's choice for the problem's shape,
- *     else 1.
+ *     else 1.  Tiles 1 and 2 skip the observation chunks whose correlations
+ *     with their nodes all round to zero in the FP16 split (products that
+ *     are exact zeros), so the fields do not depend on the tile.
  *   CESIM_PARAM_DRAW_COLS, CESIM_PARAM_DRAW_ROWS: torus columns per
  *     workgroup of draw pass A and grid rows per workgroup of pass B on the
  *     register-FFT path (square tori of 2^a from 128 to 8192 and of 3 * 2^a

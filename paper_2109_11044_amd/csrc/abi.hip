@@ -242,7 +242,8 @@ const char* cesim_status_string(cesim_status s) {
 static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
   return {&c->tt.tw1_64, &c->tt.tw2_64, &c->tt.tw1_32, &c->tt.tw2_32, &c->s64,
           &c->s32, &c->slb, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
-          &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->amat, &c->dinv,
+          &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->obs_t32s,
+          &c->gemm_circ, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
           &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
@@ -556,6 +557,9 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   CESIM_TRY(c->gamma.reserve(sizeof(double) * nobs));
   CESIM_TRY(c->phi.reserve(sizeof(double) * nobs));
   CESIM_TRY(c->obs_order.reserve(sizeof(int) * nobs));
+  const int nchunk = (nobs + kGemmChunk - 1) / kGemmChunk;
+  CESIM_TRY(c->obs_t32s.reserve(sizeof(float2) * nobs));
+  CESIM_TRY(c->gemm_circ.reserve(sizeof(float4) * nchunk));
   // transformed coordinates: FP64 path U (s - origin); mixed path kappa U (s - origin)
   const CovDev& d = c->covd;
   const double kappa = d.nu_code == 0 ? kLog2e : (d.nu_code == 2 ? kSqrt3 : kSqrt2);
@@ -606,7 +610,30 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
     t64[i] = {a, b};
     t32[i] = {(float)(kappa * a), (float)(kappa * b)};
   }
+  // the mixed grid GEMM reads the stations in the same Morton order, in
+  // chunks of kGemmChunk: coordinates in that order and the bounding circle
+  // of each chunk (centre of its box, radius to the farthest station)
+  std::vector<float2> t32s(nobs);
+  for (int j = 0; j < nobs; ++j) t32s[j] = t32[order[j]];
+  std::vector<float4> circ(nchunk);
+  for (int q = 0; q < nchunk; ++q) {
+    const int lo = q * kGemmChunk, hi = std::min(nobs, lo + kGemmChunk);
+    float xa = t32s[lo].x, xb = xa, ya = t32s[lo].y, yb = ya;
+    for (int j = lo + 1; j < hi; ++j) {
+      xa = std::min(xa, t32s[j].x); xb = std::max(xb, t32s[j].x);
+      ya = std::min(ya, t32s[j].y); yb = std::max(yb, t32s[j].y);
+    }
+    const float cx = 0.5f * (xa + xb), cy = 0.5f * (ya + yb);
+    float r = 0.f;
+    for (int j = lo; j < hi; ++j)
+      r = std::max(r, std::hypot(t32s[j].x - cx, t32s[j].y - cy));
+    circ[q] = make_float4(cx, cy, r, 0.f);
+  }
   hipStream_t s = c->stream;
+  CESIM_HIP(hipMemcpyAsync(c->obs_t32s.p, t32s.data(), sizeof(float2) * nobs,
+                           hipMemcpyHostToDevice, s));
+  CESIM_HIP(hipMemcpyAsync(c->gemm_circ.p, circ.data(), sizeof(float4) * nchunk,
+                           hipMemcpyHostToDevice, s));
   CESIM_HIP(hipMemcpyAsync(c->obs_xy.p, c->obs_host.data(), sizeof(double) * 2 * nobs,
                            hipMemcpyHostToDevice, s));
   CESIM_HIP(hipMemcpyAsync(c->obs_t64.p, t64.data(), sizeof(double2) * nobs,

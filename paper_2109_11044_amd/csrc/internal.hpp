@@ -54,6 +54,9 @@ struct DevBuf {
 // (winv) the blocked substitutions apply.
 constexpr int kSolveBlock = 256;
 
+// Observations per k-chunk of the mixed grid GEMM.
+constexpr int kGemmChunk = 32;
+
 // Stages timed with HIP events when timing is enabled on a context.
 enum Stage {
   ST_SETUP_BASE = 0, ST_SETUP_FFT, ST_SETUP_EIG, ST_DRAW_PASS_A, ST_DRAW_PASS_B,
@@ -186,6 +189,11 @@ struct cesim_ctx_s {
   cesim::DevBuf obs_t64;            // [n] double2: transformed coordinates (FP64)
   cesim::DevBuf corners, weights, gamma, phi;
   cesim::DevBuf obs_order;          // [n] int: observations in Morton order of their grid cell
+  // the mixed grid GEMM's station order (the same Morton order) and, per
+  // chunk of kGemmChunk stations in it, a bounding circle (centre, radius)
+  // in the GEMM's scaled coordinates
+  cesim::DevBuf obs_t32s;           // [n] float2: transformed coordinates in that order
+  cesim::DevBuf gemm_circ;          // [ceil(n / kGemmChunk)] float4
   // boxes holding several observations (joint sampling, CESIM_PARAM_JOINT_BOXES)
   int joint_boxes = 0;              // switched on by the parameter
   int se_chunk = 0;                 // grid nodes per standard-error chunk (0: auto)

@@ -16,6 +16,8 @@
 //               16 bits); both run at the same matrix-core rate.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace cesim {
@@ -194,18 +196,20 @@ k_predict_f64(float* __restrict__ yhat, int m1, int M, const double* __restrict_
 }
 
 // ----------------------------------------------------------- mixed kernel
-constexpr int kKC = 32;     // observations per k-chunk of the mixed kernel
+constexpr int kKC = kGemmChunk;   // observations per k-chunk of the mixed kernel
 
 // Coefficient split, one workgroup per realization r (r < Rp; rows r >= R
 // are zero): scale_r = max_i |X[r][i]|, v = X[r][i] / scale_r in [-1, 1],
 // hi = half(v), lo = half(v - hi), stored as Bh/Bl[kc][r][32] (observation
-// chunk kc of 32).  colscale[r] = scale_r sigma^2 / KS undoes the scaling in
-// the GEMM epilogue (KS is the factor the correlations are multiplied by
-// before conversion, keeping FP16 values in the normal range).
+// chunk kc of 32, observations in the GEMM's order: position i holds
+// observation order[i]).  colscale[r] = scale_r sigma^2 / KS undoes the
+// scaling in the GEMM epilogue (KS is the factor the correlations are
+// multiplied by before conversion, keeping FP16 values in the normal range).
 template <typename H>
 __global__ void __launch_bounds__(256)
 k_split_coef(const double* __restrict__ X, int n, int R, int Rp, double sigma2, double ks,
-             H* __restrict__ Bh, H* __restrict__ Bl, float* __restrict__ colscale) {
+             const int* __restrict__ order, H* __restrict__ Bh, H* __restrict__ Bl,
+             float* __restrict__ colscale) {
   __shared__ double red[256];
   const int r = blockIdx.x;
   const int npad = (n + kKC - 1) / kKC * kKC;
@@ -221,7 +225,7 @@ k_split_coef(const double* __restrict__ X, int n, int R, int Rp, double sigma2, 
   const double sc = red[0];
   const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
   for (int i = threadIdx.x; i < npad; i += 256) {
-    const double v = (i < n && r < R) ? X[(size_t)r * n + i] * inv : 0.0;
+    const double v = (i < n && r < R) ? X[(size_t)r * n + order[i]] * inv : 0.0;
     const H h = (H)(float)v;
     const H l = (H)(float)(v - (double)(float)h);
     const size_t o = ((size_t)(i / kKC) * Rp + r) * kKC + (i % kKC);
@@ -245,17 +249,51 @@ k_split_coef(const double* __restrict__ X, int n, int R, int Rp, double sigma2, 
 // Layout of v_mfma_f32_32x32x16_bf16: lane l holds A[l % 32][8 (l/32) + j]
 // and B[8 (l/32) + j][l % 32]; accumulator e of lane l is
 // D[8 (e/4) + 4 (l/32) + e % 4][l % 32].
+// One correlation in FP32 (scaled by ks) and its half-precision hi / lo
+// split; every split kernel evaluates correlations through this function.
+template <int NU, typename H>
+__device__ __forceinline__ void corr_split(float gxt, float gyt, float2 s, float ks, H& h, H& l) {
+  const float hx = gxt - s.x, hy = gyt - s.y;
+  const float c = ks * rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+  h = (H)c;
+  l = (H)(c - (float)h);
+}
+
+// Grid coordinates of node g in range units (the map U, scaled per path).
+__device__ __forceinline__ void node_coords(int g, int m1, float dx, float dy, float ux, float uxy,
+                                            float uyx, float uy, float& gxt, float& gyt) {
+  const float gx = (float)(g % m1) * dx, gy = (float)(g / m1) * dy;
+  gxt = ux * gx + uxy * gy;
+  gyt = uyx * gx + uy * gy;
+}
+
+// Bounding circle, in scaled coordinates, of the grid nodes g0 .. g0 + TG - 1
+// (flattened, x fastest): the rectangle of their rows and columns mapped by U.
+__device__ __forceinline__ void tile_circle(int g0, int TG, int M, int m1, float dx, float dy,
+                                            float ux, float uxy, float uyx, float uy, float& cx,
+                                            float& cy, float& rad) {
+  const int ga = g0, gb = min(g0 + TG, M) - 1;
+  const int ja = ga / m1, jb = gb / m1;
+  const int ia = ja == jb ? ga % m1 : 0, ib = ja == jb ? gb % m1 : m1 - 1;
+  const float x = 0.5f * (float)(ia + ib) * dx, y = 0.5f * (float)(ja + jb) * dy;
+  const float hx = 0.5f * (float)(ib - ia) * dx, hy = 0.5f * (float)(jb - ja) * dy;
+  cx = ux * x + uxy * y;
+  cy = uyx * x + uy * y;
+  const float ax = ux * hx + uxy * hy, ay = uyx * hx + uy * hy;   // half-diagonals
+  const float bx = ux * hx - uxy * hy, by = uyx * hx - uy * hy;
+  rad = __builtin_amdgcn_sqrtf(fmaxf(ax * ax + ay * ay, bx * bx + by * by)) * 1.0001f + 1e-3f;
+}
+
 template <int NU, typename H>
 __device__ __forceinline__ void k12_frag(float gxt, float gyt, const float2* __restrict__ sv,
                                          float ks, typename HalfOps<H>::V& ah,
                                          typename HalfOps<H>::V& al) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const float hx = gxt - sv[j].x, hy = gyt - sv[j].y;
-    const float c = ks * rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
-    const H h = (H)c;
+    H h, l;
+    corr_split<NU, H>(gxt, gyt, sv[j], ks, h, l);
     ah[j] = h;
-    al[j] = (H)(c - (float)h);
+    al[j] = l;
   }
 }
 
@@ -273,11 +311,10 @@ __device__ __forceinline__ void k12_step(const float2* sv, bool upper, const flo
     const float2 sj = p[j];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const float hx = gxt[f] - sj.x, hy = gyt[f] - sj.y;
-      const float c = ks * rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
-      const H h = (H)c;
+      H h, l;
+      corr_split<NU, H>(gxt[f], gyt[f], sj, ks, h, l);
       ah[f][j] = h;
-      al[f][j] = (H)(c - (float)h);
+      al[f][j] = l;
     }
   }
 }
@@ -307,16 +344,18 @@ __device__ __forceinline__ void mfma_step(const H* __restrict__ sh, const H* __r
   }
 }
 
-template <int NU, int NF, typename H>
-__global__ void __launch_bounds__(256, 3 - NF)
+template <int NU, int NF, int NB, typename H>
+__global__ void __launch_bounds__(256, NF * NB > 8 ? 1 : 2)
 k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
                const H* __restrict__ Bh, const H* __restrict__ Bl,
                const float* __restrict__ colscale, const float* __restrict__ yhat, int n,
-               const float2* __restrict__ st, float ux, float uxy, float uyx, float uy, float dx,
-               float dy, float kscale, const int* __restrict__ fail) {
+               const float2* __restrict__ st, const float4* __restrict__ circ, float xcut,
+               float ux, float uxy, float uyx, float uy, float dx, float dy, float kscale,
+               const int* __restrict__ fail) {
   if (fail[0] & 2) return;   // failed factorisation: the fields stay as drawn
   using HV = typename HalfOps<H>::V;
-  constexpr int TG = 128 * NF, TR = 256;
+  constexpr int TG = 128 * NF, TR = 32 * NB;
+  constexpr int NQ = TR * kKC / 8 / 256;      // 16-byte pieces per thread and chunk
   __shared__ __align__(16) H Sh[2][TR * kKC];
   __shared__ __align__(16) H Sl[2][TR * kKC];
   __shared__ float2 Ss[2][kKC];
@@ -324,60 +363,69 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float gxt[NF], gyt[NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    const int g = min(g0 + 32 * NF * wave + 32 * f + (lane & 31), M - 1);
-    const float gx = (float)(g % m1) * dx, gy = (float)(g / m1) * dy;
-    gxt[f] = ux * gx + uxy * gy;
-    gyt[f] = uyx * gx + uy * gy;
-  }
+  for (int f = 0; f < NF; ++f)
+    node_coords(min(g0 + 32 * NF * wave + 32 * f + (lane & 31), M - 1), m1, dx, dy, ux, uxy,
+                uyx, uy, gxt[f], gyt[f]);
   const int kb = (lane >> 5) * 8;
-  floatx16 acc[NF][8];
+  floatx16 acc[NF][NB];
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[f][b][e] = 0.0f;
   const int nchunks = (n + kKC - 1) / kKC;
-  u32x4v ph[4], pl[4];
+  u32x4v ph[NQ], pl[NQ];
   float2 ps = {0.f, 0.f};
-#define CESIM_FETCH(KC)                                                                     \
-  {                                                                                         \
-    const u32x4v* gh_ = reinterpret_cast<const u32x4v*>(Bh + ((size_t)(KC) * Rp + r0) * kKC); \
-    const u32x4v* gl_ = reinterpret_cast<const u32x4v*>(Bl + ((size_t)(KC) * Rp + r0) * kKC); \
-    ph[0] = gh_[threadIdx.x];                                                               \
-    ph[1] = gh_[threadIdx.x + 256];                                                         \
-    ph[2] = gh_[threadIdx.x + 512];                                                         \
-    ph[3] = gh_[threadIdx.x + 768];                                                         \
-    pl[0] = gl_[threadIdx.x];                                                               \
-    pl[1] = gl_[threadIdx.x + 256];                                                         \
-    pl[2] = gl_[threadIdx.x + 512];                                                         \
-    pl[3] = gl_[threadIdx.x + 768];                                                         \
-    if (threadIdx.x < kKC) ps = st[min((KC) * kKC + (int)threadIdx.x, n - 1)];              \
-  }
+  auto fetch = [&](int kc) {
+    const u32x4v* gh = reinterpret_cast<const u32x4v*>(Bh + ((size_t)kc * Rp + r0) * kKC);
+    const u32x4v* gl = reinterpret_cast<const u32x4v*>(Bl + ((size_t)kc * Rp + r0) * kKC);
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      ph[u] = gh[threadIdx.x + 256 * u];
+      pl[u] = gl[threadIdx.x + 256 * u];
+    }
+    if (threadIdx.x < kKC) ps = st[min(kc * kKC + (int)threadIdx.x, n - 1)];
+  };
   // LDS rows of 4 x 16 B; the 16-byte column is XOR-swizzled by bits 2-3
   // of the row so that 16 consecutive rows read at one column hit 16
   // distinct bank groups.
-#define CESIM_ST1(U)                                                      \
-  {                                                                       \
-    const int q = threadIdx.x + 256 * (U), row = q >> 2;                  \
-    const int pq = (row << 2) | ((q & 3) ^ ((row >> 2) & 3));             \
-    sh_[pq] = ph[U];                                                      \
-    sl_[pq] = pl[U];                                                      \
+  auto stash = [&](int buf) {
+    u32x4v* sh = reinterpret_cast<u32x4v*>(Sh[buf]);
+    u32x4v* sl = reinterpret_cast<u32x4v*>(Sl[buf]);
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int q = threadIdx.x + 256 * u, row = q >> 2;
+      const int pq = (row << 2) | ((q & 3) ^ ((row >> 2) & 3));
+      sh[pq] = ph[u];
+      sl[pq] = pl[u];
+    }
+    if (threadIdx.x < kKC) Ss[buf][threadIdx.x] = ps;
+  };
+  // Chunks whose every correlation with this tile's nodes rounds to zero in
+  // the half-precision split are skipped: their products would add exact
+  // zeros.  The test (uniform over the workgroup) compares the distance of
+  // the tile's bounding circle to the chunk's with the cut-off distance.
+  float tcx, tcy, trad;
+  tile_circle(g0, TG, M, m1, dx, dy, ux, uxy, uyx, uy, tcx, tcy, trad);
+  auto live = [&](int kc) {
+    const float4 q = circ[kc];
+    const float ddx = tcx - q.x, ddy = tcy - q.y;
+    return __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy) - trad - q.z < xcut;
+  };
+  auto next_live = [&](int kc) {
+    while (kc < nchunks && !live(kc)) ++kc;
+    return kc;
+  };
+  int kc = next_live(0);
+  if (kc < nchunks) {
+    fetch(kc);
+    stash(0);
   }
-#define CESIM_STASH(BUF)                                                  \
-  {                                                                       \
-    u32x4v* sh_ = reinterpret_cast<u32x4v*>(Sh[BUF]);                     \
-    u32x4v* sl_ = reinterpret_cast<u32x4v*>(Sl[BUF]);                     \
-    CESIM_ST1(0) CESIM_ST1(1) CESIM_ST1(2) CESIM_ST1(3)                    \
-    if (threadIdx.x < kKC) Ss[BUF][threadIdx.x] = ps;                     \
-  }
-  CESIM_FETCH(0)
-  CESIM_STASH(0)
   __syncthreads();
-  for (int kc = 0; kc < nchunks; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nchunks) CESIM_FETCH(kc + 1)
+  for (int buf = 0; kc < nchunks; buf ^= 1) {
+    const int kn = next_live(kc + 1);
+    if (kn < nchunks) fetch(kn);
 #pragma unroll
     for (int ks = 0; ks < kKC; ks += 16) {
       float2 sv[8];
@@ -387,7 +435,7 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
 #pragma unroll
       for (int f = 0; f < NF; ++f) k12_frag<NU, H>(gxt[f], gyt[f], sv, kscale, ah[f], al[f]);
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < NB; ++b) {
         const int rr = 32 * b + (lane & 31);
         const int pc = ((ks + kb) >> 3) ^ ((rr >> 2) & 3);
         const HV bh = *reinterpret_cast<const HV*>(&Sh[buf][rr * kKC + 8 * pc]);
@@ -400,19 +448,17 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
         }
       }
     }
-    if (kc + 1 < nchunks) CESIM_STASH(buf ^ 1)
+    if (kn < nchunks) stash(buf ^ 1);
     __syncthreads();
+    kc = kn;
   }
-#undef CESIM_FETCH
-#undef CESIM_STASH
-#undef CESIM_ST1
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     const int gg = g0 + 32 * NF * wave + 32 * f + (lane & 31);
     if (gg >= M) continue;
     const float yh = yhat[gg];
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int r = r0 + 32 * b + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
@@ -448,12 +494,8 @@ k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
   const int nf = wave & 3, q = wave >> 2;
   const bool upper = lane >= 32;
   float gxt[1], gyt[1];
-  {
-    const int g = min(g0 + 32 * nf + (lane & 31), M - 1);
-    const float gx = (float)(g % m1) * dx, gy = (float)(g / m1) * dy;
-    gxt[0] = ux * gx + uxy * gy;
-    gyt[0] = uyx * gx + uy * gy;
-  }
+  node_coords(min(g0 + 32 * nf + (lane & 31), M - 1), m1, dx, dy, ux, uxy, uyx, uy, gxt[0],
+              gyt[0]);
   floatx16 acc[1][8];
 #pragma unroll
   for (int b = 0; b < 8; ++b)
@@ -548,6 +590,25 @@ static void cov_map(const cesim_ctx c, double scale, double& ux, double& uxy, do
   uxy = c->covd.u01 * scale;
   uyx = c->covd.u10 * scale;
   uy = c->covd.u11 * scale;
+}
+
+// Scaled distance beyond which every correlation, multiplied by ks and
+// rounded to FP16 in the split, is zero (with an 8x margin below half the
+// smallest FP16 subnormal, 2^-25), from upper bounds of the correlation in
+// the kernel's scaled distance x: 2^-x (nu = 1/2), (1 + x) e^-x (nu = 3/2),
+// sqrt(pi x / 2) e^-x (1 + 1/(2x)) (nu = 1, from the asymptotic expansion
+// of K_1).  ks = 0 (BF16, whose range keeps every such value): no cut-off.
+static double split_cutoff(int nu_code, double ks) {
+  if (ks <= 0.0) return 1e30;
+  const double lim = std::ldexp(1.0, -28) / ks;
+  auto bound = [&](double x) {
+    if (nu_code == 0) return std::exp2(-x);
+    if (nu_code == 2) return (1.0 + x) * std::exp(-x);
+    return std::sqrt(M_PI * x / 2.0) * std::exp(-x) * (1.0 + 0.5 / x);
+  };
+  double x = 8.0;
+  while (bound(x) >= lim) x += 0.25;
+  return x + 0.5;
 }
 
 // Coefficient buffers for R realizations: [R][n] FP64 and, on the mixed
@@ -678,12 +739,13 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   uint16_t* Hl = Hh + (size_t)npad * Rp;
   float* colscale = reinterpret_cast<float*>(Hl + (size_t)npad * Rp);
   int tr = c->timer.begin(ST_COEF_SPLIT, s);
+  const int* order = c->obs_order.as<int>();
   if (f16)
-    k_split_coef<_Float16><<<Rp, 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, ks,
+    k_split_coef<_Float16><<<Rp, 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, ks, order,
                                               reinterpret_cast<_Float16*>(Hh),
                                               reinterpret_cast<_Float16*>(Hl), colscale);
   else
-    k_split_coef<__bf16><<<Rp, 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, ks,
+    k_split_coef<__bf16><<<Rp, 256, 0, s>>>(X, n, R, Rp, c->covd.sigma2, ks, order,
                                             reinterpret_cast<__bf16*>(Hh),
                                             reinterpret_cast<__bf16*>(Hl), colscale);
   CESIM_HIP(hipGetLastError());
@@ -693,7 +755,9 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   cov_map(c, kappa, ux, uxy, uyx, uy);
   tr = c->timer.begin(ST_KRIGE_GEMM, s);
   float* F = static_cast<float*>(fields);
-  const float2* S2 = c->obs_t32.as<float2>();
+  const float2* S2 = c->obs_t32s.as<float2>();        // the GEMM's station order
+  const float4* CIRC = c->gemm_circ.as<float4>();
+  const float xcut = (float)split_cutoff(c->covd.nu_code, f16 ? ks : 0.0);
   const float* YH = c->yhat.as<float>();
   const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
   const float fdx = (float)dx, fdy = (float)dy, fks = (float)ks;
@@ -701,15 +765,15 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   const int nf = tile == 2 ? 2 : 1;
   dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
   const dim3 gridx((M + 127) / 128, Rp / 512);
-#define CESIM_KS(NU, NF, H)                                                                     \
-  k_krige_split3<NU, NF, H><<<grid, 256, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh), \
-                                                 reinterpret_cast<const H*>(Hl), colscale, YH, n, \
-                                                 S2, a, b, cc, d, fdx, fdy, fks, FAIL)
-#define CESIM_KS_NU(NF, H)                  \
-  switch (c->covd.nu_code) {                \
-    case 0: CESIM_KS(0, NF, H); break;      \
-    case 1: CESIM_KS(1, NF, H); break;      \
-    default: CESIM_KS(2, NF, H); break;     \
+#define CESIM_KS(NU, NF, NB, H)                                                                 \
+  k_krige_split3<NU, NF, NB, H><<<grid, 256, 0, s>>>(                                           \
+      F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh), reinterpret_cast<const H*>(Hl), colscale, \
+      YH, n, S2, CIRC, xcut, a, b, cc, d, fdx, fdy, fks, FAIL)
+#define CESIM_KS_NU(NF, NB, H)                  \
+  switch (c->covd.nu_code) {                    \
+    case 0: CESIM_KS(0, NF, NB, H); break;      \
+    case 1: CESIM_KS(1, NF, NB, H); break;      \
+    default: CESIM_KS(2, NF, NB, H); break;     \
   }
 #define CESIM_KX(NU, H)                                                                         \
   k_krige_split3_x<NU, H><<<gridx, 512, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh),  \
@@ -724,9 +788,9 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   if (tile == 3) {
     if (f16) { CESIM_KX_NU(_Float16) } else { CESIM_KX_NU(__bf16) }
   } else if (f16) {
-    if (nf == 1) { CESIM_KS_NU(1, _Float16) } else { CESIM_KS_NU(2, _Float16) }
+    if (nf == 1) { CESIM_KS_NU(1, 8, _Float16) } else { CESIM_KS_NU(2, 8, _Float16) }
   } else {
-    if (nf == 1) { CESIM_KS_NU(1, __bf16) } else { CESIM_KS_NU(2, __bf16) }
+    if (nf == 1) { CESIM_KS_NU(1, 8, __bf16) } else { CESIM_KS_NU(2, 8, __bf16) }
   }
 #undef CESIM_KX_NU
 #undef CESIM_KX
