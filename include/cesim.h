@@ -277,9 +277,12 @@ const char* cesim_status_string(cesim_status s);
  *     shape; 0 (default) takes the tuning table's choice, else the largest.
  *   CESIM_PARAM_DRAW_CHUNK_PAIRS: realization pairs per launch of the draw
  *     passes (bounds the pair buffer); 0 (default) chooses up to 2 GiB.
- *   CESIM_PARAM_GEMM_SPLIT (changes rounding, not the method): half type of
- *     the three-product split in the mixed GEMM, 0 = FP16 (default, about
- *     22 significant bits per operand) or 1 = BF16 (about 16 bits). */
+ *   CESIM_PARAM_GEMM_SPLIT (changes rounding, not the method): arithmetic
+ *     of the mixed path's cross-covariance product, 0 = FP16 three-product
+ *     split (default, about 22 significant bits per operand), 1 = BF16
+ *     three-product split (about 16 bits), 2 = plain FP32 on matrix cores
+ *     (24 bits, no split; the comparison variant, 3x the issued time of the
+ *     split at the FP32 matrix rate). */
 #define CESIM_PARAM_GEMM_TILE 1
 #define CESIM_PARAM_DRAW_CHUNK_PAIRS 2
 #define CESIM_PARAM_GEMM_SPLIT 3

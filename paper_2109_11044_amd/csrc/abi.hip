@@ -245,7 +245,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->obs_t32s,
           &c->gemm_circ, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
-          &c->chat, &c->chat_tmp, &c->yhat, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
+          &c->chat, &c->chat_tmp, &c->yhat, &c->pred_part, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
           &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
           &c->sework, &c->nn_extra, &c->nn_work};
 }
@@ -360,7 +360,7 @@ cesim_status ce_set_param(cesim_ctx c, int param, int value) {
       c->draw_force.lcp = value == 0 ? -1 : __builtin_ctz((unsigned)value);
       return CESIM_OK;
     case CESIM_PARAM_GEMM_SPLIT:
-      if (value != 0 && value != 1) return CESIM_ERR_INVALID_ARG;
+      if (value < 0 || value > 2) return CESIM_ERR_INVALID_ARG;
       c->gemm_split = value;
       return CESIM_OK;
     case CESIM_PARAM_DRAW_CHUNK_PAIRS:
@@ -446,9 +446,11 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
   }
   c->chol_info_host[0] = 0;
   for (DevBuf* b : all_bufs(c)) b->stream = c->stream;
-  for (DevBuf* b : {&c->amat, &c->dinv, &c->winv, &c->wtmp, &c->chat, &c->chat_tmp, &c->yhat,
-                    &c->zdev, &c->chol_info, &c->winv_seq.dev})
+  for (DevBuf* b : {&c->amat, &c->dinv, &c->winv, &c->wtmp, &c->zdev, &c->chol_info,
+                    &c->winv_seq.dev})
     b->stream = c->aux;                 // written by the work condition() puts on aux
+  for (DevBuf* b : {&c->chat, &c->chat_tmp, &c->yhat, &c->pred_part})
+    b->stream = c->look;                // written by the prediction, on the look-ahead stream
   c->timer.enabled = g_default_timing;
   cesim_status st = draw_scratch_address(&c->draw_scratch);
   if (st == CESIM_OK) st = c->info_dev.reserve(sizeof(int) * 4);

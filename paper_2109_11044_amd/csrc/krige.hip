@@ -152,47 +152,112 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
 // (a few 1e-6, from the rounded lag) times a correlation below 1e-4 stays far
 // below the FP64 terms' rounding in the cancelling sum; they are summed per
 // chunk of 256 stations in FP32 and the chunk sums in FP64.
+//
+// Workgroup (x, y, z) takes a tile of 32 x 32 grid nodes and the z-th
+// slice of `slice` stations in the GEMM's Morton order (position p holds
+// station order[p]), staged through LDS kPredStage at a time, and writes
+// its FP64 partial sum to part[z][g]; k_predict_sum adds the slices in
+// order.  Stations come in chunks of kGemmChunk with bounding circles: a
+// chunk whose circle is farther than kNear range units from the tile's for
+// certain takes the FP32 branch for every pair, as the per-pair test would,
+// with no test and no divergence.  The solves run beside the prediction as
+// chains of small kernels; large workgroups (50 KB of LDS, 16 waves) hold at
+// most two per CU, so that the solves' workgroups are not queued behind
+// many small ones.
+constexpr int kPredThreads = 1024;
+constexpr int kPredStage = 1280;
 template <int NU>
-__global__ void __launch_bounds__(256)
-k_predict_f64(float* __restrict__ yhat, int m1, int M, const double* __restrict__ chat, int n,
-              const double2* __restrict__ st, double ux, double uxy, double uyx, double uy,
-              double dx, double dy, double sigma2) {
+__global__ void __launch_bounds__(kPredThreads)
+k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice,
+              const double* __restrict__ chat, const double2* __restrict__ st,
+              const int* __restrict__ order, const float4* __restrict__ circ, double ux,
+              double uxy, double uyx, double uy, double dx, double dy) {
   constexpr double kNear = NU == 0 ? 9.5 : (NU == 1 ? 8.0 : 7.0);
   constexpr double kKappa = NU == 0 ? kLog2e : (NU == 1 ? kSqrt2 : kSqrt3);
   constexpr float kNearS2 = (float)(kNear * kKappa * kNear * kKappa);
-  __shared__ double2 S[256];
-  __shared__ float2 S32[256];
-  __shared__ double Cv[256];
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  const int gg = min(g, M - 1);
-  const double gx = (double)(gg % m1) * dx, gy = (double)(gg / m1) * dy;
+  // far for certain: the lower bound of the scaled lag clears kNear kappa
+  // with room for the rounding of the FP32 coordinates and circles
+  constexpr float kFarBound = (float)(kNear * kKappa) * 1.0001f + 1e-2f;
+  __shared__ double2 S[kPredStage];
+  __shared__ float4 P[kPredStage];   // kappa-scaled FP32 coordinates, chat in FP32
+  __shared__ double Cv[kPredStage];
+  const int ix = blockIdx.x * 32 + (threadIdx.x & 31), iy = blockIdx.y * 32 + (threadIdx.x >> 5);
+  const double gx = (double)min(ix, m1 - 1) * dx, gy = (double)min(iy, m2 - 1) * dy;
   const double a = ux * gx + uxy * gy, b = uyx * gx + uy * gy;
   const float a32 = (float)(kKappa * a), b32 = (float)(kKappa * b);
-  double acc = 0.0;
-  for (int i0 = 0; i0 < n; i0 += 256) {
-    const int i = i0 + threadIdx.x;
-    __syncthreads();
-    const double2 sv = st[min(i, n - 1)];
-    S[threadIdx.x] = sv;
-    S32[threadIdx.x] = make_float2((float)(kKappa * sv.x), (float)(kKappa * sv.y));
-    Cv[threadIdx.x] = i < n ? chat[i] : 0.0;
-    __syncthreads();
-    const int cnt = min(256, n - i0);
-    float far = 0.0f;
-#pragma unroll 4
-    for (int j = 0; j < cnt; ++j) {
-      const float hx = a32 - S32[j].x, hy = b32 - S32[j].y;
-      const float xs2 = hx * hx + hy * hy;
-      if (xs2 < kNearS2) {
-        const double ex = a - S[j].x, ey = b - S[j].y;
-        acc = fma(matern_rho(NU, sqrt(ex * ex + ey * ey)), Cv[j], acc);
-      } else {
-        far = fmaf(rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(xs2)), (float)Cv[j], far);
-      }
-    }
-    acc += (double)far;
+  // bounding circle of the tile's nodes in scaled coordinates
+  float tcx, tcy, trad;
+  {
+    const int ia = blockIdx.x * 32, ib = min(ia + 31, m1 - 1);
+    const int ja = blockIdx.y * 32, jb = min(ja + 31, m2 - 1);
+    const double x = 0.5 * (ia + ib) * dx, y = 0.5 * (ja + jb) * dy;
+    const double hx = 0.5 * (ib - ia) * dx, hy = 0.5 * (jb - ja) * dy;
+    tcx = (float)(kKappa * (ux * x + uxy * y));
+    tcy = (float)(kKappa * (uyx * x + uy * y));
+    const double px = ux * hx + uxy * hy, py = uyx * hx + uy * hy;   // half-diagonals
+    const double qx = ux * hx - uxy * hy, qy = uyx * hx - uy * hy;
+    trad = (float)(kKappa * sqrt(fmax(px * px + py * py, qx * qx + qy * qy)));
   }
-  if (g < M) yhat[g] = (float)(sigma2 * acc);
+  double acc = 0.0;
+  const int pb = blockIdx.z * slice, pe = min(n, pb + slice);
+  for (int p0 = pb; p0 < pe; p0 += kPredStage) {
+    const int cnt = min(kPredStage, pe - p0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += kPredThreads) {
+      const int idx = order[p0 + t];
+      const double2 sv = st[idx];
+      const double cv = chat[idx];
+      S[t] = sv;
+      Cv[t] = cv;
+      P[t] = make_float4((float)(kKappa * sv.x), (float)(kKappa * sv.y), (float)cv, 0.f);
+    }
+    __syncthreads();
+    for (int b0 = 0; b0 < cnt; b0 += 256) {     // FP32 sums of far pairs per 256 stations
+      float far = 0.0f;
+      const int be = min(cnt, b0 + 256);
+      for (int j0 = b0; j0 < be; j0 += kGemmChunk) {
+        const float4 q = circ[(p0 + j0) / kGemmChunk];
+        const float ddx = tcx - q.x, ddy = tcy - q.y;
+        const bool all_far =
+            __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy) - trad - q.z > kFarBound;
+        const int je = min(be, j0 + kGemmChunk);
+        if (all_far) {
+#pragma unroll 4
+          for (int j = j0; j < je; ++j) {
+            const float4 pj = P[j];
+            const float hx = a32 - pj.x, hy = b32 - pj.y;
+            far = fmaf(rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy)), pj.z, far);
+          }
+        } else {
+#pragma unroll 4
+          for (int j = j0; j < je; ++j) {
+            const float4 pj = P[j];
+            const float hx = a32 - pj.x, hy = b32 - pj.y;
+            const float xs2 = hx * hx + hy * hy;
+            if (xs2 < kNearS2) {
+              const double ex = a - S[j].x, ey = b - S[j].y;
+              acc = fma(matern_rho(NU, sqrt(ex * ex + ey * ey)), Cv[j], acc);
+            } else {
+              far = fmaf(rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(xs2)), pj.z, far);
+            }
+          }
+        }
+      }
+      acc += (double)far;
+    }
+  }
+  if (ix < m1 && iy < m2) part[(size_t)blockIdx.z * m1 * m2 + (size_t)iy * m1 + ix] = acc;
+}
+
+// yhat[g] = sigma^2 (sum of the S slice sums of node g, in slice order), FP32.
+__global__ void __launch_bounds__(256)
+k_predict_sum(float* __restrict__ yhat, const double* __restrict__ part, int M, int S,
+              double sigma2) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= M) return;
+  double acc = 0.0;
+  for (int q = 0; q < S; ++q) acc += part[(size_t)q * M + g];
+  yhat[g] = (float)(sigma2 * acc);
 }
 
 // ----------------------------------------------------------- mixed kernel
@@ -580,6 +645,100 @@ k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
     }
 }
 
+// The FP32 comparison variant of the mixed grid product (no split):
+// coefficients transposed to [observation][Rp] in FP32 (scaled by sigma^2),
+// observations in the original order, rows >= n zero.
+__global__ void __launch_bounds__(256)
+k_coef_f32(const double* __restrict__ X, int n, int R, int Rp, int npad, double sigma2,
+           float* __restrict__ Xf) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)npad * Rp) return;
+  const int i = (int)(e / Rp), r = (int)(e % Rp);
+  Xf[e] = (i < n && r < R) ? (float)(X[(size_t)r * n + i] * sigma2) : 0.0f;
+}
+
+// Grid product in FP32 on matrix cores, v_mfma_f32_32x32x2f32: lane l holds
+// A[l % 32][l / 32] and B[l / 32][l % 32]; the accumulator layout is that of
+// the 32x32x16 kernels.  The product is formed transposed, D[r][g] = sum_i
+// X[r][i] K12[g][i], so the accumulator lanes run over grid nodes.
+// Workgroup: 4 waves, 128 nodes x 256 realizations; wave w owns nodes
+// [32 w, 32 w + 32) and all 8 blocks of 32 realizations.  Per pair of
+// observations a lane evaluates one FP32 correlation (its node, observation
+// l / 32) for 8 matrix instructions.  Coefficient chunks of 32 observations
+// are double-buffered in LDS as [observation][realization].
+template <int NU>
+__global__ void __launch_bounds__(256, 2)
+k_krige_fp32(float* __restrict__ fields, int m1, int M, int R, int Rp,
+             const float* __restrict__ Xf, const float* __restrict__ yhat, int n,
+             const float2* __restrict__ st, float ux, float uxy, float uyx, float uy, float dx,
+             float dy, const int* __restrict__ fail) {
+  if (fail[0] & 2) return;   // failed factorisation: the fields stay as drawn
+  constexpr int TR = 256, KC = 32;
+  __shared__ __align__(16) float Xs[2][KC][TR];
+  __shared__ float2 Ss[2][KC];
+  const int g0 = blockIdx.x * 128, r0 = blockIdx.y * TR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float gxt, gyt;
+  node_coords(min(g0 + 32 * wave + (lane & 31), M - 1), m1, dx, dy, ux, uxy, uyx, uy, gxt, gyt);
+  floatx16 acc[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[b][e] = 0.0f;
+  const int nchunks = (n + KC - 1) / KC;
+  u32x4v pv[8];
+  float2 ps = {0.f, 0.f};
+  // 16-byte piece q = t + 256 u of a chunk: observation q / 64, realizations
+  // 4 (q % 64) .. + 3
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = threadIdx.x + 256 * u;
+      pv[u] = *reinterpret_cast<const u32x4v*>(Xf + (size_t)(kc * KC + (q >> 6)) * Rp + r0 +
+                                               4 * (q & 63));
+    }
+    if (threadIdx.x < KC) ps = st[min(kc * KC + (int)threadIdx.x, n - 1)];
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = threadIdx.x + 256 * u;
+      *reinterpret_cast<u32x4v*>(&Xs[buf][q >> 6][4 * (q & 63)]) = pv[u];
+    }
+    if (threadIdx.x < KC) Ss[buf][threadIdx.x] = ps;
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int kc = 0; kc < nchunks; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nchunks) fetch(kc + 1);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 2) {
+      const int k = kk + (lane >> 5);
+      const float2 s = Ss[buf][k];
+      const float hx = gxt - s.x, hy = gyt - s.y;
+      const float kg = rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(Xs[buf][k][32 * b + (lane & 31)], kg, acc[b],
+                                                      0, 0, 0);
+    }
+    if (kc + 1 < nchunks) stash(buf ^ 1);
+    __syncthreads();
+  }
+  const int gg = g0 + 32 * wave + (lane & 31);
+  if (gg >= M) return;
+  const float yh = yhat[gg];
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = r0 + 32 * b + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      if (r < R) fields[(size_t)r * M + gg] += acc[b][e] + yh;
+    }
+}
+
 // ------------------------------------------------------------------- host
 
 
@@ -641,13 +800,13 @@ cesim_status aux_wait_last_use(cesim_ctx c) {
 // where it does not depend on aux (launches reach the GPU only as fast as
 // a long dependent chain on aux retires them): with joint sampling the box
 // factors on aux, then on the stream the synthetic data, then on aux the
-// factorisation (when the nugget or the stations changed), the solves on the
-// stream after factor_ready, the mixed path's prediction on aux, and the
-// grid GEMM after aux_done.  A new prediction (chat = A^{-1} z by its own
-// one-vector solve, then yhat) follows the factorisation on aux, so that it
-// runs beside the end of the draw and the synthetic data rather than beside
-// the grid GEMM.  Only then do the factorisations' status come back to the
-// host; after a failed pivot the GEMM has left the fields unchanged.
+// factorisation (when the nugget or the stations changed), the mixed path's
+// prediction on the look-ahead stream, the solves on the stream after
+// factor_ready, and the grid GEMM after the prediction and aux_done.  A new
+// prediction (chat = A^{-1} z by its own one-vector solve, then yhat)
+// follows the factorisation and runs beside the solves rather than after
+// them.  Only then do the factorisations' status come back to the host;
+// after a failed pivot the GEMM has left the fields unchanged.
 cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   hipStream_t s = c->stream;
   const int R = c->nreal;
@@ -681,11 +840,18 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     CESIM_HIP(hipEventRecord(c->factor_ready, c->aux));
     CESIM_HIP(hipStreamWaitEvent(s, c->factor_ready, 0));
   }
-  CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
   if (predict) {
-    CESIM_TRY(predict_device(c, c->aux));
-    c->aux_pending = true;
+    // the prediction follows the factor on the look-ahead stream (idle by
+    // then), and is queued before the solves: each launch costs the host
+    // about as long as the GPU takes to run it, so a chain queued after the
+    // solves starts only as they end
+    CESIM_HIP(hipEventRecord(c->la_panel, c->aux));
+    CESIM_HIP(hipStreamWaitEvent(c->look, c->la_panel, 0));
+    CESIM_TRY(predict_device(c, c->look));
+    CESIM_HIP(hipEventRecord(c->la_update, c->look));
   }
+  CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
+  if (predict) CESIM_HIP(hipStreamWaitEvent(s, c->la_update, 0));
   if (c->aux_pending) {
     CESIM_HIP(hipEventRecord(c->aux_done, c->aux));
     CESIM_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
@@ -708,6 +874,39 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
   return CESIM_OK;
 }
 
+// The FP32 comparison variant (CESIM_PARAM_GEMM_SPLIT = 2) of the mixed
+// grid product.
+static cesim_status krige_grid_fp32(cesim_ctx c, const double* X, float* fields) {
+  hipStream_t s = c->stream;
+  const int n = c->nobs, R = c->nreal, m1 = c->grid.m1, M = c->grid.m1 * c->grid.m2;
+  const int Rp = (R + 255) / 256 * 256, npad = (n + 31) / 32 * 32;
+  CESIM_TRY(krige_reserve(c, R));
+  float* Xf = c->coef_b16.as<float>();          // 2 x 2 bytes per entry reserved: fits FP32
+  int tr = c->timer.begin(ST_COEF_SPLIT, s);
+  const size_t tot = (size_t)npad * Rp;
+  k_coef_f32<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(X, n, R, Rp, npad, c->covd.sigma2, Xf);
+  CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
+  const double kappa = c->covd.nu_code == 0 ? kLog2e : (c->covd.nu_code == 2 ? kSqrt3 : kSqrt2);
+  double ux, uxy, uyx, uy;
+  cov_map(c, kappa, ux, uxy, uyx, uy);
+  const dim3 grid((M + 127) / 128, Rp / 256);
+  const float a = (float)ux, b = (float)uxy, cc = (float)uyx, d = (float)uy;
+  const float fdx = (float)c->grid.dx, fdy = (float)c->grid.dy;
+  const float2* S2 = c->obs_t32.as<float2>();   // original order, as Xf
+  const float* YH = c->yhat.as<float>();
+  const int* FAIL = c->chol_info.as<int>();
+  tr = c->timer.begin(ST_KRIGE_GEMM, s);
+  switch (c->covd.nu_code) {
+    case 0: k_krige_fp32<0><<<grid, 256, 0, s>>>(fields, m1, M, R, Rp, Xf, YH, n, S2, a, b, cc, d, fdx, fdy, FAIL); break;
+    case 1: k_krige_fp32<1><<<grid, 256, 0, s>>>(fields, m1, M, R, Rp, Xf, YH, n, S2, a, b, cc, d, fdx, fdy, FAIL); break;
+    default: k_krige_fp32<2><<<grid, 256, 0, s>>>(fields, m1, M, R, Rp, Xf, YH, n, S2, a, b, cc, d, fdx, fdy, FAIL); break;
+  }
+  CESIM_HIP(hipGetLastError());
+  c->timer.end(tr, s);
+  return CESIM_OK;
+}
+
 // fields[r] += K12 X[r] for the c->nreal realizations of the last draw
 // (Section 2, step 5), FP64 or three-product half-precision split.
 cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
@@ -727,6 +926,7 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
     c->timer.end(tr, s);
     return CESIM_OK;
   }
+  if (c->gemm_split == 2) return krige_grid_fp32(c, X, static_cast<float*>(fields));
   const int tile = gemm_tile(c, R);
   const int Rp = tile == 3 ? (R + 511) / 512 * 512 : (R + 255) / 256 * 256;
   const int npad = (n + kKC - 1) / kKC * kKC;
@@ -823,21 +1023,31 @@ cesim_status copy_coefficients_device(cesim_ctx c, double* out) {
 // yhat from c->chat (already A^{-1} z), on stream s.
 static cesim_status predict_from_chat(cesim_ctx c, hipStream_t s) {
   const int n = c->nobs, m1 = c->grid.m1, M = c->grid.m1 * c->grid.m2;
+  // slices of up to one LDS stage (a multiple of 256 stations), at most 16
+  const int nslice = std::min(16, (n + kPredStage - 1) / kPredStage);
+  const int slice = ((n + nslice - 1) / nslice + 255) / 256 * 256;
+  const int S = (n + slice - 1) / slice;
   CESIM_TRY(c->yhat.reserve(sizeof(float) * M));
+  CESIM_TRY(c->pred_part.reserve(sizeof(double) * (size_t)S * M));
   double ux, uxy, uyx, uy;
   cov_map(c, 1.0, ux, uxy, uyx, uy);
   const int tr = c->timer.begin(ST_PREDICT, s);
-  const dim3 grid((M + 255) / 256);
+  const int m2 = c->grid.m2;
+  const dim3 grid((m1 + 31) / 32, (m2 + 31) / 32, S);
+  double* part = c->pred_part.as<double>();
 #define CESIM_PRED(NU)                                                                        \
-  k_predict_f64<NU><<<grid, 256, 0, s>>>(c->yhat.as<float>(), m1, M, c->chat.as<double>(), n, \
-                                         c->obs_t64.as<double2>(), ux, uxy, uyx, uy,          \
-                                         c->grid.dx, c->grid.dy, c->covd.sigma2)
+  k_predict_f64<NU><<<grid, kPredThreads, 0, s>>>(                                            \
+      part, m1, m2, n, slice, c->chat.as<double>(), c->obs_t64.as<double2>(),                 \
+      c->obs_order.as<int>(), c->gemm_circ.as<float4>(), ux, uxy, uyx, uy, c->grid.dx, c->grid.dy)
   switch (c->covd.nu_code) {
     case 0: CESIM_PRED(0); break;
     case 1: CESIM_PRED(1); break;
     default: CESIM_PRED(2); break;
   }
 #undef CESIM_PRED
+  CESIM_HIP(hipGetLastError());
+  k_predict_sum<<<(M + 255) / 256, 256, 0, s>>>(c->yhat.as<float>(), part, M, S,
+                                                c->covd.sigma2);
   CESIM_HIP(hipGetLastError());
   c->timer.end(tr, s);
   c->yhat_valid = true;

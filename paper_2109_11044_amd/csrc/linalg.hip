@@ -34,10 +34,18 @@ __global__ void k_assemble_a(const double* __restrict__ obs, int n, CovDev cov, 
   A[(size_t)i * n + j] = v;
 }
 
+// The factorisation and the substitutions are chains of small dependent
+// kernels that share the CUs with throughput kernels running beside them
+// (the draw, the prediction).  Their waves take the highest issue priority
+// on their SIMD, so that the chain is not slowed by the waves it shares the
+// SIMD with; the throughput kernels fill the cycles it leaves.
+__device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Copies the inverse of each 64 x 64 diagonal factor block kb into its
 // place in the 256 x 256 block inverse W[kb / 4] (zeroed beforehand).
 __global__ void __launch_bounds__(256)
 k_place_diag(const double* __restrict__ D, int n, double* __restrict__ W) {
+  chain_priority();
   const int kb = blockIdx.x, big = kb / 4, i = kb % 4;
   const int sz = min(kNB, n - kb * kNB);
   double* w = W + (size_t)big * kSB * kSB + (size_t)(kNB * i) * kSB + kNB * i;
@@ -124,11 +132,13 @@ __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, i
 __global__ void __launch_bounds__(64)
 k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
              int* __restrict__ info) {
+  chain_priority();
   potrf_diag_body(A, n, k0, nbk, dinv, info);
 }
 
 // One diagonal block of each of several systems: workgroup q takes d[q].
 __global__ void __launch_bounds__(64) k_potrf_diag_grp(const DiagDesc* __restrict__ d) {
+  chain_priority();
   const DiagDesc e = d[blockIdx.x];
   potrf_diag_body(e.A, e.n, e.k0, e.nbk, e.dinv, e.info);
 }
@@ -225,6 +235,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
 
 template <bool LOWER>
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
+  chain_priority();
   gemm_tile<LOWER>(g, blockIdx.y, blockIdx.x);
 }
 
@@ -234,6 +245,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
 template <bool LOWER>
 __global__ void __launch_bounds__(256)
 k_gemm_f64_grp(const GemmArgs* __restrict__ gs, const int* __restrict__ tile0, int ngroups) {
+  chain_priority();
   const int b = blockIdx.x;
   int lo = 0, hi = ngroups - 1;
   while (lo < hi) {
@@ -496,6 +508,7 @@ __device__ __forceinline__ double wave_sum(double a) {
 __global__ void __launch_bounds__(256)
 k_gemv_rows(const double* __restrict__ M, size_t ld, const double* __restrict__ v, int nt,
             double* y, int rows, bool sub, const double* u) {
+  chain_priority();
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (i >= rows) return;                  // whole waves
   const double* row = M + (size_t)i * ld;
@@ -510,6 +523,7 @@ k_gemv_rows(const double* __restrict__ M, size_t ld, const double* __restrict__ 
 __global__ void __launch_bounds__(256)
 k_gemv_cols(const double* __restrict__ M, size_t ld, const double* __restrict__ v, int nt,
             double* __restrict__ y, int cols, bool sub) {
+  chain_priority();
   __shared__ double part[4][64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int i = blockIdx.x * 64 + l;

@@ -156,6 +156,15 @@ STUDY_DISTANCES = (20.0, 45.0, 70.0)
 STUDY_NP = (1, 2, 3, 4)
 
 
+def study_grid(pad=0):
+    """The study grid, optionally widened by ``pad`` grid units on every side
+    (Section 2.1: the grid is extended by at least n_p units so that every
+    observation's window lies inside it); the original 61 x 61 nodes are
+    rows and columns pad .. pad + 60 of the widened grid."""
+    m1, m2, x0, y0, dx, dy = STUDY_GRID
+    return (m1 + 2 * pad, m2 + 2 * pad, x0 - pad * dx, y0 - pad * dy, dx, dy)
+
+
 def _root_five_percent_matern32():
     """t > 0 with (1 + t) exp(-t) = 0.05 (bisection; the left side falls
     monotonically from 1)."""

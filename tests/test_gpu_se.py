@@ -101,6 +101,28 @@ def test_table1_setting():
     assert fr[0] < fr[1] < fr[2]
 
 
+@pytest.mark.parametrize("npp", [2, 3])
+def test_table1_setting_on_the_widened_grid(npp):
+    """The study grid widened by n_p on every side (Section 2.1): both maps
+    equal the oracle's on the widened grid, and the fraction correct to
+    three significant figures on the original 61 x 61 nodes equals the
+    oracle's."""
+    g = cesim.Grid(*workloads.study_grid(npp), 0, 0)
+    cov = (0.5, 1.0, 6.68)
+    xy = np.random.default_rng(9).uniform(0, 60, (35, 2))
+    k = (2 * npp) ** 2
+    se_e, se_l = run(cov, g, xy, k, 0.01)
+    og = ogrid(g)
+    ref_e = acc.se_exact(OCov(*cov), og, xy, 0.01)
+    ref_l = acc.se_local(OCov(*cov), og, xy, 0.01, k)
+    np.testing.assert_allclose(se_e, ref_e, rtol=0, atol=TOL)
+    np.testing.assert_allclose(se_l, ref_l, rtol=0, atol=TOL)
+    rows = np.array([(j + npp) * g.m1 + i + npp for j in range(61) for i in range(61)])
+    f = acc.fraction_sig3(se_l[rows], se_e[rows])
+    f_ref = acc.fraction_sig3(ref_l[rows], ref_e[rows])
+    assert abs(f - f_ref) <= 1.0 / (61 * 61) + 1e-15, (f, f_ref)
+
+
 def test_error_statuses():
     with cesim.Context(cesim.make_cov(0.5, 1.0, 0.2), cesim.unit_square_grid(16)) as ctx:
         with pytest.raises(cesim.CesimError) as e:

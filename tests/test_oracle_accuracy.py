@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import accuracy as acc
+from oracle import localkrige as lk
 from oracle.covariance import Cov
 from oracle.pipeline import Grid, exact_conditional, linear_map
 
@@ -105,3 +106,40 @@ def test_three_significant_figures_against_decimal_formatting():
                                   np.array([0.123, 0.988, 12.3, 0.000124]))
     assert acc.fraction_sig3(np.array([0.5004, 0.5006, 1.2345]),
                              np.array([0.5001, 0.5001, 1.2351])) == pytest.approx(1.0 / 3.0)
+
+
+def test_padded_grid_centres_every_window():
+    """Section 2.1 widens the grid by at least n_p grid units: on the study
+    grid widened by n_p on every side no window is clamped, every one is the
+    2 n_p x 2 n_p block of nodes around its observation's box (brute force),
+    and on the original nodes SE_E is unchanged (it does not involve the
+    grid) while SE_L changes only where clamping moved windows."""
+    from paper_2109_11044_amd import workloads
+    rng = np.random.default_rng(5)
+    xy = rng.uniform(0, 60, (35, 2))
+    xy[0] = (60.0, 60.0)                       # corner of the domain
+    xy[1] = (0.0, 37.5)                        # left edge
+    xy[2] = (59.7, 30.2)                       # one box from the right edge
+    cov = Cov(0.5, 1.0, 15.02)
+    for npp in (1, 2, 3):
+        k = (2 * npp) ** 2
+        gp = Grid(*workloads.study_grid(npp))
+        a, b = lk.window_corners(xy, gp.x0, gp.y0, gp.dx, gp.dy, gp.m1, gp.m2, npp)
+        for i, (x, y) in enumerate(xy):
+            # nodes with |x - node| < n_p per axis, counted from the node at floor(x)
+            bx, by = int(np.floor(x)), int(np.floor(y))
+            assert a[i] == (bx - npp + 1) - int(gp.x0) and b[i] == (by - npp + 1) - int(gp.y0)
+        rows = np.array([(j + npp) * gp.m1 + i + npp for j in range(61) for i in range(61)])
+        g0 = Grid(61, 61, 0.0, 0.0, 1.0, 1.0)
+        e0 = acc.se_exact(cov, g0, xy, 0.01)
+        np.testing.assert_allclose(acc.se_exact(cov, gp, xy, 0.01)[rows], e0, rtol=1e-13)
+        lp = acc.se_local(cov, gp, xy, 0.01, k)[rows]
+        l0 = acc.se_local(cov, g0, xy, 0.01, k)
+        a0, b0 = lk.window_corners(xy, 0.0, 0.0, 1.0, 1.0, 61, 61, npp)
+        moved = np.any(a0 != a - npp) or np.any(b0 != b - npp)
+        # n_p = 1 windows are the box corners, which the 61 x 61 grid holds
+        # (a station exactly on the last grid line sits on a node, where the
+        # moved window gives the same weights); from n_p = 2 the stations
+        # near the edge were clamped before and SE_L changes
+        assert moved
+        assert np.all(lp > 0) and (np.allclose(lp, l0, rtol=1e-12) == (npp == 1))
