@@ -33,12 +33,14 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 template <typename H> struct HalfOps;
 template <> struct HalfOps<__bf16> {
   using V = bf16x8;
+  static constexpr bool kF16 = false;
   static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
 };
 template <> struct HalfOps<_Float16> {
   using V = f16x8;
+  static constexpr bool kF16 = true;
   static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
@@ -316,12 +318,36 @@ k_split_coef(const double* __restrict__ X, int n, int R, int Rp, double sigma2, 
 // D[8 (e/4) + 4 (l/32) + e % 4][l % 32].
 // One correlation in FP32 (scaled by ks) and its half-precision hi / lo
 // split; every split kernel evaluates correlations through this function.
+template <int NU>
+__device__ __forceinline__ float corr_f32(float gxt, float gyt, float2 s) {
+  const float hx = gxt - s.x, hy = gyt - s.y;
+  return rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+}
+
 template <int NU, typename H>
 __device__ __forceinline__ void corr_split(float gxt, float gyt, float2 s, float ks, H& h, H& l) {
-  const float hx = gxt - s.x, hy = gyt - s.y;
-  const float c = ks * rho_scaled_f32(NU, __builtin_amdgcn_sqrtf(hx * hx + hy * hy));
+  const float c = ks * corr_f32<NU>(gxt, gyt, s);
   h = (H)c;
   l = (H)(c - (float)h);
+}
+
+// The FP16 split of two correlations e0, e1 (times ks, a power of two, so
+// that ks e is exact in FP32) into one register of hi halves and one of lo
+// halves: hi = half(ks e) and lo = half(ks e - hi), each by one fused
+// multiply-add rounded once to FP16 into the low or high half -- the values
+// of corr_split, in two instructions per correlation where the compiler's
+// own code (a multiply and a packed conversion for hi, then hi once more to
+// feed lo) takes three and a half.
+__device__ __forceinline__ void split_pair_f16(float ks, float e0, float e1, uint32_t& h,
+                                               uint32_t& l) {
+  asm("v_fma_mixlo_f16 %0, %1, %2, 0\n\t"
+      "v_fma_mixhi_f16 %0, %1, %3, 0"
+      : "=&v"(h)
+      : "v"(ks), "v"(e0), "v"(e1));
+  asm("v_fma_mixlo_f16 %0, %1, %2, -%3 op_sel_hi:[0,0,1]\n\t"
+      "v_fma_mixhi_f16 %0, %1, %4, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+      : "=&v"(l)
+      : "v"(ks), "v"(e0), "v"(h), "v"(e1));
 }
 
 // Grid coordinates of node g in range units (the map U, scaled per path).
@@ -353,12 +379,26 @@ template <int NU, typename H>
 __device__ __forceinline__ void k12_frag(float gxt, float gyt, const float2* __restrict__ sv,
                                          float ks, typename HalfOps<H>::V& ah,
                                          typename HalfOps<H>::V& al) {
+  if constexpr (HalfOps<H>::kF16) {
+    u32x4v hw, lw;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    H h, l;
-    corr_split<NU, H>(gxt, gyt, sv[j], ks, h, l);
-    ah[j] = h;
-    al[j] = l;
+    for (int q = 0; q < 4; ++q) {
+      uint32_t h, l;
+      split_pair_f16(ks, corr_f32<NU>(gxt, gyt, sv[2 * q]), corr_f32<NU>(gxt, gyt, sv[2 * q + 1]),
+                     h, l);
+      hw[q] = h;
+      lw[q] = l;
+    }
+    ah = __builtin_bit_cast(typename HalfOps<H>::V, hw);
+    al = __builtin_bit_cast(typename HalfOps<H>::V, lw);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      H h, l;
+      corr_split<NU, H>(gxt, gyt, sv[j], ks, h, l);
+      ah[j] = h;
+      al[j] = l;
+    }
   }
 }
 
@@ -371,15 +411,36 @@ __device__ __forceinline__ void k12_step(const float2* sv, bool upper, const flo
                                          typename HalfOps<H>::V (&ah)[NF],
                                          typename HalfOps<H>::V (&al)[NF]) {
   const float2* p = sv + (upper ? 8 : 0);
+  if constexpr (HalfOps<H>::kF16) {
+    u32x4v hw[NF], lw[NF];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float2 sj = p[j];
+    for (int q = 0; q < 4; ++q) {
+      const float2 s0 = p[2 * q], s1 = p[2 * q + 1];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        uint32_t h, l;
+        split_pair_f16(ks, corr_f32<NU>(gxt[f], gyt[f], s0), corr_f32<NU>(gxt[f], gyt[f], s1), h,
+                       l);
+        hw[f][q] = h;
+        lw[f][q] = l;
+      }
+    }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      H h, l;
-      corr_split<NU, H>(gxt[f], gyt[f], sj, ks, h, l);
-      ah[f][j] = h;
-      al[f][j] = l;
+      ah[f] = __builtin_bit_cast(typename HalfOps<H>::V, hw[f]);
+      al[f] = __builtin_bit_cast(typename HalfOps<H>::V, lw[f]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float2 sj = p[j];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        H h, l;
+        corr_split<NU, H>(gxt[f], gyt[f], sj, ks, h, l);
+        ah[f][j] = h;
+        al[f][j] = l;
+      }
     }
   }
 }
