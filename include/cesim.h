@@ -265,11 +265,13 @@ const char* cesim_status_string(cesim_status s);
  *   CESIM_PARAM_GEMM_TILE: workgroup tile of the mixed cross-covariance GEMM,
  *     1 = 128 grid nodes x 256 realizations (4 waves), 2 = 256 x 256 (4 waves
  *     of two 32-node fragments), 3 = 128 x 512 (8 waves; the correlations of
- *     each observation chunk are computed once for all 512 realizations);
- *     0 (default) takes the tuning table's choice for the problem's shape,
- *     else 1.  Tiles 1 and 2 skip the observation chunks whose correlations
- *     with their nodes all round to zero in the FP16 split (products that
- *     are exact zeros), so the fields do not depend on the tile.
+ *     each observation chunk are computed once for all 512 realizations),
+ *     4 = 128 x 64 and 5 = 128 x 128 (calls of few realizations: no matrix
+ *     work on padding); 0 (default) takes the tuning table's choice for the
+ *     problem's shape, else 1.  Tiles 1, 2, 4 and 5 skip the observation
+ *     chunks whose correlations with their nodes all round to zero in the
+ *     FP16 split (products that are exact zeros), so the fields do not
+ *     depend on the tile.
  *   CESIM_PARAM_DRAW_COLS, CESIM_PARAM_DRAW_ROWS: torus columns per
  *     workgroup of draw pass A and grid rows per workgroup of pass B on the
  *     register-FFT path (square tori of 2^a from 128 to 8192 and of 3 * 2^a

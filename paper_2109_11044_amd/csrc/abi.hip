@@ -244,7 +244,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->s32, &c->slb, &c->work, &c->scratch, &c->obs_xy, &c->obs_t32, &c->obs_t64,
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->obs_t32s,
           &c->gemm_circ, &c->amat, &c->dinv,
-          &c->winv, &c->wtmp, &c->solve_tmp, &c->zdev, &c->coef, &c->coef_b16,
+          &c->winv, &c->wtmp, &c->solve_tmp, &c->ainv, &c->ainv_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->chat_tmp, &c->yhat, &c->pred_part, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
           &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
           &c->sework, &c->nn_extra, &c->nn_work};
@@ -348,7 +348,7 @@ cesim_status ce_set_param(cesim_ctx c, int param, int value) {
       c->se_chunk = value;
       return CESIM_OK;
     case CESIM_PARAM_GEMM_TILE:
-      if (value < 0 || value > 3) return CESIM_ERR_INVALID_ARG;
+      if (value < 0 || value > 5) return CESIM_ERR_INVALID_ARG;
       c->gemm_tile = value;
       return CESIM_OK;
     case CESIM_PARAM_DRAW_ROWS:

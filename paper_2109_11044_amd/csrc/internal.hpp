@@ -220,6 +220,9 @@ struct cesim_ctx_s {
   cesim::DevBuf winv;               // inverses of the kSolveBlock-wide diagonal blocks
   cesim::DevBuf wtmp;               // products formed while building winv
   cesim::DevBuf solve_tmp;          // [R][n]: second buffer of the substitutions
+  bool ainv_valid = false;          // ainv holds A^{-1} of the current factor
+  cesim::DevBuf ainv;               // n x n FP64 A^{-1} (mixed path, repeated calls)
+  cesim::DevBuf ainv_tmp;           // second buffer while it is formed
   cesim::DevBuf zdev;               // observed values
   cesim::DevBuf coef;               // [R][n] FP64: z - z*, then the coefficients
   cesim::DevBuf coef_b16;           // half-precision hi / lo coefficients + column scales (mixed)
@@ -238,7 +241,7 @@ struct cesim_ctx_s {
   cesim::PinnedStage winv_stage;
   std::vector<double> z_host_cached;
 
-  int gemm_tile = 0;                // mixed grid GEMM tile, 1-3 (0: tuning table, else 1)
+  int gemm_tile = 0;                // mixed grid GEMM tile, 1-5 (0: tuning table, else 1)
   cesim::DrawShape draw_force;      // tile shape set with ce_set_param (wins over the table)
   int gemm_split = 0;               // 0: FP16 x3, 1: BF16 x3
   int draw_chunk_pairs = 0;         // pairs per draw launch (0: by a 2 GiB budget)
@@ -283,6 +286,10 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, dou
                                int stage = ST_SOLVE);
 cesim_status chol_solve_vec_device(cesim_ctx c, const double* b, double* x, hipStream_t s,
                                    double* y, int stage);
+// Largest station count for which a repeated mixed-path call forms A^{-1}.
+constexpr int kInverseMaxObs = 8192;
+cesim_status inverse_device(cesim_ctx c, hipStream_t s);
+cesim_status apply_inverse_device(cesim_ctx c, const double* X, int R, double* Y, hipStream_t s);
 cesim_status aux_wait_last_use(cesim_ctx c);
 cesim_status copy_coefficients_device(cesim_ctx c, double* out);
 cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields);

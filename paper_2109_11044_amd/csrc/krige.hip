@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <utility>
 
 #include "internal.hpp"
 
@@ -911,7 +912,19 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     CESIM_TRY(predict_device(c, c->look));
     CESIM_HIP(hipEventRecord(c->la_update, c->look));
   }
-  CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
+  // A later call on the same factor (mixed path) takes the coefficients
+  // from one GEMM with A^{-1}, formed on the first such call: calls of a few
+  // realizations then skip the substitutions' chain of dependent launches.
+  // The first call after a factorisation runs the substitutions, which need
+  // no extra work.
+  if (mixed && !refactor && c->nobs <= kInverseMaxObs) {
+    if (!c->ainv_valid) CESIM_TRY(inverse_device(c, s));
+    CESIM_TRY(apply_inverse_device(c, X, R, c->solve_tmp.as<double>(), s));
+    std::swap(c->coef, c->solve_tmp);
+    X = c->coef.as<double>();
+  } else {
+    CESIM_TRY(chol_solve_device(c, X, R, s, c->solve_tmp.as<double>()));
+  }
   if (predict) CESIM_HIP(hipStreamWaitEvent(s, c->la_update, 0));
   if (c->aux_pending) {
     CESIM_HIP(hipEventRecord(c->aux_done, c->aux));
@@ -989,7 +1002,9 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   }
   if (c->gemm_split == 2) return krige_grid_fp32(c, X, static_cast<float*>(fields));
   const int tile = gemm_tile(c, R);
-  const int Rp = tile == 3 ? (R + 511) / 512 * 512 : (R + 255) / 256 * 256;
+  // realizations per workgroup tile (tiles 4 and 5: calls of few realizations)
+  const int TRr = tile == 3 ? 512 : (tile == 4 ? 64 : (tile == 5 ? 128 : 256));
+  const int Rp = (R + TRr - 1) / TRr * TRr;
   const int npad = (n + kKC - 1) / kKC * kKC;
   const bool f16 = c->gemm_split == 0;
   // correlations enter FP16 multiplied by 2^12 (values up to 4096), which
@@ -1024,7 +1039,7 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   const float fdx = (float)dx, fdy = (float)dy, fks = (float)ks;
   const int* FAIL = c->chol_info.as<int>();
   const int nf = tile == 2 ? 2 : 1;
-  dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / 256);
+  dim3 grid((M + 128 * nf - 1) / (128 * nf), Rp / TRr);
   const dim3 gridx((M + 127) / 128, Rp / 512);
 #define CESIM_KS(NU, NF, NB, H)                                                                 \
   k_krige_split3<NU, NF, NB, H><<<grid, 256, 0, s>>>(                                           \
@@ -1048,6 +1063,10 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
   }
   if (tile == 3) {
     if (f16) { CESIM_KX_NU(_Float16) } else { CESIM_KX_NU(__bf16) }
+  } else if (tile == 4) {
+    if (f16) { CESIM_KS_NU(1, 2, _Float16) } else { CESIM_KS_NU(1, 2, __bf16) }
+  } else if (tile == 5) {
+    if (f16) { CESIM_KS_NU(1, 4, _Float16) } else { CESIM_KS_NU(1, 4, __bf16) }
   } else if (f16) {
     if (nf == 1) { CESIM_KS_NU(1, 8, _Float16) } else { CESIM_KS_NU(2, 8, _Float16) }
   } else {

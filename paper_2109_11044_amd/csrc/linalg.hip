@@ -335,6 +335,7 @@ static cesim_status build_winv(const std::vector<cesim_ctx>& cs, hipStream_t s,
 // before on s (the box factors of the joint sampling).
 cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool clear_info) {
   c->yhat_valid = false;
+  c->ainv_valid = false;
   const int n = c->nobs;
   const int nblk = (n + kNB - 1) / kNB;
   CESIM_TRY(c->amat.reserve(sizeof(double) * (size_t)n * n));
@@ -486,6 +487,42 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, dou
   std::vector<GemmArgs> steps;
   solve_steps(c, X, Y, R, steps);
   for (const GemmArgs& g : steps) CESIM_TRY(gemm_f64(g, false, s));
+  c->timer.end(tr, s);
+  return CESIM_OK;
+}
+
+// --------------------------------------------------------- explicit inverse
+
+__global__ void __launch_bounds__(256) k_identity(double* __restrict__ X, int n) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < (size_t)n * n) X[q] = (q / n == q % n) ? 1.0 : 0.0;
+}
+
+// A^{-1} of the factored observation matrix into c->ainv (n x n; row r is
+// A^{-1} e_r, and A^{-1} is symmetric), by the blocked substitutions applied
+// to the rows of the identity.
+cesim_status inverse_device(cesim_ctx c, hipStream_t s) {
+  const int n = c->nobs;
+  const size_t nn = (size_t)n * n;
+  CESIM_TRY(c->ainv.reserve(sizeof(double) * nn));
+  CESIM_TRY(c->ainv_tmp.reserve(sizeof(double) * nn));
+  k_identity<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c->ainv.as<double>(), n);
+  CESIM_HIP(hipGetLastError());
+  CESIM_TRY(chol_solve_device(c, c->ainv.as<double>(), n, s, c->ainv_tmp.as<double>()));
+  c->ainv_valid = true;
+  return CESIM_OK;
+}
+
+// Y[r][.] = A^{-1} X[r][.] for r < R as one GEMM with c->ainv.
+cesim_status apply_inverse_device(cesim_ctx c, const double* X, int R, double* Y, hipStream_t s) {
+  const int n = c->nobs;
+  const int tr = c->timer.begin(ST_SOLVE, s);
+  GemmArgs g;
+  g.M = R; g.N = n; g.K = n; g.alpha = 1.0; g.beta = 0.0;
+  g.A = X; g.sai = n; g.sak = 1;
+  g.B = c->ainv.as<double>(); g.sbk = n; g.sbj = 1;
+  g.C = Y; g.sci = n; g.scj = 1;
+  CESIM_TRY(gemm_f64(g, false, s));
   c->timer.end(tr, s);
   return CESIM_OK;
 }
@@ -705,6 +742,7 @@ cesim_status chol_factor_batch(const std::vector<cesim_ctx>& cs, const std::vect
     const int n = c->nobs, nblk = (n + kNB - 1) / kNB;
     maxnb = std::max(maxnb, nblk);
     c->yhat_valid = false;
+    c->ainv_valid = false;
     CESIM_TRY(c->amat.reserve(sizeof(double) * (size_t)n * n));
     CESIM_TRY(c->dinv.reserve(sizeof(double) * (size_t)nblk * kNB * kNB));
     CESIM_HIP(hipMemsetAsync(c->chol_info.p, 0, sizeof(int) * 4, s));

@@ -85,9 +85,9 @@ DrawShape draw_shape(cesim_ctx c) {
 }
 
 int gemm_tile(cesim_ctx c, int R) {
-  if (c->gemm_tile >= 1 && c->gemm_tile <= 3) return c->gemm_tile;
+  if (c->gemm_tile >= 1 && c->gemm_tile <= 5) return c->gemm_tile;
   std::array<int, 3> v;
-  if (lookup(gemm_key(c, R), v) && v[0] >= 1 && v[0] <= 3) return v[0];
+  if (lookup(gemm_key(c, R), v) && v[0] >= 1 && v[0] <= 5) return v[0];
   return 1;
 }
 
@@ -170,8 +170,14 @@ cesim_status ce_autotune(cesim_ctx c, int nreal, void* fields) {
     const int stg[3] = {ST_KRIGE_GEMM, -1, -1};
     double best = 1e300;
     int pick = 1;
-    const int ntiles = nreal > 256 ? 3 : 2;   // the 512-realization tile needs > 256
-    for (int nf = 1; nf <= ntiles && st == CESIM_OK; ++nf) {
+    // candidates: the 256-realization tiles, the 512-realization tile above
+    // 256 realizations, the 64- and 128-realization tiles up to 128
+    std::vector<int> cands = {1, 2};
+    if (nreal > 256) cands.push_back(3);
+    if (nreal <= 128) cands.push_back(5);
+    if (nreal <= 64) cands.push_back(4);
+    for (int nf : cands) {
+      if (st != CESIM_OK) break;
       c->gemm_tile = nf;
       double ms[3];
       st = timed([&] { return krige_grid_device(c, c->coef.as<double>(), fields); }, ms, stg);

@@ -66,4 +66,4 @@ def test_simulate_argument_errors():
         assert L.ce_simulate(ctx._h, 1, 1, -1, ctypes.c_void_p(f.data_ptr())) == 1
         assert L.ce_simulate(ctx._h, 1, 1, 0, None) == 1
         assert L.ce_set_param(ctx._h, 99, 1) == 1
-        assert L.ce_set_param(ctx._h, cesim.PARAM_GEMM_TILE, 4) == 1
+        assert L.ce_set_param(ctx._h, cesim.PARAM_GEMM_TILE, 6) == 1

@@ -46,7 +46,7 @@ def test_gemm_tiles_give_identical_fields(nreal):
     import torch
     cesim.tune_clear()
     _, v1 = run("mixed", 128, 256, [(cesim.PARAM_GEMM_TILE, 1)], nreal=nreal)
-    for tile in (2, 3):
+    for tile in (2, 3, 4, 5):
         _, v = run("mixed", 128, 256, [(cesim.PARAM_GEMM_TILE, tile)], nreal=nreal)
         assert torch.equal(v1, v), tile
 

@@ -104,6 +104,24 @@ def test_anisotropic_matern32_clustered(prec, tol):
     assert np.all(err < tol), err
 
 
+@pytest.mark.parametrize("name", ["C1", "exp512cl"])
+def test_mixed_calls_on_one_factor(name):
+    """Mixed path, three condition() calls of a few realizations on one
+    factor: the first runs the substitutions, the later ones one GEMM with
+    A^{-1} (formed once) and the small-call GEMM tiles; every field within
+    the mixed tolerance of the oracle."""
+    wl = {"C1": workloads.C1,
+          "exp512cl": workloads.Workload("exp512cl", m=192, nu=0.5, sigma2=1.0, range=0.02,
+                                         n=600, locs="clustered", k=36, tau2=0.02, nreal=6)}[name]
+    v, xy, z, t = gpu_run(wl, "mixed", 18, batches=3)
+    ocov = OCov(wl.nu, wl.sigma2, wl.range)
+    ref = conditional_simulation(ocov, OGrid.unit_square(wl.m), xy, z, wl.tau2, wl.k, 2, 18, 0,
+                                 t, t)
+    err = rel_rms(v, ref["v"])
+    print(f"\nrepeated-call error {name}: max {err.max():.3e}", flush=True)
+    assert np.all(err < MIXED_TOL), err
+
+
 def test_repeated_batches_match_one_call():
     """Two condition() calls on consecutive batches reuse the factor and
     equal one call on all realizations (FP64, bitwise-close)."""
