@@ -147,3 +147,30 @@ def test_shakemap_scale_streamed_batches_sampled(prec, tol, shakemap_factor):
     assert t == 4096
     ref = sampled_reference(ocov, wl.m, xy, z, wl.tau2, wl.k, [5, 100], t, nodes, 9, fac=fac)
     assert np.all(rel_rms(np.stack(got), ref) < tol)
+
+
+@pytest.mark.parametrize("split", [0, 1, 2])
+def test_shakemap_scale_split_errors_sampled(split, shakemap_factor):
+    """The ShakeMap-scale configuration's cross-covariance product in each
+    arithmetic of the mixed path (FP16 or BF16 three-product split, plain
+    FP32): realizations 0 and 1 at 2048 sampled nodes against the oracle;
+    the error is printed for the record."""
+    import torch
+    wl = workloads.C5
+    xy, ocov, fac = shakemap_factor
+    z = workloads.iid_values(wl.n, wl.sigma2 + wl.tau2)
+    nodes = np.random.default_rng(10).choice(wl.m * wl.m, 2048, replace=False)
+    with cesim.Context(cesim.make_cov(wl.nu, wl.sigma2, wl.range),
+                       cesim.unit_square_grid(wl.m), "mixed") as ctx:
+        ctx.set_param(cesim.PARAM_GEMM_SPLIT, split)
+        ctx.offgrid(xy, wl.k)
+        f = torch.empty((2, wl.m, wl.m), dtype=torch.float32, device="cuda")
+        ctx.simulate(2, 11, 0, out=f)
+        ctx.condition(z, wl.tau2, f)
+        got = f.view(2, -1)[:, torch.as_tensor(nodes, device="cuda")].cpu().numpy()
+        t = ctx.info()["t1"]
+        del f
+    ref = sampled_reference(ocov, wl.m, xy, z, wl.tau2, wl.k, [0, 1], t, nodes, 11, fac=fac)
+    err = rel_rms(got.astype(np.float64), ref)
+    print(f"\nsplit-error C5 split={split}: max {err.max():.3e}", flush=True)
+    assert np.all(err < MIXED_TOL), err
