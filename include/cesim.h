@@ -203,7 +203,11 @@ cesim_status offgrid_nnkrige(cesim_ctx ctx, int nobs, const double* obs_xy_host,
  * product in the half-precision split GEMM.
  * z_host: nobs observed values, host memory, copied.  nugget >= 0.  The
  * Cholesky factor of K22 + nugget I is kept and reused while the nugget and
- * the observation set are unchanged.  A batch is conditioned once: after a
+ * the observation set are unchanged.  MIXED, on a reused factor of at most
+ * 8192 stations, with at most 128 realizations: B_r comes from one FP64
+ * GEMM with (K22 + nugget I)^{-1}, formed on the first such call and kept
+ * with the factor (n^2 doubles), instead of the blocked substitutions (the
+ * same coefficients up to FP64 rounding).  A batch is conditioned once: after a
  * successful call the next condition() needs a new ce_simulate (the fields
  * are conditional now).  After NOT_POSITIVE_DEFINITE the fields are
  * unchanged and the batch may be conditioned again (e.g. with another

@@ -286,8 +286,10 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, dou
                                int stage = ST_SOLVE);
 cesim_status chol_solve_vec_device(cesim_ctx c, const double* b, double* x, hipStream_t s,
                                    double* y, int stage);
-// Largest station count for which a repeated mixed-path call forms A^{-1}.
+// Repeated mixed-path calls of at most kInverseMaxReal realizations on one
+// factor of at most kInverseMaxObs stations use A^{-1}.
 constexpr int kInverseMaxObs = 8192;
+constexpr int kInverseMaxReal = 128;
 cesim_status inverse_device(cesim_ctx c, hipStream_t s);
 cesim_status apply_inverse_device(cesim_ctx c, const double* X, int R, double* Y, hipStream_t s);
 cesim_status aux_wait_last_use(cesim_ctx c);

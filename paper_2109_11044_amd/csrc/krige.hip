@@ -912,12 +912,13 @@ cesim_status condition_device(cesim_ctx c, double nugget, void* fields) {
     CESIM_TRY(predict_device(c, c->look));
     CESIM_HIP(hipEventRecord(c->la_update, c->look));
   }
-  // A later call on the same factor (mixed path) takes the coefficients
-  // from one GEMM with A^{-1}, formed on the first such call: calls of a few
-  // realizations then skip the substitutions' chain of dependent launches.
-  // The first call after a factorisation runs the substitutions, which need
-  // no extra work.
-  if (mixed && !refactor && c->nobs <= kInverseMaxObs) {
+  // A later call of at most kInverseMaxReal realizations on the same factor
+  // (mixed path) takes the coefficients from one GEMM with A^{-1}, formed on
+  // the first such call: streams of small calls then skip the substitutions'
+  // chain of dependent launches, which costs such a call about as much as
+  // its grid GEMM.  Larger calls and the first call after a factorisation
+  // run the substitutions (forming A^{-1} costs about three chains).
+  if (mixed && !refactor && R <= kInverseMaxReal && c->nobs <= kInverseMaxObs) {
     if (!c->ainv_valid) CESIM_TRY(inverse_device(c, s));
     CESIM_TRY(apply_inverse_device(c, X, R, c->solve_tmp.as<double>(), s));
     std::swap(c->coef, c->solve_tmp);
