@@ -40,7 +40,7 @@
  *     queued; a condition() call that (re)factorises waits for the
  *     factorisation (not for the grid product) to return its status.  The
  *     calls documented below as synchronising (ce_setup, offgrid_nnkrige,
- *     ce_get_info, ce_grad_linear, ce_prediction_se, nn_surrogate, the
+ *     ce_get_info, ce_grad_linear, ce_grad_vjp, ce_prediction_se, nn_surrogate, the
  *     batch and tuning calls, the stage times) wait for their work.  A
  *     context also owns two internal streams (default priority), ordered
  *     with the given stream by events; ce_destroy drains them.
@@ -371,6 +371,23 @@ void cesim_tune_clear(void);
 cesim_status ce_grad_linear(cesim_ctx ctx, const double* z, double nugget, int nreal,
                             uint64_t seed, int first_real, const void* wgt_dev, double* out,
                             double* dz);
+
+/* ---- gradient of any ensemble statistic (vector-Jacobian product) ----
+ * For vbar_dev[r][g] (device, nreal x m1*m2 doubles, [r][m2][m1], x
+ * fastest, caller-owned) the derivatives of a statistic S with respect to
+ * the conditional fields v_r of realizations r = first_real .. first_real
+ * + nreal - 1 (the FP64 path, as for ce_grad_linear), returns
+ *   out[0] = sum_r vbar[r] . v_r,
+ *   out[1..3] = sum_r vbar[r] . dv_r/d(range, sigma2, nugget),
+ *   dz[i] = sum_r vbar[r] . dv_r/dz_i,
+ * i.e. dS/d(range, sigma2, nugget, z) by the chain rule (the adjoint of
+ * steps 1-5 of Section 2 with Section 2.1 and eq. (4)).  Each v_r is affine
+ * in its own noise, so the product is the sum of the one-realization linear
+ * statistics of ce_grad_linear with weights vbar[r]: cost about nreal times
+ * that of one ce_grad_linear call.  Errors and conventions as for
+ * ce_grad_linear.  Synchronises. */
+cesim_status ce_grad_vjp(cesim_ctx ctx, const double* z, double nugget, int nreal, uint64_t seed,
+                         int first_real, const void* vbar_dev, double* out, double* dz);
 
 /* ---- prediction standard errors ----
  * The exact Kriging standard error on the grid (Section 3, eq. (4)),

@@ -204,6 +204,23 @@ def linear_stat_gradient(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, weight
                 zeta_bar=eb, xi_bar=xb)
 
 
+def fields_vjp(cov: Cov, grid, obs_xy, z, tau2, k, seed, vbar, t1, t2, first_real=0, event=0):
+    """The vector-Jacobian product of the conditional fields: for vbar (R, m2,
+    m1), the derivatives of a statistic with respect to v_r of realizations
+    first_real .. first_real + R - 1, returns sum_r vbar[r] . v_r and
+    sum_r vbar[r] . dv_r/d(theta, sigma^2, tau^2, z).  Each v_r is affine in
+    its own noise, so this is the sum over r of the linear statistic of
+    realization r alone (nreal = 1) with weights vbar[r]."""
+    vbar = np.asarray(vbar, dtype=np.float64)
+    tot = dict(L=0.0, d_range=0.0, d_sigma2=0.0, d_tau2=0.0, d_z=0.0)
+    for r in range(vbar.shape[0]):
+        g = linear_stat_gradient(cov, grid, obs_xy, z, tau2, k, seed, 1, vbar[r], t1, t2,
+                                 first_real + r, event)
+        for key in tot:
+            tot[key] = tot[key] + g[key]
+    return tot
+
+
 def ensemble_stat(cov: Cov, grid, obs_xy, z, tau2, k, seed, nreal, weights, t1, t2,
                   first_real=0, event=0):
     """L = (1/R) sum_r sum_g w_g v_r[g] from the full simulation (Section 2)."""

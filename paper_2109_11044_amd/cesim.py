@@ -29,7 +29,7 @@ EXPORTS = ["ce_setup", "ce_simulate", "ce_simulate_noalloc", "offgrid_nnkrige", 
            "cesim_batch_create", "cesim_batch_run", "cesim_batch_get_info",
            "cesim_batch_destroy", "cesim_run_events", "ce_autotune",
            "cesim_tune_save", "cesim_tune_load", "cesim_tune_entries", "cesim_tune_clear",
-           "ce_grad_linear", "ce_prediction_se", "nn_surrogate"]
+           "ce_grad_linear", "ce_grad_vjp", "ce_prediction_se", "nn_surrogate"]
 PARAM_GEMM_TILE = 1
 PARAM_DRAW_CHUNK_PAIRS = 2
 PARAM_GEMM_SPLIT = 3
@@ -139,6 +139,7 @@ def lib():
     L.cesim_tune_clear.argtypes = []
     L.cesim_tune_clear.restype = None
     L.ce_grad_linear.argtypes = [vp, dp, d, i, u64, i, vp, dp, dp]
+    L.ce_grad_vjp.argtypes = [vp, dp, d, i, u64, i, vp, dp, dp]
     L.ce_prediction_se.argtypes = [vp, d, vp, vp]
     L.nn_surrogate.argtypes = [vp, i, dp, dp, d, i, i, dp, dp, ctypes.POINTER(ctypes.c_int)]
     for name in EXPORTS:
@@ -359,6 +360,26 @@ class Context:
         return {"L": float(out[0]), "d_range": float(out[1]), "d_sigma2": float(out[2]),
                 "d_nugget": float(out[3]), "d_z": dz}
 
+    def grad_vjp(self, z, nugget, nreal, seed, vbar, first_real=0):
+        """Vector-Jacobian product of the conditional fields (FP64 path):
+        vbar is the CUDA float64 tensor (nreal, m2, m1) of derivatives of a
+        statistic with respect to the fields of realizations first_real ...;
+        returns {"vbar_dot_v", "d_range", "d_sigma2", "d_nugget", "d_z"}."""
+        t = self._torch
+        z = np.ascontiguousarray(z, dtype=np.float64).ravel()
+        if z.size != self.nobs:
+            raise ValueError("z must hold one value per observation")
+        if (not vbar.is_cuda or vbar.dtype != t.float64 or not vbar.is_contiguous()
+                or vbar.numel() != int(nreal) * self.grid.m1 * self.grid.m2):
+            raise ValueError("vbar must be a contiguous CUDA float64 tensor of nreal x m2 x m1")
+        out = np.zeros(4)
+        dz = np.zeros(self.nobs)
+        _check(lib().ce_grad_vjp(self._h, _dptr(z), float(nugget), int(nreal), int(seed),
+                                 int(first_real), ctypes.c_void_p(vbar.data_ptr()), _dptr(out),
+                                 _dptr(dz)), "ce_grad_vjp")
+        return {"vbar_dot_v": float(out[0]), "d_range": float(out[1]), "d_sigma2": float(out[2]),
+                "d_nugget": float(out[3]), "d_z": dz}
+
     def nn_surrogate(self, obs_xy, z, nugget, k):
         """Nearest-neighbour Kriging: install the surrogate sites of the
         observations as the stations; returns (site_xy, z_site) as numpy
@@ -506,6 +527,65 @@ def _ensemble_linear_stat_function():
             return grad_out * dr, grad_out * ds, grad_out * dn, grad_out * dz, None
 
     return EnsembleLinearStat
+
+
+def _conditional_fields_function():
+    import torch
+
+    def context(range_, sigma2, spec):
+        cov = make_cov(spec["nu"], float(sigma2), float(range_), spec.get("aniso_ratio", 1.0),
+                       spec.get("aniso_angle", 0.0))
+        c = Context(cov, spec["grid"], "fp64")
+        c.set_param(PARAM_EVENT_ID, spec.get("event_id", 0))
+        c.offgrid(spec["obs_xy"], spec["k"])
+        return c
+
+    class ConditionalFields(torch.autograd.Function):
+        """The conditional realizations (FP64 path) as a function of the
+        range, sigma2, the nugget and the observed values; backward is the
+        library's vector-Jacobian product (ce_grad_vjp), so any statistic of
+        the ensemble computed from them with torch is differentiable."""
+
+        @staticmethod
+        def forward(ctx, range_, sigma2, nugget, z, spec):
+            R, g = spec["nreal"], spec["grid"]
+            zh = z.detach().cpu().numpy()
+            with context(range_, sigma2, spec) as c:
+                f = torch.empty((R, g.m2, g.m1), dtype=torch.float64, device="cuda")
+                c.simulate(R, spec["seed"], spec.get("first_real", 0), out=f)
+                c.condition(zh, float(nugget), f)
+            ctx.spec = spec
+            ctx.save_for_backward(range_.detach(), sigma2.detach(), nugget.detach(), z.detach())
+            return f
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            range_, sigma2, nugget, z = ctx.saved_tensors
+            spec = ctx.spec
+            vbar = grad_out.detach().to(torch.float64).contiguous()
+            with context(range_, sigma2, spec) as c:
+                g = c.grad_vjp(z.cpu().numpy(), float(nugget), spec["nreal"], spec["seed"], vbar,
+                               spec.get("first_real", 0))
+            f64 = dict(dtype=torch.float64)
+            return (torch.tensor(g["d_range"], **f64), torch.tensor(g["d_sigma2"], **f64),
+                    torch.tensor(g["d_nugget"], **f64), torch.as_tensor(g["d_z"], **f64), None)
+
+    return ConditionalFields
+
+
+def conditional_fields(range_, sigma2, nugget, z, spec):
+    """Differentiable (torch.autograd) conditional realizations on the FP64
+    path: (nreal, m2, m1) float64 CUDA tensor; see ConditionalFields.
+    range_, sigma2, nugget: 0-d float64 tensors; z: 1-d float64 tensor;
+    spec: nu, grid, obs_xy, k, nreal, seed and optionally aniso_ratio,
+    aniso_angle, event_id, first_real."""
+    global _CF
+    if _CF is None:
+        _CF = _conditional_fields_function()
+    return _CF.apply(range_, sigma2, nugget, z, spec)
+
+
+_CF = None
 
 
 def ensemble_linear_stat(range_, sigma2, nugget, z, spec):

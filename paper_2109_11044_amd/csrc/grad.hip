@@ -18,8 +18,14 @@
 // where t_* are the derivatives of zbar* (local-Kriging kernel k_lk_grad),
 // dybar the draw with d sqrt(lambda)/dtheta, dp = dK21 w and dK22 the
 // theta-derivatives of the cross- and observation covariances.
+//
+// The vector-Jacobian product of the fields themselves (the gradient of any
+// ensemble statistic, given its derivatives vbar[r] with respect to each
+// v_r) is the sum over r of this linear statistic for realization r alone
+// with weights vbar[r].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -163,18 +169,28 @@ __global__ void __launch_bounds__(256) k_dots(DotList d, double* __restrict__ ou
 
 using namespace cesim;
 
-extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugget, int nreal,
-                                       uint64_t seed, int first_real, const void* wgt,
-                                       double* out, double* dz) {
-  if (!c || !z || !wgt || !out || !dz || nreal < 1 || first_real < 0) return CESIM_ERR_INVALID_ARG;
+namespace {
+
+// Arguments shared by the two entry points.
+cesim_status grad_args_ok(cesim_ctx c, const double* z, double nugget, int nreal, int first_real) {
+  if (nreal < 1 || first_real < 0) return CESIM_ERR_INVALID_ARG;
   if ((long)first_real + nreal > 0x7fffffffL) return CESIM_ERR_INVALID_ARG;
   if (!(std::isfinite(nugget) && nugget >= 0.0)) return CESIM_ERR_INVALID_ARG;
   if (c->nobs < 1) return CESIM_ERR_BAD_STATE;
   if (joint_active(c)) return CESIM_ERR_INVALID_ARG;   // the adjoint is of the independent sampling
   if (c->nn_active) return CESIM_ERR_INVALID_ARG;     // and of local Kriging
-  const int n = c->nobs;
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < c->nobs; ++i)
     if (!std::isfinite(z[i])) return CESIM_ERR_INVALID_ARG;
+  return CESIM_OK;
+}
+
+// The linear statistic's value and gradient (out[0..3], dz[n] on the host)
+// for weights w (device, M doubles) over realizations first_real ..
+// first_real + nreal - 1.
+cesim_status grad_linear_core(cesim_ctx c, const double* z, double nugget, int nreal,
+                              uint64_t seed, int first_real, const double* w, double* out,
+                              double* dz) {
+  const int n = c->nobs;
   hipStream_t s = c->stream;
   // the grid GEMM of an earlier condition() may still read the factor (aux
   // work is ordered before it), and the solves below use the stream
@@ -216,7 +232,6 @@ extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugg
   CESIM_HIP(hipGetLastError());
   CESIM_TRY(ce_grad_fields_device(c, reinterpret_cast<const double2*>(eb), yb, dyb));
   CESIM_TRY(lk_grad_device(c, nugget, yb, dyb, xb, t));
-  const double* w = static_cast<const double*>(wgt);
   k_cross_gemv<<<n, 256, 0, s>>>(c->obs_xy.as<double>(), c->gridd, c->covd, w, p, dp);
   k_grad_rhs<<<(n + 255) / 256, 256, 0, s>>>(p, zd, t, n, X);
   CESIM_HIP(hipGetLastError());
@@ -258,5 +273,39 @@ extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugg
   out[1] = h[1] + h[3] - h[9] - h[6];
   out[2] = h[0] / (2.0 * s2) + h[2] / s2 - (ub - nugget * h[5]) / s2 - h[7];
   out[3] = -h[5] - h[8];
+  return CESIM_OK;
+}
+
+}  // namespace
+
+extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugget, int nreal,
+                                       uint64_t seed, int first_real, const void* wgt,
+                                       double* out, double* dz) {
+  if (!c || !z || !wgt || !out || !dz) return CESIM_ERR_INVALID_ARG;
+  CESIM_TRY(grad_args_ok(c, z, nugget, nreal, first_real));
+  return grad_linear_core(c, z, nugget, nreal, seed, first_real, static_cast<const double*>(wgt),
+                          out, dz);
+}
+
+// The vector-Jacobian product of the conditional fields: sum over r of the
+// linear statistic of realization first_real + r alone with the weights
+// vbar[r] (each v_r is affine in its own noise, so the product is the sum of
+// the R one-realization gradients).
+extern "C" cesim_status ce_grad_vjp(cesim_ctx c, const double* z, double nugget, int nreal,
+                                    uint64_t seed, int first_real, const void* vbar, double* out,
+                                    double* dz) {
+  if (!c || !z || !vbar || !out || !dz) return CESIM_ERR_INVALID_ARG;
+  CESIM_TRY(grad_args_ok(c, z, nugget, nreal, first_real));
+  const int n = c->nobs;
+  const size_t M = (size_t)c->grid.m1 * c->grid.m2;
+  std::vector<double> acc(4, 0.0), dacc(n, 0.0), o(4), d(n);
+  for (int r = 0; r < nreal; ++r) {
+    CESIM_TRY(grad_linear_core(c, z, nugget, 1, seed, first_real + r,
+                               static_cast<const double*>(vbar) + r * M, o.data(), d.data()));
+    for (int q = 0; q < 4; ++q) acc[q] += o[q];
+    for (int i = 0; i < n; ++i) dacc[i] += d[i];
+  }
+  std::copy(acc.begin(), acc.end(), out);
+  std::copy(dacc.begin(), dacc.end(), dz);
   return CESIM_OK;
 }

@@ -196,3 +196,72 @@ def test_zero_nugget():
         assert all(np.isfinite(g[a]) for a in ("L", "d_range", "d_sigma2", "d_nugget"))
     with pytest.raises(ValueError):
         ograd.linear_stat_gradient(ocov, OGrid.unit_square(m), xy_node, z, 0.0, k, 5, R, w, t, t)
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_fields_vjp_matches_oracle(case):
+    """ce_grad_vjp with the derivatives of the ensemble variance (a
+    non-linear statistic) taken from the GPU's own FP64 fields, against the
+    oracle's vector-Jacobian product with the same derivatives."""
+    import torch
+    nu, ra, an, m, t, n, k, tau2, R = case
+    th = 0.12
+    ocov = OCov(nu, 1.3, th, ra, an)
+    xy = workloads.locations("clustered", n, seed=31)
+    z = draw_observations(xy, ocov, tau2, seed=0)
+    w = torch.as_tensor(np.random.default_rng(7).standard_normal((m, m)), device="cuda")
+    with cesim.Context(cesim.make_cov(nu, 1.3, th, ra, an), cesim.unit_square_grid(m, t),
+                       "fp64") as ctx:
+        ctx.set_param(cesim.PARAM_EVENT_ID, 3)
+        ctx.offgrid(xy, k)
+        f = ctx.simulate(R, 11, 2)
+        ctx.condition(z, tau2, f)
+        vbar = ((2.0 / R) * w[None] * (f - f.mean(dim=0, keepdim=True))).contiguous()
+        g = ctx.grad_vjp(z, tau2, R, 11, vbar, first_real=2)
+        S = float((w * f.var(dim=0, unbiased=False)).sum())
+    ref = ograd.fields_vjp(ocov, OGrid.unit_square(m), xy, z, tau2, k, 11, vbar.cpu().numpy(), t,
+                           t, first_real=2, event=3)
+    scale = abs(S) + 1e-3
+    close(g["vbar_dot_v"], ref["L"], TOL, scale)
+    close(2.0 * S, ref["L"], TOL, scale)      # vbar . v = 2 S for the variance
+    close(g["d_range"], ref["d_range"], TOL, scale / th)
+    close(g["d_sigma2"], ref["d_sigma2"], TOL, scale)
+    close(g["d_nugget"], ref["d_tau2"], TOL, scale)
+    assert np.max(np.abs(g["d_z"])) < 1e-9 * scale
+
+
+def test_autograd_ensemble_variance():
+    """torch.autograd through cesim.conditional_fields: the gradient of the
+    weighted ensemble variance equals the oracle's vector-Jacobian product
+    and central differences of the statistic from the drawn fields."""
+    import torch
+    m, n, k, tau2, R = 32, 40, 16, 0.05, 6
+    xy = workloads.uniform_locations(n, seed=17)
+    z = draw_observations(xy, OCov(1.0, 1.0, 0.1), tau2, seed=0)
+    w = torch.as_tensor(np.random.default_rng(2).standard_normal((m, m)), device="cuda")
+    spec = dict(nu=1.0, grid=cesim.unit_square_grid(m, 64), obs_xy=xy, k=k, nreal=R, seed=6)
+    f64 = dict(dtype=torch.float64)
+
+    def stat(th, s2, nug, zt):
+        v = cesim.conditional_fields(th, s2, nug, zt, spec)
+        return (w * v.var(dim=0, unbiased=False)).sum()
+
+    th = torch.tensor(0.1, requires_grad=True, **f64)
+    s2 = torch.tensor(1.0, requires_grad=True, **f64)
+    nug = torch.tensor(tau2, requires_grad=True, **f64)
+    zt = torch.tensor(z, requires_grad=True, **f64)
+    S = stat(th, s2, nug, zt)
+    S.backward()
+    h = 1e-6
+    t0 = torch.tensor(0.1, **f64)
+    s0 = torch.tensor(1.0, **f64)
+    n0 = torch.tensor(tau2, **f64)
+    z0 = torch.tensor(z, **f64)
+    with torch.no_grad():
+        fd_th = float(stat(t0 + h, s0, n0, z0) - stat(t0 - h, s0, n0, z0)) / (2 * h)
+        fd_s2 = float(stat(t0, s0 + h, n0, z0) - stat(t0, s0 - h, n0, z0)) / (2 * h)
+        fd_n = float(stat(t0, s0, n0 + h, z0) - stat(t0, s0, n0 - h, z0)) / (2 * h)
+    scale = abs(float(S))
+    for adj, fd in ((th.grad, fd_th), (s2.grad, fd_s2), (nug.grad, fd_n)):
+        assert abs(float(adj) - fd) <= 1e-6 * abs(fd) + 1e-8 * scale, (float(adj), fd)
+    assert float(zt.grad.abs().max()) < 1e-9 * scale

@@ -76,3 +76,59 @@ def test_gradient_matches_central_differences(nu, ratio, angle):
         zp[i] += h
         zm[i] -= h
         close(g["d_z"][i], (L(z=zp) - L(z=zm)) / (2 * h))
+
+
+def nonlinear_stat(cov, grid, obs_xy, z, tau2, k, seed, nreal, weights, t1, t2,
+                   which="variance"):
+    """From the full simulation: S = sum_g w_g Var_r(v_r[g]) (population
+    variance over the ensemble; dS/dv_r = (2/R) w (v_r - mean)), or the
+    second moment S = sum_g w_g mean_r v_r[g]^2 (dS/dv_r = (2/R) w v_r)."""
+    from oracle.pipeline import conditional_simulation
+    v = conditional_simulation(cov, grid, obs_xy, z, tau2, k, seed, nreal, 0, t1, t2)["v"]
+    w = np.asarray(weights).reshape(grid.m2, grid.m1)
+    if which == "variance":
+        mean = v.mean(axis=0)
+        return float(np.sum(w * v.var(axis=0))), (2.0 / nreal) * w[None] * (v - mean[None])
+    return float(np.sum(w * np.mean(v * v, axis=0))), (2.0 / nreal) * w[None] * v
+
+
+@pytest.mark.parametrize("nu,ratio,angle,which", [(0.5, 1.0, 0.0, "variance"),
+                                                  (1.0, 2.0, 0.9, "variance"),
+                                                  (1.5, 1.0, 0.0, "moment2")])
+def test_fields_vjp_gives_nonlinear_statistic_gradients(nu, ratio, angle, which):
+    """The gradient of a non-linear ensemble statistic (the weighted sum of
+    the per-node ensemble variances, or of the second moments) by the
+    fields' vector-Jacobian product against central differences of the
+    statistic from the full simulation."""
+    kw, cov = small_case(nu, ratio, angle)
+    args = {key: kw[key] for key in ("grid", "obs_xy", "z", "tau2", "k", "seed", "nreal",
+                                     "weights", "t1", "t2")}
+    args["which"] = which
+    S0, vbar = nonlinear_stat(cov, **args)
+    kvjp = {key: args[key] for key in ("grid", "obs_xy", "z", "tau2", "k", "seed", "t1", "t2")}
+    g = gradient.fields_vjp(cov, vbar=vbar, **kvjp)
+    h = 1e-6
+
+    def S(cv=cov, **over):
+        a = dict(args)
+        a.update(over)
+        return nonlinear_stat(cv, **a)[0]
+
+    def close(adj, fd):
+        # central differences carry about eps |S| / h of rounding
+        assert abs(adj - fd) <= 1e-6 * abs(fd) + 1e-8 * abs(S0), (adj, fd)
+
+    close(g["d_range"], (S(Cov(nu, 1.0, 0.15 + h, ratio, angle))
+                         - S(Cov(nu, 1.0, 0.15 - h, ratio, angle))) / (2 * h))
+    close(g["d_sigma2"], (S(Cov(nu, 1.0 + h, 0.15, ratio, angle))
+                          - S(Cov(nu, 1.0 - h, 0.15, ratio, angle))) / (2 * h))
+    close(g["d_tau2"], (S(tau2=args["tau2"] + h) - S(tau2=args["tau2"] - h)) / (2 * h))
+    for i in (0, 7):
+        zp, zm = args["z"].copy(), args["z"].copy()
+        zp[i] += h
+        zm[i] -= h
+        close(g["d_z"][i], (S(z=zp) - S(z=zm)) / (2 * h))
+    if which == "variance":
+        # z moves every realization by the same prediction, so the ensemble
+        # variance does not depend on it
+        assert np.max(np.abs(g["d_z"])) < 1e-10 * abs(S0)
