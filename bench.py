@@ -468,6 +468,26 @@ def grad_main(args, torch, cesim, workloads):
     torch.cuda.synchronize()
     ms_fwd = 1000.0 * (time.perf_counter() - t0) / args.steps
     del f
+    # a non-linear statistic: the weighted sum of the per-node ensemble
+    # variances, differentiated through cesim.conditional_fields (forward
+    # draw + condition, backward ce_grad_vjp over the 200 realizations)
+    spec = dict(nu=wl.nu, grid=grid, obs_xy=xy, k=wl.k, nreal=wl.nreal, seed=args.seed)
+
+    def variance_step():
+        f64 = dict(dtype=torch.float64, requires_grad=True)
+        th, s2 = torch.tensor(wl.range, **f64), torch.tensor(wl.sigma2, **f64)
+        nug, zt = torch.tensor(wl.tau2, **f64), torch.tensor(z, **f64)
+        v = cesim.conditional_fields(th, s2, nug, zt, spec)
+        S = (w * v.var(dim=0, unbiased=False)).sum()
+        S.backward()
+        return float(S), float(th.grad), float(s2.grad), float(nug.grad)
+
+    variance_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vs = variance_step()
+    torch.cuda.synchronize()
+    ms_var = 1000.0 * (time.perf_counter() - t0)
     out = {
         "metric": "gradients/sec of a linear ensemble statistic (range, sigma2, nugget, 2000 z)",
         "value": 1000.0 / ms_step, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
@@ -480,6 +500,10 @@ def grad_main(args, torch, cesim, workloads):
                      "d_nugget": g["d_nugget"], "d_z_norm": float(np.linalg.norm(g["d_z"]))},
         "forward_ensemble": {"ms": ms_fwd, "L": Lf,
                              "rel_diff_L": abs(Lf - g["L"]) / max(1.0, abs(Lf))},
+        "variance_gradient": {"ms": ms_var, "S": vs[0], "d_range": vs[1], "d_sigma2": vs[2],
+                              "d_nugget": vs[3],
+                              "note": "S = sum_g w_g Var_r v_r[g] over the 200 realizations; "
+                                      "forward ensemble + backward ce_grad_vjp"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = grad_cpu_baseline()

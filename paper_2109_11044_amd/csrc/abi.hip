@@ -246,7 +246,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->gemm_circ, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->ainv, &c->ainv_tmp, &c->zdev, &c->coef, &c->coef_b16,
           &c->chat, &c->chat_tmp, &c->yhat, &c->pred_part, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
-          &c->gwork, &c->gvec, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
+          &c->gwork, &c->gvec, &c->vjp_work, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
           &c->sework, &c->nn_extra, &c->nn_work};
 }
 

@@ -686,7 +686,8 @@ cesim_status draw_typed(cesim_ctx c, int nreal, uint64_t seed, int first_real, r
                         const real* slb, void* work, size_t work_bytes) {
   hipStream_t s = c->stream;
   const int t1 = c->t1, t2 = c->t2, m1 = c->grid.m1, m2 = c->grid.m2;
-  const size_t pair_bytes = draw_pair_bytes(c);
+  // in this draw's precision (an FP64 draw also runs on a mixed context)
+  const size_t pair_bytes = sizeof(cpx<real>) * (size_t)t1 * m2;
   const int npairs = draw_npairs(c, nreal, first_real);
   int chunk = draw_chunk_pairs(c, nreal, first_real);
   cpx<real>* buf;
@@ -799,6 +800,40 @@ __global__ void k_crop_real(const double2* __restrict__ a, int t1, int m1, int m
   out[e] = a[(size_t)j * t1 + i].x;
 }
 
+// ds = d sqrt(lambda / N) / dtheta ([T2][T1], FP64) from the FFT of the
+// torus base's theta-derivative; tmp: N complex doubles of scratch.
+cesim_status grad_dsqrt_device(cesim_ctx c, double* ds, double2* tmp) {
+  hipStream_t s = c->stream;
+  const int t1 = c->t1, t2 = c->t2;
+  const size_t N = (size_t)t1 * t2;
+  const unsigned nb = (unsigned)((N + 255) / 256);
+  k_torus_base<true><<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy,
+                                                                t1, t2, tmp);
+  CESIM_HIP(hipGetLastError());
+  CESIM_TRY(fft2_forward<double>(tmp, t1, t2, c->tt.p1, c->tt.p2, c->tt.tw1_64.as<double2>(),
+                                 c->tt.tw2_64.as<double2>(), s));
+  k_dsqrt_lambda<<<nb, 256, 0, s>>>(tmp, c->s64.as<double>(), N, 1e-12 * c->lam_max, ds);
+  CESIM_HIP(hipGetLastError());
+  return CESIM_OK;
+}
+
+// The FP64 draw of realizations first_real .. + nreal - 1 (on either
+// context precision) with the spectrum sl ([T2][T1]) in place of
+// sqrt(lambda / N): ds gives the fields' theta-derivatives.  slb: N doubles
+// of scratch for the copy blocked by 8 columns that the register path reads.
+cesim_status draw_f64_spectrum_device(cesim_ctx c, int nreal, uint64_t seed, int first_real,
+                                      double* fields, const double* sl, double* slb) {
+  const int t1 = c->t1, t2 = c->t2;
+  const size_t N = (size_t)t1 * t2;
+  const bool reg = register_draw_torus(t1, t2);
+  if (reg) {
+    k_block_lambda<double><<<(unsigned)((N + 255) / 256), 256, 0, c->stream>>>(sl, t1, t2, slb);
+    CESIM_HIP(hipGetLastError());
+  }
+  return draw_typed<double>(c, nreal, seed, first_real, fields, c->tt.tw1_64.as<double2>(),
+                            c->tt.tw2_64.as<double2>(), sl, reg ? slb : nullptr, nullptr, 0);
+}
+
 // Mean-noise fields of the linear-statistic gradient (FP64, general FFT
 // passes on one buffer): with the complex mean noise zeta_bar,
 // yb = crop(Re FFT2(s zeta_bar)) and dyb = crop(Re FFT2(ds zeta_bar)),
@@ -813,12 +848,7 @@ cesim_status ce_grad_fields_device(cesim_ctx c, const double2* zeta_bar, double*
   const double2* tw1 = c->tt.tw1_64.as<double2>();
   const double2* tw2 = c->tt.tw2_64.as<double2>();
   const unsigned nb = (unsigned)((N + 255) / 256);
-  k_torus_base<true><<<dim3((t1 + 255) / 256, t2), 256, 0, s>>>(c->covd, c->grid.dx, c->grid.dy,
-                                                                t1, t2, buf);
-  CESIM_HIP(hipGetLastError());
-  CESIM_TRY(fft2_forward<double>(buf, t1, t2, c->tt.p1, c->tt.p2, tw1, tw2, s));
-  k_dsqrt_lambda<<<nb, 256, 0, s>>>(buf, c->s64.as<double>(), N, 1e-12 * c->lam_max, ds);
-  CESIM_HIP(hipGetLastError());
+  CESIM_TRY(grad_dsqrt_device(c, ds, buf));
   const unsigned nm = (unsigned)(((size_t)m1 * m2 + 255) / 256);
   for (int pass = 0; pass < 2; ++pass) {
     k_scale_complex<<<nb, 256, 0, s>>>(zeta_bar, pass == 0 ? c->s64.as<double>() : ds, N, buf);

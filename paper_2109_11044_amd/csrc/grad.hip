@@ -164,6 +164,141 @@ __global__ void __launch_bounds__(256) k_dots(DotList d, double* __restrict__ ou
   if (threadIdx.x == 0) out[k] = red[0];
 }
 
+// xi[r][i]: the stream-1 normal of observation i in realization first + r.
+__global__ void k_obs_noise_all(uint32_t k0, uint32_t k1, uint32_t event, int first, int R, int n,
+                                double* __restrict__ xi) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)R * n) return;
+  const int r = (int)(q / n), i = (int)(q % n);
+  double z[4];
+  normals4_f64(k0, k1, (uint32_t)(i >> 2), (uint32_t)(first + r), event, 1u, z);
+  xi[q] = z[i & 3];
+}
+
+// P[r][i] = sum_g C(s_i - g) vbar[r][g] and dP[r][i] = sum_g dC(s_i - g)/dtheta
+// vbar[r][g] for r < R, i < n.  Workgroup (bx, by): stations 16 bx .. + 15,
+// realizations 64 by .. + 63; grid nodes in chunks of 64.  Per chunk the
+// 64 x 16 covariances and derivatives (4 per thread) and the 64 x 64 tile of
+// vbar go to LDS; thread t accumulates station t % 16 for realizations
+// 4 (t / 16) .. + 3, each covariance serving 64 realizations.
+__global__ void __launch_bounds__(256)
+k_cross_adj(const double* __restrict__ obs, int n, GridDev g, CovDev cov,
+            const double* __restrict__ vbar, int R, double* __restrict__ P,
+            double* __restrict__ dP) {
+  __shared__ double Cs[64][17], dCs[64][17];
+  __shared__ double V[64][65];
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * 16, r0 = blockIdx.y * 64;
+  const int M = g.m1 * g.m2;
+  const int il = t & 15, rb = (t >> 4) * 4;
+  double ap[4] = {0.0, 0.0, 0.0, 0.0}, ad[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g0 = 0; g0 < M; g0 += 64) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = t + 256 * u, gl = e >> 4, sl = e & 15;
+      const int gg = g0 + gl, ii = i0 + sl;
+      double cv = 0.0, dv = 0.0;
+      if (gg < M && ii < n) {
+        const int x = gg % g.m1, y = gg / g.m1;
+        const double hx = __dadd_rn(g.x0, __dmul_rn((double)x, g.dx)) - obs[2 * ii];
+        const double hy = __dadd_rn(g.y0, __dmul_rn((double)y, g.dy)) - obs[2 * ii + 1];
+        cov_dcov_eval(cov, hx, hy, cv, dv);
+      }
+      Cs[gl][sl] = cv;
+      dCs[gl][sl] = dv;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u, rl = e >> 6, gl = e & 63;
+      const int rr = r0 + rl, gg = g0 + gl;
+      V[rl][gl] = (rr < R && gg < M) ? vbar[(size_t)rr * M + gg] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int gl = 0; gl < 64; ++gl) {
+      const double cv = Cs[gl][il], dv = dCs[gl][il];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double v = V[rb + q][gl];
+        ap[q] = fma(v, cv, ap[q]);
+        ad[q] = fma(v, dv, ad[q]);
+      }
+    }
+  }
+  const int ii = i0 + il;
+  if (ii >= n) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = r0 + rb + q;
+    if (rr < R) {
+      P[(size_t)rr * n + ii] = ap[q];
+      dP[(size_t)rr * n + ii] = ad[q];
+    }
+  }
+}
+
+// Right-hand sides of the solves: row r = P_r, row R + r = z - zbar*_r
+// (zbar*_{r,i} = T[r][4 i]).
+__global__ void k_vjp_rhs(const double* __restrict__ P, const double* __restrict__ z,
+                          const double* __restrict__ T, int n, int R, double* __restrict__ X) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)R * n) return;
+  const size_t r = q / n, i = q % n;
+  X[q] = P[q];
+  X[(size_t)R * n + q] = z[i] - T[r * 4 * n + 4 * i];
+}
+
+// D[i][j] = dC(s_i - s_j)/dtheta (the theta-derivative of K22).
+__global__ void k_dk22_matrix(const double* __restrict__ obs, int n, CovDev cov,
+                              double* __restrict__ D) {
+  const int j = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+  if (j >= n) return;
+  D[(size_t)i * n + j] = dcov_eval(cov, obs[2 * i] - obs[2 * j], obs[2 * i + 1] - obs[2 * j + 1]);
+}
+
+// The 11 products of the one-realization statistic for every r (one
+// workgroup per product and realization, fixed-order reduction):
+//   0 vbar.y  1 vbar.dy  2 p.cbar  3 dp.cbar  4 u.z  5 u.cbar  6 u.t_theta
+//   7 u.t_sigma  8 u.t_tau  9 u.(dK22 cbar)  10 u.zbar*
+__global__ void __launch_bounds__(256)
+k_vjp_dots(const double* __restrict__ vbar, const double* __restrict__ Y,
+           const double* __restrict__ dY, const double* __restrict__ P,
+           const double* __restrict__ dP, const double* __restrict__ X,
+           const double* __restrict__ z, const double* __restrict__ T,
+           const double* __restrict__ Q, int M, int n, int R, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, r = blockIdx.y;
+  const double* u = X + (size_t)r * n;
+  const double* cb = X + ((size_t)R + r) * n;
+  const double* t = T + (size_t)r * 4 * n;
+  const double* a;
+  const double* b;
+  int sb = 1, len = n;
+  switch (k) {
+    case 0: a = vbar + (size_t)r * M; b = Y + (size_t)r * M; len = M; break;
+    case 1: a = vbar + (size_t)r * M; b = dY + (size_t)r * M; len = M; break;
+    case 2: a = P + (size_t)r * n; b = cb; break;
+    case 3: a = dP + (size_t)r * n; b = cb; break;
+    case 4: a = u; b = z; break;
+    case 5: a = u; b = cb; break;
+    case 6: a = u; b = t + 1; sb = 4; break;
+    case 7: a = u; b = t + 2; sb = 4; break;
+    case 8: a = u; b = t + 3; sb = 4; break;
+    case 9: a = u; b = Q + (size_t)r * n; break;
+    default: a = u; b = t; sb = 4; break;
+  }
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < len; i += 256) acc += a[i] * b[(size_t)i * sb];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(size_t)r * kDots + k] = red[0];
+}
+
 }  // namespace
 }  // namespace cesim
 
@@ -184,6 +319,20 @@ cesim_status grad_args_ok(cesim_ctx c, const double* z, double nugget, int nreal
   return CESIM_OK;
 }
 
+// phi_i = sqrt(tau^2 + gamma_i): with tau^2 = 0 a station with gamma_i = 0
+// (on a grid node, where gamma_i is 0 up to round-off, taken as <= 1e-12
+// sigma^2) has dphi_i / dtau^2 = 1 / (2 phi_i) unbounded, so the nugget
+// derivative does not exist there.  After the streams have drained.
+cesim_status zero_nugget_ok(cesim_ctx c, double nugget) {
+  if (nugget != 0.0) return CESIM_OK;
+  const int n = c->nobs;
+  std::vector<double> gm(n);
+  CESIM_HIP(hipMemcpy(gm.data(), c->gamma.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i)
+    if (!(gm[i] > 1e-12 * c->covd.sigma2)) return CESIM_ERR_INVALID_ARG;
+  return CESIM_OK;
+}
+
 // The linear statistic's value and gradient (out[0..3], dz[n] on the host)
 // for weights w (device, M doubles) over realizations first_real ..
 // first_real + nreal - 1.
@@ -196,16 +345,7 @@ cesim_status grad_linear_core(cesim_ctx c, const double* z, double nugget, int n
   // work is ordered before it), and the solves below use the stream
   CESIM_HIP(hipStreamSynchronize(c->aux));
   CESIM_HIP(hipStreamSynchronize(s));
-  if (nugget == 0.0) {
-    // phi_i = sqrt(tau^2 + gamma_i): with tau^2 = 0 a station with
-    // gamma_i = 0 (on a grid node, where gamma_i is 0 up to round-off,
-    // taken as <= 1e-12 sigma^2) has dphi_i / dtau^2 = 1 / (2 phi_i)
-    // unbounded, so dL/dtau^2 does not exist there
-    std::vector<double> gm(n);
-    CESIM_HIP(hipMemcpy(gm.data(), c->gamma.p, sizeof(double) * n, hipMemcpyDeviceToHost));
-    for (int i = 0; i < n; ++i)
-      if (!(gm[i] > 1e-12 * c->covd.sigma2)) return CESIM_ERR_INVALID_ARG;
-  }
+  CESIM_TRY(zero_nugget_ok(c, nugget));
   const int M = c->grid.m1 * c->grid.m2;
   const size_t N = (size_t)c->t1 * c->t2;
   // vectors: zeta_bar 2N | ybar M | dybar M | xi_bar n | t 4n | p n | dp n | z n | X 2n | Y 2n | q n | dots
@@ -276,6 +416,85 @@ cesim_status grad_linear_core(cesim_ctx c, const double* z, double nugget, int n
   return CESIM_OK;
 }
 
+// Realizations per pass of the vector-Jacobian product (bounds its arrays).
+constexpr int kVjpChunk = 256;
+
+// The vector-Jacobian product for realizations first_real .. + R - 1, all
+// at once: the one-realization statistics of grad_linear_core with weights
+// vbar[r], whose per-realization parts are batched -- the fields y_r and
+// dy_r by two FP64 draws (with sqrt(lambda / N) and with its
+// theta-derivative), the cross products K21 vbar_r and dK21 vbar_r in one
+// kernel, the 2R solves in one chain, dK22 cbar_r as one GEMM.  Adds into
+// acc[0..3] and dacc[n] (host).
+// Y, dY [R][M] | xi [R][n] | T [R][4n] | P, dP [R][n] | X, X2 [2R][n] | Q [R][n] | dots [R][11]:
+// 2 R M + (1 + 4 + 2 + 4 + 1) R n + 11 R doubles.
+size_t vjp_chunk_doubles(cesim_ctx c, int R) {
+  const size_t M = (size_t)c->grid.m1 * c->grid.m2, Rn = (size_t)R * c->nobs;
+  return 2 * (size_t)R * M + 12 * Rn + (size_t)R * kDots;
+}
+
+// work: vjp_chunk_doubles(c, R) doubles; dk22: the n x n theta-derivative
+// of K22; zd: z on the device; ds: d sqrt(lambda / N) / dtheta; slb: N
+// doubles of scratch.
+cesim_status vjp_chunk(cesim_ctx c, const double* zd, double nugget, int R, uint64_t seed,
+                       int first_real, const double* vbar, const double* ds, double* slb,
+                       const double* dk22, double* work, double* acc, double* dacc) {
+  const int n = c->nobs;
+  const size_t M = (size_t)c->grid.m1 * c->grid.m2, Rn = (size_t)R * n;
+  hipStream_t s = c->stream;
+  // Y, dY [R][M] | xi [R][n] | T [R][4n] | P, dP [R][n] | X, X2 [2R][n] | Q [R][n] | dots [R][11]
+  double* Y = work;
+  double* dY = Y + (size_t)R * M;
+  double* xi = dY + (size_t)R * M;
+  double* T = xi + Rn;
+  double* P = T + 4 * Rn;
+  double* dP = P + Rn;
+  double* X = dP + Rn;
+  double* X2 = X + 2 * Rn;
+  double* Q = X2 + 2 * Rn;
+  double* dots = Q + Rn;
+  if ((size_t)(dots + (size_t)R * kDots - work) != vjp_chunk_doubles(c, R))
+    return CESIM_ERR_BAD_STATE;     // the layout above and its size disagree
+  CESIM_TRY(draw_f64_spectrum_device(c, R, seed, first_real, Y, c->s64.as<double>(), slb));
+  CESIM_TRY(draw_f64_spectrum_device(c, R, seed, first_real, dY, ds, slb));
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), ev = (uint32_t)c->event_id;
+  k_obs_noise_all<<<(unsigned)((Rn + 255) / 256), 256, 0, s>>>(k0, k1, ev, first_real, R, n, xi);
+  CESIM_HIP(hipGetLastError());
+  for (int r = 0; r < R; ++r)
+    CESIM_TRY(lk_grad_device(c, nugget, Y + r * M, dY + r * M, xi + (size_t)r * n,
+                             T + (size_t)r * 4 * n));
+  k_cross_adj<<<dim3((n + 15) / 16, (R + 63) / 64), 256, 0, s>>>(
+      c->obs_xy.as<double>(), n, c->gridd, c->covd, vbar, R, P, dP);
+  k_vjp_rhs<<<(unsigned)((Rn + 255) / 256), 256, 0, s>>>(P, zd, T, n, R, X);
+  CESIM_HIP(hipGetLastError());
+  CESIM_TRY(chol_solve_device(c, X, 2 * R, s, X2));        // rows: u_r, then cbar_r
+  {   // Q = Cbar dK22 (rows cbar_r; dK22 is symmetric)
+    GemmArgs g;
+    g.M = R; g.N = n; g.K = n; g.alpha = 1.0; g.beta = 0.0;
+    g.A = X + Rn; g.sai = n; g.sak = 1;
+    g.B = dk22; g.sbk = n; g.sbj = 1;
+    g.C = Q; g.sci = n; g.scj = 1;
+    CESIM_TRY(gemm_f64(g, false, s));
+  }
+  k_vjp_dots<<<dim3(kDots, R), 256, 0, s>>>(vbar, Y, dY, P, dP, X, zd, T, Q, (int)M, n, R, dots);
+  CESIM_HIP(hipGetLastError());
+  std::vector<double> h((size_t)R * kDots), u(Rn);
+  CESIM_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipMemcpyAsync(u.data(), X, sizeof(double) * Rn, hipMemcpyDeviceToHost, s));
+  CESIM_HIP(hipStreamSynchronize(s));
+  const double s2 = c->covd.sigma2;
+  for (int r = 0; r < R; ++r) {
+    const double* e = h.data() + (size_t)r * kDots;
+    const double ub = e[4] - e[10];
+    acc[0] += e[0] + ub;
+    acc[1] += e[1] + e[3] - e[9] - e[6];
+    acc[2] += e[0] / (2.0 * s2) + e[2] / s2 - (ub - nugget * e[5]) / s2 - e[7];
+    acc[3] += -e[5] - e[8];
+    for (int i = 0; i < n; ++i) dacc[i] += u[(size_t)r * n + i];
+  }
+  return CESIM_OK;
+}
+
 }  // namespace
 
 extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugget, int nreal,
@@ -290,7 +509,7 @@ extern "C" cesim_status ce_grad_linear(cesim_ctx c, const double* z, double nugg
 // The vector-Jacobian product of the conditional fields: sum over r of the
 // linear statistic of realization first_real + r alone with the weights
 // vbar[r] (each v_r is affine in its own noise, so the product is the sum of
-// the R one-realization gradients).
+// the R one-realization gradients), in chunks of kVjpChunk realizations.
 extern "C" cesim_status ce_grad_vjp(cesim_ctx c, const double* z, double nugget, int nreal,
                                     uint64_t seed, int first_real, const void* vbar, double* out,
                                     double* dz) {
@@ -298,12 +517,44 @@ extern "C" cesim_status ce_grad_vjp(cesim_ctx c, const double* z, double nugget,
   CESIM_TRY(grad_args_ok(c, z, nugget, nreal, first_real));
   const int n = c->nobs;
   const size_t M = (size_t)c->grid.m1 * c->grid.m2;
-  std::vector<double> acc(4, 0.0), dacc(n, 0.0), o(4), d(n);
-  for (int r = 0; r < nreal; ++r) {
-    CESIM_TRY(grad_linear_core(c, z, nugget, 1, seed, first_real + r,
-                               static_cast<const double*>(vbar) + r * M, o.data(), d.data()));
-    for (int q = 0; q < 4; ++q) acc[q] += o[q];
-    for (int i = 0; i < n; ++i) dacc[i] += d[i];
+  const size_t N = (size_t)c->t1 * c->t2;
+  hipStream_t s = c->stream;
+  CESIM_HIP(hipStreamSynchronize(c->aux));
+  CESIM_HIP(hipStreamSynchronize(s));
+  CESIM_TRY(zero_nugget_ok(c, nugget));
+  const int RC = std::min(nreal, kVjpChunk);
+  // vjp_work: dK22 [n][n] | z [n] | the arrays of one chunk
+  const size_t head = (size_t)n * n + n;
+  CESIM_TRY(c->vjp_work.reserve(sizeof(double) * (head + vjp_chunk_doubles(c, RC))));
+  double* dk22 = c->vjp_work.as<double>();
+  double* zd = dk22 + (size_t)n * n;
+  double* work = zd + n;
+  // gwork: ds [N] | blocked-spectrum scratch [N] | complex scratch [N]
+  CESIM_TRY(c->gwork.reserve(sizeof(double) * 4 * N));
+  double* ds = c->gwork.as<double>();
+  double* slb = ds + N;
+  double2* tmp = reinterpret_cast<double2*>(slb + N);
+  std::vector<double> zh(z, z + n);
+  CESIM_HIP(hipMemcpyAsync(zd, zh.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  CESIM_TRY(grad_dsqrt_device(c, ds, tmp));
+  k_dk22_matrix<<<dim3((n + 255) / 256, n), 256, 0, s>>>(c->obs_xy.as<double>(), n, c->covd, dk22);
+  CESIM_HIP(hipGetLastError());
+  const bool refactor = !c->chol_valid || c->chol_nugget != nugget;
+  if (refactor) {
+    c->chol_valid = false;
+    CESIM_TRY(chol_factor_device(c, nugget, s));
+  }
+  std::vector<double> acc(4, 0.0), dacc(n, 0.0);
+  for (int r0 = 0; r0 < nreal; r0 += RC) {
+    const int R = std::min(RC, nreal - r0);
+    CESIM_TRY(vjp_chunk(c, zd, nugget, R, seed, first_real + r0,
+                        static_cast<const double*>(vbar) + (size_t)r0 * M, ds, slb, dk22, work,
+                        acc.data(), dacc.data()));
+  }
+  if (refactor) {
+    if (c->chol_info_host[0] & 2) return CESIM_ERR_NOT_POSITIVE_DEFINITE;
+    c->chol_valid = true;
+    c->chol_nugget = nugget;
   }
   std::copy(acc.begin(), acc.end(), out);
   std::copy(dacc.begin(), dacc.end(), dz);

@@ -236,6 +236,7 @@ struct cesim_ctx_s {
   int* chol_info_host = nullptr;    // pinned copy, valid once factor_ready has completed
   cesim::DevBuf gwork;              // gradient: one FP64 pair buffer + d sqrt(lambda)
   cesim::DevBuf gvec;               // gradient: mean noises, fields and vectors
+  cesim::DevBuf vjp_work;           // vector-Jacobian product: per-realization arrays
   cesim::DevBuf sework;             // standard errors: chunk arrays and W1 K11 W1^T
   cesim::GroupedSeq winv_seq;       // launches that build winv (kept until they have run)
   cesim::PinnedStage winv_stage;
@@ -279,6 +280,9 @@ cesim_status box_factor_device(cesim_ctx c, double tau2, hipStream_t s);
 bool joint_active(cesim_ctx c);
 constexpr int kMaxJointBox = 32;   // observations per box of the joint sampling
 cesim_status ce_grad_fields_device(cesim_ctx c, const double2* zeta_bar, double* yb, double* dyb);
+cesim_status grad_dsqrt_device(cesim_ctx c, double* ds, double2* tmp);
+cesim_status draw_f64_spectrum_device(cesim_ctx c, int nreal, uint64_t seed, int first_real,
+                                      double* fields, const double* sl, double* slb);
 cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s);
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
                             const double* xib, double* out);
