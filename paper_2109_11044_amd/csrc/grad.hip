@@ -175,31 +175,36 @@ __global__ void k_obs_noise_all(uint32_t k0, uint32_t k1, uint32_t event, int fi
   xi[q] = z[i & 3];
 }
 
-// P[r][i] = sum_g C(s_i - g) vbar[r][g] and dP[r][i] = sum_g dC(s_i - g)/dtheta
-// vbar[r][g] for r < R, i < n.  Workgroup (bx, by): stations 16 bx .. + 15,
-// realizations 64 by .. + 63; grid nodes in chunks of 64.  Per chunk the
-// 64 x 16 covariances and derivatives (4 per thread) and the 64 x 64 tile of
-// vbar go to LDS; thread t accumulates station t % 16 for realizations
-// 4 (t / 16) .. + 3, each covariance serving 64 realizations.
+// Partial cross products over one segment of grid nodes:
+//   Pp[z][r][i] = sum_{g in segment z} C(s_i - g) vbar[r][g],
+//   dPp[z][r][i] = the same with dC(s_i - g)/dtheta,
+// for r < R, i < n.  Workgroup (bx, by, z): stations 16 bx .. + 15,
+// realizations 256 by .. + 255, nodes [z seg, (z + 1) seg) in chunks of 16.
+// Per chunk the 16 x 16 covariances and derivatives (one per thread) and
+// the 256 x 16 tile of vbar go to LDS; thread t accumulates station t % 16
+// for realizations 16 (t / 16) .. + 15, so each covariance serves 256
+// realizations.  k_cross_adj_sum adds the segments in order.
 __global__ void __launch_bounds__(256)
 k_cross_adj(const double* __restrict__ obs, int n, GridDev g, CovDev cov,
-            const double* __restrict__ vbar, int R, double* __restrict__ P,
-            double* __restrict__ dP) {
-  __shared__ double Cs[64][17], dCs[64][17];
-  __shared__ double V[64][65];
+            const double* __restrict__ vbar, int R, int seg, double* __restrict__ Pp,
+            double* __restrict__ dPp) {
+  __shared__ double Cs[16][17], dCs[16][17];
+  __shared__ double V[256][17];
   const int t = threadIdx.x;
-  const int i0 = blockIdx.x * 16, r0 = blockIdx.y * 64;
+  const int i0 = blockIdx.x * 16, r0 = blockIdx.y * 256, z = blockIdx.z;
   const int M = g.m1 * g.m2;
-  const int il = t & 15, rb = (t >> 4) * 4;
-  double ap[4] = {0.0, 0.0, 0.0, 0.0}, ad[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int g0 = 0; g0 < M; g0 += 64) {
-    __syncthreads();
+  const int gb = z * seg, ge = min(M, gb + seg);
+  const int il = t & 15, rg = (t >> 4) * 16;
+  double ap[16], ad[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = t + 256 * u, gl = e >> 4, sl = e & 15;
+  for (int q = 0; q < 16; ++q) ap[q] = ad[q] = 0.0;
+  for (int g0 = gb; g0 < ge; g0 += 16) {
+    __syncthreads();
+    {
+      const int gl = t >> 4, sl = t & 15;
       const int gg = g0 + gl, ii = i0 + sl;
       double cv = 0.0, dv = 0.0;
-      if (gg < M && ii < n) {
+      if (gg < ge && ii < n) {
         const int x = gg % g.m1, y = gg / g.m1;
         const double hx = __dadd_rn(g.x0, __dmul_rn((double)x, g.dx)) - obs[2 * ii];
         const double hy = __dadd_rn(g.y0, __dmul_rn((double)y, g.dy)) - obs[2 * ii + 1];
@@ -210,17 +215,17 @@ k_cross_adj(const double* __restrict__ obs, int n, GridDev g, CovDev cov,
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = t + 256 * u, rl = e >> 6, gl = e & 63;
+      const int e = t + 256 * u, rl = e >> 4, gl = e & 15;
       const int rr = r0 + rl, gg = g0 + gl;
-      V[rl][gl] = (rr < R && gg < M) ? vbar[(size_t)rr * M + gg] : 0.0;
+      V[rl][gl] = (rr < R && gg < ge) ? vbar[(size_t)rr * M + gg] : 0.0;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int gl = 0; gl < 64; ++gl) {
+#pragma unroll 2
+    for (int gl = 0; gl < 16; ++gl) {
       const double cv = Cs[gl][il], dv = dCs[gl][il];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double v = V[rb + q][gl];
+      for (int q = 0; q < 16; ++q) {
+        const double v = V[rg + q][gl];
         ap[q] = fma(v, cv, ap[q]);
         ad[q] = fma(v, dv, ad[q]);
       }
@@ -228,14 +233,29 @@ k_cross_adj(const double* __restrict__ obs, int n, GridDev g, CovDev cov,
   }
   const int ii = i0 + il;
   if (ii >= n) return;
+  const size_t base = (size_t)z * R * n;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int rr = r0 + rb + q;
+  for (int q = 0; q < 16; ++q) {
+    const int rr = r0 + rg + q;
     if (rr < R) {
-      P[(size_t)rr * n + ii] = ap[q];
-      dP[(size_t)rr * n + ii] = ad[q];
+      Pp[base + (size_t)rr * n + ii] = ap[q];
+      dPp[base + (size_t)rr * n + ii] = ad[q];
     }
   }
+}
+
+// P[q] = sum_z Pp[z][q], dP likewise (q < R n), segments in order.
+__global__ void k_cross_adj_sum(const double* __restrict__ Pp, const double* __restrict__ dPp,
+                                int S, size_t Rn, double* __restrict__ P, double* __restrict__ dP) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= Rn) return;
+  double a = 0.0, b = 0.0;
+  for (int z = 0; z < S; ++z) {
+    a += Pp[(size_t)z * Rn + q];
+    b += dPp[(size_t)z * Rn + q];
+  }
+  P[q] = a;
+  dP[q] = b;
 }
 
 // Right-hand sides of the solves: row r = P_r, row R + r = z - zbar*_r
@@ -426,11 +446,17 @@ constexpr int kVjpChunk = 256;
 // theta-derivative), the cross products K21 vbar_r and dK21 vbar_r in one
 // kernel, the 2R solves in one chain, dK22 cbar_r as one GEMM.  Adds into
 // acc[0..3] and dacc[n] (host).
-// Y, dY [R][M] | xi [R][n] | T [R][4n] | P, dP [R][n] | X, X2 [2R][n] | Q [R][n] | dots [R][11]:
-// 2 R M + (1 + 4 + 2 + 4 + 1) R n + 11 R doubles.
+// Node segments of the cross products: enough workgroups to fill the GPU.
+int vjp_segments(cesim_ctx c, int R) {
+  const int tiles = ((c->nobs + 15) / 16) * ((R + 255) / 256);
+  return std::max(1, std::min(32, (1024 + tiles - 1) / tiles));
+}
+
+// Y, dY [R][M] | xi [R][n] | T [R][4n] | P, dP [R][n] | X, X2 [2R][n] | Q [R][n] |
+// Pp, dPp [S][R][n] | dots [R][11]:  2 R M + (12 + 2 S) R n + 11 R doubles.
 size_t vjp_chunk_doubles(cesim_ctx c, int R) {
   const size_t M = (size_t)c->grid.m1 * c->grid.m2, Rn = (size_t)R * c->nobs;
-  return 2 * (size_t)R * M + 12 * Rn + (size_t)R * kDots;
+  return 2 * (size_t)R * M + (12 + 2 * (size_t)vjp_segments(c, R)) * Rn + (size_t)R * kDots;
 }
 
 // work: vjp_chunk_doubles(c, R) doubles; dk22: the n x n theta-derivative
@@ -438,11 +464,11 @@ size_t vjp_chunk_doubles(cesim_ctx c, int R) {
 // doubles of scratch.
 cesim_status vjp_chunk(cesim_ctx c, const double* zd, double nugget, int R, uint64_t seed,
                        int first_real, const double* vbar, const double* ds, double* slb,
-                       const double* dk22, double* work, double* acc, double* dacc) {
+                       const double* dk22, double* work, size_t work_doubles, double* acc,
+                       double* dacc) {
   const int n = c->nobs;
   const size_t M = (size_t)c->grid.m1 * c->grid.m2, Rn = (size_t)R * n;
   hipStream_t s = c->stream;
-  // Y, dY [R][M] | xi [R][n] | T [R][4n] | P, dP [R][n] | X, X2 [2R][n] | Q [R][n] | dots [R][11]
   double* Y = work;
   double* dY = Y + (size_t)R * M;
   double* xi = dY + (size_t)R * M;
@@ -452,19 +478,26 @@ cesim_status vjp_chunk(cesim_ctx c, const double* zd, double nugget, int R, uint
   double* X = dP + Rn;
   double* X2 = X + 2 * Rn;
   double* Q = X2 + 2 * Rn;
-  double* dots = Q + Rn;
-  if ((size_t)(dots + (size_t)R * kDots - work) != vjp_chunk_doubles(c, R))
-    return CESIM_ERR_BAD_STATE;     // the layout above and its size disagree
+  const int S = vjp_segments(c, R);
+  double* Pp = Q + Rn;
+  double* dPp = Pp + (size_t)S * Rn;
+  double* dots = dPp + (size_t)S * Rn;
+  if ((size_t)(dots + (size_t)R * kDots - work) != vjp_chunk_doubles(c, R) ||
+      vjp_chunk_doubles(c, R) > work_doubles)
+    return CESIM_ERR_BAD_STATE;     // the layout, its size and the reservation disagree
   CESIM_TRY(draw_f64_spectrum_device(c, R, seed, first_real, Y, c->s64.as<double>(), slb));
   CESIM_TRY(draw_f64_spectrum_device(c, R, seed, first_real, dY, ds, slb));
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), ev = (uint32_t)c->event_id;
   k_obs_noise_all<<<(unsigned)((Rn + 255) / 256), 256, 0, s>>>(k0, k1, ev, first_real, R, n, xi);
   CESIM_HIP(hipGetLastError());
-  for (int r = 0; r < R; ++r)
-    CESIM_TRY(lk_grad_device(c, nugget, Y + r * M, dY + r * M, xi + (size_t)r * n,
-                             T + (size_t)r * 4 * n));
-  k_cross_adj<<<dim3((n + 15) / 16, (R + 63) / 64), 256, 0, s>>>(
-      c->obs_xy.as<double>(), n, c->gridd, c->covd, vbar, R, P, dP);
+  CESIM_TRY(lk_grad_device(c, nugget, Y, dY, xi, T, R));
+  {
+    const int seg = (int)(((M + S - 1) / S + 15) / 16 * 16);
+    k_cross_adj<<<dim3((n + 15) / 16, (R + 255) / 256, S), 256, 0, s>>>(
+        c->obs_xy.as<double>(), n, c->gridd, c->covd, vbar, R, seg, Pp, dPp);
+    k_cross_adj_sum<<<(unsigned)((Rn + 255) / 256), 256, 0, s>>>(Pp, dPp, S, Rn, P, dP);
+    CESIM_HIP(hipGetLastError());
+  }
   k_vjp_rhs<<<(unsigned)((Rn + 255) / 256), 256, 0, s>>>(P, zd, T, n, R, X);
   CESIM_HIP(hipGetLastError());
   CESIM_TRY(chol_solve_device(c, X, 2 * R, s, X2));        // rows: u_r, then cbar_r
@@ -525,7 +558,8 @@ extern "C" cesim_status ce_grad_vjp(cesim_ctx c, const double* z, double nugget,
   const int RC = std::min(nreal, kVjpChunk);
   // vjp_work: dK22 [n][n] | z [n] | the arrays of one chunk
   const size_t head = (size_t)n * n + n;
-  CESIM_TRY(c->vjp_work.reserve(sizeof(double) * (head + vjp_chunk_doubles(c, RC))));
+  const size_t work_doubles = vjp_chunk_doubles(c, RC);
+  CESIM_TRY(c->vjp_work.reserve(sizeof(double) * (head + work_doubles)));
   double* dk22 = c->vjp_work.as<double>();
   double* zd = dk22 + (size_t)n * n;
   double* work = zd + n;
@@ -549,7 +583,7 @@ extern "C" cesim_status ce_grad_vjp(cesim_ctx c, const double* z, double nugget,
     const int R = std::min(RC, nreal - r0);
     CESIM_TRY(vjp_chunk(c, zd, nugget, R, seed, first_real + r0,
                         static_cast<const double*>(vbar) + (size_t)r0 * M, ds, slb, dk22, work,
-                        acc.data(), dacc.data()));
+                        work_doubles, acc.data(), dacc.data()));
   }
   if (refactor) {
     if (c->chol_info_host[0] & 2) return CESIM_ERR_NOT_POSITIVE_DEFINITE;

@@ -284,8 +284,9 @@ cesim_status grad_dsqrt_device(cesim_ctx c, double* ds, double2* tmp);
 cesim_status draw_f64_spectrum_device(cesim_ctx c, int nreal, uint64_t seed, int first_real,
                                       double* fields, const double* sl, double* slb);
 cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s);
+// R sets (fields [R][M], noises [R][n], outputs [R][4n]); R = 1: one set.
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
-                            const double* xib, double* out);
+                            const double* xib, double* out, int R = 1);
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y,
                                int stage = ST_SOLVE);
 cesim_status chol_solve_vec_device(cesim_ctx c, const double* b, double* x, hipStream_t s,

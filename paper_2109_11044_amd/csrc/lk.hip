@@ -100,12 +100,14 @@ k_lk_setup(const double* __restrict__ obs, int n, GridDev g, CovDev cov, int2* _
 //   out[4i + 1] = dw_i . yb[N_i] + w_i . dyb[N_i] + xi dgamma_i / (2 phi_i)
 //   out[4i + 2] = w_i . yb[N_i] / (2 sigma^2) + xi gamma_i / (2 sigma^2 phi_i)
 //   out[4i + 3] = xi / (2 phi_i)
-// (the theta-, sigma^2- and tau^2-derivatives of zbar*_i).
+// (the theta-, sigma^2- and tau^2-derivatives of zbar*_i), for R sets of
+// fields and noises at once (set r: yb + r M, dyb + r M, xib + r n,
+// out + 4 r n; the weights and their derivatives are computed once).
 template <int NPP>
 __global__ void __launch_bounds__(64)
 k_lk_grad(const double* __restrict__ obs, int n, GridDev g, CovDev cov, double tau2,
           const double* __restrict__ yb, const double* __restrict__ dyb,
-          const double* __restrict__ xib, double* __restrict__ out) {
+          const double* __restrict__ xib, double* __restrict__ out, int R) {
   constexpr int W2 = 2 * NPP;
   constexpr int K = W2 * W2;
   constexpr int LD = 65;
@@ -176,26 +178,33 @@ k_lk_grad(const double* __restrict__ obs, int n, GridDev g, CovDev cov, double t
   solve(u, nullptr);                            // u = dw_i
   const double gam = fmax(0.0, cov.sigma2 - ss);
   const double dgam = gam > 0.0 ? wdkw - 2.0 * dkw : 0.0;
-  double wy = 0.0, wdy = 0.0, dwy = 0.0;
-  for (int al = 0; al < K; ++al) {
-    const size_t node = (size_t)(b + al / W2) * g.m1 + (a + al % W2);
-    wy += v[al * LD] * yb[node];
-    wdy += v[al * LD] * dyb[node];
-    dwy += u[al * LD] * yb[node];
-  }
-  const double phi = sqrt(tau2 + gam), xi = xib[i], s2 = cov.sigma2;
+  const double phi = sqrt(tau2 + gam), s2 = cov.sigma2;
   // phi = 0 only with tau^2 = 0 and gamma_i = 0 (the host refuses that
   // case for the nugget derivative); gamma and its derivative vanish there,
   // so the noise terms of the range and sigma^2 derivatives are 0
   const double hphi = phi > 0.0 ? 0.5 / phi : 0.0;
-  out[4 * (size_t)i] = wy + phi * xi;
-  out[4 * (size_t)i + 1] = dwy + wdy + xi * dgam * hphi;
-  out[4 * (size_t)i + 2] = wy / (2.0 * s2) + xi * gam * hphi / s2;
-  out[4 * (size_t)i + 3] = xi * hphi;
+  const size_t M = (size_t)g.m1 * g.m2;
+  for (int r = 0; r < R; ++r) {
+    const double* y = yb + r * M;
+    const double* dy = dyb + r * M;
+    double wy = 0.0, wdy = 0.0, dwy = 0.0;
+    for (int al = 0; al < K; ++al) {
+      const size_t node = (size_t)(b + al / W2) * g.m1 + (a + al % W2);
+      wy += v[al * LD] * y[node];
+      wdy += v[al * LD] * dy[node];
+      dwy += u[al * LD] * y[node];
+    }
+    const double xi = xib[(size_t)r * n + i];
+    double* o = out + 4 * ((size_t)r * n + i);
+    o[0] = wy + phi * xi;
+    o[1] = dwy + wdy + xi * dgam * hphi;
+    o[2] = wy / (2.0 * s2) + xi * gam * hphi / s2;
+    o[3] = xi * hphi;
+  }
 }
 
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
-                            const double* xib, double* out) {
+                            const double* xib, double* out, int R) {
   hipStream_t s = c->stream;
   const int n = c->nobs, K = c->k;
   const size_t lds = sizeof(double) * ((size_t)K * (K + 1) + 2 * (size_t)K * 65);
@@ -205,7 +214,7 @@ cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const do
       CESIM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     kern<<<grid, 64, lds, s>>>(c->obs_xy.as<double>(), n, c->gridd, c->covd, tau2, yb, dyb, xib,
-                               out);
+                               out, R);
     CESIM_HIP(hipGetLastError());
     return CESIM_OK;
   };
