@@ -265,3 +265,30 @@ def test_autograd_ensemble_variance():
     for adj, fd in ((th.grad, fd_th), (s2.grad, fd_s2), (nug.grad, fd_n)):
         assert abs(float(adj) - fd) <= 1e-6 * abs(fd) + 1e-8 * scale, (float(adj), fd)
     assert float(zt.grad.abs().max()) < 1e-9 * scale
+
+
+def test_fields_vjp_is_additive_over_realizations():
+    """300 realizations (two chunks of the product, the second ragged) give
+    the sum of the products over realizations 0-99 and 100-299 called
+    separately, and the derivatives of the ensemble variance."""
+    import torch
+    m, t, n, k, tau2, R = 24, 64, 30, 16, 0.05, 300
+    xy = workloads.uniform_locations(n, seed=23)
+    ocov = OCov(1.5, 1.0, 0.12)
+    z = draw_observations(xy, ocov, tau2, seed=0)
+    w = torch.as_tensor(np.random.default_rng(5).standard_normal((m, m)), device="cuda")
+    with cesim.Context(cesim.make_cov(1.5, 1.0, 0.12), cesim.unit_square_grid(m, t),
+                       "fp64") as ctx:
+        ctx.offgrid(xy, k)
+        f = ctx.simulate(R, 8, 0)
+        ctx.condition(z, tau2, f)
+        vbar = ((2.0 / R) * w[None] * (f - f.mean(dim=0, keepdim=True))).contiguous()
+        g = ctx.grad_vjp(z, tau2, R, 8, vbar)
+        a = ctx.grad_vjp(z, tau2, 100, 8, vbar[:100].contiguous())
+        b = ctx.grad_vjp(z, tau2, 200, 8, vbar[100:].contiguous(), first_real=100)
+        S = float((w * f.var(dim=0, unbiased=False)).sum())
+    scale = abs(S) + 1e-3
+    for key in ("vbar_dot_v", "d_range", "d_sigma2", "d_nugget"):
+        close(g[key], a[key] + b[key], 1e-11, scale)
+    close(g["vbar_dot_v"], 2.0 * S, 1e-11, scale)
+    np.testing.assert_allclose(g["d_z"], a["d_z"] + b["d_z"], rtol=0, atol=1e-11 * scale)
