@@ -452,7 +452,15 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
   for (DevBuf* b : {&c->chat, &c->chat_tmp, &c->yhat, &c->pred_part})
     b->stream = c->look;                // written by the prediction, on the look-ahead stream
   c->timer.enabled = g_default_timing;
-  cesim_status st = draw_scratch_address(&c->draw_scratch);
+  cesim_status st = CESIM_OK;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess)
+      st = CESIM_ERR_HIP;
+  }
+  if (st == CESIM_OK) st = draw_scratch_address(&c->draw_scratch);
   if (st == CESIM_OK) st = c->info_dev.reserve(sizeof(int) * 4);
   if (st == CESIM_OK) st = c->chol_info.reserve(sizeof(int) * 4);
   if (st == CESIM_OK && hipMemsetAsync(c->chol_info.p, 0, sizeof(int) * 4, c->stream) != hipSuccess)

@@ -169,6 +169,7 @@ struct cesim_ctx_s {
   cesim::CovDev covd{};
   cesim::GridDev gridd{};
   int t1 = 0, t2 = 0;
+  int num_cu = 0;                   // compute units of the device the context runs on
   double lam_min = 0, lam_max = 0, lam_sum = 0, max_imag = 0;
   int torus_tries = 0;
   double ms_setup = 0, ms_offgrid = 0;
@@ -283,7 +284,9 @@ cesim_status ce_grad_fields_device(cesim_ctx c, const double2* zeta_bar, double*
 cesim_status grad_dsqrt_device(cesim_ctx c, double* ds, double2* tmp);
 cesim_status draw_f64_spectrum_device(cesim_ctx c, int nreal, uint64_t seed, int first_real,
                                       double* fields, const double* sl, double* slb);
-cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s);
+// rows_in_place: C is A's storage with N <= 64 (a workgroup must read the
+// whole row block before writing it), which keeps 64 x 64 tiles.
+cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s, bool rows_in_place = false);
 // R sets (fields [R][M], noises [R][n], outputs [R][4n]); R = 1: one set.
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
                             const double* xib, double* out, int R = 1);

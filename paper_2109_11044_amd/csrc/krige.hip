@@ -154,45 +154,58 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
 // kappa (as in the mixed GEMM) and the FP32 correlation: its relative error
 // (a few 1e-6, from the rounded lag) times a correlation below 1e-4 stays far
 // below the FP64 terms' rounding in the cancelling sum; they are summed per
-// chunk of 256 stations in FP32 and the chunk sums in FP64.
+// chunk of 256 stations in FP32 and the chunk sums in FP64.  Pairs farther
+// than kSkip range units (correlation below 1e-13) are left out: each such
+// term is under 1e-13 |chat_i|, a thousandth of the error (a few
+// 1e-10 |chat_i|) of one FP32 far term at the near bound.
 //
-// Workgroup (x, y, z) takes a tile of 32 x 32 grid nodes and the z-th
-// slice of `slice` stations in the GEMM's Morton order (position p holds
-// station order[p]), staged through LDS kPredStage at a time, and writes
-// its FP64 partial sum to part[z][g]; k_predict_sum adds the slices in
-// order.  Stations come in chunks of kGemmChunk with bounding circles: a
+// Work item (x, y, z) is a tile of 32 x 32 grid nodes and the z-th slice
+// of `slice` stations in the GEMM's Morton order (position p holds station
+// order[p]), staged through LDS kPredStage at a time; its FP64 partial sums
+// go to part[z][g], and k_predict_sum adds the slices in order.  A
+// workgroup takes items blockIdx.x, blockIdx.x + gridDim.x, ...  Stations come in chunks of kGemmChunk with bounding circles: a
 // chunk whose circle is farther than kNear range units from the tile's for
 // certain takes the FP32 branch for every pair, as the per-pair test would,
-// with no test and no divergence.  The solves run beside the prediction as
-// chains of small kernels; large workgroups (50 KB of LDS, 16 waves) hold at
-// most two per CU, so that the solves' workgroups are not queued behind
-// many small ones.
+// with no test and no divergence, and one farther than kSkip is passed
+// over.  The solves run beside the prediction as chains of small kernels;
+// with one workgroup (50 KB of LDS, 16 waves) per CU their workgroups find
+// free wave slots at once instead of queueing behind prediction tiles.
 constexpr int kPredThreads = 1024;
 constexpr int kPredStage = 1280;
 template <int NU>
 __global__ void __launch_bounds__(kPredThreads)
-k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice,
-              const double* __restrict__ chat, const double2* __restrict__ st,
-              const int* __restrict__ order, const float4* __restrict__ circ, double ux,
-              double uxy, double uyx, double uy, double dx, double dy) {
+k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice, int gx_tiles,
+              int gy_tiles, int nitems, const double* __restrict__ chat,
+              const double2* __restrict__ st, const int* __restrict__ order,
+              const float4* __restrict__ circ, double ux, double uxy, double uyx, double uy,
+              double dx, double dy) {
   constexpr double kNear = NU == 0 ? 9.5 : (NU == 1 ? 8.0 : 7.0);
   constexpr double kKappa = NU == 0 ? kLog2e : (NU == 1 ? kSqrt2 : kSqrt3);
   constexpr float kNearS2 = (float)(kNear * kKappa * kNear * kKappa);
   // far for certain: the lower bound of the scaled lag clears kNear kappa
   // with room for the rounding of the FP32 coordinates and circles
   constexpr float kFarBound = (float)(kNear * kKappa) * 1.0001f + 1e-2f;
+  // negligible for certain: beyond kSkip range units every correlation is
+  // below 1e-13 (exp(-x) at x = 29.9, x sqrt 2 K1(x sqrt 2) at 22.6,
+  // (1 + x sqrt 3) exp(-x sqrt 3) at 19.3)
+  constexpr double kSkip = NU == 0 ? 30.5 : (NU == 1 ? 23.0 : 19.8);
+  constexpr float kSkipBound = (float)(kSkip * kKappa);
   __shared__ double2 S[kPredStage];
   __shared__ float4 P[kPredStage];   // kappa-scaled FP32 coordinates, chat in FP32
   __shared__ double Cv[kPredStage];
-  const int ix = blockIdx.x * 32 + (threadIdx.x & 31), iy = blockIdx.y * 32 + (threadIdx.x >> 5);
+  // work item w: tile (w % gx_tiles, (w / gx_tiles) % gy_tiles), slice
+  // w / (gx_tiles gy_tiles); every wave runs the same items
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+  const int tx = w % gx_tiles, ty = (w / gx_tiles) % gy_tiles, tz = w / (gx_tiles * gy_tiles);
+  const int ix = tx * 32 + (threadIdx.x & 31), iy = ty * 32 + (threadIdx.x >> 5);
   const double gx = (double)min(ix, m1 - 1) * dx, gy = (double)min(iy, m2 - 1) * dy;
   const double a = ux * gx + uxy * gy, b = uyx * gx + uy * gy;
   const float a32 = (float)(kKappa * a), b32 = (float)(kKappa * b);
   // bounding circle of the tile's nodes in scaled coordinates
   float tcx, tcy, trad;
   {
-    const int ia = blockIdx.x * 32, ib = min(ia + 31, m1 - 1);
-    const int ja = blockIdx.y * 32, jb = min(ja + 31, m2 - 1);
+    const int ia = tx * 32, ib = min(ia + 31, m1 - 1);
+    const int ja = ty * 32, jb = min(ja + 31, m2 - 1);
     const double x = 0.5 * (ia + ib) * dx, y = 0.5 * (ja + jb) * dy;
     const double hx = 0.5 * (ib - ia) * dx, hy = 0.5 * (jb - ja) * dy;
     tcx = (float)(kKappa * (ux * x + uxy * y));
@@ -202,7 +215,7 @@ k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice,
     trad = (float)(kKappa * sqrt(fmax(px * px + py * py, qx * qx + qy * qy)));
   }
   double acc = 0.0;
-  const int pb = blockIdx.z * slice, pe = min(n, pb + slice);
+  const int pb = tz * slice, pe = min(n, pb + slice);
   for (int p0 = pb; p0 < pe; p0 += kPredStage) {
     const int cnt = min(kPredStage, pe - p0);
     __syncthreads();
@@ -221,10 +234,10 @@ k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice,
       for (int j0 = b0; j0 < be; j0 += kGemmChunk) {
         const float4 q = circ[(p0 + j0) / kGemmChunk];
         const float ddx = tcx - q.x, ddy = tcy - q.y;
-        const bool all_far =
-            __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy) - trad - q.z > kFarBound;
+        const float lb = __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy) - trad - q.z;
+        if (lb > kSkipBound) continue;
         const int je = min(be, j0 + kGemmChunk);
-        if (all_far) {
+        if (lb > kFarBound) {
 #pragma unroll 4
           for (int j = j0; j < je; ++j) {
             const float4 pj = P[j];
@@ -249,7 +262,8 @@ k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice,
       acc += (double)far;
     }
   }
-  if (ix < m1 && iy < m2) part[(size_t)blockIdx.z * m1 * m2 + (size_t)iy * m1 + ix] = acc;
+  if (ix < m1 && iy < m2) part[(size_t)tz * m1 * m2 + (size_t)iy * m1 + ix] = acc;
+  }
 }
 
 // yhat[g] = sigma^2 (sum of the S slice sums of node g, in slice order), FP32.
@@ -1114,11 +1128,16 @@ static cesim_status predict_from_chat(cesim_ctx c, hipStream_t s) {
   cov_map(c, 1.0, ux, uxy, uyx, uy);
   const int tr = c->timer.begin(ST_PREDICT, s);
   const int m2 = c->grid.m2;
-  const dim3 grid((m1 + 31) / 32, (m2 + 31) / 32, S);
+  // one workgroup per CU, each looping over tiles x slices: half of each
+  // CU's wave slots and most of its LDS stay free for the solves' GEMMs
+  // and the draw, which then start without waiting for prediction tiles
+  const int gxt = (m1 + 31) / 32, gyt = (m2 + 31) / 32;
+  const int nitems = gxt * gyt * S;
+  const int nwg = std::min(nitems, std::max(1, c->num_cu));
   double* part = c->pred_part.as<double>();
 #define CESIM_PRED(NU)                                                                        \
-  k_predict_f64<NU><<<grid, kPredThreads, 0, s>>>(                                            \
-      part, m1, m2, n, slice, c->chat.as<double>(), c->obs_t64.as<double2>(),                 \
+  k_predict_f64<NU><<<nwg, kPredThreads, 0, s>>>(                                             \
+      part, m1, m2, n, slice, gxt, gyt, nitems, c->chat.as<double>(), c->obs_t64.as<double2>(), \
       c->obs_order.as<int>(), c->gemm_circ.as<float4>(), ux, uxy, uyx, uy, c->grid.dx, c->grid.dy)
   switch (c->covd.nu_code) {
     case 0: CESIM_PRED(0); break;

@@ -3,11 +3,11 @@
 //   A = K22 + tau^2 I,  A = L L^T (blocked right-looking Cholesky),
 //   X = A^{-1} RHS for all realizations (blocked forward and backward
 //   substitution with the inverses of the diagonal blocks).
-// Besides the single-wave diagonal factorisation, every step (panel solves,
+// Besides the diagonal-block factorisation, every step (panel solves,
 // trailing updates, diagonal-block applications, solve updates) is one call
 // of the FP64 matrix-core GEMM below.
 // The O(n^3) trailing updates and O(n^2 R) solve updates run in one generic
-// FP64 matrix-core GEMM (v_mfma_f64_16x16x4f64, 64 x 64 tiles).
+// FP64 matrix-core GEMM (v_mfma_f64_16x16x4f64, 64 x 64 or 32 x 32 tiles).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -21,6 +21,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNB = 64;   // Cholesky block size
 constexpr int kSB = kSolveBlock;  // substitution block size (4 Cholesky blocks)
+constexpr long kSmallGemmTiles = 320;   // fewer 64 x 64 tiles than this: 32 x 32 tiles
 
 // A = K22 + tau^2 I (+ diag(extra) for the surrogate sites of
 // nearest-neighbour Kriging, whose nugget is inflated site by site).
@@ -56,80 +57,85 @@ k_place_diag(const double* __restrict__ D, int n, double* __restrict__ W) {
   }
 }
 
-// The diagonal factorisation runs as a single wave: its LDS accesses are
-// executed in program order, so a lane reads what another lane of the same
-// wave wrote by an earlier instruction without a barrier.  This keeps the
-// compiler from moving LDS accesses across the point (no instruction is
-// emitted).
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+// Lane l's value of v (l uniform): two 32-bit lane reads into scalar
+// registers, which the next instruction takes as an operand.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __hiloint2double(hi, lo);
 }
 
-// Factor the nbk x nbk diagonal block at (k0, k0) with one wave and form
-// the inverse of its factor.  Lane i holds row i in registers (every index
-// static, the loops unrolled).  Right-looking: at pivot j every lane posts
-// its column-j entry to LDS, reads the pivot and, for each k > j, the
-// broadcast entry of row k, and updates its row.  The inverse X = L^{-1} is then formed column by
-// column (lane c holds column c) by forward substitution on the identity
-// from an LDS copy of L.  Writes L back (lower part) and the inverse to
-// dinv (kNB x kNB, row-major, zero above the diagonal, the identity past
-// nbk); bit 2 of *info marks a non-positive pivot.
+// Factor the nbk x nbk diagonal block at (k0, k0) and form the inverse of
+// its factor; 256 threads.  Wave 0 factors: lane i holds row i in registers
+// (every index static, the loops unrolled) and, right-looking, at pivot j
+// reads the pivot and the unscaled column-j entries of the rows k > j from
+// their lanes and updates its row.  The inverse X = L^{-1} is then formed
+// by rows with all four waves: at step k row k of X is final, X[k][c] =
+// x_k[c] / L[k][k], and every row i > k subtracts L[i][k] X[k][c]; wave w
+// holds the columns c = 4 m + w of row i in lane i and reads L from LDS.
+// Each entry of X is the same sum in the same order as by forward
+// substitution on the columns of the identity.  Writes L back (lower part)
+// and the inverse to dinv (kNB x kNB, row-major, zero above the diagonal,
+// the identity past nbk); bit 2 of *info marks a non-positive pivot.
 __device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int n, int k0, int nbk,
                                                 double* __restrict__ dinv, int* __restrict__ info) {
-  // L packed by rows (row r at r (r + 1) / 2): 16.6 KB, small enough to
-  // share a CU with the draw kernels when condition() overlaps them
-  __shared__ double Ls[kNB * (kNB + 1) / 2];
-  __shared__ double col[kNB];
-  __shared__ double rinv[kNB];
-  const int i = threadIdx.x;
-  double a[kNB];
-  bool bad = false;
+  // L packed by columns (column k holds rows k..63 from kcol(k)): 16.6 KB,
+  // small enough to share a CU with the draw kernels when condition()
+  // overlaps them
+  __shared__ double Lc[kNB * (kNB + 1) / 2];
+  __shared__ double rinv[kNB];          // 1 / L[i][i]
+  auto kcol = [](int k) { return k * kNB - k * (k - 1) / 2; };
+  const int t = threadIdx.x, i = t & 63;
+  if (t < 64) {
+    double a[kNB];
+    bool bad = false;
 #pragma unroll
-  for (int k = 0; k < kNB; ++k)
-    a[k] = (i < nbk && k < nbk) ? A[(size_t)(k0 + i) * n + k0 + k] : (i == k ? 1.0 : 0.0);
+    for (int k = 0; k < kNB; ++k)
+      a[k] = (i < nbk && k < nbk) ? A[(size_t)(k0 + i) * n + k0 + k] : (i == k ? 1.0 : 0.0);
+    double myinv = 0.0;
 #pragma unroll
-  for (int j = 0; j < kNB; ++j) {
-    col[i] = a[j];                        // column j, not yet scaled
-    wave_lds_order();
-    const double d = col[j];
-    bad |= (j < nbk && !(d > 0.0));
-    const double piv = sqrt(d), r = 1.0 / piv;
-    a[j] = (i > j) ? a[j] * r : (i == j ? piv : 0.0);
-    const double lij = a[j] * r;          // L[i][j] / L[j][j]: pairs with unscaled col[k]
+    for (int j = 0; j < kNB; ++j) {
+      const double cj = a[j];               // column j of row i, not yet scaled
+      const double d = lane_value(cj, j);
+      bad |= (j < nbk && !(d > 0.0));
+      const double piv = sqrt(d), r = 1.0 / piv;
+      a[j] = (i > j) ? cj * r : (i == j ? piv : 0.0);
+      const double lij = a[j] * r;          // L[i][j] / L[j][j]: pairs with unscaled entries
+      if (i == j) myinv = r;
 #pragma unroll
-    for (int k = j + 1; k < kNB; ++k) {   // entries k > i of row i are never read
-      a[k] = fma(-lij, col[k], a[k]);
-      if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      for (int k = j + 1; k < kNB; ++k)     // entries k > i of row i are never read
+        a[k] = fma(-lij, lane_value(cj, k), a[k]);
     }
-    rinv[j] = r;
-    wave_lds_order();
-  }
-  const int prow = i * (i + 1) / 2;
 #pragma unroll
+    for (int k = 0; k < kNB; ++k) {
+      if (k <= i) Lc[kcol(k) + i - k] = a[k];
+      if (i < nbk && k <= i) A[(size_t)(k0 + i) * n + k0 + k] = a[k];
+    }
+    rinv[i] = myinv;
+    if (bad && i == 0) atomicOr(info, 2);
+  }
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  double x[kNB / 4];
+#pragma unroll
+  for (int m = 0; m < kNB / 4; ++m) x[m] = (4 * m + w == i) ? 1.0 : 0.0;
   for (int k = 0; k < kNB; ++k) {
-    if (k <= i) Ls[prow + k] = a[k];
-    if (i < nbk && k <= i) A[(size_t)(k0 + i) * n + k0 + k] = a[k];
+    const double lik = (i > k) ? Lc[kcol(k) + i - k] : 0.0;
+    const double rk = rinv[k];
+    // columns c > k of row k are zero and leave x unchanged
+#pragma unroll
+    for (int m = 0; m < kNB / 4; ++m) x[m] = fma(-lik, lane_value(x[m], k) * rk, x[m]);
   }
-  wave_lds_order();
-  double x[kNB];
+  const double ri = rinv[i];
 #pragma unroll
-  for (int r = 0; r < kNB; ++r) x[r] = (r == i) ? 1.0 : 0.0;
-#pragma unroll
-  for (int q = 0; q < kNB; ++q) {
-    x[q] *= rinv[q];
-#pragma unroll
-    for (int r = q + 1; r < kNB; ++r) {
-      x[r] = fma(-Ls[r * (r + 1) / 2 + q], x[q], x[r]);
-      if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-    }
+  for (int m = 0; m < kNB / 4; ++m) {
+    const int c = 4 * m + w;
+    dinv[i * kNB + c] = (c <= i) ? x[m] * ri : 0.0;
   }
-#pragma unroll
-  for (int r = 0; r < kNB; ++r) dinv[r * kNB + i] = (r >= i) ? x[r] : 0.0;
-  if (bad && i == 0) atomicOr(info, 2);
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict__ dinv,
              int* __restrict__ info) {
   chain_priority();
@@ -137,45 +143,49 @@ k_potrf_diag(double* __restrict__ A, int n, int k0, int nbk, double* __restrict_
 }
 
 // One diagonal block of each of several systems: workgroup q takes d[q].
-__global__ void __launch_bounds__(64) k_potrf_diag_grp(const DiagDesc* __restrict__ d) {
+__global__ void __launch_bounds__(256) k_potrf_diag_grp(const DiagDesc* __restrict__ d) {
   chain_priority();
   const DiagDesc e = d[blockIdx.x];
   potrf_diag_body(e.A, e.n, e.k0, e.nbk, e.dinv, e.info);
 }
 
-// Generic FP64 GEMM on matrix cores (GemmArgs): 64 x 64 tiles, 4 waves of 32 x 32, k-step 16.
-// LOWER: skip tiles strictly above the diagonal (symmetric updates).
+// Generic FP64 GEMM on matrix cores (GemmArgs): T x T tiles (T = 64 or 32),
+// 4 waves of T/2 x T/2, k-step 16.  LOWER: skip tiles strictly above the
+// diagonal (symmetric updates).  Both tile sizes sum every output element
+// in the same order (k-steps of 4 in ascending order), so the choice of T
+// never changes a result.
 // Operand layouts of v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16]
 // and B[l / 16][l % 16]; accumulator v of lane l is D[l / 16 + 4 v][l % 16].
-template <bool LOWER>
-__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ double As[2][TK][TM + 2];
-  __shared__ double Bs[2][TK][TN + 2];
+template <int T, bool LOWER>
+__device__ __forceinline__ void f64_tile(const GemmArgs& g, int bi, int bj) {
+  constexpr int TK = 16, WT = T / 2, FB = WT / 16;   // FB x FB blocks of 16 x 16 per wave
+  constexpr int NE = T * TK / 256;                   // operand elements per thread and k-step
+  __shared__ double As[2][TK][T + 2];
+  __shared__ double Bs[2][TK][T + 2];
   if (LOWER && bj > bi) return;
-  const int i0 = bi * TM, j0 = bj * TN;
+  const int i0 = bi * T, j0 = bj * T;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  doublex4 acc[2][2];
+  const int wr = (wave >> 1) * WT, wc = (wave & 1) * WT;
+  doublex4 acc[FB][FB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (doublex4){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < FB; ++b) acc[a][b] = (doublex4){0.0, 0.0, 0.0, 0.0};
   const bool a_ifast = (g.sai == 1);
   const bool b_jfast = (g.sbj == 1);
   // element u of this thread's share of a k-step: (row, k) of the A tile
   // and (k, column) of the B tile, along the operand's contiguous index
-  int ai[4], ak[4], bj_[4], bk[4];
+  int ai[NE], ak[NE], bj_[NE], bk[NE];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < NE; ++u) {
     const int e = threadIdx.x + 256 * u;
-    if (a_ifast) { ai[u] = e % TM; ak[u] = e / TM; } else { ak[u] = e % TK; ai[u] = e / TK; }
-    if (b_jfast) { bj_[u] = e % TN; bk[u] = e / TN; } else { bk[u] = e % TK; bj_[u] = e / TK; }
+    if (a_ifast) { ai[u] = e % T; ak[u] = e / T; } else { ak[u] = e % TK; ai[u] = e / TK; }
+    if (b_jfast) { bj_[u] = e % T; bk[u] = e / T; } else { bk[u] = e % TK; bj_[u] = e / TK; }
   }
-  double ra[4], rb[4];
+  double ra[NE], rb[NE];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NE; ++u) {
       const int gi = i0 + ai[u], gk = k0 + ak[u];
       ra[u] = (gi < g.M && gk < g.K) ? g.A[gi * g.sai + gk * g.sak] : 0.0;
       const int gj = j0 + bj_[u], gk2 = k0 + bk[u];
@@ -184,7 +194,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NE; ++u) {
       As[buf][ak[u]][ai[u]] = ra[u];
       Bs[buf][bk[u]][bj_[u]] = rb[u];
     }
@@ -201,16 +211,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
-      double a[2], b[2];
+      double a[FB], b[FB];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < FB; ++t) {
         a[t] = As[buf][kk][wr + 16 * t + (lane & 15)];
         b[t] = Bs[buf][kk][wc + 16 * t + (lane & 15)];
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < FB; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < FB; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
     if (more) stash(buf ^ 1);
@@ -218,9 +228,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
     buf ^= 1;
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < FB; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gi = i0 + wr + 16 * x + (lane >> 4) + 4 * v;
@@ -233,10 +243,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bi, int bj) {
       }
 }
 
-template <bool LOWER>
+template <int T, bool LOWER>
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
   chain_priority();
-  gemm_tile<LOWER>(g, blockIdx.y, blockIdx.x);
+  f64_tile<T, LOWER>(g, blockIdx.y, blockIdx.x);
 }
 
 // Several independent GEMMs in one launch: group q owns workgroups
@@ -256,14 +266,27 @@ k_gemm_f64_grp(const GemmArgs* __restrict__ gs, const int* __restrict__ tile0, i
   const GemmArgs g = gs[lo];
   const int t = b - tile0[lo];
   const int tn = (g.N + 63) / 64;
-  gemm_tile<LOWER>(g, t / tn, t % tn);
+  f64_tile<64, LOWER>(g, t / tn, t % tn);
 }
 
-cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s) {
+// 64 x 64 tiles, or 32 x 32 where 64 x 64 tiles would leave most CUs idle
+// (the diagonal-block applications of the substitutions, the column
+// updates of the factorisation): four times the workgroups at half the
+// operand reuse.  An in-place product (rows_in_place) keeps one workgroup
+// per row block.
+cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s, bool rows_in_place) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return CESIM_OK;
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
-  if (lower) k_gemm_f64<true><<<grid, 256, 0, s>>>(g);
-  else k_gemm_f64<false><<<grid, 256, 0, s>>>(g);
+  if (rows_in_place && g.N > 64) return CESIM_ERR_INVALID_ARG;
+  const long tiles64 = (long)((g.N + 63) / 64) * ((g.M + 63) / 64);
+  if (tiles64 < kSmallGemmTiles && !rows_in_place) {
+    dim3 grid((g.N + 31) / 32, (g.M + 31) / 32);
+    if (lower) k_gemm_f64<32, true><<<grid, 256, 0, s>>>(g);
+    else k_gemm_f64<32, false><<<grid, 256, 0, s>>>(g);
+  } else {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    if (lower) k_gemm_f64<64, true><<<grid, 256, 0, s>>>(g);
+    else k_gemm_f64<64, false><<<grid, 256, 0, s>>>(g);
+  }
   CESIM_HIP(hipGetLastError());
   return CESIM_OK;
 }
@@ -358,7 +381,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool cl
   bool la_pending = false;            // la_update marks look work s has not joined
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * kNB, nbk = std::min(kNB, n - k0);
-    k_potrf_diag<<<1, 64, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
+    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, D + (size_t)kb * kNB * kNB, info);
     CESIM_HIP(hipGetLastError());
     const int rest = n - k0 - nbk;
     if (rest <= 0) break;
@@ -369,7 +392,7 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool cl
       g.A = A + (size_t)(k0 + nbk) * n + k0; g.sai = n; g.sak = 1;
       g.B = D + (size_t)kb * kNB * kNB; g.sbk = 1; g.sbj = kNB;     // B(t, c) = Linv[c][t]
       g.C = A + (size_t)(k0 + nbk) * n + k0; g.sci = n; g.scj = 1;
-      CESIM_TRY(gemm_f64(g, false, s));
+      CESIM_TRY(gemm_f64(g, false, s, true));
     }
     // trailing update A[i][j] -= sum_t P[i][t] P[j][t] (P: the panel) of
     // the rows and columns from c0, on the tiles of the lower triangle
@@ -717,7 +740,7 @@ cesim_status GroupedSeq::upload(hipStream_t s) {
 cesim_status GroupedSeq::launch(hipStream_t s) const {
   for (const Launch& l : launches) {
     if (l.kind == 0)
-      k_potrf_diag_grp<<<l.blocks, 64, 0, s>>>(d_diag + l.first);
+      k_potrf_diag_grp<<<l.blocks, 256, 0, s>>>(d_diag + l.first);
     else if (l.kind == 1)
       k_gemm_f64_grp<false><<<l.blocks, 256, 0, s>>>(d_gemm + l.first, d_pfx + l.pfx, l.count);
     else
