@@ -588,8 +588,18 @@ k_gemv_cols(const double* __restrict__ M, size_t ld, const double* __restrict__ 
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int i = blockIdx.x * 64 + l;
   double a = 0.0;
-  if (i < cols)
-    for (int t = w; t < nt; t += 4) a = fma(M[(size_t)t * ld + i], v[t], a);
+  if (i < cols) {
+    // eight loads in flight per lane, the sum in row order
+    int t = w;
+    for (; t + 28 < nt; t += 32) {
+      double m[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m[u] = M[(size_t)(t + 4 * u) * ld + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a = fma(m[u], v[t + 4 * u], a);
+    }
+    for (; t < nt; t += 4) a = fma(M[(size_t)t * ld + i], v[t], a);
+  }
   part[w][l] = a;
   __syncthreads();
   if (w == 0 && i < cols) {
