@@ -460,6 +460,18 @@ __device__ __forceinline__ void k12_step(const float2* sv, bool upper, const flo
   }
 }
 
+// Whether any lane of the wave holds a half with a nonzero bit pattern in
+// v (uniform).  A fragment of exact zeros multiplies to exact zeros, so its
+// products are skipped without changing a bit of the sums: the low halves
+// of the FP16 split vanish once ks C falls into FP16's subnormal range (the
+// high half then holds the whole value), and both halves of correlations
+// below half the smallest subnormal.
+template <typename HV>
+__device__ __forceinline__ bool wave_any_nonzero(const HV& v) {
+  const u32x4v w = __builtin_bit_cast(u32x4v, v);
+  return __builtin_amdgcn_ballot_w64((w[0] | w[1] | w[2] | w[3]) != 0u) != 0;
+}
+
 // Three products hi.hi + hi.lo + lo.hi of one k-step (ks = 0 or 16 within
 // the chunk) for the 8 blocks of 32 realizations whose coefficients start at
 // sh / sl (rows of 32 observations, swizzled as stored).
@@ -470,6 +482,12 @@ __device__ __forceinline__ void mfma_step(const H* __restrict__ sh, const H* __r
                                           floatx16 (&acc)[NF][8]) {
   using HV = typename HalfOps<H>::V;
   const int kb = (lane >> 5) * 8;
+  bool nzh[NF], nzl[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    nzh[f] = wave_any_nonzero(ah[f]);
+    nzl[f] = wave_any_nonzero(al[f]);
+  }
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
     const int rr = 32 * b + (lane & 31);
@@ -478,9 +496,9 @@ __device__ __forceinline__ void mfma_step(const H* __restrict__ sh, const H* __r
     const HV bl = *reinterpret_cast<const HV*>(&sl[rr * kKC + 8 * pc]);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      acc[f][b] = HalfOps<H>::mfma(bh, ah[f], acc[f][b]);
-      acc[f][b] = HalfOps<H>::mfma(bh, al[f], acc[f][b]);
-      acc[f][b] = HalfOps<H>::mfma(bl, ah[f], acc[f][b]);
+      if (nzh[f]) acc[f][b] = HalfOps<H>::mfma(bh, ah[f], acc[f][b]);
+      if (nzl[f]) acc[f][b] = HalfOps<H>::mfma(bh, al[f], acc[f][b]);
+      if (nzh[f]) acc[f][b] = HalfOps<H>::mfma(bl, ah[f], acc[f][b]);
     }
   }
 }
@@ -573,8 +591,13 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
 #pragma unroll
       for (int j = 0; j < 8; ++j) sv[j] = Ss[buf][ks + kb + j];
       HV ah[NF], al[NF];
+      bool nzh[NF], nzl[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) k12_frag<NU, H>(gxt[f], gyt[f], sv, kscale, ah[f], al[f]);
+      for (int f = 0; f < NF; ++f) {
+        k12_frag<NU, H>(gxt[f], gyt[f], sv, kscale, ah[f], al[f]);
+        nzh[f] = wave_any_nonzero(ah[f]);
+        nzl[f] = wave_any_nonzero(al[f]);
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int rr = 32 * b + (lane & 31);
@@ -583,9 +606,9 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
         const HV bl = *reinterpret_cast<const HV*>(&Sl[buf][rr * kKC + 8 * pc]);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-          acc[f][b] = HalfOps<H>::mfma(bh, ah[f], acc[f][b]);
-          acc[f][b] = HalfOps<H>::mfma(bh, al[f], acc[f][b]);
-          acc[f][b] = HalfOps<H>::mfma(bl, ah[f], acc[f][b]);
+          if (nzh[f]) acc[f][b] = HalfOps<H>::mfma(bh, ah[f], acc[f][b]);
+          if (nzl[f]) acc[f][b] = HalfOps<H>::mfma(bh, al[f], acc[f][b]);
+          if (nzh[f]) acc[f][b] = HalfOps<H>::mfma(bl, ah[f], acc[f][b]);
         }
       }
     }
