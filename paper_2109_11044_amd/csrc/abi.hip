@@ -529,6 +529,41 @@ cesim_status ce_simulate_noalloc(cesim_ctx c, int nreal, uint64_t seed, int firs
   return CESIM_OK;
 }
 
+// The low 16 bits of v spread to the even bit positions of the result.
+static inline uint32_t spread_bits16(uint32_t v) {
+  v &= 0xffffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+// Indices 0..n-1 ordered by key, equal keys in index order (LSD radix sort
+// by bytes, skipping the bytes in which all keys agree).
+static std::vector<int> stable_radix_order(const std::vector<uint64_t>& key) {
+  const int n = (int)key.size();
+  std::vector<int> a(n), b(n);
+  std::vector<uint64_t> ka(key), kb(n);
+  for (int i = 0; i < n; ++i) a[i] = i;
+  uint64_t diff = 0;
+  for (int i = 1; i < n; ++i) diff |= key[i] ^ key[0];
+  for (int sh = 0; sh < 64; sh += 8) {
+    if (((diff >> sh) & 0xff) == 0) continue;
+    int cnt[257] = {0};
+    for (int i = 0; i < n; ++i) ++cnt[((ka[i] >> sh) & 0xff) + 1];
+    for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
+    for (int i = 0; i < n; ++i) {
+      const int dst = cnt[(ka[i] >> sh) & 0xff]++;
+      b[dst] = a[i];
+      kb[dst] = ka[i];
+    }
+    a.swap(b);
+    ka.swap(kb);
+  }
+  return a;
+}
+
 cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   if (!c || !xy || nobs < 1) return CESIM_ERR_INVALID_ARG;
   int npp = 0;
@@ -576,38 +611,35 @@ cesim_status offgrid_nnkrige(cesim_ctx c, int nobs, const double* xy, int k) {
   std::vector<double2> t64(nobs);
   std::vector<float2> t32(nobs);
   // processing order of the gathers: Morton (Z) order of the grid cell
-  std::vector<std::pair<uint64_t, int>> key(nobs);
+  // (ties in station order); the boxes of several observations (joint
+  // sampling) in order of the cell's (column, row), members ascending.
+  // Both orders by a stable radix sort of the keys (the station set-up is
+  // host time the GPU waits for at every new event).
+  std::vector<uint64_t> mkey(nobs), bkey(nobs);
   for (int i = 0; i < nobs; ++i) {
     const double fx = std::floor((xy[2 * i] - g.x0) / g.dx), fy = std::floor((xy[2 * i + 1] - g.y0) / g.dy);
     const uint32_t cx = (uint32_t)std::min(std::max(fx, 0.0), 65535.0);
     const uint32_t cy = (uint32_t)std::min(std::max(fy, 0.0), 65535.0);
-    uint64_t m = 0;
-    for (int b = 0; b < 16; ++b) m |= (uint64_t)((cx >> b) & 1) << (2 * b) | (uint64_t)((cy >> b) & 1) << (2 * b + 1);
-    key[i] = {m, i};
+    mkey[i] = spread_bits16(cx) | (uint64_t)spread_bits16(cy) << 1;
+    // cells start at -1 at the lower slack of the grid's extent
+    bkey[i] = (uint64_t)((long)fx + 1) << 32 | (uint64_t)((long)fy + 1);
   }
-  std::sort(key.begin(), key.end());
-  std::vector<int> order(nobs);
-  for (int i = 0; i < nobs; ++i) order[i] = key[i].second;
-  // boxes of several observations (joint sampling): members in ascending order
-  std::vector<std::pair<std::pair<long, long>, int>> bk(nobs);
-  for (int i = 0; i < nobs; ++i)
-    bk[i] = {{(long)std::floor((xy[2 * i] - g.x0) / g.dx), (long)std::floor((xy[2 * i + 1] - g.y0) / g.dy)},
-             i};
-  std::sort(bk.begin(), bk.end());
+  const std::vector<int> order = stable_radix_order(mkey);
+  const std::vector<int> bord = stable_radix_order(bkey);
   std::vector<int2> box_of(nobs, make_int2(-1, 0));
   std::vector<int4> box_desc;
   std::vector<int> box_members;
   int fac_total = 0, max_box = 0;
   for (int lo = 0; lo < nobs;) {
     int hi = lo + 1;
-    while (hi < nobs && bk[hi].first == bk[lo].first) ++hi;
+    while (hi < nobs && bkey[bord[hi]] == bkey[bord[lo]]) ++hi;
     const int sz = hi - lo;
     if (sz > 1) {
       const int d = (int)box_desc.size();
       box_desc.push_back(make_int4((int)box_members.size(), sz, fac_total, 0));
       for (int q = 0; q < sz; ++q) {
-        box_members.push_back(bk[lo + q].second);
-        box_of[bk[lo + q].second] = make_int2(d, q);
+        box_members.push_back(bord[lo + q]);
+        box_of[bord[lo + q]] = make_int2(d, q);
       }
       fac_total += sz * (sz + 1) / 2;
       max_box = std::max(max_box, sz);
