@@ -290,8 +290,10 @@ cesim_status gemm_f64(const GemmArgs& g, bool lower, hipStream_t s, bool rows_in
 // R sets (fields [R][M], noises [R][n], outputs [R][4n]); R = 1: one set.
 cesim_status lk_grad_device(cesim_ctx c, double tau2, const double* yb, const double* dyb,
                             const double* xib, double* out, int R = 1);
+// identity: X holds I (R = n) and Y zeros; the forward steps skip the rows
+// whose forward solution is still zero.
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y,
-                               int stage = ST_SOLVE);
+                               int stage = ST_SOLVE, bool identity = false);
 cesim_status chol_solve_vec_device(cesim_ctx c, const double* b, double* x, hipStream_t s,
                                    double* y, int stage);
 // Repeated mixed-path calls of at most kInverseMaxReal realizations on one

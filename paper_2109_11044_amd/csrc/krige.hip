@@ -595,8 +595,10 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         k12_frag<NU, H>(gxt[f], gyt[f], sv, kscale, ah[f], al[f]);
-        nzh[f] = wave_any_nonzero(ah[f]);
-        nzl[f] = wave_any_nonzero(al[f]);
+        // tiles of 64 and 128 realizations issue too few products per
+        // fragment for the test and its branches to pay
+        nzh[f] = NB < 8 || wave_any_nonzero(ah[f]);
+        nzl[f] = NB < 8 || wave_any_nonzero(al[f]);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {

@@ -448,9 +448,12 @@ cesim_status chol_factor_device(cesim_ctx c, double tau2, hipStream_t s, bool cl
 // X holds the right-hand sides and ends with the solution; no GEMM writes
 // what it reads.  Forward step kb is fwd[kb], backward step st (counted from
 // the last block) bwd[st].
+// identity: X = I (R = n) and Y zero on entry; row r of the forward
+// solution L^{-1} e_r is zero before entry r, so forward block kb touches
+// only rows r < K0 + nb (a third of the forward GEMMs' work).
 static void solve_step_lists(cesim_ctx c, double* X, double* Y, int R,
                              std::vector<std::vector<GemmArgs>>& fwd,
-                             std::vector<std::vector<GemmArgs>>& bwd) {
+                             std::vector<std::vector<GemmArgs>>& bwd, bool identity = false) {
   const int n = c->nobs, nbig = (n + kSB - 1) / kSB;
   const double* L = c->amat.as<double>();
   const double* W = c->winv.as<double>();
@@ -459,14 +462,15 @@ static void solve_step_lists(cesim_ctx c, double* X, double* Y, int R,
   for (int kb = 0; kb < nbig; ++kb) {
     const int K0 = kb * kSB, nb = std::min(kSB, n - K0), rest = n - K0 - nb;
     const double* WB = W + (size_t)kb * kSB * kSB;
+    const int rows = identity ? std::min(R, K0 + nb) : R;
     GemmArgs g;
-    g.M = R; g.N = nb; g.K = nb; g.alpha = 1.0; g.beta = 0.0;
+    g.M = rows; g.N = nb; g.K = nb; g.alpha = 1.0; g.beta = 0.0;
     g.A = X + K0; g.sai = n; g.sak = 1;
     g.B = WB; g.sbk = 1; g.sbj = kSB;
     g.C = Y + K0; g.sci = n; g.scj = 1;
     fwd[kb].push_back(g);
     if (rest > 0) {
-      g.M = R; g.N = rest; g.K = nb; g.alpha = -1.0; g.beta = 1.0;
+      g.M = rows; g.N = rest; g.K = nb; g.alpha = -1.0; g.beta = 1.0;
       g.A = Y + K0; g.sai = n; g.sak = 1;
       g.B = L + (size_t)(K0 + nb) * n + K0; g.sbk = 1; g.sbj = n;
       g.C = X + K0 + nb; g.sci = n; g.scj = 1;
@@ -492,9 +496,10 @@ static void solve_step_lists(cesim_ctx c, double* X, double* Y, int R,
   }
 }
 
-static void solve_steps(cesim_ctx c, double* X, double* Y, int R, std::vector<GemmArgs>& out) {
+static void solve_steps(cesim_ctx c, double* X, double* Y, int R, std::vector<GemmArgs>& out,
+                        bool identity = false) {
   std::vector<std::vector<GemmArgs>> fwd, bwd;
-  solve_step_lists(c, X, Y, R, fwd, bwd);
+  solve_step_lists(c, X, Y, R, fwd, bwd, identity);
   for (auto& v : fwd) out.insert(out.end(), v.begin(), v.end());
   for (auto& v : bwd) out.insert(out.end(), v.begin(), v.end());
 }
@@ -505,10 +510,10 @@ static void solve_steps(cesim_ctx c, double* X, double* Y, int R, std::vector<Ge
 // [R][n], observation index fastest).
 // Y: second buffer of at least R n doubles; stage: the timer stage it counts in.
 cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, double* Y,
-                               int stage) {
+                               int stage, bool identity) {
   const int tr = c->timer.begin(stage, s);
   std::vector<GemmArgs> steps;
-  solve_steps(c, X, Y, R, steps);
+  solve_steps(c, X, Y, R, steps, identity);
   for (const GemmArgs& g : steps) CESIM_TRY(gemm_f64(g, false, s));
   c->timer.end(tr, s);
   return CESIM_OK;
@@ -516,9 +521,14 @@ cesim_status chol_solve_device(cesim_ctx c, double* X, int R, hipStream_t s, dou
 
 // --------------------------------------------------------- explicit inverse
 
-__global__ void __launch_bounds__(256) k_identity(double* __restrict__ X, int n) {
+// X = I and Y = 0 (n x n each).
+__global__ void __launch_bounds__(256) k_identity(double* __restrict__ X, double* __restrict__ Y,
+                                                  int n) {
   const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (q < (size_t)n * n) X[q] = (q / n == q % n) ? 1.0 : 0.0;
+  if (q < (size_t)n * n) {
+    X[q] = (q / n == q % n) ? 1.0 : 0.0;
+    Y[q] = 0.0;
+  }
 }
 
 // A^{-1} of the factored observation matrix into c->ainv (n x n; row r is
@@ -529,9 +539,11 @@ cesim_status inverse_device(cesim_ctx c, hipStream_t s) {
   const size_t nn = (size_t)n * n;
   CESIM_TRY(c->ainv.reserve(sizeof(double) * nn));
   CESIM_TRY(c->ainv_tmp.reserve(sizeof(double) * nn));
-  k_identity<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c->ainv.as<double>(), n);
+  k_identity<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c->ainv.as<double>(),
+                                                          c->ainv_tmp.as<double>(), n);
   CESIM_HIP(hipGetLastError());
-  CESIM_TRY(chol_solve_device(c, c->ainv.as<double>(), n, s, c->ainv_tmp.as<double>()));
+  CESIM_TRY(chol_solve_device(c, c->ainv.as<double>(), n, s, c->ainv_tmp.as<double>(), ST_SOLVE,
+                              true));
   c->ainv_valid = true;
   return CESIM_OK;
 }
