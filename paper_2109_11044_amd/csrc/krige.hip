@@ -646,8 +646,9 @@ __global__ void __launch_bounds__(512, 1)
 k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
                  const H* __restrict__ Bh, const H* __restrict__ Bl,
                  const float* __restrict__ colscale, const float* __restrict__ yhat, int n,
-                 const float2* __restrict__ st, float ux, float uxy, float uyx, float uy,
-                 float dx, float dy, float kscale, const int* __restrict__ fail) {
+                 const float2* __restrict__ st, const float4* __restrict__ circ, float xcut,
+                 float ux, float uxy, float uyx, float uy, float dx, float dy, float kscale,
+                 const int* __restrict__ fail) {
   if (fail[0] & 2) return;   // failed factorisation: the fields stay as drawn
   using HV = typename HalfOps<H>::V;
   constexpr int TG = 128, TR = 512;
@@ -695,11 +696,26 @@ k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
     u32x4v* sl_ = reinterpret_cast<u32x4v*>(Sl[BUF]);                     \
     CESIM_ST1X(0) CESIM_ST1X(1) CESIM_ST1X(2) CESIM_ST1X(3)               \
   }
-  // stations rotate through three chunk buffers as in the 4-wave kernel
+  // the chunks whose split correlations with the tile are all exact zeros
+  // are skipped, as in the 4-wave kernel (uniform over the workgroup)
+  float tcx, tcy, trad;
+  tile_circle(g0, TG, M, m1, dx, dy, ux, uxy, uyx, uy, tcx, tcy, trad);
+  auto next_live = [&](int kc) {
+    for (; kc < nchunks; ++kc) {
+      const float4 c4 = circ[kc];
+      const float ddx = tcx - c4.x, ddy = tcy - c4.y;
+      if (__builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy) - trad - c4.z < xcut) break;
+    }
+    return kc;
+  };
+  // stations rotate through three chunk buffers as in the 4-wave kernel:
+  // the current live chunk, the next (its correlations are formed during
+  // the current one's products) and the one after (its stations loaded)
   const int sl_ = threadIdx.x & (kKC - 1);
-  Ss[0][sl_] = st[min(sl_, n - 1)];
-  Ss[1][sl_] = st[min(kKC + sl_, n - 1)];
-  CESIM_FETCHX(0)
+  int cur = next_live(0), nxt = next_live(cur + 1);
+  Ss[0][sl_] = st[min(cur * kKC + sl_, n - 1)];
+  Ss[1][sl_] = st[min(nxt * kKC + sl_, n - 1)];
+  CESIM_FETCHX(min(cur, nchunks - 1))
   CESIM_STASHX(0)
   __syncthreads();
   HV own_h[1], own_l[1], oth_h[1], oth_l[1];
@@ -707,13 +723,14 @@ k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
   Kx[nf][q][0][lane] = own_h[0];
   Kx[nf][q][1][lane] = own_l[0];
   __syncthreads();
-  for (int kc = 0; kc < nchunks; ++kc) {
-    const int buf = kc & 1;
-    const int sb = kc % 3, sb1 = sb == 2 ? 0 : sb + 1, sb2 = sb1 == 2 ? 0 : sb1 + 1;
+  for (int it = 0; cur < nchunks; ++it) {
+    const int buf = it & 1;
+    const int sb = it % 3, sb1 = sb == 2 ? 0 : sb + 1, sb2 = sb1 == 2 ? 0 : sb1 + 1;
+    const int nn = next_live(nxt + 1);
     oth_h[0] = Kx[nf][1 - q][0][lane];
     oth_l[0] = Kx[nf][1 - q][1][lane];
-    CESIM_FETCHX(min(kc + 1, nchunks - 1))
-    const float2 ps = st[min((kc + 2) * kKC + sl_, n - 1)];
+    CESIM_FETCHX(min(nxt, nchunks - 1))
+    const float2 ps = st[min(nn * kKC + sl_, n - 1)];
     // k-step 0 is wave group 0's correlations, k-step 1 group 1's
     if (q == 0) {
       mfma_step<1, H>(Sh[buf] + 256 * q * kKC, Sl[buf] + 256 * q * kKC, 0, lane, own_h, own_l, acc);
@@ -729,6 +746,8 @@ k_krige_split3_x(float* __restrict__ fields, int m1, int M, int R, int Rp,
     CESIM_STASHX(buf ^ 1)
     Ss[sb2][sl_] = ps;
     __syncthreads();
+    cur = nxt;
+    nxt = nn;
   }
 #undef CESIM_FETCHX
 #undef CESIM_STASHX
@@ -1094,7 +1113,7 @@ cesim_status krige_grid_device(cesim_ctx c, const double* X, void* fields) {
 #define CESIM_KX(NU, H)                                                                         \
   k_krige_split3_x<NU, H><<<gridx, 512, 0, s>>>(F, m1, M, R, Rp, reinterpret_cast<const H*>(Hh),  \
                                                 reinterpret_cast<const H*>(Hl), colscale, YH, n,  \
-                                                S2, a, b, cc, d, fdx, fdy, fks, FAIL)
+                                                S2, CIRC, xcut, a, b, cc, d, fdx, fdy, fks, FAIL)
 #define CESIM_KX_NU(H)                      \
   switch (c->covd.nu_code) {                \
     case 0: CESIM_KX(0, H); break;          \
