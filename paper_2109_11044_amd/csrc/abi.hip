@@ -245,7 +245,7 @@ static std::vector<DevBuf*> all_bufs(cesim_ctx c) {
           &c->corners, &c->weights, &c->gamma, &c->phi, &c->obs_order, &c->obs_t32s,
           &c->gemm_circ, &c->amat, &c->dinv,
           &c->winv, &c->wtmp, &c->solve_tmp, &c->ainv, &c->ainv_tmp, &c->zdev, &c->coef, &c->coef_b16,
-          &c->chat, &c->chat_tmp, &c->yhat, &c->pred_part, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
+          &c->chat, &c->chat_tmp, &c->yhat, &c->pred_part, &c->pred_next, &c->info_dev, &c->chol_info, &c->winv_seq.dev,
           &c->gwork, &c->gvec, &c->vjp_work, &c->box_of, &c->box_desc, &c->box_members, &c->box_fac,
           &c->sework, &c->nn_extra, &c->nn_work};
 }
@@ -449,7 +449,7 @@ cesim_status ce_setup(const cesim_cov* cov, const cesim_grid* grid, cesim_precis
   for (DevBuf* b : {&c->amat, &c->dinv, &c->winv, &c->wtmp, &c->zdev, &c->chol_info,
                     &c->winv_seq.dev})
     b->stream = c->aux;                 // written by the work condition() puts on aux
-  for (DevBuf* b : {&c->chat, &c->chat_tmp, &c->yhat, &c->pred_part})
+  for (DevBuf* b : {&c->chat, &c->chat_tmp, &c->yhat, &c->pred_part, &c->pred_next})
     b->stream = c->look;                // written by the prediction, on the look-ahead stream
   c->timer.enabled = g_default_timing;
   cesim_status st = CESIM_OK;

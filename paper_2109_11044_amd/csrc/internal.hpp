@@ -231,6 +231,7 @@ struct cesim_ctx_s {
   cesim::DevBuf chat_tmp;           // second buffer of that solve
   cesim::DevBuf yhat;               // mixed path: K12 A^{-1} z on the grid, FP32 [M]
   cesim::DevBuf pred_part;          // its partial sums per slice of stations, FP64 [S][M]
+  cesim::DevBuf pred_next;          // item counter of the prediction kernel
   cesim::DevBuf info_dev;           // int flags of the local-Kriging setup
   cesim::DevBuf chol_info;          // int[4]: bit 2 of [0] marks a failed factorisation;
                                     // the grid GEMM leaves the fields alone when it is set

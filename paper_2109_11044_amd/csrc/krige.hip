@@ -162,8 +162,12 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
 // Work item (x, y, z) is a tile of 32 x 32 grid nodes and the z-th slice
 // of `slice` stations in the GEMM's Morton order (position p holds station
 // order[p]), staged through LDS kPredStage at a time; its FP64 partial sums
-// go to part[z][g], and k_predict_sum adds the slices in order.  A
-// workgroup takes items blockIdx.x, blockIdx.x + gridDim.x, ...  Stations come in chunks of kGemmChunk with bounding circles: a
+// go to part[z][g], and k_predict_sum adds the slices in order.  Each
+// workgroup takes the next item from the counter *next (zero at launch)
+// until none is left: items cost more near station clusters, and a fixed
+// share per workgroup left the slowest one running alone at the end; the
+// sums do not depend on which workgroup computes an item.  Stations come
+// in chunks of kGemmChunk with bounding circles: a
 // chunk whose circle is farther than kNear range units from the tile's for
 // certain takes the FP32 branch for every pair, as the per-pair test would,
 // with no test and no divergence, and one farther than kSkip is passed
@@ -178,7 +182,7 @@ k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice, int g
               int gy_tiles, int nitems, const double* __restrict__ chat,
               const double2* __restrict__ st, const int* __restrict__ order,
               const float4* __restrict__ circ, double ux, double uxy, double uyx, double uy,
-              double dx, double dy) {
+              double dx, double dy, int* __restrict__ next) {
   constexpr double kNear = NU == 0 ? 9.5 : (NU == 1 ? 8.0 : 7.0);
   constexpr double kKappa = NU == 0 ? kLog2e : (NU == 1 ? kSqrt2 : kSqrt3);
   constexpr float kNearS2 = (float)(kNear * kKappa * kNear * kKappa);
@@ -193,9 +197,15 @@ k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice, int g
   __shared__ double2 S[kPredStage];
   __shared__ float4 P[kPredStage];   // kappa-scaled FP32 coordinates, chat in FP32
   __shared__ double Cv[kPredStage];
+  __shared__ int s_item;
   // work item w: tile (w % gx_tiles, (w / gx_tiles) % gy_tiles), slice
   // w / (gx_tiles gy_tiles); every wave runs the same items
-  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+  for (;;) {
+  if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
+  __syncthreads();
+  const int w = s_item;
+  __syncthreads();
+  if (w >= nitems) break;
   const int tx = w % gx_tiles, ty = (w / gx_tiles) % gy_tiles, tz = w / (gx_tiles * gy_tiles);
   const int ix = tx * 32 + (threadIdx.x & 31), iy = ty * 32 + (threadIdx.x >> 5);
   const double gx = (double)min(ix, m1 - 1) * dx, gy = (double)min(iy, m2 - 1) * dy;
@@ -265,6 +275,8 @@ k_predict_f64(double* __restrict__ part, int m1, int m2, int n, int slice, int g
   if (ix < m1 && iy < m2) part[(size_t)tz * m1 * m2 + (size_t)iy * m1 + ix] = acc;
   }
 }
+
+__global__ void k_zero_int(int* __restrict__ v) { *v = 0; }
 
 // yhat[g] = sigma^2 (sum of the S slice sums of node g, in slice order), FP32.
 __global__ void __launch_bounds__(256)
@@ -1179,10 +1191,14 @@ static cesim_status predict_from_chat(cesim_ctx c, hipStream_t s) {
   const int nitems = gxt * gyt * S;
   const int nwg = std::min(nitems, std::max(1, c->num_cu));
   double* part = c->pred_part.as<double>();
+  CESIM_TRY(c->pred_next.reserve(sizeof(int)));
+  int* next = c->pred_next.as<int>();
+  k_zero_int<<<1, 1, 0, s>>>(next);
 #define CESIM_PRED(NU)                                                                        \
   k_predict_f64<NU><<<nwg, kPredThreads, 0, s>>>(                                             \
       part, m1, m2, n, slice, gxt, gyt, nitems, c->chat.as<double>(), c->obs_t64.as<double2>(), \
-      c->obs_order.as<int>(), c->gemm_circ.as<float4>(), ux, uxy, uyx, uy, c->grid.dx, c->grid.dy)
+      c->obs_order.as<int>(), c->gemm_circ.as<float4>(), ux, uxy, uyx, uy, c->grid.dx, c->grid.dy, \
+      next)
   switch (c->covd.nu_code) {
     case 0: CESIM_PRED(0); break;
     case 1: CESIM_PRED(1); break;
