@@ -202,7 +202,7 @@ def run_path(prec, wl, xy, z, args, torch, cesim):
 COUNTED_STAGES = {
     "draw_noise_colfft": ("k_p2_cols_noise<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp", "devmath.hpp"]),
     "draw_rowfft_crop": ("k_p2_rows_crop<float", ["ce.hip", "fft_pow2.hpp", "fft.hpp"]),
-    "krige_grid_gemm": ("k_krige_split3", ["krige.hip", "devmath.hpp"]),
+    "krige_grid_gemm": ("k_krige_split3", ["krige_mixed.hpp", "krige_tile1.hip", "devmath.hpp"]),
     "krige_predict_fp64": ("k_predict_f64", ["krige.hip", "devmath.hpp"]),
     "synth_obs_rhs": ("k_synth_rhs<float, false,", ["lk.hip", "devmath.hpp"]),
 }
