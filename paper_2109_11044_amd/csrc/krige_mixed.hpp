@@ -288,14 +288,29 @@ k_krige_split3(float* __restrict__ fields, int m1, int M, int R, int Rp,
   // the tile's bounding circle to the chunk's with the cut-off distance.
   float tcx, tcy, trad;
   tile_circle(g0, TG, M, m1, dx, dy, ux, uxy, uyx, uy, tcx, tcy, trad);
-  auto live = [&](int kc) {
-    const float4 q = circ[kc];
-    const float ddx = tcx - q.x, ddy = tcy - q.y;
-    return __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy) - trad - q.z < xcut;
-  };
+  // The test runs for 64 chunks at once, one per lane, into a wave-wide
+  // mask (the same in every wave of the workgroup), so that finding the
+  // next live chunk waits for one load per 64 chunks, not one per chunk.
+  uint64_t mask = 0;
+  int base = -64;
   auto next_live = [&](int kc) {
-    while (kc < nchunks && !live(kc)) ++kc;
-    return kc;
+    for (;;) {
+      if (kc >= nchunks) return nchunks;
+      if (kc >= base + 64) {
+        base = kc;
+        const int q = base + lane;
+        bool lv = false;
+        if (q < nchunks) {
+          const float4 c4 = circ[q];
+          const float ddx = tcx - c4.x, ddy = tcy - c4.y;
+          lv = __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy) - trad - c4.z < xcut;
+        }
+        mask = __builtin_amdgcn_ballot_w64(lv);
+      }
+      const uint64_t m = mask >> (kc - base);
+      if (m) return kc + (int)__builtin_ctzll(m);
+      kc = base + 64;
+    }
   };
   int kc = next_live(0);
   if (kc < nchunks) {
