@@ -139,3 +139,28 @@ def test_conditional_mixed_small_exact_config():
     v, B, ref = run_both(workloads.C1, "mixed", workloads.C1.nreal)
     err = rel_rms(v, ref["v"])
     assert np.all(err < MIXED_TOL), err
+
+
+def test_mixed_new_observations_rerun_the_prediction():
+    """Two conditionings on one mixed context with different observed values:
+    each runs its own prediction of the data term, whose workgroups take
+    their items from a counter reset before every launch, and each matches
+    the oracle (eq. (4) with the new values)."""
+    wl = workloads.C1
+    xy = wl.obs_xy()
+    ocov = OCov(wl.nu, wl.sigma2, wl.range, wl.aniso_ratio, wl.aniso_angle)
+    seed, nreal = 2, wl.nreal
+    with cesim.Context(cesim.make_cov(wl.nu, wl.sigma2, wl.range, wl.aniso_ratio,
+                                      wl.aniso_angle),
+                       cesim.unit_square_grid(wl.m, wl.torus), "mixed") as ctx:
+        ctx.offgrid(xy, wl.k)
+        for zseed in (0, 1):
+            z = draw_observations(xy, ocov, wl.tau2, seed=zseed)
+            f = ctx.simulate(nreal, seed, 0)
+            ctx.condition(z, wl.tau2, f)
+            v = f.cpu().numpy()
+            t1 = ctx.info()["t1"]
+            ref = conditional_simulation(ocov, OGrid.unit_square(wl.m), xy, z, wl.tau2, wl.k,
+                                         seed, nreal, 0, t1, t1)
+            err = rel_rms(v, ref["v"])
+            assert np.all(err < MIXED_TOL), (zseed, err)
