@@ -144,13 +144,13 @@ k_krige_f64(double* __restrict__ fields, int m1, int M, int R, const double* __r
 // until none is left: items cost more near station clusters, and a fixed
 // share per workgroup left the slowest one running alone at the end; the
 // sums do not depend on which workgroup computes an item.  Stations come
-// in chunks of kGemmChunk with bounding circles: a
-// chunk whose circle is farther than kNear range units from the tile's for
-// certain takes the FP32 branch for every pair, as the per-pair test would,
-// with no test and no divergence, and one farther than kSkip is passed
-// over.  The solves run beside the prediction as chains of small kernels;
-// with one workgroup (50 KB of LDS, 16 waves) per CU their workgroups find
-// free wave slots at once instead of queueing behind prediction tiles.
+// in chunks of kGemmChunk with bounding circles: a chunk whose circle is
+// farther than kNear range units from the tile's for certain takes the
+// FP32 branch for every pair, as the per-pair test would, with no test and
+// no divergence, and one farther than kSkip is passed over.  The solves run
+// beside the prediction as chains of small kernels; with one workgroup
+// (50 KB of LDS, 16 waves) per CU their workgroups find free wave slots at
+// once instead of queueing behind prediction tiles.
 constexpr int kPredThreads = 1024;
 constexpr int kPredStage = 1280;
 template <int NU>
